@@ -1,0 +1,189 @@
+"""Benchmark of the PIC Boltzmann step (arXiv:1208.0961) on one MI355X.
+
+A step is the whole per-time-step update: streaming, wall reflection,
+binning (count, scan, scatter), the pair tests with claims and kinematics,
+and the T00/T0x profiles every 50 steps.  The default workload is the 3-D
+binned Riemann tube: 10 x 2 x 2 fm, 100 x 10 x 10 cells, r_test = 2500,
+1 020 851 test particles, sigma = 0.4 fm^2, dt = 0.02 fm/c, FP64.  Inputs
+are synthetic (seeded thermal gases) and resident in HBM before timing.
+
+Prints one JSON line: particle-steps/s (whole job) plus pair tests/s, the
+roofline of the dominant kernel (the pair-test kernel, bound by integer
+ALU work: Philox4x32-10), per-stage times and HBM rates, and the CPU oracle
+timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks.
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+# 32-bit VALU lane operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+INT32_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Algorithmic work of one pair test.
+PHILOX_OPS_PER_PAIR = 20 + 40 + 1   # 32x32->64 products, XORs, the compare
+FP64_FLOPS_PER_PAIR = 12            # Eq. (3): dot, E1 E2, s, s/(2 E1 E2), x K
+# Algorithmic HBM bytes per particle of the binning stages.
+BYTES_COUNT = 48                    # read x y z px py pz
+BYTES_SCATTER = 52 + 52             # read and write the state and id
+BYTES_OBSERVE = 24                  # read px py pz
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="tube3d", choices=["tube1d", "tube3d", "full"])
+    ap.add_argument("--cpu-steps", type=int, default=None,
+                    help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--cpu-threads", type=int, default=None)
+    ap.add_argument("--traffic", default=None,
+                    help="JSON file with measured FETCH/WRITE bytes per collide launch")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, state, steps, threads):
+    from oracle import oracle as O
+    st = O.State(*state)
+    p = O.make_params(**w.params())
+    t0 = time.perf_counter()
+    O.run(p, st, 0, steps, threads)
+    dt = time.perf_counter() - t0
+    return {"value": w.n * steps / dt, "unit": "particle-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{w.name}: {steps} steps of all {w.n} particles from the "
+                      f"benchmark's initial state, {threads} threads over cells, "
+                      f"{dt:.1f} s wall"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the method's "
+              "multi-GPU slab decomposition is not part of this build.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    from paper_1208_0961_amd import build as hip_build
+    if not os.path.exists(hip_build.LIB):
+        hip_build.build()
+    from paper_1208_0961_amd import cuba as C
+    from paper_1208_0961_amd import sim as S
+    from paper_1208_0961_amd import workload as W
+
+    w = W.ALIASES[a.workload]
+    state = W.riemann_state(w)
+    sim = S.Sim(w.params(), state)
+    print(f"# {w.name}: {w.n} particles, {w.n_cells} cells; warmup {a.warmup}",
+          file=sys.stderr, flush=True)
+    sim.step(a.warmup)
+    sim.sync()
+    c0 = C.cuba_counters(sim.ctx)
+    n_obs = sum(1 for s in range(a.steps) if (a.warmup + s + 1) % w.observe_every == 0)
+    C.cuba_timing_begin(sim.ctx, 4 * a.steps + n_obs + 8)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(a.steps):
+        C.cuba_step(sim.ctx, 1)
+        if (a.warmup + s + 1) % w.observe_every == 0:
+            sim.observe_async()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+
+    stages = C.cuba_timing_end(sim.ctx)
+    c1 = C.cuba_counters(sim.ctx)
+    sim.sync()
+    elapsed = t1 - t0
+    pairs = c1["pair_tests"] - c0["pair_tests"]
+    cand = c1["candidates"] - c0["candidates"]
+    claims = c1["claims"] - c0["claims"]
+    value = w.n * a.steps / elapsed
+
+    def avg_ms(name):
+        ms, k = stages[name]
+        return ms / k if k else float("nan")
+
+    coll_ms = avg_ms("collide")
+    pairs_per_launch = pairs / a.steps
+    achieved_tops = PHILOX_OPS_PER_PAIR * pairs_per_launch / (coll_ms * 1e-3) / 1e12
+    traffic = None
+    if a.traffic and os.path.exists(a.traffic):
+        with open(a.traffic) as f:
+            traffic = json.load(f).get("collide_bytes_per_launch")
+
+    def gbs(nbytes, ms):
+        return nbytes / (ms * 1e-3) / 1e9
+
+    stage_out = {}
+    for name in C.STAGES:
+        ms, k = stages[name]
+        stage_out[name] = {"ms_per_launch": ms / k if k else None, "launches": k}
+    stage_out["count"]["gbs"] = gbs(BYTES_COUNT * w.n, avg_ms("count"))
+    stage_out["scatter"]["gbs"] = gbs(BYTES_SCATTER * w.n, avg_ms("scatter"))
+    for name in ("count", "scatter"):
+        stage_out[name]["frac_hbm"] = stage_out[name]["gbs"] / HBM_PEAK_GBS
+    stage_out["collide"]["pair_tests_per_launch"] = pairs_per_launch
+    stage_out["collide"]["fp64_tflops_algorithmic"] = (
+        FP64_FLOPS_PER_PAIR * pairs_per_launch / (coll_ms * 1e-3) / 1e12)
+    bin_ms = avg_ms("count") + avg_ms("scan") + avg_ms("scatter")
+    stage_out["binning_total"] = {
+        "ms_per_step": bin_ms,
+        "gbs": gbs((BYTES_COUNT + BYTES_SCATTER) * w.n, bin_ms),
+        "frac_hbm": gbs((BYTES_COUNT + BYTES_SCATTER) * w.n, bin_ms) / HBM_PEAK_GBS}
+
+    cpu = None
+    cpu_steps = a.cpu_steps if a.cpu_steps is not None else {"tube1d": 100, "tube3d": 24,
+                                                              "full": 2}[a.workload]
+    if cpu_steps > 0:
+        threads = a.cpu_threads or max(1, min(16, os.cpu_count() or 1))
+        print(f"# cpu baseline: {cpu_steps} oracle steps, {threads} threads",
+              file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w, state, cpu_steps, threads)
+
+    out = {
+        "metric": "particle-steps/s + FP64 pair-tests/s; ensemble p50/p99 latency vs plain",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * elapsed / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: seeded thermal Riemann gas (T 0.40 / 0.32 GeV), no dataset",
+        "config": {"workload": w.name, "n_particles": w.n, "cells": list(w.cells),
+                   "box_fm": list(w.box), "r_test": w.r_test, "sigma_fm2": w.sigma,
+                   "dt_fm": w.dt, "observe_every": w.observe_every},
+        "pair_tests_per_s": pairs / elapsed,
+        "candidates_per_step": cand / a.steps,
+        "scatterings_per_step": claims / a.steps,
+        "roofline": {"bound": "alu", "kernel": "collide",
+                     "achieved": achieved_tops, "peak": INT32_PEAK_TOPS,
+                     "unit": "Tops/s", "frac": achieved_tops / INT32_PEAK_TOPS,
+                     "traffic": traffic,
+                     "ops_per_pair_test": PHILOX_OPS_PER_PAIR,
+                     "ms_per_launch": coll_ms},
+        "stages": stage_out,
+        "cpu_baseline": cpu,
+    }
+    sim.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

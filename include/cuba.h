@@ -1,0 +1,188 @@
+/*
+ * cuba.h -- C ABI of libcuba.so, an MI355X (gfx950) implementation of the
+ * per-time-step particle-in-cell Boltzmann update of "CuBA - a CUDA
+ * implementation of BAMPS" (Cardoso, Bicudo, Eilhauer, Bouras;
+ * arXiv:1208.0961).
+ *
+ * The method (Sec. 2 of the paper): a massless gluon gas is represented by
+ * test particles with position r and momentum p in a box with reflecting
+ * walls, divided into cells of volume V_cell = dx dy dz.  One step of length
+ * dt
+ *   1. free-streams every particle, x <- x + (p_x / E) dt with E = |p|
+ *      (Eq. (2), c = 1), likewise y and z;
+ *   2. reflects it elastically at the six walls (mirror the overshoot, flip
+ *      the normal momentum component);
+ *   3. bins the particles into cells;
+ *   4. tests every pair (a < b) of particles in the same cell for a binary
+ *      collision with probability P22 = v_rel sigma / r_test * dt / V_cell,
+ *      v_rel = s / (2 E1 E2) (Eq. (3) with the test-particle rescaling);
+ *      a particle scatters at most once per step: pairs are taken in
+ *      lexicographic order of their canonical indices and skipped when a
+ *      member has already scattered in the step;
+ *   5. gives each accepted pair an isotropic direction in its CM frame with
+ *      |p*| = sqrt(s)/2 and boosts back to the lab.
+ *
+ * Determinism contract.  Within a cell, particles are ordered by id (the
+ * index in the arrays given to cuba_init); pair (a, b) of an n-particle
+ * cell c has index k = a (2n - a - 1) / 2 + (b - a - 1).  Its acceptance
+ * uniform is u = ((w1:w0) >> 11) 2^-53 of the Philox4x32-10 block with
+ * counter (k, c, t, 0) and key (seed low word, seed high word), t the step
+ * index; the outgoing direction takes cos(theta) = 2 U53(w0, w1) - 1 and
+ * phi = 2 pi U53(w2, w3) of the block with counter (k, c, t, 1), and the
+ * lower index a takes +n.  Cell ids are x-major: c = (ix ny + iy) nz + iz,
+ * i_d = min(floor(x_d / dx_d), n_d - 1).  Given the same state, step index
+ * and seed, cell indices, the canonical order, the candidate and accepted
+ * pairs, positions, and the momenta of particles that did not scatter are
+ * bit-identical to any correct implementation of this contract; scattered
+ * momenta agree to rounding of sin and cos (|dp| <= 1e-12 (Ea + Eb)).
+ *
+ * Conventions for every function below.
+ *  - Units: fm for lengths, GeV for momenta, c = 1.
+ *  - "device" pointers are HIP device allocations owned by the caller;
+ *    "host" pointers are ordinary host memory.  The library allocates no
+ *    device memory: all of its device state lives in the caller's
+ *    workspace.  It allocates only the small host-side context.
+ *  - stream arguments are hipStream_t values passed as void* (NULL: the
+ *    null stream).  All device work of a context is issued on its stream,
+ *    asynchronously; errors raised by the device (a cell holding more than
+ *    CUBA_MAX_CELL_OCCUPANCY particles, a trace buffer too small) are
+ *    reported by the next cuba_sync.
+ *  - A context is not thread-safe; one context per stream.
+ *  - Return values: CUBA_OK (0) or a negative CUBA_E* code; cuba_strerror
+ *    names the code and cuba_last_error() gives the detail of the most
+ *    recent failure on the calling thread.
+ */
+#ifndef CUBA_H
+#define CUBA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CUBA_OK 0
+#define CUBA_EINVAL -1  /* invalid parameters or arguments                 */
+#define CUBA_ERANGE -2  /* a particle outside the box, a non-finite value,
+                           |p| = 0, or a cell over the occupancy limit      */
+#define CUBA_ENOMEM -3  /* workspace (or trace buffer) too small           */
+#define CUBA_EDEVICE -4 /* HIP runtime error; see cuba_last_error()         */
+
+/* Largest number of particles one cell may hold in a step. */
+#define CUBA_MAX_CELL_OCCUPANCY 1024
+
+typedef struct cuba_ctx cuba_ctx;
+
+/* Problem definition (Sec. 2; the step-size rule is from Sec. 5). */
+typedef struct {
+  double box[3];    /* Lx, Ly, Lz [fm] > 0; walls at 0 and L_d on each axis */
+  int32_t cells[3]; /* nx, ny, nz >= 1; dx_d = L_d / n_d (FP64)             */
+  double sigma;     /* total isotropic cross section [fm^2], >= 0           */
+  double r_test;    /* test particles per physical particle, > 0            */
+  double dt;        /* time step [fm/c], 0 < dt < min_d dx_d                */
+  uint64_t seed;    /* Philox key: key[0] = low 32 bits, key[1] = high      */
+  uint32_t step0;   /* index t of the first step (0, or t when resuming)    */
+} cuba_params;
+
+/* Bytes of device workspace cuba_init needs for n particles with these
+ * parameters (for admission by memory footprint).  Returns 0 if the
+ * parameters are invalid.  The workspace must be 256-byte aligned. */
+size_t cuba_workspace_bytes(const cuba_params *params, int64_t n);
+
+/* Creates a context.  x..pz are device arrays of n doubles (particle id =
+ * array index), copied into the workspace; they may be freed once the
+ * stream has passed this call.  workspace: device memory of ws_bytes >=
+ * cuba_workspace_bytes(params, n), owned by the caller and used by the
+ * context until cuba_destroy.  Validates the parameters (CUBA_EINVAL:
+ * non-finite or non-positive box, cells, r_test or dt; sigma < 0;
+ * dt >= min dx_d; 2 K > 1 with K = sigma / r_test * dt / V_cell, which
+ * would let P22 exceed 1) and the particles (CUBA_ERANGE: outside
+ * [0, L_d], non-finite, |p| = 0; this check synchronizes the stream), then
+ * bins the initial state.  On success *out receives the context. */
+int cuba_init(cuba_ctx **out, const cuba_params *params, int64_t n,
+              const double *x, const double *y, const double *z,
+              const double *px, const double *py, const double *pz,
+              void *workspace, size_t ws_bytes, void *stream);
+
+/* Advances the state by nsteps >= 0 steps, asynchronously on the stream.
+ * Step indices continue from params->step0. */
+int cuba_step(cuba_ctx *ctx, int32_t nsteps);
+
+/* Lab-frame energy and x-momentum density profiles over the nx slabs of
+ * cells along x, of the current state (Fig. 2 of the paper shows the
+ * energy density): T00[ix] = sum_{particles in slab} E / (r_test dx Ly Lz),
+ * T0x[ix] = sum p_x / (same) [GeV/fm^3].  T00, T0x: device arrays of nx
+ * doubles.  Sums run in the (unspecified) storage order. */
+int cuba_observe(cuba_ctx *ctx, double *T00, double *T0x);
+
+/* Copies the current state into device arrays of n doubles in id order. */
+int cuba_get_state(cuba_ctx *ctx, double *x, double *y, double *z,
+                   double *px, double *py, double *pz);
+
+/* One step with a record of its decisions, for parity checks.  All arrays
+ * are device memory owned by the caller; a NULL array is not written.
+ *   cell    [n]      cell of each particle (by id) after this step's binning
+ *   perm    [n]      ids in canonical (cell, id) order
+ *   offsets [C+1]    start of each cell in perm (C = nx ny nz)
+ *   cand    [3*cand_cap]   (cell, a, b) of every pair with u < P22 judged on
+ *                          the momenta before the cell's collisions, in
+ *                          unspecified order
+ *   claim   [3*claim_cap]  (cell, a, b) of the pairs that scattered,
+ *                          unspecified order
+ *   counts  [2]      number of candidates and claims (written even when
+ *                    they exceed the capacities; then cuba_sync reports
+ *                    CUBA_ENOMEM and only the first *_cap are stored) */
+typedef struct {
+  uint32_t *cell;
+  uint32_t *perm;
+  uint32_t *offsets;
+  uint32_t *cand;
+  int64_t cand_cap;
+  uint32_t *claim;
+  int64_t claim_cap;
+  uint32_t *counts;
+} cuba_trace;
+
+int cuba_trace_step(cuba_ctx *ctx, const cuba_trace *trace);
+
+/* Waits for the context's stream and reports device-side errors raised
+ * since the last cuba_sync (CUBA_ERANGE, CUBA_ENOMEM) or CUBA_EDEVICE. */
+int cuba_sync(cuba_ctx *ctx);
+
+/* Index of the next step, number of particles, number of cells. */
+int cuba_info(const cuba_ctx *ctx, uint32_t *next_step, int64_t *n,
+              int64_t *n_cells);
+
+/* Cumulative work and decision counts since cuba_init (synchronizes the
+ * stream): out[0] pair tests (sum over cells of n(n-1)/2 per step),
+ * out[1] candidate pairs (u < P22), out[2] scatterings (claimed pairs). */
+int cuba_counters(cuba_ctx *ctx, uint64_t out[3]);
+
+/* Stage timing.  cuba_timing_begin makes the following steps and
+ * observations record a HIP event on the context's stream between their
+ * stages, for at most max_launches stage launches; cuba_timing_end waits
+ * for the stream and writes, per stage, the summed duration in ms and the
+ * number of launches timed.  Stages (index into the arrays):
+ *   0 count   (stream + reflect + cell histogram)
+ *   1 scan    (cell offsets)
+ *   2 scatter (stream + reflect + permutation into cell order)
+ *   3 collide (pair tests, claims, kinematics)
+ *   4 observe (slab profiles)
+ * Events are host-side runtime objects; no device memory is allocated. */
+#define CUBA_NUM_STAGES 5
+int cuba_timing_begin(cuba_ctx *ctx, int32_t max_launches);
+int cuba_timing_end(cuba_ctx *ctx, double stage_ms[CUBA_NUM_STAGES],
+                    int64_t stage_launches[CUBA_NUM_STAGES]);
+
+/* Frees the host context; the caller's workspace is not touched. */
+void cuba_destroy(cuba_ctx *ctx);
+
+/* Name of an error code; detail of the calling thread's last failure. */
+const char *cuba_strerror(int code);
+const char *cuba_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CUBA_H */

@@ -174,6 +174,18 @@ def step(p: Params, st: State, t: int, nthreads: int = 1, trace: bool = False,
         return None
     C = int(p.cells[0]) * int(p.cells[1]) * int(p.cells[2])
     cap = cand_cap if cand_cap is not None else max(64, n)
+    saved = [a.copy() for a in st.arrs]
+    while True:
+        out = _traced_step(p, st, t, n, C, cap)
+        if out is not None:
+            return out
+        # more candidates than room: redo the step from the saved state
+        for a, b in zip(st.arrs, saved):
+            a[:] = b
+        cap = _traced_step.last_count + 64
+
+
+def _traced_step(p, st, t, n, C, cap):
     cell = np.zeros(n, np.uint32)
     perm = np.zeros(n, np.uint32)
     offs = np.zeros(C + 1, np.uint32)
@@ -185,7 +197,8 @@ def step(p: Params, st: State, t: int, nthreads: int = 1, trace: bool = False,
     if rc != OK:
         raise RuntimeError(f"orc_step failed: {rc}")
     if tr.n_cand > cap:
-        raise RuntimeError("candidate capacity exceeded")
+        _traced_step.last_count = tr.n_cand
+        return None
     return {"cell": cell, "perm": perm, "offsets": offs,
             "cand": cand[:tr.n_cand].copy(), "claim": claim[:tr.n_claim].copy()}
 

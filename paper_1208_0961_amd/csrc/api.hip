@@ -1,0 +1,453 @@
+// api.hip -- the C ABI of libcuba.so (declared in include/cuba.h): parameter
+// validation, the workspace layout, the launch order of one step, and
+// error reporting.  All device state lives in the caller's workspace.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cuba.h"
+#include "internal.hpp"
+
+using namespace cuba;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *where) {
+  return fail(CUBA_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+inline size_t align256(size_t v) { return (v + 255u) & ~(size_t)255u; }
+
+// Byte offsets of every array inside the workspace.
+struct Layout {
+  size_t status;
+  size_t soa[2][7];  // x y z px py pz id, for the two buffers
+  size_t counts, offsets, cursor, tile_sums, obs_partial;
+  size_t total;
+};
+
+Layout make_layout(int64_t n, int64_t n_cells, int64_t nx) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&off](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  const size_t cc = (size_t)n_cells;
+  const size_t tiles = (cc + kScanTile - 1) / kScanTile;
+  L.status = take(sizeof(DevStatus));
+  for (int b = 0; b < 2; ++b) {
+    for (int a = 0; a < 6; ++a) L.soa[b][a] = take(nn * sizeof(double));
+    L.soa[b][6] = take(nn * sizeof(uint32_t));
+  }
+  L.counts = take(cc * sizeof(uint32_t));
+  L.offsets = take((cc + 1) * sizeof(uint32_t));
+  L.cursor = take(cc * sizeof(uint32_t));
+  L.tile_sums = take(tiles * sizeof(uint32_t));
+  L.obs_partial = take((size_t)nx * kObsChunks * 2 * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+// Validated problem constants (same formulas as the determinism contract).
+struct Derived {
+  Geometry g;
+  double vcell, kfac, vol;
+  int64_t n_cells;
+};
+
+int derive(const cuba_params *p, Derived &d) {
+  if (!p) return fail(CUBA_EINVAL, "params is NULL");
+  int64_t nc = 1;
+  for (int k = 0; k < 3; ++k) {
+    if (!(std::isfinite(p->box[k]) && p->box[k] > 0.0))
+      return fail(CUBA_EINVAL, "box edges must be finite and > 0");
+    if (p->cells[k] < 1) return fail(CUBA_EINVAL, "cells must be >= 1");
+    nc *= p->cells[k];
+  }
+  if (nc >= ((int64_t)1 << 31)) return fail(CUBA_EINVAL, "too many cells (>= 2^31)");
+  if (!(std::isfinite(p->sigma) && p->sigma >= 0.0))
+    return fail(CUBA_EINVAL, "sigma must be finite and >= 0");
+  if (!(std::isfinite(p->r_test) && p->r_test > 0.0))
+    return fail(CUBA_EINVAL, "r_test must be finite and > 0");
+  if (!(std::isfinite(p->dt) && p->dt > 0.0))
+    return fail(CUBA_EINVAL, "dt must be finite and > 0");
+  for (int k = 0; k < 3; ++k) {
+    d.g.L[k] = p->box[k];
+    d.g.n[k] = p->cells[k];
+    d.g.dx[k] = p->box[k] / (double)p->cells[k];
+    // Sec. 5: dt below the cell edge, so a particle moves at most one cell
+    if (!(p->dt < d.g.dx[k])) return fail(CUBA_EINVAL, "dt must be below every cell edge");
+  }
+  d.g.dt = p->dt;
+  d.vcell = (d.g.dx[0] * d.g.dx[1]) * d.g.dx[2];
+  d.kfac = ((p->sigma / p->r_test) * p->dt) / d.vcell;
+  if (!(2.0 * d.kfac <= 1.0))
+    return fail(CUBA_EINVAL, "sigma / r_test * dt / V_cell > 1/2: P22 could exceed 1");
+  d.vol = ((p->r_test * d.g.dx[0]) * p->box[1]) * p->box[2];
+  d.n_cells = nc;
+  return CUBA_OK;
+}
+
+// Pairs can only be accepted when the Philox high word w1 is below this:
+// u >= w1 2^-32 and P22 <= 2 K (1 + 13 eps) < 2 K (1 + 2^-30).
+uint64_t w1_limit(double kfac) {
+  const double pmax = (2.0 * kfac) * (1.0 + 0x1p-30);
+  const double lim = std::ceil(pmax * 0x1p32);
+  if (lim >= 0x1p32) return (uint64_t)1 << 32;
+  return (uint64_t)lim;
+}
+
+}  // namespace
+
+// One timed stage launch: events recorded just before and after it.
+struct TimedLaunch {
+  int stage;
+  hipEvent_t before, after;
+};
+
+struct cuba_ctx {
+  Derived d;
+  PairArgs pa;
+  int64_t n;
+  uint32_t next_step;
+  hipStream_t stream;
+  DevStatus *status;
+  SoA buf[2];
+  int cur;
+  uint32_t *counts, *offsets, *cursor, *tile_sums;
+  double *obs_partial;
+  // stage timing (cuba_timing_begin / cuba_timing_end)
+  bool timing = false;
+  size_t timing_cap = 0;
+  std::vector<hipEvent_t> event_pool;
+  std::vector<TimedLaunch> timed;
+};
+
+namespace {
+
+int check_launch(const char *where) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, where);
+  return CUBA_OK;
+}
+
+enum Stage { kStageCount = 0, kStageScan, kStageScatter, kStageCollide, kStageObserve };
+
+// Runs launch(); while timing, brackets it with two events on the stream.
+template <typename F>
+void stage(cuba_ctx *c, int which, F &&launch) {
+  if (c->timing && c->timed.size() < c->timing_cap) {
+    const size_t k = c->timed.size();
+    TimedLaunch t{which, c->event_pool[2 * k], c->event_pool[2 * k + 1]};
+    (void)hipEventRecord(t.before, c->stream);
+    launch();
+    (void)hipEventRecord(t.after, c->stream);
+    c->timed.push_back(t);
+  } else {
+    launch();
+  }
+}
+
+void drop_timing(cuba_ctx *c) {
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  c->event_pool.clear();
+  c->timed.clear();
+  c->timing = false;
+  c->timing_cap = 0;
+}
+
+// One step: stream+count, scan, stream+scatter into the other buffer,
+// collide in place there.
+int run_step(cuba_ctx *c, const TraceArgs *tr) {
+  const SoA &src = c->buf[c->cur];
+  const SoA &dst = c->buf[c->cur ^ 1];
+  stage(c, kStageCount,
+        [&] { launch_count(src, c->n, c->d.g, true, c->counts, c->stream); });
+  stage(c, kStageScan, [&] {
+    launch_scan(c->counts, c->offsets, c->cursor, c->tile_sums, c->d.n_cells, c->stream);
+  });
+  stage(c, kStageScatter, [&] {
+    launch_scatter(src, dst, c->n, c->d.g, true, c->cursor, tr ? tr->cell : nullptr,
+                   c->stream);
+  });
+  stage(c, kStageCollide, [&] {
+    launch_collide(c->offsets, dst, c->d.n_cells, c->next_step, c->pa, c->status, tr,
+                   c->stream);
+  });
+  c->cur ^= 1;
+  c->next_step += 1;
+  return check_launch("step launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t cuba_workspace_bytes(const cuba_params *params, int64_t n) {
+  Derived d;
+  if (derive(params, d) != CUBA_OK || n < 0 || n >= 0xFFFFFFFFll) return 0;
+  return make_layout(n, d.n_cells, params->cells[0]).total;
+}
+
+int cuba_init(cuba_ctx **out, const cuba_params *params, int64_t n, const double *x,
+              const double *y, const double *z, const double *px, const double *py,
+              const double *pz, void *workspace, size_t ws_bytes, void *stream) {
+  if (!out) return fail(CUBA_EINVAL, "out is NULL");
+  *out = nullptr;
+  Derived d;
+  int rc = derive(params, d);
+  if (rc != CUBA_OK) return rc;
+  if (n < 0 || n >= 0xFFFFFFFFll) return fail(CUBA_EINVAL, "n must be in [0, 2^32 - 1)");
+  if (n > 0 && !(x && y && z && px && py && pz))
+    return fail(CUBA_EINVAL, "particle arrays must not be NULL");
+  if (!workspace) return fail(CUBA_EINVAL, "workspace is NULL");
+  if (((uintptr_t)workspace & 255u) != 0)
+    return fail(CUBA_EINVAL, "workspace must be 256-byte aligned");
+  const Layout L = make_layout(n, d.n_cells, params->cells[0]);
+  if (ws_bytes < L.total)
+    return fail(CUBA_ENOMEM, "workspace too small: need " + std::to_string(L.total) +
+                                 " bytes, got " + std::to_string(ws_bytes));
+
+  cuba_ctx *c = new (std::nothrow) cuba_ctx();
+  if (!c) return fail(CUBA_ENOMEM, "host allocation failed");
+  c->d = d;
+  c->pa.kfac = d.kfac;
+  c->pa.w1_limit = w1_limit(d.kfac);
+  c->pa.key0 = (uint32_t)(params->seed & 0xFFFFFFFFu);
+  c->pa.key1 = (uint32_t)(params->seed >> 32);
+  c->n = n;
+  c->next_step = params->step0;
+  c->stream = (hipStream_t)stream;
+  char *ws = (char *)workspace;
+  c->status = (DevStatus *)(ws + L.status);
+  for (int b = 0; b < 2; ++b) {
+    c->buf[b].x = (double *)(ws + L.soa[b][0]);
+    c->buf[b].y = (double *)(ws + L.soa[b][1]);
+    c->buf[b].z = (double *)(ws + L.soa[b][2]);
+    c->buf[b].px = (double *)(ws + L.soa[b][3]);
+    c->buf[b].py = (double *)(ws + L.soa[b][4]);
+    c->buf[b].pz = (double *)(ws + L.soa[b][5]);
+    c->buf[b].id = (uint32_t *)(ws + L.soa[b][6]);
+  }
+  c->counts = (uint32_t *)(ws + L.counts);
+  c->offsets = (uint32_t *)(ws + L.offsets);
+  c->cursor = (uint32_t *)(ws + L.cursor);
+  c->tile_sums = (uint32_t *)(ws + L.tile_sums);
+  c->obs_partial = (double *)(ws + L.obs_partial);
+  c->cur = 0;
+
+  // clear status and counts, load and check the particles
+  launch_fill_u32((uint32_t *)c->status, 0u, sizeof(DevStatus) / sizeof(uint32_t),
+                  c->stream);
+  launch_fill_u32(c->counts, 0u, d.n_cells, c->stream);
+  launch_load(x, y, z, px, py, pz, c->buf[0], n, d.g, c->status, c->stream);
+  rc = check_launch("init launch");
+  if (rc != CUBA_OK) {
+    delete c;
+    return rc;
+  }
+  uint32_t err = 0;
+  hipError_t e = hipMemcpyAsync(&err, &c->status->err, sizeof(err),
+                                hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "init check");
+  }
+  if (err & kErrRange) {
+    delete c;
+    return fail(CUBA_ERANGE,
+                "a particle is outside [0, L], non-finite, or has |p| = 0");
+  }
+  // bin the initial state (no streaming) into the other buffer
+  launch_count(c->buf[0], n, d.g, false, c->counts, c->stream);
+  launch_scan(c->counts, c->offsets, c->cursor, c->tile_sums, d.n_cells, c->stream);
+  launch_scatter(c->buf[0], c->buf[1], n, d.g, false, c->cursor, nullptr, c->stream);
+  c->cur = 1;
+  rc = check_launch("init binning");
+  if (rc != CUBA_OK) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return CUBA_OK;
+}
+
+int cuba_step(cuba_ctx *c, int32_t nsteps) {
+  if (!c) return fail(CUBA_EINVAL, "ctx is NULL");
+  if (nsteps < 0) return fail(CUBA_EINVAL, "nsteps must be >= 0");
+  for (int32_t s = 0; s < nsteps; ++s) {
+    const int rc = run_step(c, nullptr);
+    if (rc != CUBA_OK) return rc;
+  }
+  return CUBA_OK;
+}
+
+int cuba_trace_step(cuba_ctx *c, const cuba_trace *t) {
+  if (!c || !t) return fail(CUBA_EINVAL, "ctx or trace is NULL");
+  if (!t->counts) return fail(CUBA_EINVAL, "trace counts is NULL");
+  if (t->cand_cap < 0 || t->claim_cap < 0 || t->cand_cap > 0xFFFFFFFFll ||
+      t->claim_cap > 0xFFFFFFFFll)
+    return fail(CUBA_EINVAL, "trace capacities out of range");
+  TraceArgs tr{};
+  tr.cell = t->cell;
+  tr.perm = t->perm;
+  tr.cand = t->cand;
+  tr.cand_cap = (uint32_t)t->cand_cap;
+  tr.claim = t->claim;
+  tr.claim_cap = (uint32_t)t->claim_cap;
+  tr.counts = t->counts;
+  launch_fill_u32(t->counts, 0u, 2, c->stream);
+  int rc = run_step(c, &tr);
+  if (rc != CUBA_OK) return rc;
+  if (t->offsets) {
+    const hipError_t e =
+        hipMemcpyAsync(t->offsets, c->offsets, (size_t)(c->d.n_cells + 1) * sizeof(uint32_t),
+                       hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "trace offsets copy");
+  }
+  return CUBA_OK;
+}
+
+int cuba_observe(cuba_ctx *c, double *T00, double *T0x) {
+  if (!c || !T00 || !T0x) return fail(CUBA_EINVAL, "NULL argument");
+  stage(c, kStageObserve, [&] {
+    launch_observe(c->offsets, c->buf[c->cur], c->d.g, c->d.vol, c->obs_partial, T00, T0x,
+                   c->stream);
+  });
+  return check_launch("observe launch");
+}
+
+int cuba_get_state(cuba_ctx *c, double *x, double *y, double *z, double *px,
+                   double *py, double *pz) {
+  if (!c) return fail(CUBA_EINVAL, "ctx is NULL");
+  if (c->n > 0 && !(x && y && z && px && py && pz))
+    return fail(CUBA_EINVAL, "NULL output array");
+  launch_gather_by_id(c->buf[c->cur], c->n, x, y, z, px, py, pz, c->stream);
+  return check_launch("get_state launch");
+}
+
+int cuba_sync(cuba_ctx *c) {
+  if (!c) return fail(CUBA_EINVAL, "ctx is NULL");
+  uint32_t err = 0;
+  hipError_t e = hipMemcpyAsync(&err, &c->status->err, sizeof(err), hipMemcpyDeviceToHost,
+                                c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(e, "sync");
+  if (err != 0) {
+    launch_fill_u32(&c->status->err, 0u, 1, c->stream);
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "sync reset");
+    if (err & kErrOccupancy)
+      return fail(CUBA_ERANGE, "a cell held more than " +
+                                   std::to_string(CUBA_MAX_CELL_OCCUPANCY) +
+                                   " particles; its collisions were skipped");
+    if (err & kErrTrace) return fail(CUBA_ENOMEM, "trace buffer too small");
+    return fail(CUBA_ERANGE, "device reported an invalid state");
+  }
+  return CUBA_OK;
+}
+
+int cuba_info(const cuba_ctx *c, uint32_t *next_step, int64_t *n, int64_t *n_cells) {
+  if (!c) return fail(CUBA_EINVAL, "ctx is NULL");
+  if (next_step) *next_step = c->next_step;
+  if (n) *n = c->n;
+  if (n_cells) *n_cells = c->d.n_cells;
+  return CUBA_OK;
+}
+
+int cuba_counters(cuba_ctx *c, uint64_t out[3]) {
+  if (!c || !out) return fail(CUBA_EINVAL, "NULL argument");
+  static_assert(sizeof(unsigned long long) == sizeof(uint64_t), "counter width");
+  std::vector<unsigned long long> h(3 * kCounterSlots);
+  hipError_t e = hipMemcpyAsync(h.data(), c->status->pairs, h.size() * sizeof(h[0]),
+                                hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(e, "counters");
+  for (int k = 0; k < 3; ++k) {
+    uint64_t sum = 0;
+    for (uint32_t j = 0; j < kCounterSlots; ++j) sum += h[k * kCounterSlots + j];
+    out[k] = sum;
+  }
+  return CUBA_OK;
+}
+
+int cuba_timing_begin(cuba_ctx *c, int32_t max_launches) {
+  if (!c || max_launches < 1) return fail(CUBA_EINVAL, "bad timing arguments");
+  drop_timing(c);
+  c->event_pool.resize(2 * (size_t)max_launches);
+  for (size_t k = 0; k < c->event_pool.size(); ++k) {
+    const hipError_t e = hipEventCreate(&c->event_pool[k]);
+    if (e != hipSuccess) {
+      c->event_pool.resize(k);
+      drop_timing(c);
+      return hip_fail(e, "timing events");
+    }
+  }
+  c->timed.reserve((size_t)max_launches);
+  c->timing_cap = (size_t)max_launches;
+  c->timing = true;
+  return CUBA_OK;
+}
+
+int cuba_timing_end(cuba_ctx *c, double stage_ms[CUBA_NUM_STAGES],
+                    int64_t stage_launches[CUBA_NUM_STAGES]) {
+  if (!c || !stage_ms || !stage_launches) return fail(CUBA_EINVAL, "NULL argument");
+  for (int k = 0; k < CUBA_NUM_STAGES; ++k) {
+    stage_ms[k] = 0.0;
+    stage_launches[k] = 0;
+  }
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    drop_timing(c);
+    return hip_fail(e, "timing sync");
+  }
+  for (const TimedLaunch &t : c->timed) {
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, t.before, t.after);
+    if (e != hipSuccess) {
+      drop_timing(c);
+      return hip_fail(e, "timing elapsed");
+    }
+    stage_ms[t.stage] += ms;
+    stage_launches[t.stage] += 1;
+  }
+  drop_timing(c);
+  return CUBA_OK;
+}
+
+void cuba_destroy(cuba_ctx *c) {
+  if (!c) return;
+  drop_timing(c);
+  delete c;
+}
+
+const char *cuba_strerror(int code) {
+  switch (code) {
+    case CUBA_OK: return "CUBA_OK";
+    case CUBA_EINVAL: return "CUBA_EINVAL: invalid parameters or arguments";
+    case CUBA_ERANGE: return "CUBA_ERANGE: particle state out of range";
+    case CUBA_ENOMEM: return "CUBA_ENOMEM: workspace or buffer too small";
+    case CUBA_EDEVICE: return "CUBA_EDEVICE: HIP runtime error";
+    default: return "unknown cuba error code";
+  }
+}
+
+const char *cuba_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

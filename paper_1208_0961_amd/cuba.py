@@ -1,0 +1,187 @@
+"""ctypes binding of libcuba.so -- the functions of include/cuba.h under the
+same names, argument marshalling only.  Pointers are passed as integers
+(device addresses, e.g. ``tensor.data_ptr()``); a non-zero return code
+raises :class:`CubaError` carrying the library's detail message.
+
+Importing this module loads libcuba.so and raises if it has not been built
+(``python -c "import __graft_entry__ as g; g.build()"``): there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcuba.so")
+
+CUBA_OK = 0
+CUBA_EINVAL = -1
+CUBA_ERANGE = -2
+CUBA_ENOMEM = -3
+CUBA_EDEVICE = -4
+CUBA_MAX_CELL_OCCUPANCY = 1024
+
+
+class CubaError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        super().__init__(f"{where}: {cuba_strerror(code)} ({detail})")
+        self.code = code
+
+
+class cuba_params(ctypes.Structure):
+    _fields_ = [("box", ctypes.c_double * 3),
+                ("cells", ctypes.c_int32 * 3),
+                ("sigma", ctypes.c_double),
+                ("r_test", ctypes.c_double),
+                ("dt", ctypes.c_double),
+                ("seed", ctypes.c_uint64),
+                ("step0", ctypes.c_uint32)]
+
+
+class cuba_trace(ctypes.Structure):
+    _fields_ = [("cell", ctypes.c_void_p),
+                ("perm", ctypes.c_void_p),
+                ("offsets", ctypes.c_void_p),
+                ("cand", ctypes.c_void_p),
+                ("cand_cap", ctypes.c_int64),
+                ("claim", ctypes.c_void_p),
+                ("claim_cap", ctypes.c_int64),
+                ("counts", ctypes.c_void_p)]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is not built: the HIP library is required "
+                          "(build it with paper_1208_0961_amd.build.build())")
+    L = ctypes.CDLL(_LIB_PATH)
+    vp, i64, i32, u32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32
+    P = ctypes.POINTER(cuba_params)
+    L.cuba_workspace_bytes.argtypes = [P, i64]
+    L.cuba_workspace_bytes.restype = ctypes.c_size_t
+    L.cuba_init.argtypes = [ctypes.POINTER(vp), P, i64] + [vp] * 6 + [vp, ctypes.c_size_t, vp]
+    L.cuba_init.restype = ctypes.c_int
+    L.cuba_step.argtypes = [vp, i32]
+    L.cuba_step.restype = ctypes.c_int
+    L.cuba_observe.argtypes = [vp, vp, vp]
+    L.cuba_observe.restype = ctypes.c_int
+    L.cuba_get_state.argtypes = [vp] + [vp] * 6
+    L.cuba_get_state.restype = ctypes.c_int
+    L.cuba_trace_step.argtypes = [vp, ctypes.POINTER(cuba_trace)]
+    L.cuba_trace_step.restype = ctypes.c_int
+    L.cuba_sync.argtypes = [vp]
+    L.cuba_sync.restype = ctypes.c_int
+    L.cuba_info.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(i64),
+                            ctypes.POINTER(i64)]
+    L.cuba_info.restype = ctypes.c_int
+    L.cuba_counters.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
+    L.cuba_counters.restype = ctypes.c_int
+    L.cuba_timing_begin.argtypes = [vp, i32]
+    L.cuba_timing_begin.restype = ctypes.c_int
+    L.cuba_timing_end.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_int64)]
+    L.cuba_timing_end.restype = ctypes.c_int
+    L.cuba_destroy.argtypes = [vp]
+    L.cuba_destroy.restype = None
+    L.cuba_strerror.argtypes = [ctypes.c_int]
+    L.cuba_strerror.restype = ctypes.c_char_p
+    L.cuba_last_error.argtypes = []
+    L.cuba_last_error.restype = ctypes.c_char_p
+    return L
+
+
+_lib = _load()
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != CUBA_OK:
+        raise CubaError(rc, where, cuba_last_error())
+
+
+def make_params(box, cells, sigma, r_test, dt, seed, step0=0) -> cuba_params:
+    p = cuba_params()
+    for d in range(3):
+        p.box[d] = float(box[d])
+        p.cells[d] = int(cells[d])
+    p.sigma, p.r_test, p.dt = float(sigma), float(r_test), float(dt)
+    p.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    p.step0 = int(step0) & 0xFFFFFFFF
+    return p
+
+
+def cuba_strerror(code: int) -> str:
+    return _lib.cuba_strerror(int(code)).decode()
+
+
+def cuba_last_error() -> str:
+    return _lib.cuba_last_error().decode()
+
+
+def cuba_workspace_bytes(params: cuba_params, n: int) -> int:
+    return int(_lib.cuba_workspace_bytes(ctypes.byref(params), int(n)))
+
+
+def cuba_init(params: cuba_params, n: int, x: int, y: int, z: int, px: int, py: int,
+              pz: int, workspace: int, ws_bytes: int, stream: int | None) -> int:
+    ctx = ctypes.c_void_p()
+    rc = _lib.cuba_init(ctypes.byref(ctx), ctypes.byref(params), int(n), x, y, z, px, py,
+                        pz, workspace, int(ws_bytes), stream)
+    _check(rc, "cuba_init")
+    return ctx.value
+
+
+def cuba_step(ctx: int, nsteps: int) -> None:
+    _check(_lib.cuba_step(ctx, int(nsteps)), "cuba_step")
+
+
+def cuba_observe(ctx: int, T00: int, T0x: int) -> None:
+    _check(_lib.cuba_observe(ctx, T00, T0x), "cuba_observe")
+
+
+def cuba_get_state(ctx: int, x: int, y: int, z: int, px: int, py: int, pz: int) -> None:
+    _check(_lib.cuba_get_state(ctx, x, y, z, px, py, pz), "cuba_get_state")
+
+
+def cuba_trace_step(ctx: int, trace: cuba_trace) -> None:
+    _check(_lib.cuba_trace_step(ctx, ctypes.byref(trace)), "cuba_trace_step")
+
+
+def cuba_sync(ctx: int) -> None:
+    _check(_lib.cuba_sync(ctx), "cuba_sync")
+
+
+def cuba_info(ctx: int):
+    t = ctypes.c_uint32()
+    n = ctypes.c_int64()
+    c = ctypes.c_int64()
+    _check(_lib.cuba_info(ctx, ctypes.byref(t), ctypes.byref(n), ctypes.byref(c)),
+           "cuba_info")
+    return t.value, n.value, c.value
+
+
+CUBA_NUM_STAGES = 5
+STAGES = ("count", "scan", "scatter", "collide", "observe")
+
+
+def cuba_counters(ctx: int):
+    out = (ctypes.c_uint64 * 3)()
+    _check(_lib.cuba_counters(ctx, out), "cuba_counters")
+    return {"pair_tests": int(out[0]), "candidates": int(out[1]), "claims": int(out[2])}
+
+
+def cuba_timing_begin(ctx: int, max_launches: int) -> None:
+    _check(_lib.cuba_timing_begin(ctx, int(max_launches)), "cuba_timing_begin")
+
+
+def cuba_timing_end(ctx: int):
+    ms = (ctypes.c_double * CUBA_NUM_STAGES)()
+    nl = (ctypes.c_int64 * CUBA_NUM_STAGES)()
+    _check(_lib.cuba_timing_end(ctx, ms, nl), "cuba_timing_end")
+    return {STAGES[k]: (float(ms[k]), int(nl[k])) for k in range(CUBA_NUM_STAGES)}
+
+
+def cuba_destroy(ctx: int) -> None:
+    _lib.cuba_destroy(ctx)

@@ -1,0 +1,356 @@
+"""Parity of the HIP library (through its C ABI) with the CPU oracle.
+
+One step from an identical state, step index and seed must give identical
+cells, canonical order, offsets, candidate pairs and claimed pairs,
+bit-identical positions and bit-identical momenta for particles that did
+not scatter; scattered momenta agree within 1e-12 of the pair energy (sin
+and cos differ in the last bits).  Observables agree within the rounding
+bound of their sums.  Multi-step profiles agree statistically with an
+oracle ensemble.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1208_0961_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1208_0961_amd import build
+    if build.sources_newer_than_lib():
+        build.build()
+    from paper_1208_0961_amd import sim
+    return sim
+
+
+def _orc_params(orc, params, t0=0):
+    q = {k: v for k, v in params.items() if k != "step0"}
+    return orc.make_params(**q)
+
+
+def _rows(a):
+    a = np.asarray(a, dtype=np.int64).reshape(-1, 3)
+    if len(a) == 0:
+        return a
+    return a[np.lexsort((a[:, 2], a[:, 1], a[:, 0]))]
+
+
+def compare_step(orc, lib, params, state, t, label=""):
+    """Run step t from state on both sides; assert the parity contract.
+    Returns the GPU state after the step (id order) and the GPU trace."""
+    say(f"[parity] {label} n={len(state[0])} t={t}")
+    st = orc.State(*state)
+    tr_o = orc.step(_orc_params(orc, params), st, t & 0xFFFFFFFF, trace=True)
+    sim = lib.Sim({**params, "step0": t}, state)
+    tr_g = sim.trace_step(cand_cap=len(tr_o["cand"]) + 1024)
+    gs = sim.get_state()
+    sim.close()
+    assert np.array_equal(tr_g["cell"], tr_o["cell"]), "cell indices differ"
+    assert np.array_equal(tr_g["offsets"], tr_o["offsets"]), "offsets differ"
+    assert np.array_equal(tr_g["perm"], tr_o["perm"]), "canonical order differs"
+    assert np.array_equal(_rows(tr_g["cand"]), _rows(tr_o["cand"])), "candidates differ"
+    assert np.array_equal(_rows(tr_g["claim"]), _rows(tr_o["claim"])), "claims differ"
+    for d in range(3):
+        assert np.array_equal(gs[d], st[d]), f"positions differ on axis {d}"
+    # momenta: bit-exact unless scattered
+    scattered = np.zeros(len(state[0]), bool)
+    pair_e = np.zeros(len(state[0]))
+    offs = tr_o["offsets"].astype(np.int64)
+    E = np.sqrt(st[3] ** 2 + st[4] ** 2 + st[5] ** 2)
+    for c, a, b in _rows(tr_o["claim"]):
+        ia = tr_o["perm"][offs[c] + a]
+        ib = tr_o["perm"][offs[c] + b]
+        scattered[[ia, ib]] = True
+        pair_e[[ia, ib]] = E[ia] + E[ib]
+    for d in range(3, 6):
+        assert np.array_equal(gs[d][~scattered], st[d][~scattered]), "unscattered p differs"
+        dev = np.abs(gs[d][scattered] - st[d][scattered])
+        assert np.all(dev <= 1e-12 * pair_e[scattered]), dev.max()
+    return gs, tr_g
+
+
+def test_init_state_roundtrip_and_observe(orc, lib):
+    w = W.TUBE_1D
+    state = W.riemann_state(w)
+    sim = lib.Sim(w.params(), state)
+    back = sim.get_state()
+    for a, b in zip(back, state):
+        assert np.array_equal(a, b)
+    T00, T0x = sim.observe()
+    p = _orc_params(orc, w.params())
+    oT00, oT0x = orc.observe(p, orc.State(*state))
+    _assert_profiles_close(p, state, T00, T0x, oT00, oT0x)
+    sim.close()
+
+
+def _assert_profiles_close(p, state, T00, T0x, oT00, oT0x):
+    """Two summation orders of the same slab sums differ by at most
+    2 n_slab eps sum|term| (recursive summation bound, both sides)."""
+    dx = p.box[0] / p.cells[0]
+    vol = p.r_test * dx * p.box[1] * p.box[2]
+    E = np.sqrt(state[3] ** 2 + state[4] ** 2 + state[5] ** 2)
+    ix = np.clip(np.floor(state[0] / dx).astype(np.int64), 0, p.cells[0] - 1)
+    cnt = np.bincount(ix, minlength=p.cells[0])
+    sE = np.bincount(ix, E, p.cells[0]) / vol
+    sP = np.bincount(ix, np.abs(state[3]), p.cells[0]) / vol
+    eps = 2.0 ** -53
+    assert np.all(np.abs(T00 - oT00) <= 2 * (cnt + 2) * eps * sE + 1e-300)
+    assert np.all(np.abs(T0x - oT0x) <= 2 * (cnt + 2) * eps * sP + 1e-300)
+
+
+def test_step_parity_tube1d_many_steps(orc, lib):
+    w = W.TUBE_1D
+    state = W.riemann_state(w)
+    n_claims = n_cand = 0
+    for t in range(12):
+        state, tr = compare_step(orc, lib, w.params(), state, t, "tube1d")
+        n_claims += len(tr["claim"])
+        n_cand += len(tr["cand"])
+    assert n_claims > 1000 and n_cand > n_claims
+
+
+def test_step_parity_tube3d(orc, lib):
+    w = W.TUBE_3D
+    state = W.riemann_state(w)
+    compare_step(orc, lib, w.params(), state, 0, "tube3d")
+
+
+def test_observe_parity_after_steps(orc, lib):
+    w = W.TUBE_1D
+    state = W.riemann_state(w, seed=77)
+    sim = lib.Sim(w.params(), state)
+    sim.step(25)
+    T00, T0x = sim.observe()
+    gs = sim.get_state()
+    sim.close()
+    p = _orc_params(orc, w.params())
+    oT00, oT0x = orc.observe(p, orc.State(*gs))
+    _assert_profiles_close(p, gs, T00, T0x, oT00, oT0x)
+    E = np.sqrt(gs[3] ** 2 + gs[4] ** 2 + gs[5] ** 2)
+    dx = 0.1
+    assert abs(T00.sum() * (p.r_test * dx) - E.sum()) <= 1e-12 * E.sum()
+
+
+def _cells_box(occupancies, L=1.0, m=4, T=0.4, seed=3):
+    """Particles placed so that cell j of an m x m x m grid (edge L/m) holds
+    occupancies[j] particles, away from the faces so that one step of
+    dt = 0.001 keeps them in their cell."""
+    rng = np.random.default_rng(seed)
+    dxc = L / m
+    xs, ys, zs = [], [], []
+    for j, k in enumerate(occupancies):
+        ix, iy, iz = j // (m * m), (j // m) % m, j % m
+        lo = np.array([ix, iy, iz]) * dxc + 0.1 * dxc
+        r = lo + 0.8 * dxc * rng.random((k, 3))
+        xs.append(r[:, 0]); ys.append(r[:, 1]); zs.append(r[:, 2])
+    n = int(sum(occupancies))
+    _, _, _, px, py, pz = W.sample_gas(rng, n, T, (0, 0, 0), (1, 1, 1))
+    perm = rng.permutation(n)
+    arrs = [np.concatenate(xs), np.concatenate(ys), np.concatenate(zs), px, py, pz]
+    return [np.ascontiguousarray(a[perm]) for a in arrs]
+
+
+def test_ragged_occupancies_and_tile_edges(orc, lib):
+    occ = [0, 1, 2, 3, 63, 64, 65, 127, 128, 129, 191, 200, 255, 256, 257, 300] + [5] * 48
+    state = _cells_box(occ)
+    # K = sigma / r_test * dt / V large enough for many candidates per cell
+    params = dict(box=(1.0, 1.0, 1.0), cells=(4, 4, 4), sigma=2.0, r_test=1.0,
+                  dt=0.001, seed=12345)
+    for t in range(3):
+        state, tr = compare_step(orc, lib, params, state, t, "ragged")
+    assert len(tr["claim"]) > 50
+
+
+def test_full_occupancy_cell_and_filter_disabled(orc, lib):
+    # one cell at the occupancy limit; K = 0.5 (2K = 1): every pair passes
+    # the Philox pre-filter, so the compaction buffer is flushed many times
+    state = _cells_box([1024], m=1)
+    V = 1.0
+    params = dict(box=(1.0, 1.0, 1.0), cells=(1, 1, 1), sigma=0.5 * V / 0.001,
+                  r_test=1.0, dt=0.001, seed=99)
+    state, tr = compare_step(orc, lib, params, state, 5, "cap1024-K0.5")
+    assert len(tr["claim"]) > 400
+    # a smaller K with the same cell
+    params["sigma"] = 2.0
+    compare_step(orc, lib, params, state, 6, "cap1024")
+
+
+def test_occupancy_over_limit_is_reported(lib):
+    from paper_1208_0961_amd import cuba as C
+    state = _cells_box([1025], m=1)
+    params = dict(box=(1.0, 1.0, 1.0), cells=(1, 1, 1), sigma=1.0, r_test=1.0,
+                  dt=0.001, seed=1)
+    sim = lib.Sim(params, state)
+    sim.step(1)
+    with pytest.raises(C.CubaError) as e:
+        sim.sync()
+    assert e.value.code == C.CUBA_ERANGE
+    sim.sync()       # the error is reported once
+    sim.close()
+
+
+def test_empty_and_tiny_inputs(orc, lib):
+    params = dict(box=(1.0, 1.0, 1.0), cells=(2, 2, 2), sigma=1.0, r_test=1.0,
+                  dt=0.01, seed=7)
+    empty = [np.zeros(0) for _ in range(6)]
+    sim = lib.Sim(params, empty)
+    sim.step(3)
+    T00, T0x = sim.observe()
+    assert np.all(T00 == 0) and np.all(T0x == 0)
+    sim.close()
+    one = _cells_box([1], m=1)
+    compare_step(orc, lib, {**params, "cells": (1, 1, 1)}, one, 0, "single")
+    two = _cells_box([2] * 8, m=2)
+    state = two
+    for t in range(5):
+        state, _ = compare_step(orc, lib, {**params, "sigma": 6.0}, state, t, "pairs")
+
+
+def test_sigma_zero_has_no_candidates(orc, lib):
+    w = W.TUBE_1D
+    params = {**w.params(), "sigma": 0.0}
+    _, tr = compare_step(orc, lib, params, W.riemann_state(w), 0, "sigma0")
+    assert len(tr["cand"]) == 0 and len(tr["claim"]) == 0
+
+
+def test_step_index_wraps_like_the_counter_word(orc, lib):
+    w = W.TUBE_1D
+    state = W.riemann_state(w, seed=8)
+    for t in (0xFFFFFFFE, 0xFFFFFFFF):
+        state, _ = compare_step(orc, lib, w.params(), state, t, "wrap")
+    sim = lib.Sim({**w.params(), "step0": 0xFFFFFFFF}, state)
+    sim.step(2)
+    assert sim.next_step == 1
+    sim.close()
+
+
+def test_init_rejects_out_of_range_particles(lib):
+    from paper_1208_0961_amd import cuba as C
+    params = dict(box=(1.0, 1.0, 1.0), cells=(2, 2, 2), sigma=1.0, r_test=1.0,
+                  dt=0.01, seed=7)
+    base = _cells_box([3] * 8, m=2)
+    for which, val in ((0, 1.5), (1, -0.1), (2, np.nan), (3, np.inf)):
+        bad = [a.copy() for a in base]
+        bad[which][4] = val
+        with pytest.raises(C.CubaError) as e:
+            lib.Sim(params, bad)
+        assert e.value.code == C.CUBA_ERANGE
+    bad = [a.copy() for a in base]
+    bad[3][2] = bad[4][2] = bad[5][2] = 0.0
+    with pytest.raises(C.CubaError) as e:
+        lib.Sim(params, bad)
+    assert e.value.code == C.CUBA_ERANGE
+
+
+def test_determinism_and_resume(lib):
+    w = W.TUBE_1D
+    state = W.riemann_state(w, seed=9)
+    a = lib.Sim(w.params(), state)
+    a.step(15)
+    sa = a.get_state()
+    b = lib.Sim(w.params(), state)
+    b.step(10)
+    mid = b.get_state()
+    b.close()
+    c = lib.Sim({**w.params(), "step0": 10}, mid)
+    c.step(5)
+    sc = c.get_state()
+    for x, y in zip(sa, sc):
+        assert np.array_equal(x, y)
+    d = lib.Sim({**w.params(), "seed": 2}, state)
+    d.step(15)
+    assert not np.array_equal(d.get_state()[3], sa[3])
+    a.close(); c.close(); d.close()
+
+
+def test_full_scale_step_properties(orc, lib):
+    """The full 160k-cell tube (16.3 M particles) in the benchmark's launch
+    configuration: after one production step, positions equal the oracle's
+    bit for bit, the set of scattered particles is the oracle's, unscattered
+    momenta are bit-exact and scattered ones within 1e-12 of twice the
+    largest energy in the cell."""
+    import os
+    w = W.TUBE_FULL
+    state = W.riemann_state(w)
+    say("[full] GPU step")
+    sim = lib.Sim(w.params(), state)
+    pre = sim.get_state()
+    sim.step(1)
+    gs = sim.get_state()
+    sim.close()
+    nthreads = max(1, min(16, os.cpu_count() or 1))
+    p = _orc_params(orc, w.params())
+    say(f"[full] oracle step, {nthreads} threads")
+    st = orc.State(*pre)
+    orc.run(p, st, 0, 1, nthreads)
+    say("[full] oracle free streaming")
+    free = orc.State(*pre)
+    orc.run(_orc_params(orc, {**w.params(), "sigma": 0.0}), free, 0, 1, nthreads)
+    for d in range(3):
+        assert np.array_equal(gs[d], st[d])
+        assert np.array_equal(gs[d], free[d])
+    moved_o = np.zeros(w.n, bool)
+    moved_g = np.zeros(w.n, bool)
+    for d in range(3, 6):
+        moved_o |= st[d] != free[d]
+        moved_g |= gs[d] != free[d]
+    assert np.array_equal(moved_o, moved_g)
+    assert 0.05 * w.n < moved_o.sum() < 0.2 * w.n
+    dxs = np.array(w.box) / np.array(w.cells)
+    idx = [np.clip(np.floor(st[d] / dxs[d]).astype(np.int64), 0, w.cells[d] - 1) for d in range(3)]
+    cell = (idx[0] * w.cells[1] + idx[1]) * w.cells[2] + idx[2]
+    E = np.sqrt(st[3] ** 2 + st[4] ** 2 + st[5] ** 2)
+    emax = np.zeros(w.n_cells)
+    np.maximum.at(emax, cell, E)
+    tol = 1e-12 * 2 * emax[cell]
+    for d in range(3, 6):
+        assert np.array_equal(gs[d][~moved_o], st[d][~moved_o])
+        assert np.all(np.abs(gs[d] - st[d]) <= tol)
+
+
+def test_multistep_profiles_match_oracle_ensemble(orc, lib):
+    """Independent ensembles, 16 runs per side (GPU seeds 1..16, oracle seeds
+    101..116, each with its own initial state), 200 steps of the 1-D tube.
+    Per bin, the Welch t statistic of T00 and T0x at steps 50, 100, 150 and
+    200, mapped to a normal score: at most 1 % of the scores beyond 3, and
+    the chi-square of the 200 scores at step 200 with p above 1e-3."""
+    import os
+    from scipy import stats
+    w = W.TUBE_1D
+    obs_at = (50, 100, 150, 200)
+    nthreads = max(1, min(16, os.cpu_count() or 1))
+    g = {t: [] for t in obs_at}
+    o = {t: [] for t in obs_at}
+    for s in range(1, 17):
+        say(f"[ensemble] run {s}")
+        sim = lib.Sim({**w.params(), "seed": s}, W.riemann_state(w, seed=1000 + s))
+        st = orc.State(*W.riemann_state(w, seed=2000 + s))
+        p = orc.make_params(w.box, w.cells, w.sigma, w.r_test, w.dt, 100 + s)
+        t = 0
+        for t_obs in obs_at:
+            sim.step(t_obs - t)
+            orc.run(p, st, t, t_obs - t, nthreads)
+            t = t_obs
+            g[t_obs].append(np.concatenate(sim.observe()))
+            o[t_obs].append(np.concatenate(orc.observe(p, st)))
+        sim.close()
+    scores = {}
+    for t_obs in obs_at:
+        G, O = np.array(g[t_obs]), np.array(o[t_obs])
+        res = stats.ttest_ind(G, O, axis=0, equal_var=False)
+        scores[t_obs] = stats.norm.isf(res.pvalue / 2) * np.sign(res.statistic)
+    allz = np.concatenate([scores[t] for t in obs_at])
+    assert np.all(np.isfinite(allz))
+    assert np.mean(np.abs(allz) > 3) <= 0.01
+    assert stats.chi2.sf((scores[200] ** 2).sum(), len(scores[200])) > 1e-3

@@ -1,0 +1,89 @@
+"""The C-ABI library loads, exports every function include/cuba.h declares,
+and its host-side validation behaves as documented (no device work)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cuba.h")
+
+
+@pytest.fixture(scope="module")
+def C():
+    from paper_1208_0961_amd import build
+    if build.sources_newer_than_lib():
+        build.build()
+    from paper_1208_0961_amd import cuba
+    return cuba
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cuba_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(C):
+    names = declared_functions()
+    assert len(names) >= 11
+    out = subprocess.run(["nm", "-D", "--defined-only", C.library_path()],
+                         capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (cuba_\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    lib = ctypes.CDLL(C.library_path())
+    for n in names:
+        getattr(lib, n)
+
+
+def test_code_object_targets_gfx950(C, tmp_path):
+    fatbin = str(tmp_path / "fatbin.bin")
+    r = subprocess.run(["/opt/rocm/llvm/bin/llvm-objcopy", "--dump-section=.hip_fatbin=" + fatbin,
+                        C.library_path(), str(tmp_path / "copy.so")], capture_output=True)
+    if r.returncode != 0:
+        pytest.skip("llvm-objcopy cannot read the library")
+    out = subprocess.run(["/opt/rocm/llvm/bin/clang-offload-bundler", "--list", "--type=o",
+                          "--input=" + fatbin], capture_output=True, text=True, check=True)
+    targets = [t for t in out.stdout.split() if "amdgcn" in t]
+    assert targets == ["hipv4-amdgcn-amd-amdhsa--gfx950"], out.stdout
+
+
+def test_workspace_bytes_and_parameter_checks(C):
+    p = C.make_params((10, 2, 2), (100, 10, 10), 0.4, 2500, 0.02, 1)
+    n = 1020851
+    ws = C.cuba_workspace_bytes(p, n)
+    # two SoA buffers of 52 B per particle plus per-cell arrays, 256 B aligned
+    assert 104 * n <= ws <= 104 * n + 16 * 10000 + 64 * 1024
+    assert C.cuba_workspace_bytes(p, 2 * n) > ws
+    bad = [
+        C.make_params((10, 2, 2), (100, 10, 10), 0.4, 2500, 0.1, 1),     # dt >= dx
+        C.make_params((10, 2, 2), (100, 10, 10), -0.4, 2500, 0.02, 1),   # sigma < 0
+        C.make_params((10, 2, 2), (100, 10, 10), 0.4, 0.0, 0.02, 1),     # r_test = 0
+        C.make_params((10, 2, 2), (0, 10, 10), 0.4, 2500, 0.02, 1),      # no cells
+        C.make_params((float("nan"), 2, 2), (100, 10, 10), 0.4, 2500, 0.02, 1),
+        C.make_params((10, 2, 2), (100, 10, 10), 400.0, 1.0, 0.02, 1),   # 2K > 1
+    ]
+    for b in bad:
+        assert C.cuba_workspace_bytes(b, 10) == 0
+        assert C.cuba_last_error() != ""
+
+
+def test_init_rejects_before_touching_the_device(C):
+    ctx = ctypes.c_void_p()
+    L = C._lib
+    bad = C.make_params((10, 1, 1), (100, 1, 1), 0.4, 100, 0.5, 1)
+    rc = L.cuba_init(ctypes.byref(ctx), ctypes.byref(bad), 10, *([None] * 6), None, 0, None)
+    assert rc == C.CUBA_EINVAL and ctx.value is None
+    good = C.make_params((10, 1, 1), (100, 1, 1), 0.4, 100, 0.02, 1)
+    rc = L.cuba_init(ctypes.byref(ctx), ctypes.byref(good), 10, *([None] * 6), None, 0, None)
+    assert rc == C.CUBA_EINVAL and "NULL" in C.cuba_last_error()
+    # misaligned workspace and a too-small one are refused by the host code
+    rc = L.cuba_init(ctypes.byref(ctx), ctypes.byref(good), 0, *([None] * 6), 8, 1 << 20, None)
+    assert rc == C.CUBA_EINVAL and "aligned" in C.cuba_last_error()
+    rc = L.cuba_init(ctypes.byref(ctx), ctypes.byref(good), 0, *([None] * 6), 256, 16, None)
+    assert rc == C.CUBA_ENOMEM
+    for code in (0, -1, -2, -3, -4):
+        assert C.cuba_strerror(code).startswith("CUBA_")
