@@ -29,8 +29,11 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 # 32-bit VALU lane operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 INT32_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# Algorithmic work of one pair test.
-PHILOX_OPS_PER_PAIR = 20 + 40 + 1   # 32x32->64 products, XORs, the compare
+# Algorithmic work of one pair test: the integer operations that the Philox
+# word w1 deciding acceptance depends on, when the counter's cell and step
+# words are shared by the cell's pairs: 16 products (32x32 -> 64, hi or lo),
+# 15 three-input XORs, and the compare.
+PHILOX_OPS_PER_PAIR = 16 + 15 + 1
 FP64_FLOPS_PER_PAIR = 12            # Eq. (3): dot, E1 E2, s, s/(2 E1 E2), x K
 # Algorithmic HBM bytes per particle of the binning stages.
 BYTES_COUNT = 48                    # read x y z px py pz
@@ -49,6 +52,9 @@ def parse():
     ap.add_argument("--cpu-threads", type=int, default=None)
     ap.add_argument("--traffic", default=None,
                     help="JSON file with measured FETCH/WRITE bytes per collide launch")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the run, copy a 1 GiB device buffer 3 times (a plain "
+                         "copy kernel of known size for scaling HBM counters)")
     return ap.parse_args()
 
 
@@ -182,6 +188,13 @@ def main():
         "cpu_baseline": cpu,
     }
     sim.close()
+    if a.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 1 << 30
     print(json.dumps(out), flush=True)
 
 

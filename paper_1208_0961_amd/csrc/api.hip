@@ -227,7 +227,9 @@ int cuba_init(cuba_ctx **out, const cuba_params *params, int64_t n, const double
   if (!c) return fail(CUBA_ENOMEM, "host allocation failed");
   c->d = d;
   c->pa.kfac = d.kfac;
-  c->pa.w1_limit = w1_limit(d.kfac);
+  const uint64_t lim = w1_limit(d.kfac);
+  c->pa.any = lim > 0 ? 1u : 0u;
+  c->pa.w1_max = lim > 0 ? (uint32_t)(lim - 1) : 0u;
   c->pa.key0 = (uint32_t)(params->seed & 0xFFFFFFFFu);
   c->pa.key1 = (uint32_t)(params->seed >> 32);
   c->n = n;

@@ -49,7 +49,8 @@ struct TraceArgs {
 
 struct PairArgs {
   double kfac;       // K = sigma / r_test * dt / V_cell
-  uint64_t w1_limit; // pairs whose high word w1 >= w1_limit cannot be accepted
+  uint32_t w1_max;   // a pair can be accepted only if its Philox word w1 <= w1_max
+  uint32_t any;      // 0 when no pair can be accepted (K = 0)
   uint32_t key0, key1;
 };
 

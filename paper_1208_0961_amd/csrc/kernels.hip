@@ -26,28 +26,64 @@ constexpr uint32_t kFiltCap = 512;  // filtered pairs held before resolving
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
 // Slot = old value of ctr[key] + rank of this lane among the active lanes
-// of its wave with the same key; one atomic per distinct key per wave.
+// of its wave with the same key.  The lanes are grouped by key with ballots
+// first (ALU only); then every group leader issues its atomic in the same
+// instruction, so the wave waits for one atomic round trip, not one per key.
 __device__ __forceinline__ uint32_t aggregated_fetch_add(uint32_t *ctr, uint32_t key,
                                                          bool active) {
   const uint32_t lane = lane_id();
-  uint32_t slot = 0;
-  bool todo = active;
-  uint64_t pending = __ballot(todo);
-  while (pending != 0) {
-    const int leader = __builtin_ctzll(pending);
-    const uint32_t lkey = __shfl(key, leader);
-    const bool mine = todo && key == lkey;
-    const uint64_t group = __ballot(mine);
-    uint32_t base = 0;
-    if ((int)lane == leader) base = atomicAdd(&ctr[lkey], (uint32_t)__popcll(group));
-    base = __shfl(base, leader);
-    if (mine) {
-      slot = base + (uint32_t)__popcll(group & ((1ull << lane) - 1ull));
-      todo = false;
+  const uint64_t below = (1ull << lane) - 1ull;
+  uint32_t leader = lane, rank = 0, size = 0;
+  uint64_t todo = __ballot(active);
+  while (todo != 0) {
+    const int l = __builtin_ctzll(todo);
+    const uint32_t lkey = __shfl(key, l);
+    const uint64_t group = __ballot(active && key == lkey);
+    if (active && key == lkey) {
+      leader = (uint32_t)l;
+      rank = (uint32_t)__popcll(group & below);
+      size = (uint32_t)__popcll(group);
     }
-    pending = __ballot(todo);
+    todo &= ~group;
   }
-  return slot;
+  uint32_t base = 0;
+  if (active && leader == lane) base = atomicAdd(&ctr[key], size);
+  base = __shfl(base, (int)leader);
+  return base + rank;
+}
+
+// Count-only variant: the leaders add their group sizes (no value returned).
+__device__ __forceinline__ void aggregated_add(uint32_t *ctr, uint32_t key, bool active) {
+  const uint32_t lane = lane_id();
+  uint32_t leader = lane, size = 0;
+  uint64_t todo = __ballot(active);
+  while (todo != 0) {
+    const int l = __builtin_ctzll(todo);
+    const uint32_t lkey = __shfl(key, l);
+    const uint64_t group = __ballot(active && key == lkey);
+    if (active && key == lkey) {
+      leader = (uint32_t)l;
+      size = (uint32_t)__popcll(group);
+    }
+    todo &= ~group;
+  }
+  if (active && leader == lane) atomicAdd(&ctr[key], size);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs of the MI355X
+// (workgroup b runs on XCD b mod 8), each XCD with its own L2.
+constexpr uint32_t kXcds = 8;
+
+// Bijection on [0, nblocks) giving each XCD runs of kRun consecutive logical
+// blocks, interleaved over the XCDs (balances work that varies along the
+// block range while keeping neighbouring blocks on one L2).
+template <uint32_t kRun>
+__device__ __forceinline__ uint32_t xcd_runs(uint32_t b, uint32_t nblocks) {
+  constexpr uint32_t kSuper = kXcds * kRun;
+  const uint32_t full = nblocks / kSuper * kSuper;
+  if (b >= full) return b;
+  const uint32_t s = b / kSuper, r = b % kSuper;
+  return s * kSuper + (r % kXcds) * kRun + r / kXcds;
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, uint32_t v,
@@ -91,7 +127,7 @@ __global__ __launch_bounds__(kBlock) void k_count(SoA src, int64_t n, Geometry g
     advance<kStream>(g, x, y, z, px, py, pz);
     c = cell_id(g, x, y, z);
   }
-  (void)aggregated_fetch_add(counts, c, active);
+  aggregated_add(counts, c, active);
 }
 
 template <bool kStream>
@@ -260,14 +296,19 @@ template <bool kTrace>
 __global__ __launch_bounds__(64) void k_collide(const uint32_t *__restrict__ offsets,
                                                 SoA st, uint32_t t, PairArgs pa,
                                                 DevStatus *status, TraceArgs tr) {
-  __shared__ __align__(16) uint32_t s_id[kCellCap];
+  // s_buf holds the cell's ids while the canonical order is built; after
+  // that its first half holds the filtered pairs and its second half the
+  // claimed pairs.
+  __shared__ __align__(16) uint32_t s_buf[kCellCap];
   __shared__ uint16_t s_perm[kCellCap];
-  __shared__ uint32_t s_filt[kFiltCap];
-  __shared__ uint32_t s_claim[kCellCap / 2];
+  static_assert(kFiltCap + kCellCap / 2 <= kCellCap, "LDS aliasing");
+  uint32_t *const s_id = s_buf;
+  uint32_t *const s_filt = s_buf;
+  uint32_t *const s_claim = s_buf + kFiltCap;
 
   const uint32_t lane = lane_id();
   CellView cv;
-  cv.c = blockIdx.x;
+  cv.c = xcd_runs<8>(blockIdx.x, gridDim.x);
   cv.t = t;
   cv.base = offsets[cv.c];
   cv.n = offsets[cv.c + 1] - cv.base;
@@ -301,27 +342,47 @@ __global__ __launch_bounds__(64) void k_collide(const uint32_t *__restrict__ off
   }
   __syncthreads();
 
-  // every pair k = 0 .. n(n-1)/2 - 1, lane-strided; pairs whose Philox high
-  // word rules out acceptance are dropped at once, the rest are compacted
-  // (in increasing k) for the exact test
+  // every pair k = 0 .. n(n-1)/2 - 1, lane-strided; pairs whose Philox word
+  // w1 rules out acceptance (u >= w1 2^-32 > P22) are dropped at once, the
+  // rest are compacted (in increasing k) for the exact test.  The main loop
+  // takes two full rows of 64 pairs per iteration with no bounds checks.
   const uint32_t npairs = n * (n - 1u) / 2u;
   const uint64_t below = (1ull << lane) - 1ull;
+  const uint32_t lim = pa.w1_max;
   uint32_t nf = 0, nclaim = 0, claimed_bits = 0, n_acc = 0;
-  for (uint32_t k0 = 0; k0 < npairs; k0 += 64) {
-    const uint32_t k = k0 + lane;
-    bool pass = false;
-    if (k < npairs) {
-      const Words4 w = philox10(k, cv.c, t, 0u, pa.key0, pa.key1);
-      pass = (uint64_t)w.w1 < pa.w1_limit;
+  uint32_t k0 = 0;
+  if (pa.any) {
+    for (; k0 + 128u <= npairs; k0 += 128u) {
+      const uint32_t ka = k0 + lane, kb = k0 + 64u + lane;
+      const uint32_t wa = philox10_w1(ka, cv.c, t, 0u, pa.key0, pa.key1);
+      const uint32_t wb = philox10_w1(kb, cv.c, t, 0u, pa.key0, pa.key1);
+      const bool pass_a = wa <= lim, pass_b = wb <= lim;
+      const uint64_t ma = __ballot(pass_a), mb = __ballot(pass_b);
+      if ((ma | mb) != 0) {
+        if (pass_a) s_filt[nf + (uint32_t)__popcll(ma & below)] = ka;
+        nf += (uint32_t)__popcll(ma);
+        if (pass_b) s_filt[nf + (uint32_t)__popcll(mb & below)] = kb;
+        nf += (uint32_t)__popcll(mb);
+        if (nf > kFiltCap - 128u) {
+          resolve_filtered<kTrace>(nf, cv, pa, st, s_perm, s_filt, s_claim, nclaim,
+                                   claimed_bits, n_acc, tr, status);
+          nf = 0;
+        }
+      }
     }
-    const uint64_t m = __ballot(pass);
-    if (m != 0) {
-      if (pass) s_filt[nf + (uint32_t)__popcll(m & below)] = k;
-      nf += (uint32_t)__popcll(m);
-      if (nf > kFiltCap - 64) {
-        resolve_filtered<kTrace>(nf, cv, pa, st, s_perm, s_filt, s_claim, nclaim,
-                                 claimed_bits, n_acc, tr, status);
-        nf = 0;
+    for (; k0 < npairs; k0 += 64u) {
+      const uint32_t k = k0 + lane;
+      bool pass = false;
+      if (k < npairs) pass = philox10_w1(k, cv.c, t, 0u, pa.key0, pa.key1) <= lim;
+      const uint64_t m = __ballot(pass);
+      if (m != 0) {
+        if (pass) s_filt[nf + (uint32_t)__popcll(m & below)] = k;
+        nf += (uint32_t)__popcll(m);
+        if (nf > kFiltCap - 64u) {
+          resolve_filtered<kTrace>(nf, cv, pa, st, s_perm, s_filt, s_claim, nclaim,
+                                   claimed_bits, n_acc, tr, status);
+          nf = 0;
+        }
       }
     }
   }
