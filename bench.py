@@ -35,10 +35,10 @@ INT32_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # 15 three-input XORs, and the compare.
 PHILOX_OPS_PER_PAIR = 16 + 15 + 1
 FP64_FLOPS_PER_PAIR = 12            # Eq. (3): dot, E1 E2, s, s/(2 E1 E2), x K
-# Algorithmic HBM bytes per particle of the binning stages.
-BYTES_COUNT = 48                    # read x y z px py pz
-BYTES_SCATTER = 52 + 52             # read and write the state and id
-BYTES_OBSERVE = 24                  # read px py pz
+# Algorithmic HBM bytes per particle of the streaming + binning work (read
+# and write x y z px py pz id), done by the fused step kernel for all but
+# the first step of a run and by the stream-bin kernel for that one.
+BYTES_BIN = 52 + 52
 
 
 def parse():
@@ -97,14 +97,21 @@ def main():
     sim.step(a.warmup)
     sim.sync()
     c0 = C.cuba_counters(sim.ctx)
-    n_obs = sum(1 for s in range(a.steps) if (a.warmup + s + 1) % w.observe_every == 0)
-    C.cuba_timing_begin(sim.ctx, 4 * a.steps + n_obs + 8)
+    # runs of steps between observations (every observe_every steps)
+    runs = []
+    done = 0
+    while done < a.steps:
+        t_abs = a.warmup + done
+        k = min(a.steps - done, w.observe_every - t_abs % w.observe_every)
+        runs.append((k, (t_abs + k) % w.observe_every == 0))
+        done += k
+    C.cuba_timing_begin(sim.ctx, a.steps + 3 * len(runs) + 8)
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s in range(a.steps):
-        C.cuba_step(sim.ctx, 1)
-        if (a.warmup + s + 1) % w.observe_every == 0:
+    for k, obs in runs:
+        C.cuba_step(sim.ctx, k)
+        if obs:
             sim.observe_async()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -122,13 +129,15 @@ def main():
         ms, k = stages[name]
         return ms / k if k else float("nan")
 
-    coll_ms = avg_ms("collide")
-    pairs_per_launch = pairs / a.steps
-    achieved_tops = PHILOX_OPS_PER_PAIR * pairs_per_launch / (coll_ms * 1e-3) / 1e12
+    # the dominant kernel: the fused step (collisions of step t, streaming and
+    # binning of step t+1)
+    step_ms = avg_ms("step") if stages["step"][1] else avg_ms("collide")
+    pairs_per_step = pairs / a.steps
+    achieved_tops = PHILOX_OPS_PER_PAIR * pairs_per_step / (step_ms * 1e-3) / 1e12
     traffic = None
     if a.traffic and os.path.exists(a.traffic):
         with open(a.traffic) as f:
-            traffic = json.load(f).get("collide_bytes_per_launch")
+            traffic = json.load(f).get("step_bytes_per_launch")
 
     def gbs(nbytes, ms):
         return nbytes / (ms * 1e-3) / 1e9
@@ -137,18 +146,12 @@ def main():
     for name in C.STAGES:
         ms, k = stages[name]
         stage_out[name] = {"ms_per_launch": ms / k if k else None, "launches": k}
-    stage_out["count"]["gbs"] = gbs(BYTES_COUNT * w.n, avg_ms("count"))
-    stage_out["scatter"]["gbs"] = gbs(BYTES_SCATTER * w.n, avg_ms("scatter"))
-    for name in ("count", "scatter"):
-        stage_out[name]["frac_hbm"] = stage_out[name]["gbs"] / HBM_PEAK_GBS
-    stage_out["collide"]["pair_tests_per_launch"] = pairs_per_launch
-    stage_out["collide"]["fp64_tflops_algorithmic"] = (
-        FP64_FLOPS_PER_PAIR * pairs_per_launch / (coll_ms * 1e-3) / 1e12)
-    bin_ms = avg_ms("count") + avg_ms("scan") + avg_ms("scatter")
-    stage_out["binning_total"] = {
-        "ms_per_step": bin_ms,
-        "gbs": gbs((BYTES_COUNT + BYTES_SCATTER) * w.n, bin_ms),
-        "frac_hbm": gbs((BYTES_COUNT + BYTES_SCATTER) * w.n, bin_ms) / HBM_PEAK_GBS}
+    stage_out["bin"]["gbs"] = gbs(BYTES_BIN * w.n, avg_ms("bin"))
+    stage_out["bin"]["frac_hbm"] = stage_out["bin"]["gbs"] / HBM_PEAK_GBS
+    stage_out["step"]["pair_tests_per_launch"] = pairs_per_step
+    stage_out["step"]["hbm_gbs_algorithmic"] = gbs(BYTES_BIN * w.n, step_ms)
+    stage_out["step"]["fp64_tflops_algorithmic"] = (
+        FP64_FLOPS_PER_PAIR * pairs_per_step / (step_ms * 1e-3) / 1e12)
 
     cpu = None
     cpu_steps = a.cpu_steps if a.cpu_steps is not None else {"tube1d": 100, "tube3d": 24,
@@ -178,12 +181,12 @@ def main():
         "pair_tests_per_s": pairs / elapsed,
         "candidates_per_step": cand / a.steps,
         "scatterings_per_step": claims / a.steps,
-        "roofline": {"bound": "alu", "kernel": "collide",
+        "roofline": {"bound": "alu", "kernel": "k_step (fused)",
                      "achieved": achieved_tops, "peak": INT32_PEAK_TOPS,
                      "unit": "Tops/s", "frac": achieved_tops / INT32_PEAK_TOPS,
                      "traffic": traffic,
                      "ops_per_pair_test": PHILOX_OPS_PER_PAIR,
-                     "ms_per_launch": coll_ms},
+                     "ms_per_launch": step_ms},
         "stages": stage_out,
         "cpu_baseline": cpu,
     }

@@ -69,7 +69,7 @@ extern "C" {
 #define CUBA_ENOMEM -3  /* workspace (or trace buffer) too small           */
 #define CUBA_EDEVICE -4 /* HIP runtime error; see cuba_last_error()         */
 
-/* Largest number of particles one cell may hold in a step. */
+/* Largest per-cell capacity (particles one cell may hold in a step). */
 #define CUBA_MAX_CELL_OCCUPANCY 1024
 
 typedef struct cuba_ctx cuba_ctx;
@@ -83,11 +83,17 @@ typedef struct {
   double dt;        /* time step [fm/c], 0 < dt < min_d dx_d                */
   uint64_t seed;    /* Philox key: key[0] = low 32 bits, key[1] = high      */
   uint32_t step0;   /* index t of the first step (0, or t when resuming)    */
+  int32_t cell_capacity; /* slots reserved per cell in the workspace, in
+                            [1, CUBA_MAX_CELL_OCCUPANCY]; 0 selects 512.  A
+                            cell that receives more particles drops the
+                            surplus and cuba_sync reports CUBA_ERANGE.     */
 } cuba_params;
 
 /* Bytes of device workspace cuba_init needs for n particles with these
- * parameters (for admission by memory footprint).  Returns 0 if the
- * parameters are invalid.  The workspace must be 256-byte aligned. */
+ * parameters (for admission by memory footprint): two state buffers of
+ * cells x cell_capacity slots of 52 bytes plus per-cell bookkeeping.
+ * Returns 0 if the parameters are invalid.  The workspace must be 256-byte
+ * aligned. */
 size_t cuba_workspace_bytes(const cuba_params *params, int64_t n);
 
 /* Creates a context.  x..pz are device arrays of n doubles (particle id =
@@ -106,7 +112,10 @@ int cuba_init(cuba_ctx **out, const cuba_params *params, int64_t n,
               void *workspace, size_t ws_bytes, void *stream);
 
 /* Advances the state by nsteps >= 0 steps, asynchronously on the stream.
- * Step indices continue from params->step0. */
+ * Step indices continue from params->step0.  Internally one kernel per
+ * step does the collisions of step t and the streaming and binning of step
+ * t+1; a call issues nsteps + 1 launches, so advancing many steps per call
+ * is cheaper than one step per call. */
 int cuba_step(cuba_ctx *ctx, int32_t nsteps);
 
 /* Lab-frame energy and x-momentum density profiles over the nx slabs of
@@ -160,15 +169,16 @@ int cuba_info(const cuba_ctx *ctx, uint32_t *next_step, int64_t *n,
 int cuba_counters(cuba_ctx *ctx, uint64_t out[3]);
 
 /* Stage timing.  cuba_timing_begin makes the following steps and
- * observations record a HIP event on the context's stream between their
- * stages, for at most max_launches stage launches; cuba_timing_end waits
+ * observations record HIP events on the context's stream around each
+ * kernel launch, for at most max_launches launches; cuba_timing_end waits
  * for the stream and writes, per stage, the summed duration in ms and the
  * number of launches timed.  Stages (index into the arrays):
- *   0 count   (stream + reflect + cell histogram)
- *   1 scan    (cell offsets)
- *   2 scatter (stream + reflect + permutation into cell order)
- *   3 collide (pair tests, claims, kinematics)
- *   4 observe (slab profiles)
+ *   0 bin      stream + reflect + bin (first step of a cuba_step call)
+ *   1 step     fused: pair tests, claims and kinematics of step t, then
+ *              stream + reflect + bin of step t+1
+ *   2 collide  pair tests, claims and kinematics (last step of a call)
+ *   3 observe  slab profiles
+ *   4 offsets  compact cell offsets (cuba_trace_step only)
  * Events are host-side runtime objects; no device memory is allocated. */
 #define CUBA_NUM_STAGES 5
 int cuba_timing_begin(cuba_ctx *ctx, int32_t max_launches);

@@ -33,12 +33,13 @@ inline size_t align256(size_t v) { return (v + 255u) & ~(size_t)255u; }
 // Byte offsets of every array inside the workspace.
 struct Layout {
   size_t status;
-  size_t soa[2][7];  // x y z px py pz id, for the two buffers
-  size_t counts, offsets, cursor, tile_sums, obs_partial;
+  size_t soa[2][7];  // x y z px py pz id, for the two buffers (C x cap slots)
+  size_t count[2];   // per-cell occupancy of the two buffers
+  size_t offsets, tile_sums, cell_sums;
   size_t total;
 };
 
-Layout make_layout(int64_t n, int64_t n_cells, int64_t nx) {
+Layout make_layout(int64_t n_cells, uint32_t cap) {
   Layout L{};
   size_t off = 0;
   auto take = [&off](size_t bytes) {
@@ -46,19 +47,18 @@ Layout make_layout(int64_t n, int64_t n_cells, int64_t nx) {
     off = align256(off + bytes);
     return o;
   };
-  const size_t nn = (size_t)(n > 0 ? n : 1);
   const size_t cc = (size_t)n_cells;
+  const size_t slots = cc * cap;
   const size_t tiles = (cc + kScanTile - 1) / kScanTile;
   L.status = take(sizeof(DevStatus));
   for (int b = 0; b < 2; ++b) {
-    for (int a = 0; a < 6; ++a) L.soa[b][a] = take(nn * sizeof(double));
-    L.soa[b][6] = take(nn * sizeof(uint32_t));
+    for (int a = 0; a < 6; ++a) L.soa[b][a] = take(slots * sizeof(double));
+    L.soa[b][6] = take(slots * sizeof(uint32_t));
+    L.count[b] = take(cc * sizeof(uint32_t));
   }
-  L.counts = take(cc * sizeof(uint32_t));
   L.offsets = take((cc + 1) * sizeof(uint32_t));
-  L.cursor = take(cc * sizeof(uint32_t));
   L.tile_sums = take(tiles * sizeof(uint32_t));
-  L.obs_partial = take((size_t)nx * kObsChunks * 2 * sizeof(double));
+  L.cell_sums = take(cc * 2 * sizeof(double));
   L.total = off;
   return L;
 }
@@ -68,7 +68,10 @@ struct Derived {
   Geometry g;
   double vcell, kfac, vol;
   int64_t n_cells;
+  uint32_t cap;
 };
+
+constexpr uint32_t kDefaultCellCapacity = 512;
 
 int derive(const cuba_params *p, Derived &d) {
   if (!p) return fail(CUBA_EINVAL, "params is NULL");
@@ -100,6 +103,11 @@ int derive(const cuba_params *p, Derived &d) {
     return fail(CUBA_EINVAL, "sigma / r_test * dt / V_cell > 1/2: P22 could exceed 1");
   d.vol = ((p->r_test * d.g.dx[0]) * p->box[1]) * p->box[2];
   d.n_cells = nc;
+  if (p->cell_capacity < 0 || p->cell_capacity > (int32_t)kCellCap)
+    return fail(CUBA_EINVAL, "cell_capacity must be in [0, " + std::to_string(kCellCap) + "]");
+  d.cap = p->cell_capacity == 0 ? kDefaultCellCapacity : (uint32_t)p->cell_capacity;
+  if ((size_t)nc * d.cap >= ((size_t)1 << 40))
+    return fail(CUBA_EINVAL, "cells x cell_capacity too large");
   return CUBA_OK;
 }
 
@@ -127,10 +135,10 @@ struct cuba_ctx {
   uint32_t next_step;
   hipStream_t stream;
   DevStatus *status;
-  SoA buf[2];
+  Cells buf[2];
   int cur;
-  uint32_t *counts, *offsets, *cursor, *tile_sums;
-  double *obs_partial;
+  uint32_t *offsets, *tile_sums;
+  double *cell_sums;
   // stage timing (cuba_timing_begin / cuba_timing_end)
   bool timing = false;
   size_t timing_cap = 0;
@@ -146,7 +154,7 @@ int check_launch(const char *where) {
   return CUBA_OK;
 }
 
-enum Stage { kStageCount = 0, kStageScan, kStageScatter, kStageCollide, kStageObserve };
+enum Stage { kStageBin = 0, kStageStep, kStageCollide, kStageObserve, kStageOffsets };
 
 // Runs launch(); while timing, brackets it with two events on the stream.
 template <typename F>
@@ -171,25 +179,37 @@ void drop_timing(cuba_ctx *c) {
   c->timing_cap = 0;
 }
 
-// One step: stream+count, scan, stream+scatter into the other buffer,
-// collide in place there.
-int run_step(cuba_ctx *c, const TraceArgs *tr) {
-  const SoA &src = c->buf[c->cur];
-  const SoA &dst = c->buf[c->cur ^ 1];
-  stage(c, kStageCount,
-        [&] { launch_count(src, c->n, c->d.g, true, c->counts, c->stream); });
-  stage(c, kStageScan, [&] {
-    launch_scan(c->counts, c->offsets, c->cursor, c->tile_sums, c->d.n_cells, c->stream);
-  });
-  stage(c, kStageScatter, [&] {
-    launch_scatter(src, dst, c->n, c->d.g, true, c->cursor, tr ? tr->cell : nullptr,
-                   c->stream);
-  });
-  stage(c, kStageCollide, [&] {
-    launch_collide(c->offsets, dst, c->d.n_cells, c->next_step, c->pa, c->status, tr,
-                   c->stream);
+// nsteps steps: stream + bin into the other buffer, then nsteps - 1 fused
+// steps (collide, then stream + bin into the other buffer), then the last
+// collisions in place.  With a trace (nsteps = 1) the binning records cells
+// and the compact offsets are built before the collisions.
+int run_steps(cuba_ctx *c, int32_t nsteps, const TraceArgs *trace_in) {
+  if (nsteps <= 0) return CUBA_OK;
+  stage(c, kStageBin, [&] {
+    launch_stream_bin(c->buf[c->cur], c->buf[c->cur ^ 1], c->d.n_cells, c->d.g, c->status,
+                      trace_in ? trace_in->cell : nullptr, c->stream);
   });
   c->cur ^= 1;
+  for (int32_t s = 1; s < nsteps; ++s) {
+    stage(c, kStageStep, [&] {
+      launch_step(c->buf[c->cur], c->buf[c->cur ^ 1], true, c->d.n_cells, c->next_step,
+                  c->pa, c->d.g, c->status, nullptr, c->stream);
+    });
+    c->cur ^= 1;
+    c->next_step += 1;
+  }
+  TraceArgs tr{};
+  if (trace_in) {
+    tr = *trace_in;
+    stage(c, kStageOffsets, [&] {
+      launch_offsets(c->buf[c->cur], const_cast<uint32_t *>(tr.offsets), c->tile_sums,
+                     c->d.n_cells, c->stream);
+    });
+  }
+  stage(c, kStageCollide, [&] {
+    launch_step(c->buf[c->cur], c->buf[c->cur ^ 1], false, c->d.n_cells, c->next_step,
+                c->pa, c->d.g, c->status, trace_in ? &tr : nullptr, c->stream);
+  });
   c->next_step += 1;
   return check_launch("step launch");
 }
@@ -201,7 +221,7 @@ extern "C" {
 size_t cuba_workspace_bytes(const cuba_params *params, int64_t n) {
   Derived d;
   if (derive(params, d) != CUBA_OK || n < 0 || n >= 0xFFFFFFFFll) return 0;
-  return make_layout(n, d.n_cells, params->cells[0]).total;
+  return make_layout(d.n_cells, d.cap).total;
 }
 
 int cuba_init(cuba_ctx **out, const cuba_params *params, int64_t n, const double *x,
@@ -218,7 +238,7 @@ int cuba_init(cuba_ctx **out, const cuba_params *params, int64_t n, const double
   if (!workspace) return fail(CUBA_EINVAL, "workspace is NULL");
   if (((uintptr_t)workspace & 255u) != 0)
     return fail(CUBA_EINVAL, "workspace must be 256-byte aligned");
-  const Layout L = make_layout(n, d.n_cells, params->cells[0]);
+  const Layout L = make_layout(d.n_cells, d.cap);
   if (ws_bytes < L.total)
     return fail(CUBA_ENOMEM, "workspace too small: need " + std::to_string(L.total) +
                                  " bytes, got " + std::to_string(ws_bytes));
@@ -238,26 +258,28 @@ int cuba_init(cuba_ctx **out, const cuba_params *params, int64_t n, const double
   char *ws = (char *)workspace;
   c->status = (DevStatus *)(ws + L.status);
   for (int b = 0; b < 2; ++b) {
-    c->buf[b].x = (double *)(ws + L.soa[b][0]);
-    c->buf[b].y = (double *)(ws + L.soa[b][1]);
-    c->buf[b].z = (double *)(ws + L.soa[b][2]);
-    c->buf[b].px = (double *)(ws + L.soa[b][3]);
-    c->buf[b].py = (double *)(ws + L.soa[b][4]);
-    c->buf[b].pz = (double *)(ws + L.soa[b][5]);
-    c->buf[b].id = (uint32_t *)(ws + L.soa[b][6]);
+    SoA &st = c->buf[b].st;
+    st.x = (double *)(ws + L.soa[b][0]);
+    st.y = (double *)(ws + L.soa[b][1]);
+    st.z = (double *)(ws + L.soa[b][2]);
+    st.px = (double *)(ws + L.soa[b][3]);
+    st.py = (double *)(ws + L.soa[b][4]);
+    st.pz = (double *)(ws + L.soa[b][5]);
+    st.id = (uint32_t *)(ws + L.soa[b][6]);
+    c->buf[b].count = (uint32_t *)(ws + L.count[b]);
+    c->buf[b].cap = d.cap;
   }
-  c->counts = (uint32_t *)(ws + L.counts);
   c->offsets = (uint32_t *)(ws + L.offsets);
-  c->cursor = (uint32_t *)(ws + L.cursor);
   c->tile_sums = (uint32_t *)(ws + L.tile_sums);
-  c->obs_partial = (double *)(ws + L.obs_partial);
+  c->cell_sums = (double *)(ws + L.cell_sums);
   c->cur = 0;
 
-  // clear status and counts, load and check the particles
+  // clear status and counts, then check and bin the particles
   launch_fill_u32((uint32_t *)c->status, 0u, sizeof(DevStatus) / sizeof(uint32_t),
                   c->stream);
-  launch_fill_u32(c->counts, 0u, d.n_cells, c->stream);
-  launch_load(x, y, z, px, py, pz, c->buf[0], n, d.g, c->status, c->stream);
+  launch_fill_u32(c->buf[0].count, 0u, d.n_cells, c->stream);
+  launch_fill_u32(c->buf[1].count, 0u, d.n_cells, c->stream);
+  launch_init_bin(x, y, z, px, py, pz, c->buf[0], n, d.g, c->status, c->stream);
   rc = check_launch("init launch");
   if (rc != CUBA_OK) {
     delete c;
@@ -276,15 +298,10 @@ int cuba_init(cuba_ctx **out, const cuba_params *params, int64_t n, const double
     return fail(CUBA_ERANGE,
                 "a particle is outside [0, L], non-finite, or has |p| = 0");
   }
-  // bin the initial state (no streaming) into the other buffer
-  launch_count(c->buf[0], n, d.g, false, c->counts, c->stream);
-  launch_scan(c->counts, c->offsets, c->cursor, c->tile_sums, d.n_cells, c->stream);
-  launch_scatter(c->buf[0], c->buf[1], n, d.g, false, c->cursor, nullptr, c->stream);
-  c->cur = 1;
-  rc = check_launch("init binning");
-  if (rc != CUBA_OK) {
+  if (err & kErrCapacity) {
     delete c;
-    return rc;
+    return fail(CUBA_ERANGE, "a cell holds more particles than cell_capacity (" +
+                                 std::to_string(d.cap) + ")");
   }
   *out = c;
   return CUBA_OK;
@@ -293,11 +310,7 @@ int cuba_init(cuba_ctx **out, const cuba_params *params, int64_t n, const double
 int cuba_step(cuba_ctx *c, int32_t nsteps) {
   if (!c) return fail(CUBA_EINVAL, "ctx is NULL");
   if (nsteps < 0) return fail(CUBA_EINVAL, "nsteps must be >= 0");
-  for (int32_t s = 0; s < nsteps; ++s) {
-    const int rc = run_step(c, nullptr);
-    if (rc != CUBA_OK) return rc;
-  }
-  return CUBA_OK;
+  return run_steps(c, nsteps, nullptr);
 }
 
 int cuba_trace_step(cuba_ctx *c, const cuba_trace *t) {
@@ -309,28 +322,20 @@ int cuba_trace_step(cuba_ctx *c, const cuba_trace *t) {
   TraceArgs tr{};
   tr.cell = t->cell;
   tr.perm = t->perm;
+  tr.offsets = t->offsets ? t->offsets : c->offsets;
   tr.cand = t->cand;
   tr.cand_cap = (uint32_t)t->cand_cap;
   tr.claim = t->claim;
   tr.claim_cap = (uint32_t)t->claim_cap;
   tr.counts = t->counts;
   launch_fill_u32(t->counts, 0u, 2, c->stream);
-  int rc = run_step(c, &tr);
-  if (rc != CUBA_OK) return rc;
-  if (t->offsets) {
-    const hipError_t e =
-        hipMemcpyAsync(t->offsets, c->offsets, (size_t)(c->d.n_cells + 1) * sizeof(uint32_t),
-                       hipMemcpyDeviceToDevice, c->stream);
-    if (e != hipSuccess) return hip_fail(e, "trace offsets copy");
-  }
-  return CUBA_OK;
+  return run_steps(c, 1, &tr);
 }
 
 int cuba_observe(cuba_ctx *c, double *T00, double *T0x) {
   if (!c || !T00 || !T0x) return fail(CUBA_EINVAL, "NULL argument");
   stage(c, kStageObserve, [&] {
-    launch_observe(c->offsets, c->buf[c->cur], c->d.g, c->d.vol, c->obs_partial, T00, T0x,
-                   c->stream);
+    launch_observe(c->buf[c->cur], c->d.g, c->d.vol, c->cell_sums, T00, T0x, c->stream);
   });
   return check_launch("observe launch");
 }
@@ -340,7 +345,7 @@ int cuba_get_state(cuba_ctx *c, double *x, double *y, double *z, double *px,
   if (!c) return fail(CUBA_EINVAL, "ctx is NULL");
   if (c->n > 0 && !(x && y && z && px && py && pz))
     return fail(CUBA_EINVAL, "NULL output array");
-  launch_gather_by_id(c->buf[c->cur], c->n, x, y, z, px, py, pz, c->stream);
+  launch_gather_by_id(c->buf[c->cur], c->d.n_cells, x, y, z, px, py, pz, c->stream);
   return check_launch("get_state launch");
 }
 
@@ -355,10 +360,10 @@ int cuba_sync(cuba_ctx *c) {
     launch_fill_u32(&c->status->err, 0u, 1, c->stream);
     e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "sync reset");
-    if (err & kErrOccupancy)
-      return fail(CUBA_ERANGE, "a cell held more than " +
-                                   std::to_string(CUBA_MAX_CELL_OCCUPANCY) +
-                                   " particles; its collisions were skipped");
+    if (err & kErrCapacity)
+      return fail(CUBA_ERANGE, "a cell received more particles than cell_capacity (" +
+                                   std::to_string(c->d.cap) +
+                                   "); the surplus particles were dropped");
     if (err & kErrTrace) return fail(CUBA_ENOMEM, "trace buffer too small");
     return fail(CUBA_ERANGE, "device reported an invalid state");
   }

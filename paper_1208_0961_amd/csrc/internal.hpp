@@ -12,17 +12,25 @@ namespace cuba {
 
 constexpr uint32_t kCellCap = 1024;  // = CUBA_MAX_CELL_OCCUPANCY
 constexpr uint32_t kScanTile = 2048; // counts per scan tile
-constexpr uint32_t kObsChunks = 16;  // partial sums per slab in the observe pass
 
 // Device-side error bits, accumulated until the next cuba_sync.
-constexpr uint32_t kErrOccupancy = 1u;  // a cell over kCellCap
-constexpr uint32_t kErrTrace = 2u;      // trace buffer too small
-constexpr uint32_t kErrRange = 4u;      // invalid initial particle
+constexpr uint32_t kErrCapacity = 1u;  // a cell received more than its capacity
+constexpr uint32_t kErrTrace = 2u;     // trace buffer too small
+constexpr uint32_t kErrRange = 4u;     // invalid initial particle
 
 // Structure-of-arrays particle state (FP64 position and momentum, u32 id).
 struct SoA {
   double *x, *y, *z, *px, *py, *pz;
   uint32_t *id;
+};
+
+// A binned state with a fixed capacity per cell: cell c owns slots
+// [c cap, c cap + count[c]) of every array (count may exceed cap only after
+// an overflow, which is flagged; readers clamp it).
+struct Cells {
+  SoA st;
+  uint32_t *count;
+  uint32_t cap;
 };
 
 // Device-resident bookkeeping at the head of the workspace.  The work
@@ -40,6 +48,7 @@ struct DevStatus {
 struct TraceArgs {
   uint32_t *cell;     // [n] by id
   uint32_t *perm;     // [n]
+  const uint32_t *offsets;  // [C+1] compact offsets of the traced binning
   uint32_t *cand;     // [3 cap]
   uint32_t cand_cap;
   uint32_t *claim;    // [3 cap]
@@ -55,25 +64,22 @@ struct PairArgs {
 };
 
 // Launchers (kernels.hip).  All asynchronous on stream s.
-void launch_load(const double *x, const double *y, const double *z,
-                 const double *px, const double *py, const double *pz, SoA dst,
-                 int64_t n, const Geometry &g, DevStatus *st, hipStream_t s);
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s);
-void launch_count(const SoA &src, int64_t n, const Geometry &g, bool stream,
-                  uint32_t *counts, hipStream_t s);
-void launch_scan(uint32_t *counts, uint32_t *offsets, uint32_t *cursor,
-                 uint32_t *tile_sums, int64_t n_cells, hipStream_t s);
-void launch_scatter(const SoA &src, SoA dst, int64_t n, const Geometry &g,
-                    bool stream, uint32_t *cursor, uint32_t *trace_cell,
-                    hipStream_t s);
-void launch_collide(const uint32_t *offsets, SoA st, int64_t n_cells,
-                    uint32_t t, const PairArgs &pa, DevStatus *status,
-                    const TraceArgs *trace, hipStream_t s);
-void launch_observe(const uint32_t *offsets, const SoA &st, const Geometry &g,
-                    double vol, double *partial, double *T00, double *T0x,
-                    hipStream_t s);
-void launch_gather_by_id(const SoA &st, int64_t n, double *x, double *y,
-                         double *z, double *px, double *py, double *pz,
-                         hipStream_t s);
+void launch_init_bin(const double *x, const double *y, const double *z,
+                     const double *px, const double *py, const double *pz,
+                     const Cells &dst, int64_t n, const Geometry &g, DevStatus *st,
+                     hipStream_t s);
+void launch_stream_bin(const Cells &src, const Cells &dst, int64_t n_cells,
+                       const Geometry &g, DevStatus *status, uint32_t *trace_cell,
+                       hipStream_t s);
+void launch_offsets(const Cells &cur, uint32_t *offsets, uint32_t *tile_sums,
+                    int64_t n_cells, hipStream_t s);
+void launch_step(const Cells &src, const Cells &dst, bool fused, int64_t n_cells,
+                 uint32_t t, const PairArgs &pa, const Geometry &g, DevStatus *status,
+                 const TraceArgs *trace, hipStream_t s);
+void launch_observe(const Cells &cur, const Geometry &g, double vol, double *cell_sums,
+                    double *T00, double *T0x, hipStream_t s);
+void launch_gather_by_id(const Cells &cur, int64_t n_cells, double *x, double *y,
+                         double *z, double *px, double *py, double *pz, hipStream_t s);
 
 }  // namespace cuba

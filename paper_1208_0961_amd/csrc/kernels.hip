@@ -1,17 +1,25 @@
 // kernels.hip -- gfx950 kernels of the PIC Boltzmann step (arXiv:1208.0961).
 //
-// Per step, on the structure-of-arrays state kept in cell order:
-//   count    stream + reflect each particle in registers, find its new cell,
-//            count cells with wave-aggregated atomics        (HBM: 48 B read)
-//   scan     exclusive prefix sum of the cell counts -> offsets and cursors
-//   scatter  stream + reflect again (bit-identical), claim a slot in the new
-//            cell, write the particle there                  (HBM: 52 B + 52 B)
-//   collide  one wave64 per cell: ids to LDS, canonical (id) order by rank
-//            counting, all n(n-1)/2 pair tests spread over the lanes with a
-//            Philox block each, ballot-compaction of the pairs that can pass,
-//            exact Eq. (3) test on those, greedy claim in pair order, then
-//            the CM-frame kinematics of the claimed pairs   (ALU bound)
-// plus the observe pass (slab sums of E and p_x) and state export by id.
+// State layout: two structure-of-arrays buffers with a fixed capacity of
+// `cap` slots per cell; cell c owns slots [c cap, c cap + count[c]).  One
+// buffer holds the current state, the other receives the next binning.
+//
+// A step t is stream + reflect + bin (Eq. (2), walls, cells), then the
+// collisions of every cell (Eq. (3), claims, CM kinematics).  The kernels:
+//   k_stream_bin   one wave per source cell: stream + reflect each particle,
+//                  find its new cell, append it there (wave-aggregated slot
+//                  atomics, one round trip per wave).       HBM: 52 B + 52 B
+//   k_step<F>      one wave per cell: ids to LDS, canonical (id) order by
+//                  rank counting, all n(n-1)/2 pair tests over the lanes with
+//                  a Philox block each, ballot compaction of the pairs that
+//                  can pass, exact Eq. (3) test on those, greedy claim in
+//                  pair order, CM kinematics.  With F (fused) the same wave
+//                  then streams and bins its particles for step t+1, so the
+//                  binning traffic overlaps the ALU-bound pair tests.
+//   observe        per-cell sums of E and p_x, then fixed-order slab sums.
+//   gather         state export by id.
+// A run of n steps is one stream_bin, n-1 fused steps and one collide-only
+// step, which leaves the state binned and collided (positions of step t+n-1).
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"
@@ -22,6 +30,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr uint32_t kFiltCap = 512;  // filtered pairs held before resolving
+constexpr uint32_t kCellsPerBlock = kBlock / 64;
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
@@ -52,31 +61,13 @@ __device__ __forceinline__ uint32_t aggregated_fetch_add(uint32_t *ctr, uint32_t
   return base + rank;
 }
 
-// Count-only variant: the leaders add their group sizes (no value returned).
-__device__ __forceinline__ void aggregated_add(uint32_t *ctr, uint32_t key, bool active) {
-  const uint32_t lane = lane_id();
-  uint32_t leader = lane, size = 0;
-  uint64_t todo = __ballot(active);
-  while (todo != 0) {
-    const int l = __builtin_ctzll(todo);
-    const uint32_t lkey = __shfl(key, l);
-    const uint64_t group = __ballot(active && key == lkey);
-    if (active && key == lkey) {
-      leader = (uint32_t)l;
-      size = (uint32_t)__popcll(group);
-    }
-    todo &= ~group;
-  }
-  if (active && leader == lane) atomicAdd(&ctr[key], size);
-}
-
 // Workgroups are dispatched round-robin over the 8 XCDs of the MI355X
-// (workgroup b runs on XCD b mod 8), each XCD with its own L2.
+// (workgroup b runs on XCD b mod 8), each XCD with its own L2.  This
+// bijection on [0, nblocks) gives each XCD runs of kRun consecutive logical
+// blocks, interleaved over the XCDs: neighbouring cells (which share cache
+// lines at their boundaries and exchange particles) stay on one L2, while
+// work that varies along the cell range stays balanced.
 constexpr uint32_t kXcds = 8;
-
-// Bijection on [0, nblocks) giving each XCD runs of kRun consecutive logical
-// blocks, interleaved over the XCDs (balances work that varies along the
-// block range while keeping neighbouring blocks on one L2).
 template <uint32_t kRun>
 __device__ __forceinline__ uint32_t xcd_runs(uint32_t b, uint32_t nblocks) {
   constexpr uint32_t kSuper = kXcds * kRun;
@@ -86,85 +77,106 @@ __device__ __forceinline__ uint32_t xcd_runs(uint32_t b, uint32_t nblocks) {
   return s * kSuper + (r % kXcds) * kRun + r / kXcds;
 }
 
+// Appends particle (r, p, id) to cell c2 of dst; slots past the capacity
+// are dropped and flagged (reported as CUBA_ERANGE at the next sync).
+__device__ __forceinline__ void append(const Cells &dst, uint32_t c2, bool active,
+                                       double x, double y, double z, double px,
+                                       double py, double pz, uint32_t id,
+                                       DevStatus *status) {
+  const uint32_t slot = aggregated_fetch_add(dst.count, c2, active);
+  if (active) {
+    if (slot < dst.cap) {
+      const size_t o = (size_t)c2 * dst.cap + slot;
+      dst.st.x[o] = x;
+      dst.st.y[o] = y;
+      dst.st.z[o] = z;
+      dst.st.px[o] = px;
+      dst.st.py[o] = py;
+      dst.st.pz[o] = pz;
+      dst.st.id[o] = id;
+    } else {
+      atomicOr(&status->err, kErrCapacity);
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t occupancy(const Cells &c, uint32_t cell) {
+  const uint32_t n = c.count[cell];
+  return n < c.cap ? n : c.cap;
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, uint32_t v,
                                                      int64_t count) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < count) p[i] = v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_load(
+// Initial state (id order) -> validated and binned without streaming.
+__global__ __launch_bounds__(kBlock) void k_init_bin(
     const double *__restrict__ x, const double *__restrict__ y,
     const double *__restrict__ z, const double *__restrict__ px,
-    const double *__restrict__ py, const double *__restrict__ pz, SoA dst,
+    const double *__restrict__ py, const double *__restrict__ pz, Cells dst,
     int64_t n, Geometry g, DevStatus *status) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const double a = x[i], b = y[i], c = z[i], qa = px[i], qb = py[i], qc = pz[i];
-  dst.x[i] = a;
-  dst.y[i] = b;
-  dst.z[i] = c;
-  dst.px[i] = qa;
-  dst.py[i] = qb;
-  dst.pz[i] = qc;
-  dst.id[i] = (uint32_t)i;
-  const bool ok = __builtin_isfinite(a) && __builtin_isfinite(b) &&
-                  __builtin_isfinite(c) && __builtin_isfinite(qa) &&
-                  __builtin_isfinite(qb) && __builtin_isfinite(qc) && a >= 0.0 &&
-                  a <= g.L[0] && b >= 0.0 && b <= g.L[1] && c >= 0.0 &&
-                  c <= g.L[2] && norm3(qa, qb, qc) > 0.0;
-  if (!ok) atomicOr(&status->err, kErrRange);
-}
-
-template <bool kStream>
-__global__ __launch_bounds__(kBlock) void k_count(SoA src, int64_t n, Geometry g,
-                                                  uint32_t *counts) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool active = i < n;
-  uint32_t c = 0;
+  double a = 0, b = 0, c = 0, qa = 0, qb = 0, qc = 0;
+  uint32_t cell = 0;
   if (active) {
-    double x = src.x[i], y = src.y[i], z = src.z[i];
-    double px = src.px[i], py = src.py[i], pz = src.pz[i];
-    advance<kStream>(g, x, y, z, px, py, pz);
-    c = cell_id(g, x, y, z);
+    a = x[i];
+    b = y[i];
+    c = z[i];
+    qa = px[i];
+    qb = py[i];
+    qc = pz[i];
+    const bool ok = __builtin_isfinite(a) && __builtin_isfinite(b) &&
+                    __builtin_isfinite(c) && __builtin_isfinite(qa) &&
+                    __builtin_isfinite(qb) && __builtin_isfinite(qc) && a >= 0.0 &&
+                    a <= g.L[0] && b >= 0.0 && b <= g.L[1] && c >= 0.0 &&
+                    c <= g.L[2] && norm3(qa, qb, qc) > 0.0;
+    if (!ok) atomicOr(&status->err, kErrRange);
+    cell = cell_id(g, a, b, c);
   }
-  aggregated_add(counts, c, active);
+  append(dst, cell, active, a, b, c, qa, qb, qc, (uint32_t)i, status);
 }
 
-template <bool kStream>
-__global__ __launch_bounds__(kBlock) void k_scatter(SoA src, SoA dst, int64_t n,
-                                                    Geometry g, uint32_t *cursor,
-                                                    uint32_t *trace_cell) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool active = i < n;
-  double x = 0, y = 0, z = 0, px = 0, py = 0, pz = 0;
-  uint32_t id = 0, c = 0;
-  if (active) {
-    x = src.x[i];
-    y = src.y[i];
-    z = src.z[i];
-    px = src.px[i];
-    py = src.py[i];
-    pz = src.pz[i];
-    id = src.id[i];
-    advance<kStream>(g, x, y, z, px, py, pz);
-    c = cell_id(g, x, y, z);
+// Stream + reflect + bin, one wave per source cell (four cells per block).
+// Clears the source counts, so the source buffer can receive the next
+// binning.
+__global__ __launch_bounds__(kBlock) void k_stream_bin(Cells src, Cells dst,
+                                                       uint32_t n_cells, Geometry g,
+                                                       DevStatus *status,
+                                                       uint32_t *trace_cell) {
+  const uint32_t lane = lane_id();
+  const uint32_t c = xcd_runs<2>(blockIdx.x, gridDim.x) * kCellsPerBlock +
+                     threadIdx.x / 64;
+  if (c >= n_cells) return;
+  const uint32_t n = occupancy(src, c);
+  const size_t base = (size_t)c * src.cap;
+  for (uint32_t j0 = 0; j0 < n; j0 += 64) {
+    const uint32_t j = j0 + lane;
+    const bool active = j < n;
+    double x = 0, y = 0, z = 0, px = 0, py = 0, pz = 0;
+    uint32_t id = 0, c2 = 0;
+    if (active) {
+      x = src.st.x[base + j];
+      y = src.st.y[base + j];
+      z = src.st.z[base + j];
+      px = src.st.px[base + j];
+      py = src.st.py[base + j];
+      pz = src.st.pz[base + j];
+      id = src.st.id[base + j];
+      advance<true>(g, x, y, z, px, py, pz);
+      c2 = cell_id(g, x, y, z);
+      if (trace_cell) trace_cell[id] = c2;
+    }
+    append(dst, c2, active, x, y, z, px, py, pz, id, status);
   }
-  const uint32_t slot = aggregated_fetch_add(cursor, c, active);
-  if (active) {
-    dst.x[slot] = x;
-    dst.y[slot] = y;
-    dst.z[slot] = z;
-    dst.px[slot] = px;
-    dst.py[slot] = py;
-    dst.pz[slot] = pz;
-    dst.id[slot] = id;
-    if (trace_cell) trace_cell[id] = c;
-  }
+  if (lane == 0) src.count[c] = 0u;
 }
 
-// Tile-local exclusive scan of counts (kScanTile per block, 8 per thread);
-// clears the counts for the next step.
-__global__ __launch_bounds__(kBlock) void k_scan_tiles(uint32_t *counts,
+// Exclusive scan of the counts into compact offsets (trace only; the counts
+// are left intact).  Tile-local pass, then carries from earlier tiles.
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(const Cells cur,
                                                        uint32_t *offsets,
                                                        uint32_t *tile_sums,
                                                        int64_t n_cells) {
@@ -176,7 +188,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(uint32_t *counts,
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int64_t idx = base + j;
-    const uint32_t cnt = idx < n_cells ? counts[idx] : 0u;
+    const uint32_t cnt = idx < n_cells ? occupancy(cur, (uint32_t)idx) : 0u;
     v[j] = sum;
     sum += cnt;
   }
@@ -194,17 +206,12 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(uint32_t *counts,
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int64_t idx = base + j;
-    if (idx < n_cells) {
-      offsets[idx] = excl + v[j];
-      counts[idx] = 0u;
-    }
+    if (idx < n_cells) offsets[idx] = excl + v[j];
   }
   if (threadIdx.x == kBlock - 1) tile_sums[blockIdx.x] = wave_off + incl;
 }
 
-// Adds the sum of all earlier tiles; copies the offsets into the cursors.
 __global__ __launch_bounds__(kBlock) void k_scan_carry(uint32_t *offsets,
-                                                       uint32_t *cursor,
                                                        const uint32_t *tile_sums,
                                                        int64_t n_cells) {
   __shared__ uint32_t s_red[kBlock / 64];
@@ -221,11 +228,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_carry(uint32_t *offsets,
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int64_t idx = base + j;
-    if (idx < n_cells) {
-      const uint32_t o = offsets[idx] + carry;
-      offsets[idx] = o;
-      cursor[idx] = o;
-    }
+    if (idx < n_cells) offsets[idx] += carry;
   }
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
     offsets[n_cells] = carry + tile_sums[blockIdx.x];
@@ -235,7 +238,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_carry(uint32_t *offsets,
 // Collisions: one wave64 (one workgroup) per cell.
 // ---------------------------------------------------------------------------
 struct CellView {
-  uint32_t c, n, base, t;
+  uint32_t c, n, t;
+  size_t base;
 };
 
 // Exact Eq. (3) test of the nf filtered pairs in s_filt (increasing pair
@@ -256,7 +260,7 @@ __device__ __forceinline__ void resolve_filtered(
     const double u = uniform53(w.w0, w.w1);
     uint32_t a, b;
     pair_of_index(k, cv.n, a, b);
-    const uint32_t ia = cv.base + s_perm[a], ib = cv.base + s_perm[b];
+    const size_t ia = cv.base + s_perm[a], ib = cv.base + s_perm[b];
     const double P = p22(st.px[ia], st.py[ia], st.pz[ia], st.px[ib], st.py[ib],
                          st.pz[ib], pa.kfac);
     const bool acc = u < P;
@@ -292,15 +296,19 @@ __device__ __forceinline__ void resolve_filtered(
   __syncthreads();
 }
 
-template <bool kTrace>
-__global__ __launch_bounds__(64) void k_collide(const uint32_t *__restrict__ offsets,
-                                                SoA st, uint32_t t, PairArgs pa,
-                                                DevStatus *status, TraceArgs tr) {
+// Collisions of one cell of src at step t.  kFused: afterwards stream and
+// bin the cell's particles into dst for step t+1 and clear src's count.
+template <bool kFused, bool kTrace>
+__global__ __launch_bounds__(64) void k_step(Cells src, Cells dst, uint32_t t,
+                                             PairArgs pa, Geometry g,
+                                             DevStatus *status, TraceArgs tr) {
   // s_buf holds the cell's ids while the canonical order is built; after
   // that its first half holds the filtered pairs and its second half the
-  // claimed pairs.
+  // claimed pairs.  s_mark flags (by storage index) the particles whose
+  // scattering already binned them.
   __shared__ __align__(16) uint32_t s_buf[kCellCap];
   __shared__ uint16_t s_perm[kCellCap];
+  __shared__ uint8_t s_mark[kFused ? kCellCap : 1];
   static_assert(kFiltCap + kCellCap / 2 <= kCellCap, "LDS aliasing");
   uint32_t *const s_id = s_buf;
   uint32_t *const s_filt = s_buf;
@@ -310,147 +318,235 @@ __global__ __launch_bounds__(64) void k_collide(const uint32_t *__restrict__ off
   CellView cv;
   cv.c = xcd_runs<8>(blockIdx.x, gridDim.x);
   cv.t = t;
-  cv.base = offsets[cv.c];
-  cv.n = offsets[cv.c + 1] - cv.base;
+  cv.base = (size_t)cv.c * src.cap;
+  cv.n = occupancy(src, cv.c);
   const uint32_t n = cv.n;
-  if (n > kCellCap) {
-    if (lane == 0) atomicOr(&status->err, kErrOccupancy);
-    return;
-  }
-  if (n < 2) {
-    if (kTrace && n == 1 && lane == 0 && tr.perm) tr.perm[cv.base] = st.id[cv.base];
-    return;
-  }
+  const SoA &st = src.st;
 
-  // ids to LDS, padded to a multiple of 4 with an id no particle has
-  const uint32_t n4 = (n + 3u) & ~3u;
-  for (uint32_t j = lane; j < n4; j += 64)
-    s_id[j] = j < n ? st.id[cv.base + j] : 0xFFFFFFFFu;
-  __syncthreads();
+  uint32_t nclaim = 0;
+  if (n >= 2) {
+    // ids to LDS, padded to a multiple of 4 with an id no particle has
+    const uint32_t n4 = (n + 3u) & ~3u;
+    for (uint32_t j = lane; j < n4; j += 64)
+      s_id[j] = j < n ? st.id[cv.base + j] : 0xFFFFFFFFu;
+    if (kFused)
+      for (uint32_t j = lane; j < n; j += 64) s_mark[j] = 0;
+    __syncthreads();
 
-  // canonical order: the rank of each id among the cell's ids
-  const uint4 *s_id4 = reinterpret_cast<const uint4 *>(s_id);
-  for (uint32_t j = lane; j < n; j += 64) {
-    const uint32_t me = s_id[j];
-    uint32_t r = 0;
-    for (uint32_t m = 0; m < n4 / 4; ++m) {
-      const uint4 q = s_id4[m];
-      r += (q.x < me) + (q.y < me) + (q.z < me) + (q.w < me);
+    // canonical order: the rank of each id among the cell's ids
+    const uint4 *s_id4 = reinterpret_cast<const uint4 *>(s_id);
+    for (uint32_t j = lane; j < n; j += 64) {
+      const uint32_t me = s_id[j];
+      uint32_t r = 0;
+      for (uint32_t m = 0; m < n4 / 4; ++m) {
+        const uint4 q = s_id4[m];
+        r += (q.x < me) + (q.y < me) + (q.z < me) + (q.w < me);
+      }
+      s_perm[r] = (uint16_t)j;
+      if (kTrace && tr.perm) tr.perm[tr.offsets[cv.c] + r] = me;
     }
-    s_perm[r] = (uint16_t)j;
-    if (kTrace && tr.perm) tr.perm[cv.base + r] = me;
-  }
-  __syncthreads();
+    __syncthreads();
 
-  // every pair k = 0 .. n(n-1)/2 - 1, lane-strided; pairs whose Philox word
-  // w1 rules out acceptance (u >= w1 2^-32 > P22) are dropped at once, the
-  // rest are compacted (in increasing k) for the exact test.  The main loop
-  // takes two full rows of 64 pairs per iteration with no bounds checks.
-  const uint32_t npairs = n * (n - 1u) / 2u;
-  const uint64_t below = (1ull << lane) - 1ull;
-  const uint32_t lim = pa.w1_max;
-  uint32_t nf = 0, nclaim = 0, claimed_bits = 0, n_acc = 0;
-  uint32_t k0 = 0;
-  if (pa.any) {
-    for (; k0 + 128u <= npairs; k0 += 128u) {
-      const uint32_t ka = k0 + lane, kb = k0 + 64u + lane;
-      const uint32_t wa = philox10_w1(ka, cv.c, t, 0u, pa.key0, pa.key1);
-      const uint32_t wb = philox10_w1(kb, cv.c, t, 0u, pa.key0, pa.key1);
-      const bool pass_a = wa <= lim, pass_b = wb <= lim;
-      const uint64_t ma = __ballot(pass_a), mb = __ballot(pass_b);
-      if ((ma | mb) != 0) {
-        if (pass_a) s_filt[nf + (uint32_t)__popcll(ma & below)] = ka;
-        nf += (uint32_t)__popcll(ma);
-        if (pass_b) s_filt[nf + (uint32_t)__popcll(mb & below)] = kb;
-        nf += (uint32_t)__popcll(mb);
-        if (nf > kFiltCap - 128u) {
-          resolve_filtered<kTrace>(nf, cv, pa, st, s_perm, s_filt, s_claim, nclaim,
-                                   claimed_bits, n_acc, tr, status);
-          nf = 0;
+    // every pair k = 0 .. n(n-1)/2 - 1, lane-strided; pairs whose Philox
+    // word w1 rules out acceptance (u >= w1 2^-32 > P22) are dropped at
+    // once, the rest are compacted (in increasing k) for the exact test.
+    // The main loop takes two full rows of 64 pairs per iteration.
+    const uint32_t npairs = n * (n - 1u) / 2u;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const uint32_t lim = pa.w1_max;
+    uint32_t nf = 0, claimed_bits = 0, n_acc = 0;
+    uint32_t k0 = 0;
+    if (pa.any) {
+      for (; k0 + 128u <= npairs; k0 += 128u) {
+        const uint32_t ka = k0 + lane, kb = k0 + 64u + lane;
+        const uint32_t wa = philox10_w1(ka, cv.c, t, 0u, pa.key0, pa.key1);
+        const uint32_t wb = philox10_w1(kb, cv.c, t, 0u, pa.key0, pa.key1);
+        const bool pass_a = wa <= lim, pass_b = wb <= lim;
+        const uint64_t ma = __ballot(pass_a), mb = __ballot(pass_b);
+        if ((ma | mb) != 0) {
+          if (pass_a) s_filt[nf + (uint32_t)__popcll(ma & below)] = ka;
+          nf += (uint32_t)__popcll(ma);
+          if (pass_b) s_filt[nf + (uint32_t)__popcll(mb & below)] = kb;
+          nf += (uint32_t)__popcll(mb);
+          if (nf > kFiltCap - 128u) {
+            resolve_filtered<kTrace>(nf, cv, pa, st, s_perm, s_filt, s_claim, nclaim,
+                                     claimed_bits, n_acc, tr, status);
+            nf = 0;
+          }
+        }
+      }
+      for (; k0 < npairs; k0 += 64u) {
+        const uint32_t k = k0 + lane;
+        bool pass = false;
+        if (k < npairs) pass = philox10_w1(k, cv.c, t, 0u, pa.key0, pa.key1) <= lim;
+        const uint64_t m = __ballot(pass);
+        if (m != 0) {
+          if (pass) s_filt[nf + (uint32_t)__popcll(m & below)] = k;
+          nf += (uint32_t)__popcll(m);
+          if (nf > kFiltCap - 64u) {
+            resolve_filtered<kTrace>(nf, cv, pa, st, s_perm, s_filt, s_claim, nclaim,
+                                     claimed_bits, n_acc, tr, status);
+            nf = 0;
+          }
         }
       }
     }
-    for (; k0 < npairs; k0 += 64u) {
-      const uint32_t k = k0 + lane;
-      bool pass = false;
-      if (k < npairs) pass = philox10_w1(k, cv.c, t, 0u, pa.key0, pa.key1) <= lim;
-      const uint64_t m = __ballot(pass);
-      if (m != 0) {
-        if (pass) s_filt[nf + (uint32_t)__popcll(m & below)] = k;
-        nf += (uint32_t)__popcll(m);
-        if (nf > kFiltCap - 64u) {
-          resolve_filtered<kTrace>(nf, cv, pa, st, s_perm, s_filt, s_claim, nclaim,
-                                   claimed_bits, n_acc, tr, status);
-          nf = 0;
-        }
-      }
-    }
-  }
-  if (nf != 0)
-    resolve_filtered<kTrace>(nf, cv, pa, st, s_perm, s_filt, s_claim, nclaim,
-                             claimed_bits, n_acc, tr, status);
-  __syncthreads();
+    if (nf != 0)
+      resolve_filtered<kTrace>(nf, cv, pa, st, s_perm, s_filt, s_claim, nclaim,
+                               claimed_bits, n_acc, tr, status);
+    __syncthreads();
 
-  // work counters: candidates are summed over the lanes that tested them
+    // work counters (spread over slots by cell against contention)
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) n_acc += __shfl_down(n_acc, o);
-  if (lane == 0) {
-    const uint32_t slot = cv.c % kCounterSlots;
-    atomicAdd(&status->pairs[slot], (unsigned long long)npairs);
-    atomicAdd(&status->cand[slot], (unsigned long long)n_acc);
-    atomicAdd(&status->claims[slot], (unsigned long long)nclaim);
-  }
+    for (int o = 32; o > 0; o >>= 1) n_acc += __shfl_down(n_acc, o);
+    if (lane == 0) {
+      const uint32_t slot = cv.c % kCounterSlots;
+      atomicAdd(&status->pairs[slot], (unsigned long long)npairs);
+      atomicAdd(&status->cand[slot], (unsigned long long)n_acc);
+      atomicAdd(&status->claims[slot], (unsigned long long)nclaim);
+    }
 
-  // kinematics of the claimed pairs (disjoint: one writer per particle)
-  for (uint32_t i = lane; i < nclaim; i += 64) {
-    const uint32_t v = s_claim[i];
-    const uint32_t a = (v >> 10) & 1023u, b = v & 1023u;
-    const uint32_t k = row_start(a, n) + (b - a - 1u);
-    const Words4 w = philox10(k, cv.c, t, 1u, pa.key0, pa.key1);
-    const double uc = uniform53(w.w0, w.w1);
-    const double uphi = uniform53(w.w2, w.w3);
-    const uint32_t ia = cv.base + s_perm[a], ib = cv.base + s_perm[b];
-    double ax = st.px[ia], ay = st.py[ia], az = st.pz[ia];
-    double bx = st.px[ib], by = st.py[ib], bz = st.pz[ib];
-    scatter_pair(ax, ay, az, bx, by, bz, uc, uphi);
-    st.px[ia] = ax;
-    st.py[ia] = ay;
-    st.pz[ia] = az;
-    st.px[ib] = bx;
-    st.py[ib] = by;
-    st.pz[ib] = bz;
-    if (kTrace && tr.claim) {
-      const uint32_t slot = atomicAdd(&tr.counts[1], 1u);
-      if (slot < tr.claim_cap) {
-        tr.claim[3 * (size_t)slot + 0] = cv.c;
-        tr.claim[3 * (size_t)slot + 1] = a;
-        tr.claim[3 * (size_t)slot + 2] = b;
-      } else {
-        atomicOr(&status->err, kErrTrace);
+    // kinematics of the claimed pairs (disjoint: one writer per particle).
+    // Fused: the lane that scattered a pair also streams and bins it.
+    for (uint32_t i0 = 0; i0 < nclaim; i0 += 64) {
+      const uint32_t i = i0 + lane;
+      const bool active = i < nclaim;
+      double ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0;
+      uint32_t ja = 0, jb = 0;
+      if (active) {
+        const uint32_t v = s_claim[i];
+        const uint32_t a = (v >> 10) & 1023u, b = v & 1023u;
+        const uint32_t k = row_start(a, n) + (b - a - 1u);
+        const Words4 w = philox10(k, cv.c, t, 1u, pa.key0, pa.key1);
+        const double uc = uniform53(w.w0, w.w1);
+        const double uphi = uniform53(w.w2, w.w3);
+        ja = s_perm[a];
+        jb = s_perm[b];
+        const size_t ia = cv.base + ja, ib = cv.base + jb;
+        ax = st.px[ia];
+        ay = st.py[ia];
+        az = st.pz[ia];
+        bx = st.px[ib];
+        by = st.py[ib];
+        bz = st.pz[ib];
+        scatter_pair(ax, ay, az, bx, by, bz, uc, uphi);
+        if (!kFused) {
+          st.px[ia] = ax;
+          st.py[ia] = ay;
+          st.pz[ia] = az;
+          st.px[ib] = bx;
+          st.py[ib] = by;
+          st.pz[ib] = bz;
+        }
+        if (kTrace && tr.claim) {
+          const uint32_t slot = atomicAdd(&tr.counts[1], 1u);
+          if (slot < tr.claim_cap) {
+            tr.claim[3 * (size_t)slot + 0] = cv.c;
+            tr.claim[3 * (size_t)slot + 1] = a;
+            tr.claim[3 * (size_t)slot + 2] = b;
+          } else {
+            atomicOr(&status->err, kErrTrace);
+          }
+        }
+      }
+      if (kFused) {
+        double x = 0, y = 0, z = 0;
+        uint32_t id = 0, c2 = 0;
+        if (active) {
+          const size_t ia = cv.base + ja;
+          x = st.x[ia];
+          y = st.y[ia];
+          z = st.z[ia];
+          id = st.id[ia];
+          s_mark[ja] = 1;
+          advance<true>(g, x, y, z, ax, ay, az);
+          c2 = cell_id(g, x, y, z);
+        }
+        append(dst, c2, active, x, y, z, ax, ay, az, id, status);
+        if (active) {
+          const size_t ib = cv.base + jb;
+          x = st.x[ib];
+          y = st.y[ib];
+          z = st.z[ib];
+          id = st.id[ib];
+          s_mark[jb] = 1;
+          advance<true>(g, x, y, z, bx, by, bz);
+          c2 = cell_id(g, x, y, z);
+        }
+        append(dst, c2, active, x, y, z, bx, by, bz, id, status);
       }
     }
+    if (kFused) __syncthreads();
+  } else if (kTrace && n == 1 && lane == 0 && tr.perm) {
+    tr.perm[tr.offsets[cv.c]] = st.id[cv.base];
+  }
+
+  if (kFused) {
+    // stream and bin the particles that did not scatter
+    for (uint32_t j0 = 0; j0 < n; j0 += 64) {
+      const uint32_t j = j0 + lane;
+      const bool active = j < n && (n < 2 || nclaim == 0 || s_mark[j] == 0);
+      double x = 0, y = 0, z = 0, px = 0, py = 0, pz = 0;
+      uint32_t id = 0, c2 = 0;
+      if (active) {
+        const size_t o = cv.base + j;
+        x = st.x[o];
+        y = st.y[o];
+        z = st.z[o];
+        px = st.px[o];
+        py = st.py[o];
+        pz = st.pz[o];
+        id = st.id[o];
+        advance<true>(g, x, y, z, px, py, pz);
+        c2 = cell_id(g, x, y, z);
+      }
+      append(dst, c2, active, x, y, z, px, py, pz, id, status);
+    }
+    if (lane == 0) src.count[cv.c] = 0u;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Observe: per-slab sums of E and p_x.  Slab ix is the contiguous cell range
-// [ix ny nz, (ix+1) ny nz), hence a contiguous particle range.
+// Observe: per-cell sums of E and p_x (one wave per cell), then per-slab
+// sums over the slab's cells in cell order.  Slab ix is the contiguous cell
+// range [ix ny nz, (ix+1) ny nz).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_observe_partial(
-    const uint32_t *__restrict__ offsets, SoA st, uint32_t cells_per_slab,
-    double *partial) {
-  __shared__ double s_e[kBlock / 64], s_p[kBlock / 64];
-  const uint32_t ix = blockIdx.x / kObsChunks, chunk = blockIdx.x % kObsChunks;
-  const uint64_t lo = offsets[(uint64_t)ix * cells_per_slab];
-  const uint64_t hi = offsets[(uint64_t)(ix + 1) * cells_per_slab];
-  const uint64_t len = hi - lo;
-  const uint64_t b0 = lo + len * chunk / kObsChunks;
-  const uint64_t b1 = lo + len * (chunk + 1) / kObsChunks;
+__global__ __launch_bounds__(kBlock) void k_observe_cells(Cells cur, uint32_t n_cells,
+                                                          double *cell_sums) {
+  const uint32_t lane = lane_id();
+  const uint32_t c = blockIdx.x * kCellsPerBlock + threadIdx.x / 64;
+  if (c >= n_cells) return;
+  const uint32_t n = occupancy(cur, c);
+  const size_t base = (size_t)c * cur.cap;
   double se = 0.0, sp = 0.0;
-  for (uint64_t i = b0 + threadIdx.x; i < b1; i += kBlock) {
-    const double px = st.px[i], py = st.py[i], pz = st.pz[i];
+  for (uint32_t j = lane; j < n; j += 64) {
+    const double px = cur.st.px[base + j], py = cur.st.py[base + j],
+                 pz = cur.st.pz[base + j];
     se += norm3(px, py, pz);
     sp += px;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    se += __shfl_down(se, o);
+    sp += __shfl_down(sp, o);
+  }
+  if (lane == 0) {
+    cell_sums[2 * (size_t)c + 0] = se;
+    cell_sums[2 * (size_t)c + 1] = sp;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_observe_slabs(const double *cell_sums,
+                                                          uint32_t cells_per_slab,
+                                                          double vol, double *T00,
+                                                          double *T0x) {
+  __shared__ double s_e[kBlock / 64], s_p[kBlock / 64];
+  const uint32_t ix = blockIdx.x;
+  const size_t c0 = (size_t)ix * cells_per_slab;
+  double se = 0.0, sp = 0.0;
+  for (uint32_t j = threadIdx.x; j < cells_per_slab; j += kBlock) {
+    se += cell_sums[2 * (c0 + j) + 0];
+    sp += cell_sums[2 * (c0 + j) + 1];
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -469,41 +565,35 @@ __global__ __launch_bounds__(kBlock) void k_observe_partial(
       te += s_e[w];
       tp += s_p[w];
     }
-    partial[2 * (size_t)blockIdx.x + 0] = te;
-    partial[2 * (size_t)blockIdx.x + 1] = tp;
+    T00[ix] = te / vol;
+    T0x[ix] = tp / vol;
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_observe_final(const double *partial,
-                                                          int32_t nx, double vol,
-                                                          double *T00, double *T0x) {
-  const int32_t ix = blockIdx.x * kBlock + threadIdx.x;
-  if (ix >= nx) return;
-  double te = 0.0, tp = 0.0;
-  for (uint32_t ch = 0; ch < kObsChunks; ++ch) {
-    te += partial[2 * ((size_t)ix * kObsChunks + ch) + 0];
-    tp += partial[2 * ((size_t)ix * kObsChunks + ch) + 1];
-  }
-  T00[ix] = te / vol;
-  T0x[ix] = tp / vol;
-}
-
-__global__ __launch_bounds__(kBlock) void k_gather_by_id(SoA st, int64_t n, double *x,
-                                                         double *y, double *z,
+__global__ __launch_bounds__(kBlock) void k_gather_by_id(Cells cur, uint32_t n_cells,
+                                                         double *x, double *y, double *z,
                                                          double *px, double *py,
                                                          double *pz) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t id = st.id[i];
-  x[id] = st.x[i];
-  y[id] = st.y[i];
-  z[id] = st.z[i];
-  px[id] = st.px[i];
-  py[id] = st.py[i];
-  pz[id] = st.pz[i];
+  const uint32_t lane = lane_id();
+  const uint32_t c = blockIdx.x * kCellsPerBlock + threadIdx.x / 64;
+  if (c >= n_cells) return;
+  const uint32_t n = occupancy(cur, c);
+  const size_t base = (size_t)c * cur.cap;
+  for (uint32_t j = lane; j < n; j += 64) {
+    const uint32_t id = cur.st.id[base + j];
+    x[id] = cur.st.x[base + j];
+    y[id] = cur.st.y[base + j];
+    z[id] = cur.st.z[base + j];
+    px[id] = cur.st.px[base + j];
+    py[id] = cur.st.py[base + j];
+    pz[id] = cur.st.pz[base + j];
+  }
 }
 
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+inline unsigned cell_blocks(int64_t n_cells) {
+  return (unsigned)((n_cells + kCellsPerBlock - 1) / kCellsPerBlock);
+}
 
 }  // namespace
 
@@ -515,74 +605,63 @@ void launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(count)), dim3(kBlock), 0, s, p, v, count);
 }
 
-void launch_load(const double *x, const double *y, const double *z,
-                 const double *px, const double *py, const double *pz, SoA dst,
-                 int64_t n, const Geometry &g, DevStatus *st, hipStream_t s) {
+void launch_init_bin(const double *x, const double *y, const double *z,
+                     const double *px, const double *py, const double *pz,
+                     const Cells &dst, int64_t n, const Geometry &g, DevStatus *st,
+                     hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_load, dim3(grid_for(n)), dim3(kBlock), 0, s, x, y, z, px, py,
+  hipLaunchKernelGGL(k_init_bin, dim3(grid_for(n)), dim3(kBlock), 0, s, x, y, z, px, py,
                      pz, dst, n, g, st);
 }
 
-void launch_count(const SoA &src, int64_t n, const Geometry &g, bool stream,
-                  uint32_t *counts, hipStream_t s) {
-  if (n <= 0) return;
-  if (stream)
-    hipLaunchKernelGGL(k_count<true>, dim3(grid_for(n)), dim3(kBlock), 0, s, src, n, g,
-                       counts);
-  else
-    hipLaunchKernelGGL(k_count<false>, dim3(grid_for(n)), dim3(kBlock), 0, s, src, n,
-                       g, counts);
+void launch_stream_bin(const Cells &src, const Cells &dst, int64_t n_cells,
+                       const Geometry &g, DevStatus *status, uint32_t *trace_cell,
+                       hipStream_t s) {
+  if (n_cells <= 0) return;
+  hipLaunchKernelGGL(k_stream_bin, dim3(cell_blocks(n_cells)), dim3(kBlock), 0, s, src,
+                     dst, (uint32_t)n_cells, g, status, trace_cell);
 }
 
-void launch_scan(uint32_t *counts, uint32_t *offsets, uint32_t *cursor,
-                 uint32_t *tile_sums, int64_t n_cells, hipStream_t s) {
+void launch_offsets(const Cells &cur, uint32_t *offsets, uint32_t *tile_sums,
+                    int64_t n_cells, hipStream_t s) {
   const unsigned tiles = (unsigned)((n_cells + kScanTile - 1) / kScanTile);
-  hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kBlock), 0, s, counts, offsets,
+  hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kBlock), 0, s, cur, offsets,
                      tile_sums, n_cells);
-  hipLaunchKernelGGL(k_scan_carry, dim3(tiles), dim3(kBlock), 0, s, offsets, cursor,
+  hipLaunchKernelGGL(k_scan_carry, dim3(tiles), dim3(kBlock), 0, s, offsets,
                      (const uint32_t *)tile_sums, n_cells);
 }
 
-void launch_scatter(const SoA &src, SoA dst, int64_t n, const Geometry &g,
-                    bool stream, uint32_t *cursor, uint32_t *trace_cell,
-                    hipStream_t s) {
-  if (n <= 0) return;
-  if (stream)
-    hipLaunchKernelGGL(k_scatter<true>, dim3(grid_for(n)), dim3(kBlock), 0, s, src, dst,
-                       n, g, cursor, trace_cell);
-  else
-    hipLaunchKernelGGL(k_scatter<false>, dim3(grid_for(n)), dim3(kBlock), 0, s, src,
-                       dst, n, g, cursor, trace_cell);
-}
-
-void launch_collide(const uint32_t *offsets, SoA st, int64_t n_cells, uint32_t t,
-                    const PairArgs &pa, DevStatus *status, const TraceArgs *trace,
-                    hipStream_t s) {
+void launch_step(const Cells &src, const Cells &dst, bool fused, int64_t n_cells,
+                 uint32_t t, const PairArgs &pa, const Geometry &g, DevStatus *status,
+                 const TraceArgs *trace, hipStream_t s) {
   if (n_cells <= 0) return;
+  const dim3 grid((unsigned)n_cells), block(64);
   if (trace)
-    hipLaunchKernelGGL(k_collide<true>, dim3((unsigned)n_cells), dim3(64), 0, s, offsets,
-                       st, t, pa, status, *trace);
+    hipLaunchKernelGGL((k_step<false, true>), grid, block, 0, s, src, dst, t, pa, g,
+                       status, *trace);
+  else if (fused)
+    hipLaunchKernelGGL((k_step<true, false>), grid, block, 0, s, src, dst, t, pa, g,
+                       status, TraceArgs{});
   else
-    hipLaunchKernelGGL(k_collide<false>, dim3((unsigned)n_cells), dim3(64), 0, s,
-                       offsets, st, t, pa, status, TraceArgs{});
+    hipLaunchKernelGGL((k_step<false, false>), grid, block, 0, s, src, dst, t, pa, g,
+                       status, TraceArgs{});
 }
 
-void launch_observe(const uint32_t *offsets, const SoA &st, const Geometry &g,
-                    double vol, double *partial, double *T00, double *T0x,
-                    hipStream_t s) {
-  const uint32_t nx = (uint32_t)g.n[0];
-  const uint32_t cps = (uint32_t)g.n[1] * (uint32_t)g.n[2];
-  hipLaunchKernelGGL(k_observe_partial, dim3(nx * kObsChunks), dim3(kBlock), 0, s,
-                     offsets, st, cps, partial);
-  hipLaunchKernelGGL(k_observe_final, dim3(grid_for(nx)), dim3(kBlock), 0, s,
-                     (const double *)partial, (int32_t)nx, vol, T00, T0x);
+void launch_observe(const Cells &cur, const Geometry &g, double vol, double *cell_sums,
+                    double *T00, double *T0x, hipStream_t s) {
+  const int64_t n_cells = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  hipLaunchKernelGGL(k_observe_cells, dim3(cell_blocks(n_cells)), dim3(kBlock), 0, s, cur,
+                     (uint32_t)n_cells, cell_sums);
+  hipLaunchKernelGGL(k_observe_slabs, dim3((unsigned)g.n[0]), dim3(kBlock), 0, s,
+                     (const double *)cell_sums, (uint32_t)(g.n[1] * g.n[2]), vol, T00,
+                     T0x);
 }
 
-void launch_gather_by_id(const SoA &st, int64_t n, double *x, double *y, double *z,
-                         double *px, double *py, double *pz, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_gather_by_id, dim3(grid_for(n)), dim3(kBlock), 0, s, st, n, x, y,
-                     z, px, py, pz);
+void launch_gather_by_id(const Cells &cur, int64_t n_cells, double *x, double *y,
+                         double *z, double *px, double *py, double *pz, hipStream_t s) {
+  if (n_cells <= 0) return;
+  hipLaunchKernelGGL(k_gather_by_id, dim3(cell_blocks(n_cells)), dim3(kBlock), 0, s, cur,
+                     (uint32_t)n_cells, x, y, z, px, py, pz);
 }
 
 }  // namespace cuba

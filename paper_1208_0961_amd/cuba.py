@@ -35,7 +35,8 @@ class cuba_params(ctypes.Structure):
                 ("r_test", ctypes.c_double),
                 ("dt", ctypes.c_double),
                 ("seed", ctypes.c_uint64),
-                ("step0", ctypes.c_uint32)]
+                ("step0", ctypes.c_uint32),
+                ("cell_capacity", ctypes.c_int32)]
 
 
 class cuba_trace(ctypes.Structure):
@@ -101,7 +102,8 @@ def _check(rc: int, where: str) -> None:
         raise CubaError(rc, where, cuba_last_error())
 
 
-def make_params(box, cells, sigma, r_test, dt, seed, step0=0) -> cuba_params:
+def make_params(box, cells, sigma, r_test, dt, seed, step0=0,
+                cell_capacity=0) -> cuba_params:
     p = cuba_params()
     for d in range(3):
         p.box[d] = float(box[d])
@@ -109,6 +111,7 @@ def make_params(box, cells, sigma, r_test, dt, seed, step0=0) -> cuba_params:
     p.sigma, p.r_test, p.dt = float(sigma), float(r_test), float(dt)
     p.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
     p.step0 = int(step0) & 0xFFFFFFFF
+    p.cell_capacity = int(cell_capacity)
     return p
 
 
@@ -163,7 +166,7 @@ def cuba_info(ctx: int):
 
 
 CUBA_NUM_STAGES = 5
-STAGES = ("count", "scan", "scatter", "collide", "observe")
+STAGES = ("bin", "step", "collide", "observe", "offsets")
 
 
 def cuba_counters(ctx: int):

@@ -16,17 +16,40 @@ def _dev(a, device):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device)
 
 
+def suggest_cell_capacity(params: dict, state, headroom: float = 2.0, margin: int = 32) -> int:
+    """Slots per cell for the workspace: headroom x the largest initial cell
+    occupancy plus a margin, rounded up to 32, within [64, 1024].  (Sizing
+    only; the library reports any overflow at the next sync.)"""
+    if len(state[0]) == 0:
+        return 64
+    box = np.asarray(params["box"], np.float64)
+    cells = np.asarray(params["cells"], np.int64)
+    r = [np.asarray(state[d], np.float64) for d in range(3)]
+    ok = np.isfinite(r[0]) & np.isfinite(r[1]) & np.isfinite(r[2])
+    if not ok.any():
+        return 64
+    idx = [np.clip(np.floor(r[d][ok] / (box[d] / cells[d])), 0, cells[d] - 1)
+           .astype(np.int64) for d in range(3)]
+    flat = (idx[0] * cells[1] + idx[1]) * cells[2] + idx[2]
+    occ = int(np.bincount(flat).max())
+    cap = int(np.ceil((headroom * occ + margin) / 32.0)) * 32
+    return max(64, min(C.CUBA_MAX_CELL_OCCUPANCY, cap))
+
+
 class Sim:
     """A box of test particles advanced by libcuba.so.
 
     params: dict with box, cells, sigma, r_test, dt, seed and optionally
-    step0.  state: six arrays (x, y, z, px, py, pz) indexed by particle id.
+    step0 and cell_capacity (default: suggest_cell_capacity of the initial
+    state).  state: six arrays (x, y, z, px, py, pz) indexed by particle id.
     """
 
     def __init__(self, params: dict, state, device: str | torch.device = "cuda",
                  stream: torch.cuda.Stream | None = None):
         self.device = torch.device(device)
         self.params = dict(params)
+        if not self.params.get("cell_capacity"):
+            self.params["cell_capacity"] = suggest_cell_capacity(self.params, state)
         self.p = C.make_params(**self.params)
         self.n = int(len(state[0]))
         self.nx = int(self.params["cells"][0])

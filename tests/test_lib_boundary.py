@@ -52,12 +52,19 @@ def test_code_object_targets_gfx950(C, tmp_path):
 
 
 def test_workspace_bytes_and_parameter_checks(C):
-    p = C.make_params((10, 2, 2), (100, 10, 10), 0.4, 2500, 0.02, 1)
+    p = C.make_params((10, 2, 2), (100, 10, 10), 0.4, 2500, 0.02, 1, cell_capacity=256)
     n = 1020851
     ws = C.cuba_workspace_bytes(p, n)
-    # two SoA buffers of 52 B per particle plus per-cell arrays, 256 B aligned
-    assert 104 * n <= ws <= 104 * n + 16 * 10000 + 64 * 1024
-    assert C.cuba_workspace_bytes(p, 2 * n) > ws
+    # two buffers of cells x capacity slots of 52 B plus per-cell arrays
+    slots = 10000 * 256
+    assert 104 * slots <= ws <= 104 * slots + 32 * 10000 + 64 * 1024
+    p2 = C.make_params((10, 2, 2), (100, 10, 10), 0.4, 2500, 0.02, 1, cell_capacity=512)
+    assert C.cuba_workspace_bytes(p2, n) > ws
+    p0 = C.make_params((10, 2, 2), (100, 10, 10), 0.4, 2500, 0.02, 1)   # default 512
+    assert C.cuba_workspace_bytes(p0, n) == C.cuba_workspace_bytes(p2, n)
+    for cap in (-1, 1025):
+        bad = C.make_params((10, 2, 2), (100, 10, 10), 0.4, 2500, 0.02, 1, cell_capacity=cap)
+        assert C.cuba_workspace_bytes(bad, n) == 0
     bad = [
         C.make_params((10, 2, 2), (100, 10, 10), 0.4, 2500, 0.1, 1),     # dt >= dx
         C.make_params((10, 2, 2), (100, 10, 10), -0.4, 2500, 0.02, 1),   # sigma < 0
