@@ -192,6 +192,69 @@ void cuba_destroy(cuba_ctx *ctx);
 const char *cuba_strerror(int code);
 const char *cuba_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent events (each a cuba_ctx with its own
+ * parameters, seed, step index and workspace) advanced together, one
+ * kernel launch per step for all of them.  Work items are runs of
+ * `cells per item` consecutive cells of one event; each event's result is
+ * bit-identical to running it alone with cuba_step (same per-cell code,
+ * same keys and step indices).  All device work runs on the batch's
+ * stream; the events' own calls (cuba_observe, cuba_get_state,
+ * cuba_counters, cuba_info) may be used through cuba_batch_slot.
+ * ------------------------------------------------------------------------ */
+typedef struct cuba_batch cuba_batch;
+
+/* Device bytes of the batch's event table for max_slots slots. */
+size_t cuba_batch_workspace_bytes(int32_t max_slots);
+
+/* Creates a batch.  workspace: device memory of ws_bytes >=
+ * cuba_batch_workspace_bytes(max_slots), 256-byte aligned, owned by the
+ * caller.  stream: hipStream_t (must not be NULL if graphs are enabled). */
+int cuba_batch_create(cuba_batch **out, int32_t max_slots, void *workspace,
+                      size_t ws_bytes, void *stream);
+
+/* Admits an event into a free slot: as cuba_init (same arguments, same
+ * validation and errors; synchronizes the batch stream), on the batch's
+ * stream.  The event joins the next cuba_batch_step. */
+int cuba_batch_admit(cuba_batch *b, int32_t slot, const cuba_params *params,
+                     int64_t n, const double *x, const double *y,
+                     const double *z, const double *px, const double *py,
+                     const double *pz, void *workspace, size_t ws_bytes);
+
+/* Frees a slot (synchronizes the stream); the event's workspace may then
+ * be reused by the caller. */
+int cuba_batch_retire(cuba_batch *b, int32_t slot);
+
+/* The context of an occupied slot, or NULL.  Owned by the batch. */
+cuba_ctx *cuba_batch_slot(cuba_batch *b, int32_t slot);
+
+/* Cells per work item of a slot's event (default: about 64 particles per
+ * item, at most 64 cells); set by the autotuner. */
+int cuba_batch_set_cells_per_item(cuba_batch *b, int32_t slot, int32_t cells);
+
+/* Launch shape: persistent_waves > 0 runs the step kernels on that many
+ * persistent waves taking work items with a grid stride (0: one workgroup
+ * per item); use_graphs != 0 captures each run of n steps as a hipGraph
+ * (cached per n, rebuilt after admissions and retirements). */
+int cuba_batch_set_launch(cuba_batch *b, int32_t persistent_waves,
+                          int32_t use_graphs);
+
+/* Advances every live event by nsteps steps (asynchronous). */
+int cuba_batch_step(cuba_batch *b, int32_t nsteps);
+
+/* Waits for the stream and reports the first event's device error (its
+ * slot in *bad_slot, else -1). */
+int cuba_batch_sync(cuba_batch *b, int32_t *bad_slot);
+
+/* Stage timing of the following non-graph runs, as cuba_timing_begin/end
+ * (stages 0 bin, 1 step, 2 collide). */
+int cuba_batch_timing_begin(cuba_batch *b, int32_t max_launches);
+int cuba_batch_timing_end(cuba_batch *b, double stage_ms[CUBA_NUM_STAGES],
+                          int64_t stage_launches[CUBA_NUM_STAGES]);
+
+/* Destroys the batch and its events' contexts (not the workspaces). */
+void cuba_batch_destroy(cuba_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

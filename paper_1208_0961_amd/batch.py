@@ -1,0 +1,130 @@
+"""Batch: many independent events advanced together by libcuba.so, with
+PyTorch supplying device memory (each event's workspace and the event
+table) and the stream.  Every step runs inside the library; this class only
+allocates, marshals and keeps the per-slot bookkeeping.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import cuba as C
+from .sim import _dev, suggest_cell_capacity
+
+
+def event_workspace_bytes(params: dict, n: int) -> int:
+    """Device bytes one event needs (the admission footprint)."""
+    nbytes = C.cuba_workspace_bytes(C.make_params(**params), n)
+    if nbytes == 0:
+        raise C.CubaError(C.CUBA_EINVAL, "cuba_workspace_bytes", C.cuba_last_error())
+    return nbytes
+
+
+def with_capacity(params: dict, state) -> dict:
+    """params with a cell_capacity chosen from the initial state if unset."""
+    q = dict(params)
+    if not q.get("cell_capacity"):
+        q["cell_capacity"] = suggest_cell_capacity(q, state)
+    return q
+
+
+class Batch:
+    def __init__(self, max_slots: int, device: str | torch.device = "cuda",
+                 stream: torch.cuda.Stream | None = None, persistent_waves: int = 0,
+                 use_graphs: bool = False):
+        self.device = torch.device(device)
+        # a dedicated stream (graph capture needs one that is not the null stream)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self.max_slots = int(max_slots)
+        nbytes = C.cuba_batch_workspace_bytes(self.max_slots)
+        with torch.cuda.stream(self.stream):
+            self.table = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.b = C.cuba_batch_create(self.max_slots, self.table.data_ptr(), nbytes,
+                                     self.stream.cuda_stream)
+        self.slots: dict[int, dict] = {}
+        self.set_launch(persistent_waves, use_graphs)
+
+    # -- admission ------------------------------------------------------------
+    def free_slot(self) -> int | None:
+        for s in range(self.max_slots):
+            if s not in self.slots:
+                return s
+        return None
+
+    def admit(self, slot: int, params: dict, state, workspace: torch.Tensor | None = None):
+        """Admits an event (params as for Sim; state: six id-ordered arrays)."""
+        params = with_capacity(params, state)
+        n = int(len(state[0]))
+        p = C.make_params(**params)
+        nbytes = C.cuba_workspace_bytes(p, n)
+        if nbytes == 0:
+            raise C.CubaError(C.CUBA_EINVAL, "cuba_workspace_bytes", C.cuba_last_error())
+        with torch.cuda.stream(self.stream):
+            if workspace is None:
+                workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            arrs = [_dev(a, self.device) for a in state]
+            nx = int(params["cells"][0])
+            T00 = torch.empty(nx, dtype=torch.float64, device=self.device)
+            T0x = torch.empty(nx, dtype=torch.float64, device=self.device)
+        C.cuba_batch_admit(self.b, slot, p, n, *[a.data_ptr() for a in arrs],
+                           workspace.data_ptr(), nbytes)
+        self.slots[slot] = {"params": params, "n": n, "workspace": workspace,
+                            "T00": T00, "T0x": T0x}
+
+    def retire(self, slot: int) -> torch.Tensor:
+        """Frees the slot; returns the event's workspace for reuse."""
+        C.cuba_batch_retire(self.b, slot)
+        return self.slots.pop(slot)["workspace"]
+
+    def ctx(self, slot: int):
+        return C.cuba_batch_slot(self.b, slot)
+
+    # -- stepping -------------------------------------------------------------
+    def set_cells_per_item(self, slot: int, cells: int) -> None:
+        C.cuba_batch_set_cells_per_item(self.b, slot, cells)
+
+    def set_launch(self, persistent_waves: int = 0, use_graphs: bool = False) -> None:
+        C.cuba_batch_set_launch(self.b, persistent_waves, use_graphs)
+
+    def step(self, nsteps: int) -> None:
+        C.cuba_batch_step(self.b, nsteps)
+
+    def sync(self) -> None:
+        C.cuba_batch_sync(self.b)
+
+    # -- outputs --------------------------------------------------------------
+    def observe_async(self, slot: int):
+        s = self.slots[slot]
+        C.cuba_observe(self.ctx(slot), s["T00"].data_ptr(), s["T0x"].data_ptr())
+        return s["T00"], s["T0x"]
+
+    def observe(self, slot: int):
+        T00, T0x = self.observe_async(slot)
+        self.sync()
+        return T00.cpu().numpy().copy(), T0x.cpu().numpy().copy()
+
+    def get_state(self, slot: int):
+        n = self.slots[slot]["n"]
+        with torch.cuda.stream(self.stream):
+            out = [torch.empty(n, dtype=torch.float64, device=self.device) for _ in range(6)]
+        C.cuba_get_state(self.ctx(slot), *[o.data_ptr() for o in out])
+        self.sync()
+        return [o.cpu().numpy() for o in out]
+
+    def next_step(self, slot: int) -> int:
+        return C.cuba_info(self.ctx(slot))[0]
+
+    def counters(self, slot: int):
+        return C.cuba_counters(self.ctx(slot))
+
+    def close(self) -> None:
+        if getattr(self, "b", None):
+            C.cuba_batch_destroy(self.b)
+            self.b = None
+            self.slots.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -456,5 +457,303 @@ const char *cuba_strerror(int code) {
 }
 
 const char *cuba_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches of independent events
+// ---------------------------------------------------------------------------
+struct cuba_batch {
+  int32_t max_slots = 0;
+  hipStream_t stream = nullptr;
+  BatchEvent *dev_table = nullptr;  // in the caller's batch workspace
+  std::vector<cuba_ctx *> slot_ctx;
+  std::vector<int32_t> slot_cpi;
+  std::vector<int32_t> table_slots;  // slots in table order
+  uint32_t n_items = 0;
+  bool dirty = true;
+  uint32_t persistent_waves = 0;
+  bool use_graphs = false;
+  std::map<int32_t, hipGraphExec_t> graphs;
+  // stage timing of direct (non-graph) runs
+  bool timing = false;
+  size_t timing_cap = 0;
+  std::vector<hipEvent_t> event_pool;
+  std::vector<TimedLaunch> timed;
+  int pending_stage = -1;
+};
+
+namespace {
+
+void drop_graphs(cuba_batch *b) {
+  for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  b->graphs.clear();
+}
+
+void drop_batch_timing(cuba_batch *b) {
+  for (hipEvent_t e : b->event_pool) (void)hipEventDestroy(e);
+  b->event_pool.clear();
+  b->timed.clear();
+  b->timing = false;
+  b->timing_cap = 0;
+}
+
+// Default cells per work item: enough cells that an item holds about 64
+// particles (a full wave), at most 64 cells.
+int32_t default_cpi(const cuba_ctx *c) {
+  const double mean = c->d.n_cells > 0 ? (double)c->n / (double)c->d.n_cells : 0.0;
+  int32_t cpi = mean > 0.0 ? (int32_t)(64.0 / mean) : 64;
+  if (cpi < 1) cpi = 1;
+  if (cpi > 64) cpi = 64;
+  return cpi;
+}
+
+// Rebuilds the device table from the live slots (in slot order).
+int upload_table(cuba_batch *b) {
+  std::vector<BatchEvent> host;
+  b->table_slots.clear();
+  uint32_t items = 0;
+  for (int32_t s = 0; s < b->max_slots; ++s) {
+    cuba_ctx *c = b->slot_ctx[s];
+    if (!c || c->d.n_cells == 0) continue;
+    BatchEvent e{};
+    e.buf[0] = c->buf[0];
+    e.buf[1] = c->buf[1];
+    e.g = c->d.g;
+    e.pa = c->pa;
+    e.status = c->status;
+    e.n_cells = (uint32_t)c->d.n_cells;
+    e.cpi = (uint32_t)b->slot_cpi[s];
+    e.item_begin = items;
+    e.cur = (uint32_t)c->cur;
+    e.t = c->next_step;
+    const uint64_t ni = (e.n_cells + e.cpi - 1) / e.cpi;
+    if (items + ni >= 0xFFFFFFFFull) return fail(CUBA_EINVAL, "too many work items");
+    items += (uint32_t)ni;
+    host.push_back(e);
+    b->table_slots.push_back(s);
+  }
+  b->n_items = items;
+  if (!host.empty()) {
+    hipError_t e = hipMemcpyAsync(b->dev_table, host.data(), host.size() * sizeof(BatchEvent),
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch table upload");
+  }
+  drop_graphs(b);
+  b->dirty = false;
+  return CUBA_OK;
+}
+
+void batch_between(void *vb, int next) {
+  cuba_batch *b = (cuba_batch *)vb;
+  if (!b->timing) return;
+  // close the launch bracketed by the previous call
+  if (b->pending_stage >= 0) {
+    (void)hipEventRecord(b->timed.back().after, b->stream);
+    b->pending_stage = -1;
+  }
+  if (next < 0 || b->timed.size() >= b->timing_cap) return;
+  const size_t k = b->timed.size();
+  TimedLaunch t{next, b->event_pool[2 * k], b->event_pool[2 * k + 1]};
+  (void)hipEventRecord(t.before, b->stream);
+  b->timed.push_back(t);
+  b->pending_stage = next;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t cuba_batch_workspace_bytes(int32_t max_slots) {
+  if (max_slots < 1) return 0;
+  return align256((size_t)max_slots * sizeof(BatchEvent));
+}
+
+int cuba_batch_create(cuba_batch **out, int32_t max_slots, void *workspace,
+                      size_t ws_bytes, void *stream) {
+  if (!out) return fail(CUBA_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (max_slots < 1) return fail(CUBA_EINVAL, "max_slots must be >= 1");
+  if (!workspace || ((uintptr_t)workspace & 255u) != 0)
+    return fail(CUBA_EINVAL, "batch workspace must be non-NULL and 256-byte aligned");
+  if (ws_bytes < cuba_batch_workspace_bytes(max_slots))
+    return fail(CUBA_ENOMEM, "batch workspace too small");
+  cuba_batch *b = new (std::nothrow) cuba_batch();
+  if (!b) return fail(CUBA_ENOMEM, "host allocation failed");
+  b->max_slots = max_slots;
+  b->stream = (hipStream_t)stream;
+  b->dev_table = (BatchEvent *)workspace;
+  b->slot_ctx.assign(max_slots, nullptr);
+  b->slot_cpi.assign(max_slots, 1);
+  *out = b;
+  return CUBA_OK;
+}
+
+int cuba_batch_admit(cuba_batch *b, int32_t slot, const cuba_params *params, int64_t n,
+                     const double *x, const double *y, const double *z, const double *px,
+                     const double *py, const double *pz, void *workspace,
+                     size_t ws_bytes) {
+  if (!b) return fail(CUBA_EINVAL, "batch is NULL");
+  if (slot < 0 || slot >= b->max_slots) return fail(CUBA_EINVAL, "slot out of range");
+  if (b->slot_ctx[slot]) return fail(CUBA_EINVAL, "slot is occupied");
+  cuba_ctx *c = nullptr;
+  const int rc = cuba_init(&c, params, n, x, y, z, px, py, pz, workspace, ws_bytes,
+                           (void *)b->stream);
+  if (rc != CUBA_OK) return rc;
+  b->slot_ctx[slot] = c;
+  b->slot_cpi[slot] = default_cpi(c);
+  b->dirty = true;
+  return CUBA_OK;
+}
+
+int cuba_batch_retire(cuba_batch *b, int32_t slot) {
+  if (!b) return fail(CUBA_EINVAL, "batch is NULL");
+  if (slot < 0 || slot >= b->max_slots || !b->slot_ctx[slot])
+    return fail(CUBA_EINVAL, "slot is not occupied");
+  const hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return hip_fail(e, "retire sync");
+  cuba_destroy(b->slot_ctx[slot]);
+  b->slot_ctx[slot] = nullptr;
+  b->dirty = true;
+  return CUBA_OK;
+}
+
+cuba_ctx *cuba_batch_slot(cuba_batch *b, int32_t slot) {
+  if (!b || slot < 0 || slot >= b->max_slots) return nullptr;
+  return b->slot_ctx[slot];
+}
+
+int cuba_batch_set_cells_per_item(cuba_batch *b, int32_t slot, int32_t cells) {
+  if (!b || slot < 0 || slot >= b->max_slots || !b->slot_ctx[slot])
+    return fail(CUBA_EINVAL, "slot is not occupied");
+  if (cells < 1 || cells > 4096) return fail(CUBA_EINVAL, "cells per item out of range");
+  b->slot_cpi[slot] = cells;
+  b->dirty = true;
+  return CUBA_OK;
+}
+
+int cuba_batch_set_launch(cuba_batch *b, int32_t persistent_waves, int32_t use_graphs) {
+  if (!b || persistent_waves < 0) return fail(CUBA_EINVAL, "bad launch settings");
+  if (use_graphs && b->stream == nullptr)
+    return fail(CUBA_EINVAL, "graph capture needs a non-null stream");
+  b->persistent_waves = (uint32_t)persistent_waves;
+  b->use_graphs = use_graphs != 0;
+  drop_graphs(b);
+  return CUBA_OK;
+}
+
+int cuba_batch_step(cuba_batch *b, int32_t nsteps) {
+  if (!b) return fail(CUBA_EINVAL, "batch is NULL");
+  if (nsteps < 0) return fail(CUBA_EINVAL, "nsteps must be >= 0");
+  if (nsteps == 0) return CUBA_OK;
+  if (b->dirty) {
+    const int rc = upload_table(b);
+    if (rc != CUBA_OK) return rc;
+  }
+  const uint32_t n_events = (uint32_t)b->table_slots.size();
+  if (n_events > 0) {
+    if (b->use_graphs && !b->timing) {
+      auto it = b->graphs.find(nsteps);
+      if (it == b->graphs.end()) {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "graph capture begin");
+        launch_batch_run(b->dev_table, n_events, b->n_items, nsteps, b->persistent_waves,
+                         b->stream, nullptr, nullptr);
+        e = hipStreamEndCapture(b->stream, &graph);
+        if (e != hipSuccess) return hip_fail(e, "graph capture end");
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+        it = b->graphs.emplace(nsteps, exec).first;
+      }
+      const hipError_t e = hipGraphLaunch(it->second, b->stream);
+      if (e != hipSuccess) return hip_fail(e, "graph launch");
+    } else {
+      launch_batch_run(b->dev_table, n_events, b->n_items, nsteps, b->persistent_waves,
+                       b->stream, b->timing ? batch_between : nullptr, b);
+      const int rc = check_launch("batch run launch");
+      if (rc != CUBA_OK) return rc;
+    }
+  }
+  for (int32_t s : b->table_slots) {
+    cuba_ctx *c = b->slot_ctx[s];
+    c->cur ^= (nsteps & 1);
+    c->next_step += (uint32_t)nsteps;
+  }
+  return CUBA_OK;
+}
+
+int cuba_batch_sync(cuba_batch *b, int32_t *bad_slot) {
+  if (!b) return fail(CUBA_EINVAL, "batch is NULL");
+  if (bad_slot) *bad_slot = -1;
+  const hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return hip_fail(e, "batch sync");
+  for (int32_t s = 0; s < b->max_slots; ++s) {
+    if (!b->slot_ctx[s]) continue;
+    const int rc = cuba_sync(b->slot_ctx[s]);
+    if (rc != CUBA_OK) {
+      if (bad_slot) *bad_slot = s;
+      g_last_error = "slot " + std::to_string(s) + ": " + g_last_error;
+      return rc;
+    }
+  }
+  return CUBA_OK;
+}
+
+int cuba_batch_timing_begin(cuba_batch *b, int32_t max_launches) {
+  if (!b || max_launches < 1) return fail(CUBA_EINVAL, "bad timing arguments");
+  drop_batch_timing(b);
+  b->event_pool.resize(2 * (size_t)max_launches);
+  for (size_t k = 0; k < b->event_pool.size(); ++k) {
+    const hipError_t e = hipEventCreate(&b->event_pool[k]);
+    if (e != hipSuccess) {
+      b->event_pool.resize(k);
+      drop_batch_timing(b);
+      return hip_fail(e, "timing events");
+    }
+  }
+  b->timing_cap = (size_t)max_launches;
+  b->timing = true;
+  b->pending_stage = -1;
+  return CUBA_OK;
+}
+
+int cuba_batch_timing_end(cuba_batch *b, double stage_ms[CUBA_NUM_STAGES],
+                          int64_t stage_launches[CUBA_NUM_STAGES]) {
+  if (!b || !stage_ms || !stage_launches) return fail(CUBA_EINVAL, "NULL argument");
+  for (int k = 0; k < CUBA_NUM_STAGES; ++k) {
+    stage_ms[k] = 0.0;
+    stage_launches[k] = 0;
+  }
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) {
+    drop_batch_timing(b);
+    return hip_fail(e, "timing sync");
+  }
+  for (const TimedLaunch &t : b->timed) {
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, t.before, t.after);
+    if (e != hipSuccess) {
+      drop_batch_timing(b);
+      return hip_fail(e, "timing elapsed");
+    }
+    stage_ms[t.stage] += ms;
+    stage_launches[t.stage] += 1;
+  }
+  drop_batch_timing(b);
+  return CUBA_OK;
+}
+
+void cuba_batch_destroy(cuba_batch *b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  drop_graphs(b);
+  drop_batch_timing(b);
+  for (cuba_ctx *c : b->slot_ctx) cuba_destroy(c);
+  delete b;
+}
 
 }  // extern "C"

@@ -63,6 +63,20 @@ struct PairArgs {
   uint32_t key0, key1;
 };
 
+// One event of a batch as the batched kernels see it (device table).
+struct BatchEvent {
+  Cells buf[2];
+  Geometry g;
+  PairArgs pa;
+  DevStatus *status;
+  uint32_t n_cells;
+  uint32_t cpi;         // cells per work item
+  uint32_t item_begin;  // first work item of this event
+  uint32_t cur;         // buffer holding the state at the start of a run
+  uint32_t t;           // step index of the next step
+  uint32_t pad[3];
+};
+
 // Launchers (kernels.hip).  All asynchronous on stream s.
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s);
 void launch_init_bin(const double *x, const double *y, const double *z,
@@ -79,6 +93,16 @@ void launch_step(const Cells &src, const Cells &dst, bool fused, int64_t n_cells
                  const TraceArgs *trace, hipStream_t s);
 void launch_observe(const Cells &cur, const Geometry &g, double vol, double *cell_sums,
                     double *T00, double *T0x, hipStream_t s);
+// A run of k >= 1 steps of every event in the device table ev (n_events
+// live events, n_items work items): stream + bin, k - 1 fused steps, the
+// last collisions, then the table advance.  persistent_waves > 0 caps the
+// step grid (persistent waves taking items with a grid stride).  between
+// (may be NULL) is called before each launch with the kind of launch that
+// follows (0 stream-bin, 1 fused step, 2 collide) and with -1 after the last
+// one: a hook for stage timing.
+void launch_batch_run(BatchEvent *ev, uint32_t n_events, uint32_t n_items, int32_t k,
+                      uint32_t persistent_waves, hipStream_t s,
+                      void (*between)(void *, int), void *ctx);
 void launch_gather_by_id(const Cells &cur, int64_t n_cells, double *x, double *y,
                          double *z, double *px, double *py, double *pz, hipStream_t s);
 

@@ -139,17 +139,12 @@ __global__ __launch_bounds__(kBlock) void k_init_bin(
   append(dst, cell, active, a, b, c, qa, qb, qc, (uint32_t)i, status);
 }
 
-// Stream + reflect + bin, one wave per source cell (four cells per block).
-// Clears the source counts, so the source buffer can receive the next
-// binning.
-__global__ __launch_bounds__(kBlock) void k_stream_bin(Cells src, Cells dst,
-                                                       uint32_t n_cells, Geometry g,
-                                                       DevStatus *status,
-                                                       uint32_t *trace_cell) {
+// Stream + reflect + bin the particles of source cell c (one wave).  Clears
+// the source count, so the source buffer can receive the next binning.
+__device__ __forceinline__ void cell_stream_bin(const Cells &src, const Cells &dst,
+                                                uint32_t c, const Geometry &g,
+                                                DevStatus *status, uint32_t *trace_cell) {
   const uint32_t lane = lane_id();
-  const uint32_t c = xcd_runs<2>(blockIdx.x, gridDim.x) * kCellsPerBlock +
-                     threadIdx.x / 64;
-  if (c >= n_cells) return;
   const uint32_t n = occupancy(src, c);
   const size_t base = (size_t)c * src.cap;
   for (uint32_t j0 = 0; j0 < n; j0 += 64) {
@@ -172,6 +167,17 @@ __global__ __launch_bounds__(kBlock) void k_stream_bin(Cells src, Cells dst,
     append(dst, c2, active, x, y, z, px, py, pz, id, status);
   }
   if (lane == 0) src.count[c] = 0u;
+}
+
+// One wave per source cell, four cells per block.
+__global__ __launch_bounds__(kBlock) void k_stream_bin(Cells src, Cells dst,
+                                                       uint32_t n_cells, Geometry g,
+                                                       DevStatus *status,
+                                                       uint32_t *trace_cell) {
+  const uint32_t c = xcd_runs<2>(blockIdx.x, gridDim.x) * kCellsPerBlock +
+                     threadIdx.x / 64;
+  if (c >= n_cells) return;
+  cell_stream_bin(src, dst, c, g, status, trace_cell);
 }
 
 // Exclusive scan of the counts into compact offsets (trace only; the counts
@@ -296,27 +302,36 @@ __device__ __forceinline__ void resolve_filtered(
   __syncthreads();
 }
 
-// Collisions of one cell of src at step t.  kFused: afterwards stream and
-// bin the cell's particles into dst for step t+1 and clear src's count.
+// LDS of one wave's cell: s_buf holds the cell's ids while the canonical
+// order is built; after that its first half holds the filtered pairs and its
+// second half the claimed pairs.  s_mark flags (by storage index) the
+// particles whose scattering already binned them (fused steps only).
+template <bool kFused>
+struct CellLds {
+  __align__(16) uint32_t buf[kCellCap];
+  uint16_t perm[kCellCap];
+  uint8_t mark[kFused ? kCellCap : 1];
+};
+
+// Collisions of cell c of src at step t (one wave).  kFused: afterwards
+// stream and bin the cell's particles into dst for step t+1 and clear src's
+// count.  Starts with a barrier, so a wave may call it for several cells.
 template <bool kFused, bool kTrace>
-__global__ __launch_bounds__(64) void k_step(Cells src, Cells dst, uint32_t t,
-                                             PairArgs pa, Geometry g,
-                                             DevStatus *status, TraceArgs tr) {
-  // s_buf holds the cell's ids while the canonical order is built; after
-  // that its first half holds the filtered pairs and its second half the
-  // claimed pairs.  s_mark flags (by storage index) the particles whose
-  // scattering already binned them.
-  __shared__ __align__(16) uint32_t s_buf[kCellCap];
-  __shared__ uint16_t s_perm[kCellCap];
-  __shared__ uint8_t s_mark[kFused ? kCellCap : 1];
+__device__ __forceinline__ void cell_step(const Cells &src, const Cells &dst, uint32_t c,
+                                          uint32_t t, const PairArgs &pa,
+                                          const Geometry &g, DevStatus *status,
+                                          const TraceArgs &tr, CellLds<kFused> &lds) {
   static_assert(kFiltCap + kCellCap / 2 <= kCellCap, "LDS aliasing");
-  uint32_t *const s_id = s_buf;
-  uint32_t *const s_filt = s_buf;
-  uint32_t *const s_claim = s_buf + kFiltCap;
+  uint32_t *const s_id = lds.buf;
+  uint32_t *const s_filt = lds.buf;
+  uint32_t *const s_claim = lds.buf + kFiltCap;
+  uint16_t *const s_perm = lds.perm;
+  uint8_t *const s_mark = lds.mark;
+  __syncthreads();
 
   const uint32_t lane = lane_id();
   CellView cv;
-  cv.c = xcd_runs<8>(blockIdx.x, gridDim.x);
+  cv.c = c;
   cv.t = t;
   cv.base = (size_t)cv.c * src.cap;
   cv.n = occupancy(src, cv.c);
@@ -506,6 +521,78 @@ __global__ __launch_bounds__(64) void k_step(Cells src, Cells dst, uint32_t t,
   }
 }
 
+template <bool kFused, bool kTrace>
+__global__ __launch_bounds__(64) void k_step(Cells src, Cells dst, uint32_t t,
+                                             PairArgs pa, Geometry g,
+                                             DevStatus *status, TraceArgs tr) {
+  __shared__ CellLds<kFused> lds;
+  cell_step<kFused, kTrace>(src, dst, xcd_runs<8>(blockIdx.x, gridDim.x), t, pa, g,
+                            status, tr, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Batched steps: all live events of a batch advance together.  Work item i
+// is a run of cpi consecutive cells of one event (events are laid out one
+// after another in item space); a wave takes items with a grid stride, so a
+// grid smaller than the item count is a persistent launch.  Within a run of
+// k steps, launch j (0: stream + bin, 1..k-1: fused, k: collisions only)
+// reads buffer cur ^ (j & 1) of each event and uses step index t + j - 1;
+// the run ends with k_batch_advance.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t find_event(const BatchEvent *ev, uint32_t n_events,
+                                               uint32_t item) {
+  uint32_t lo = 0, hi = n_events;  // ev[lo].item_begin <= item < ev[hi].item_begin
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (ev[mid].item_begin <= item) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_bin(const BatchEvent *ev,
+                                                      uint32_t n_events, uint32_t n_items) {
+  const uint32_t w = threadIdx.x / 64;
+  for (uint32_t item = blockIdx.x * kCellsPerBlock + w; item < n_items;
+       item += gridDim.x * kCellsPerBlock) {
+    const uint32_t e = find_event(ev, n_events, item);
+    const BatchEvent &E = ev[e];
+    const uint32_t c0 = (item - E.item_begin) * E.cpi;
+    const uint32_t c1 = c0 + E.cpi < E.n_cells ? c0 + E.cpi : E.n_cells;
+    for (uint32_t c = c0; c < c1; ++c)
+      cell_stream_bin(E.buf[E.cur], E.buf[E.cur ^ 1u], c, E.g, E.status, nullptr);
+  }
+}
+
+template <bool kFused>
+__global__ __launch_bounds__(64) void k_batch_step(const BatchEvent *ev,
+                                                   uint32_t n_events, uint32_t n_items,
+                                                   uint32_t j) {
+  __shared__ CellLds<kFused> lds;
+  const uint32_t first = gridDim.x < n_items ? blockIdx.x
+                                             : xcd_runs<8>(blockIdx.x, gridDim.x);
+  for (uint32_t item = first; item < n_items; item += gridDim.x) {
+    const uint32_t e = find_event(ev, n_events, item);
+    const BatchEvent &E = ev[e];
+    const uint32_t p = E.cur ^ (j & 1u);
+    const uint32_t t = E.t + j - 1u;
+    const uint32_t c0 = (item - E.item_begin) * E.cpi;
+    const uint32_t c1 = c0 + E.cpi < E.n_cells ? c0 + E.cpi : E.n_cells;
+    for (uint32_t c = c0; c < c1; ++c)
+      cell_step<kFused, false>(E.buf[p], E.buf[p ^ 1u], c, t, E.pa, E.g, E.status,
+                               TraceArgs{}, lds);
+  }
+}
+
+// End of a run of k steps: every event moved k buffers and k step indices.
+__global__ void k_batch_advance(BatchEvent *ev, uint32_t n_events, uint32_t k) {
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n_events) {
+    ev[e].cur ^= (k & 1u);
+    ev[e].t += k;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Observe: per-cell sums of E and p_x (one wave per cell), then per-slab
 // sums over the slab's cells in cell order.  Slab ix is the contiguous cell
@@ -655,6 +742,30 @@ void launch_observe(const Cells &cur, const Geometry &g, double vol, double *cel
   hipLaunchKernelGGL(k_observe_slabs, dim3((unsigned)g.n[0]), dim3(kBlock), 0, s,
                      (const double *)cell_sums, (uint32_t)(g.n[1] * g.n[2]), vol, T00,
                      T0x);
+}
+
+void launch_batch_run(BatchEvent *ev, uint32_t n_events, uint32_t n_items, int32_t k,
+                      uint32_t persistent_waves, hipStream_t s,
+                      void (*between)(void *, int), void *ctx) {
+  if (n_events == 0 || n_items == 0 || k <= 0) return;
+  const uint32_t step_grid =
+      persistent_waves > 0 && persistent_waves < n_items ? persistent_waves : n_items;
+  const uint32_t bin_waves = step_grid;
+  const uint32_t bin_grid = (bin_waves + kCellsPerBlock - 1) / kCellsPerBlock;
+  if (between) between(ctx, 0);
+  hipLaunchKernelGGL(k_batch_bin, dim3(bin_grid), dim3(kBlock), 0, s,
+                     (const BatchEvent *)ev, n_events, n_items);
+  for (int32_t j = 1; j < k; ++j) {
+    if (between) between(ctx, 1);
+    hipLaunchKernelGGL((k_batch_step<true>), dim3(step_grid), dim3(64), 0, s,
+                       (const BatchEvent *)ev, n_events, n_items, (uint32_t)j);
+  }
+  if (between) between(ctx, 2);
+  hipLaunchKernelGGL((k_batch_step<false>), dim3(step_grid), dim3(64), 0, s,
+                     (const BatchEvent *)ev, n_events, n_items, (uint32_t)k);
+  if (between) between(ctx, -1);
+  hipLaunchKernelGGL(k_batch_advance, dim3((n_events + 63) / 64), dim3(64), 0, s, ev,
+                     n_events, (uint32_t)k);
 }
 
 void launch_gather_by_id(const Cells &cur, int64_t n_cells, double *x, double *y,

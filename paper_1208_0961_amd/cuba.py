@@ -81,6 +81,31 @@ def _load() -> ctypes.CDLL:
     L.cuba_timing_end.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_int64)]
     L.cuba_timing_end.restype = ctypes.c_int
+    L.cuba_batch_workspace_bytes.argtypes = [i32]
+    L.cuba_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.cuba_batch_create.argtypes = [ctypes.POINTER(vp), i32, vp, ctypes.c_size_t, vp]
+    L.cuba_batch_create.restype = ctypes.c_int
+    L.cuba_batch_admit.argtypes = [vp, i32, P, i64] + [vp] * 6 + [vp, ctypes.c_size_t]
+    L.cuba_batch_admit.restype = ctypes.c_int
+    L.cuba_batch_retire.argtypes = [vp, i32]
+    L.cuba_batch_retire.restype = ctypes.c_int
+    L.cuba_batch_slot.argtypes = [vp, i32]
+    L.cuba_batch_slot.restype = vp
+    L.cuba_batch_set_cells_per_item.argtypes = [vp, i32, i32]
+    L.cuba_batch_set_cells_per_item.restype = ctypes.c_int
+    L.cuba_batch_set_launch.argtypes = [vp, i32, i32]
+    L.cuba_batch_set_launch.restype = ctypes.c_int
+    L.cuba_batch_step.argtypes = [vp, i32]
+    L.cuba_batch_step.restype = ctypes.c_int
+    L.cuba_batch_sync.argtypes = [vp, ctypes.POINTER(i32)]
+    L.cuba_batch_sync.restype = ctypes.c_int
+    L.cuba_batch_timing_begin.argtypes = [vp, i32]
+    L.cuba_batch_timing_begin.restype = ctypes.c_int
+    L.cuba_batch_timing_end.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int64)]
+    L.cuba_batch_timing_end.restype = ctypes.c_int
+    L.cuba_batch_destroy.argtypes = [vp]
+    L.cuba_batch_destroy.restype = None
     L.cuba_destroy.argtypes = [vp]
     L.cuba_destroy.restype = None
     L.cuba_strerror.argtypes = [ctypes.c_int]
@@ -188,3 +213,69 @@ def cuba_timing_end(ctx: int):
 
 def cuba_destroy(ctx: int) -> None:
     _lib.cuba_destroy(ctx)
+
+
+# -- batches ------------------------------------------------------------------
+def cuba_batch_workspace_bytes(max_slots: int) -> int:
+    return int(_lib.cuba_batch_workspace_bytes(int(max_slots)))
+
+
+def cuba_batch_create(max_slots: int, workspace: int, ws_bytes: int,
+                      stream: int | None) -> int:
+    b = ctypes.c_void_p()
+    _check(_lib.cuba_batch_create(ctypes.byref(b), int(max_slots), workspace,
+                                  int(ws_bytes), stream), "cuba_batch_create")
+    return b.value
+
+
+def cuba_batch_admit(b: int, slot: int, params: cuba_params, n: int, x: int, y: int,
+                     z: int, px: int, py: int, pz: int, workspace: int,
+                     ws_bytes: int) -> None:
+    _check(_lib.cuba_batch_admit(b, int(slot), ctypes.byref(params), int(n), x, y, z, px,
+                                 py, pz, workspace, int(ws_bytes)), "cuba_batch_admit")
+
+
+def cuba_batch_retire(b: int, slot: int) -> None:
+    _check(_lib.cuba_batch_retire(b, int(slot)), "cuba_batch_retire")
+
+
+def cuba_batch_slot(b: int, slot: int):
+    return _lib.cuba_batch_slot(b, int(slot))
+
+
+def cuba_batch_set_cells_per_item(b: int, slot: int, cells: int) -> None:
+    _check(_lib.cuba_batch_set_cells_per_item(b, int(slot), int(cells)),
+           "cuba_batch_set_cells_per_item")
+
+
+def cuba_batch_set_launch(b: int, persistent_waves: int, use_graphs: bool) -> None:
+    _check(_lib.cuba_batch_set_launch(b, int(persistent_waves), 1 if use_graphs else 0),
+           "cuba_batch_set_launch")
+
+
+def cuba_batch_step(b: int, nsteps: int) -> None:
+    _check(_lib.cuba_batch_step(b, int(nsteps)), "cuba_batch_step")
+
+
+def cuba_batch_sync(b: int) -> None:
+    bad = ctypes.c_int32(-1)
+    rc = _lib.cuba_batch_sync(b, ctypes.byref(bad))
+    if rc != CUBA_OK:
+        err = CubaError(rc, "cuba_batch_sync", cuba_last_error())
+        err.slot = bad.value
+        raise err
+
+
+def cuba_batch_timing_begin(b: int, max_launches: int) -> None:
+    _check(_lib.cuba_batch_timing_begin(b, int(max_launches)), "cuba_batch_timing_begin")
+
+
+def cuba_batch_timing_end(b: int):
+    ms = (ctypes.c_double * CUBA_NUM_STAGES)()
+    nl = (ctypes.c_int64 * CUBA_NUM_STAGES)()
+    _check(_lib.cuba_batch_timing_end(b, ms, nl), "cuba_batch_timing_end")
+    return {STAGES[k]: (float(ms[k]), int(nl[k])) for k in range(CUBA_NUM_STAGES)}
+
+
+def cuba_batch_destroy(b: int) -> None:
+    _lib.cuba_batch_destroy(b)

@@ -1,0 +1,133 @@
+"""Batched events: every event advanced in a batch (mixed with other events,
+admitted and retired at different times, under any launch shape) ends in
+exactly the state it reaches when run alone through cuba_step."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1208_0961_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mods():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1208_0961_amd import build
+    if build.sources_newer_than_lib():
+        build.build()
+    from paper_1208_0961_amd import batch, sim
+    return batch, sim
+
+
+def small_events():
+    """Heterogeneous events: the 1-D tube and four small ensemble-style events
+    of different r_test, sigma, temperature and box size."""
+    evs = [W.TUBE_1D]
+    for i, (rt, sig, TL, L) in enumerate(((50.0, 0.9, 0.45, 1.0), (400.0, 0.1, 0.31, 1.0),
+                                          (150.0, 0.5, 0.38, 2.0), (60.0, 0.05, 0.5, 2.0))):
+        n = int(round(5 * L))
+        evs.append(W.Workload(f"small{i}", (10.0, L, L), (100, n, n), rt, sig, 0.02, TL,
+                              0.8 * TL, seed=1000 + i))
+    return evs
+
+
+def alone(sim, w, state, nsteps):
+    s = sim.Sim(w.params(), state)
+    s.step(nsteps)
+    out = s.get_state()
+    s.close()
+    return out
+
+
+def assert_same(a, b, label):
+    for d in range(6):
+        assert np.array_equal(a[d], b[d]), f"{label}: array {d} differs"
+
+
+def test_batch_equals_alone(mods):
+    batch, sim = mods
+    evs = small_events()
+    states = [W.riemann_state(w, seed=77 + i) for i, w in enumerate(evs)]
+    say(f"[batch] {len(evs)} events, n = {[w.n for w in evs]}")
+    B = batch.Batch(8)
+    for i, (w, st) in enumerate(zip(evs, states)):
+        B.admit(i, w.params(), st)
+    for k in (7, 1, 12):
+        B.step(k)
+    B.sync()
+    for i, (w, st) in enumerate(zip(evs, states)):
+        assert B.next_step(i) == 20
+        assert_same(B.get_state(i), alone(sim, w, st, 20), w.name)
+    B.close()
+
+
+@pytest.mark.parametrize("cpi,persistent,graphs", [(1, 0, False), (3, 97, False),
+                                                   (64, 0, True), (2, 300, True)])
+def test_batch_launch_shapes(mods, cpi, persistent, graphs):
+    batch, sim = mods
+    evs = small_events()[1:]
+    states = [W.riemann_state(w, seed=5 + i) for i, w in enumerate(evs)]
+    say(f"[batch] cpi={cpi} persistent={persistent} graphs={graphs}")
+    B = batch.Batch(4, persistent_waves=persistent, use_graphs=graphs)
+    for i, (w, st) in enumerate(zip(evs, states)):
+        B.admit(i, w.params(), st)
+        B.set_cells_per_item(i, cpi)
+    # repeated replays of the same run shape, with eager work in between
+    for r in range(3):
+        B.step(5)
+        B.observe(r % len(evs))
+    B.step(2)
+    B.sync()
+    for i, (w, st) in enumerate(zip(evs, states)):
+        assert_same(B.get_state(i), alone(sim, w, st, 17), w.name)
+    B.close()
+
+
+def test_batch_staggered_admission_and_slot_reuse(mods):
+    batch, sim = mods
+    a, b, c = small_events()[1:4]
+    sa, sb, sc = (W.riemann_state(w, seed=s) for w, s in ((a, 1), (b, 2), (c, 3)))
+    B = batch.Batch(2, use_graphs=True)
+    B.admit(0, a.params(), sa)
+    B.step(10)
+    B.admit(1, b.params(), sb)
+    B.step(10)
+    got_a = B.get_state(0)
+    ws = B.retire(0)
+    need = batch.event_workspace_bytes(batch.with_capacity(c.params(), sc), c.n)
+    B.admit(0, c.params(), sc, workspace=ws if ws.numel() >= need else None)
+    B.step(5)
+    B.sync()
+    assert_same(got_a, alone(sim, a, sa, 20), "A")
+    assert_same(B.get_state(1), alone(sim, b, sb, 15), "B")
+    assert_same(B.get_state(0), alone(sim, c, sc, 5), "C")
+    B.close()
+
+
+def test_batch_reports_the_failing_slot(mods):
+    batch, _ = mods
+    from paper_1208_0961_amd import cuba as C
+    ok = small_events()[1]
+    n = 60
+    rng = np.random.default_rng(4)
+    x = np.concatenate([0.1 + 0.3 * rng.random(n), 0.5 + 0.004 * rng.random(n)])
+    bad_state = [x, rng.random(2 * n), rng.random(2 * n),
+                 np.concatenate([np.ones(n), -np.ones(n)]), np.zeros(2 * n), np.zeros(2 * n)]
+    bad = dict(box=(1.0, 1.0, 1.0), cells=(2, 1, 1), sigma=0.0, r_test=1.0, dt=0.01,
+               seed=1, cell_capacity=64)
+    B = batch.Batch(3)
+    B.admit(0, ok.params(), W.riemann_state(ok))
+    B.admit(2, bad, bad_state)
+    B.step(1)
+    with pytest.raises(C.CubaError) as e:
+        B.sync()
+    assert e.value.code == C.CUBA_ERANGE and e.value.slot == 2
+    B.close()
