@@ -46,7 +46,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="tube3d", choices=["tube1d", "tube3d", "full"])
+    ap.add_argument("--workload", default="tube3d",
+                    choices=["tube1d", "tube3d", "full", "batch", "serve"])
+    ap.add_argument("--events", type=int, default=256,
+                    help="batch: number of ensemble events")
+    ap.add_argument("--requests", type=int, default=2000,
+                    help="serve: number of requests")
+    ap.add_argument("--retune", action="store_true",
+                    help="batch: ignore a stored tuning table")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="batch: skip the one-at-a-time comparison")
     ap.add_argument("--cpu-steps", type=int, default=None,
                     help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--cpu-threads", type=int, default=None)
@@ -72,6 +81,84 @@ def cpu_baseline(w, state, steps, threads):
                       f"{dt:.1f} s wall"}
 
 
+def bench_batch(a):
+    """Ensemble of independent Riemann events (r_test log-uniform in
+    [50, 2500], sigma in [0.05, 1] fm^2, T_L in [0.30, 0.50] GeV, T_R = 0.8 T_L,
+    10 x L x L fm boxes with L in {1, 2, 4}) advanced together by the batch
+    API in graph-captured runs of 50 steps with all profiles observed after
+    each run, against the same events run one at a time through cuba_step."""
+    import torch
+    from paper_1208_0961_amd import autotune as AT
+    from paper_1208_0961_amd import batch as BT
+    from paper_1208_0961_amd import sim as S
+    from paper_1208_0961_amd import workload as W
+
+    events = W.ensemble_events(a.events)
+    total_n = sum(w.n for w in events)
+    table = None if a.retune else AT.load()
+    if table is None:
+        print("# tuning", file=sys.stderr, flush=True)
+        table = AT.tune(events)
+        AT.save(table)
+    print(f"# batch: {len(events)} events, {total_n} particles; tuning {table}",
+          file=sys.stderr, flush=True)
+    B = BT.Batch(len(events))
+    for i, w in enumerate(events):
+        st = W.riemann_state_torch(w, 100000 + i)
+        B.admit(i, {**w.params(), "cell_capacity": W.capacity_for(w)}, st)
+        del st
+    AT.apply(B, table, dict(enumerate(events)), use_graphs=True)
+    B.step(a.warmup)
+    B.sync()
+    oe = events[0].observe_every
+    runs = [oe] * (a.steps // oe) + ([a.steps % oe] if a.steps % oe else [])
+    pairs0 = sum(B.counters(i)["pair_tests"] for i in range(len(events)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in runs:
+        B.step(k)
+        for i in range(len(events)):
+            B.observe_async(i)
+    B.sync()
+    t1 = time.perf_counter()
+    batched = total_n * a.steps / (t1 - t0)
+    pairs = sum(B.counters(i)["pair_tests"] for i in range(len(events))) - pairs0
+    B.close()
+    del B
+    torch.cuda.empty_cache()
+
+    seq = None
+    if not a.no_sequential:
+        print("# one event at a time", file=sys.stderr, flush=True)
+        busy = 0.0
+        for i, w in enumerate(events):
+            st = W.riemann_state_torch(w, 100000 + i)
+            sim = S.Sim({**w.params(), "cell_capacity": W.capacity_for(w)}, st)
+            del st
+            sim.step(a.warmup)
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            for k in runs:
+                sim.step(k)
+                sim.observe_async()
+            torch.cuda.synchronize()
+            busy += time.perf_counter() - s0
+            sim.close()
+        seq = total_n * a.steps / busy
+    out = {"metric": "batched ensemble particle-steps/s vs one event at a time",
+           "value": batched, "unit": "particle-steps/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup,
+           "ms_per_step": 1e3 * (t1 - t0) / a.steps, "higher_is_better": True,
+           "dtype": "f64", "data": "synthetic: seeded thermal Riemann events",
+           "config": {"workload": f"ensemble-{len(events)}-events", "n_particles": total_n,
+                      "observe_every": events[0].observe_every},
+           "pair_tests_per_s": pairs / (t1 - t0),
+           "sequential_value": seq,
+           "speedup_vs_sequential": (batched / seq) if seq else None,
+           "tuning": table}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -89,6 +176,11 @@ def main():
     from paper_1208_0961_amd import sim as S
     from paper_1208_0961_amd import workload as W
 
+    if a.workload == "batch":
+        return bench_batch(a)
+    if a.workload == "serve":
+        from paper_1208_0961_amd import serve
+        return serve.bench(a)
     w = W.ALIASES[a.workload]
     state = W.riemann_state(w)
     sim = S.Sim(w.params(), state)

@@ -59,6 +59,8 @@ class Batch:
         nbytes = C.cuba_workspace_bytes(p, n)
         if nbytes == 0:
             raise C.CubaError(C.CUBA_EINVAL, "cuba_workspace_bytes", C.cuba_last_error())
+        # the inputs may have been produced on another stream
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         with torch.cuda.stream(self.stream):
             if workspace is None:
                 workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)

@@ -1,0 +1,252 @@
+"""Serving: continuous batching of simulation requests.
+
+Each request is one Riemann event (parameters from the ensemble
+distribution, an initial state drawn from its seed) to be advanced a fixed
+number of steps, with T00/T0x observed every 50 steps; the result is the
+final profile.  The server admits arrived requests in FIFO order as a batch
+slot and enough HBM (the event's workspace footprint) free up, advances all
+live events together in runs of `run_steps` steps (one launch per step for
+all of them), and retires events that are done.  Requests that arrive while
+others run join at the next run boundary, so their work overlaps on the
+device.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from collections import deque
+
+import numpy as np
+import torch
+
+from . import workload as W
+from .batch import Batch, event_workspace_bytes
+from .sim import Sim
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    work: W.Workload
+    arrival: float      # seconds from the start of the trace
+    state_seed: int
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    n: int
+    arrival: float
+    admitted: float
+    finished: float
+    T00: np.ndarray
+    T0x: np.ndarray
+    state: list | None = None
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+def request_stream(n_requests: int, rate: float, seed: int = 5, nmin: float = 1e4,
+                   nmax: float = 4e6, steps: int = 200) -> list[Request]:
+    """Requests from the ensemble distribution truncated to nmin <= N <= nmax,
+    with Poisson arrivals at `rate` requests per second."""
+    rng = np.random.default_rng(seed)
+    out, t = [], 0.0
+    i = 0
+    while len(out) < n_requests:
+        r_test = float(math.exp(rng.uniform(math.log(50.0), math.log(2500.0))))
+        sigma = float(rng.uniform(0.05, 1.0))
+        TL = float(rng.uniform(0.30, 0.50))
+        L = float(rng.choice([1.0, 2.0, 4.0]))
+        nt = int(round(5 * L))
+        w = W.Workload(f"req{i}", (10.0, L, L), (100, nt, nt), r_test, sigma, 0.02, TL,
+                       0.8 * TL, steps=steps, seed=5000 + i)
+        i += 1
+        if not (nmin <= w.n <= nmax):
+            continue
+        t += float(rng.exponential(1.0 / rate)) if rate > 0 else 0.0
+        out.append(Request(len(out), w, t, 700000 + i))
+    return out
+
+
+def footprint(req: Request) -> int:
+    return event_workspace_bytes({**req.work.params(),
+                                  "cell_capacity": W.capacity_for(req.work)}, req.work.n)
+
+
+class Server:
+    def __init__(self, max_slots: int = 256, hbm_budget: int | None = None,
+                 run_steps: int = 25, device: str = "cuda", use_graphs: bool = False,
+                 tuning: dict | None = None, keep_states: bool = False):
+        self.device = device
+        self.run_steps = run_steps
+        self.keep_states = keep_states
+        if hbm_budget is None:
+            free, _ = torch.cuda.mem_get_info(device)
+            hbm_budget = int(0.7 * free)
+        self.budget = hbm_budget
+        self.B = Batch(max_slots, device=device, use_graphs=use_graphs)
+        self.tuning = tuning
+        self.use_graphs = use_graphs
+        self.peak_live = 0
+        self.peak_bytes = 0
+
+    def _admit(self, slot: int, req: Request):
+        from . import autotune as AT
+        with torch.cuda.stream(self.B.stream):
+            state = W.riemann_state_torch(req.work, req.state_seed, device=self.device)
+        self.B.admit(slot, {**req.work.params(), "cell_capacity": W.capacity_for(req.work)},
+                     state)
+        if self.tuning:
+            k = AT.occupancy_class(W.max_mean_occupancy(req.work))
+            c = self.tuning["cells_per_item"].get(str(k))
+            if c:
+                self.B.set_cells_per_item(slot, int(c))
+
+    def run(self, requests: list[Request], realtime: bool = True) -> list[Result]:
+        """Serves the requests; with realtime, a request is only admitted once
+        its arrival time has passed on the wall clock."""
+        if self.tuning:
+            self.B.set_launch(int(self.tuning.get("persistent_waves", 0)), self.use_graphs)
+        queue = deque(sorted(requests, key=lambda r: r.arrival))
+        live: dict[int, dict] = {}
+        used = 0
+        results: list[Result] = []
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0
+        while queue or live:
+            # admission: FIFO, by free slot and HBM footprint
+            while queue and (not realtime or queue[0].arrival <= now()):
+                req = queue[0]
+                need = footprint(req)
+                slot = self.B.free_slot()
+                if slot is None or (used + need > self.budget and live):
+                    break
+                queue.popleft()
+                self._admit(slot, req)
+                used += need
+                live[slot] = {"req": req, "need": need, "done": 0, "admitted": now()}
+                self.peak_live = max(self.peak_live, len(live))
+                self.peak_bytes = max(self.peak_bytes, used)
+            if not live:
+                if queue and realtime:
+                    time.sleep(max(0.0, min(queue[0].arrival - now(), 0.01)))
+                continue
+            k = self.run_steps
+            self.B.step(k)
+            finished = []
+            for slot, ev in live.items():
+                ev["done"] += k
+                w = ev["req"].work
+                if ev["done"] % w.observe_every == 0 or ev["done"] >= w.steps:
+                    self.B.observe_async(slot)
+                if ev["done"] >= w.steps:
+                    finished.append(slot)
+            self.B.sync()
+            t_done = now()
+            for slot in finished:
+                ev = live.pop(slot)
+                s = self.B.slots[slot]
+                res = Result(ev["req"].rid, ev["req"].work.n, ev["req"].arrival,
+                             ev["admitted"], t_done, s["T00"].cpu().numpy().copy(),
+                             s["T0x"].cpu().numpy().copy())
+                if self.keep_states:
+                    res.state = self.B.get_state(slot)
+                self.B.retire(slot)
+                used -= ev["need"]
+                results.append(res)
+        return results
+
+    def close(self):
+        self.B.close()
+
+
+def run_alone(req: Request, device: str = "cuda", keep_state: bool = False):
+    """The same request through the plain path: (service seconds, T00, T0x, state)."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    state = W.riemann_state_torch(req.work, req.state_seed, device=device)
+    sim = Sim({**req.work.params(), "cell_capacity": W.capacity_for(req.work)}, state,
+              device=device)
+    del state
+    w = req.work
+    done = 0
+    while done < w.steps:
+        k = min(w.observe_every, w.steps - done)
+        sim.step(k)
+        done += k
+        sim.observe_async()
+    T00, T0x = sim.observe()
+    st = sim.get_state() if keep_state else None
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sim.close()
+    return dt, T00, T0x, st
+
+
+def fifo_replay(requests: list[Request], service: dict) -> dict:
+    """Completion times of a one-at-a-time FIFO server with the given
+    service times and the requests' arrival times."""
+    finish, t = {}, 0.0
+    for r in sorted(requests, key=lambda r: r.arrival):
+        t = max(t, r.arrival) + service[r.rid]
+        finish[r.rid] = t
+    return finish
+
+
+def percentiles(lat):
+    lat = np.asarray(lat)
+    return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+
+
+def bench(a):
+    """2000 requests (sizes 1e4 .. 4e6 test particles), Poisson arrivals at 0.8
+    of the measured batched capacity; p50/p99 time-to-result and aggregate
+    particle-steps/s of the served stream against a one-at-a-time FIFO of
+    plain runs on the same trace."""
+    import json
+    import sys
+    from . import autotune as AT
+    n_req = int(a.requests)
+    tuning = AT.load()
+    # capacity: a closed batch of 64 requests all present at t = 0
+    probe = request_stream(64, 0.0, seed=55)
+    srv = Server(tuning=tuning, use_graphs=False)
+    t0 = time.perf_counter()
+    srv.run(probe, realtime=False)
+    cap_dt = time.perf_counter() - t0
+    srv.close()
+    probe_ps = sum(r.work.n * r.work.steps for r in probe)
+    throughput = probe_ps / cap_dt
+    reqs0 = request_stream(n_req, 1.0, seed=5)
+    mean_ps = float(np.mean([r.work.n * r.work.steps for r in reqs0]))
+    rate = 0.8 * throughput / mean_ps
+    reqs = request_stream(n_req, rate, seed=5)
+    print(f"# serve: {n_req} requests at {rate:.1f}/s (capacity {throughput:.3e} "
+          f"particle-steps/s)", file=sys.stderr, flush=True)
+    srv = Server(tuning=tuning, use_graphs=False)
+    t0 = time.perf_counter()
+    res = srv.run(reqs, realtime=True)
+    makespan = time.perf_counter() - t0
+    srv.close()
+    p50, p99 = percentiles([r.latency for r in res])
+    total_ps = sum(r.work.n * r.work.steps for r in reqs)
+    out = {"metric": "served request stream: p50/p99 time-to-result and particle-steps/s",
+           "value": total_ps / makespan, "unit": "particle-steps/s",
+           "p50_s": p50, "p99_s": p99, "requests": len(res), "arrival_rate_per_s": rate,
+           "capacity_particle_steps_per_s": throughput, "makespan_s": makespan}
+    if not getattr(a, "no_sequential", False):
+        print("# sequential FIFO replay", file=sys.stderr, flush=True)
+        service = {}
+        for r in reqs:
+            service[r.rid] = run_alone(r)[0]
+        fin = fifo_replay(reqs, service)
+        lat = [fin[r.rid] - r.arrival for r in reqs]
+        sp50, sp99 = percentiles(lat)
+        out.update({"sequential_p50_s": sp50, "sequential_p99_s": sp99,
+                    "sequential_value": total_ps / max(fin.values()),
+                    "sequential_busy_particle_steps_per_s": total_ps / sum(service.values())})
+    print(json.dumps(out), flush=True)

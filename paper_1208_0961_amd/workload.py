@@ -141,3 +141,53 @@ def ensemble_events(n_events=256, seed=4, dt=0.02, steps=200):
         out.append(Workload(f"event{i}", (10.0, L, L), (100, nt, nt), r_test,
                             sigma, dt, TL, 0.8 * TL, steps=steps, seed=1000 + i))
     return out
+
+
+# ---------------------------------------------------------------------------
+# The same recipe drawn on the GPU (large ensembles: ~1e8 particles)
+# ---------------------------------------------------------------------------
+def sample_gas_torch(gen, n, T, lo, hi, device):
+    """As sample_gas, drawn with a seeded torch generator on `device`;
+    returns six float64 tensors."""
+    import torch
+    kw = dict(generator=gen, device=device, dtype=torch.float64)
+    lo_t = torch.tensor(lo, dtype=torch.float64, device=device)
+    hi_t = torch.tensor(hi, dtype=torch.float64, device=device)
+    r = lo_t + (hi_t - lo_t) * torch.rand((n, 3), **kw)
+    u = 1.0 - torch.rand((n, 3), **kw)                      # (0, 1]
+    pm = -T * torch.log(u[:, 0] * u[:, 1] * u[:, 2])
+    pm = torch.where(pm > 0.0, pm, torch.full_like(pm, T))  # |p| = 0: probability ~2^-159
+    cth = 2.0 * torch.rand(n, **kw) - 1.0
+    phi = 2.0 * math.pi * torch.rand(n, **kw)
+    sth = torch.sqrt((1.0 - cth) * (1.0 + cth))
+    return (r[:, 0].contiguous(), r[:, 1].contiguous(), r[:, 2].contiguous(),
+            (pm * sth * torch.cos(phi)).contiguous(), (pm * sth * torch.sin(phi)).contiguous(),
+            (pm * cth).contiguous())
+
+
+def riemann_state_torch(w: Workload, seed: int, device="cuda"):
+    """Riemann state of workload w drawn on the GPU (ids not shuffled: the
+    canonical order depends on ids only within a cell)."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    nl, nr = w.side_counts()
+    L = w.box
+    left = sample_gas_torch(gen, nl, w.T_left, (0.0, 0.0, 0.0), (0.5 * L[0], L[1], L[2]), device)
+    right = sample_gas_torch(gen, nr, w.T_right, (0.5 * L[0], 0.0, 0.0), (L[0], L[1], L[2]), device)
+    return [torch.cat([a, b]) for a, b in zip(left, right)]
+
+
+def max_mean_occupancy(w: Workload) -> float:
+    """Mean test particles per cell on the denser (left) side."""
+    vcell = w.box[0] * w.box[1] * w.box[2] / w.n_cells
+    return w.r_test * gluon_density(w.T_left) * vcell
+
+
+def capacity_for(w: Workload, headroom: float = 2.0, margin: int = 32) -> int:
+    """Cell capacity from the expected occupancy (mean + 5 sigma on the
+    denser side), as suggest_cell_capacity would choose from a sample."""
+    m = max_mean_occupancy(w)
+    occ = m + 5.0 * math.sqrt(m) + 2.0
+    cap = int(math.ceil((headroom * occ + margin) / 32.0)) * 32
+    return max(64, min(1024, cap))
