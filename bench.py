@@ -59,12 +59,74 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=None,
                     help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--cpu-threads", type=int, default=None)
-    ap.add_argument("--traffic", default=None,
-                    help="JSON file with measured FETCH/WRITE bytes per collide launch")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the run, copy a 1 GiB device buffer 3 times (a plain "
                          "copy kernel of known size for scaling HBM counters)")
+    ap.add_argument("--pmc-csv", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="rocprofv3 counter_collection.csv files of a --calibrate-copy run "
+                         "(FETCH_SIZE, WRITE_SIZE): write the measured HBM traffic of "
+                         "the dominant kernel to profiles/ and exit")
     return ap.parse_args()
+
+
+KERNEL_SOURCES = ("paper_1208_0961_amd/csrc/kernels.hip", "paper_1208_0961_amd/csrc/device.hpp")
+DOMINANT_KERNEL = "k_step<true, false,"   # the fused step, any cell capacity
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_path(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"traffic_step_{workload}.json")
+
+
+def write_traffic(a):
+    """HBM bytes per launch of the dominant kernel from FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads
+    for the 1 GiB device copy of --calibrate-copy."""
+    import csv
+
+    def per_kernel(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        kern = [float(r["Counter_Value"]) for r in rows
+                if DOMINANT_KERNEL.replace(" ", "") in r["Kernel_Name"].replace(" ", "")]
+        # the profiled run uses the benchmark's workload, whose capacity
+        # selects one instantiation
+        copy = [float(r["Counter_Value"]) for r in rows
+                if "copyBuffer" in r["Kernel_Name"] and int(r["Grid_Size"]) >= 65536]
+        if not kern or not copy:
+            raise SystemExit(f"{path}: no {DOMINANT_KERNEL} or 1 GiB copy dispatches")
+        scale = (1 << 30) / (sorted(copy)[len(copy) // 2] * 1024.0)
+        return sum(kern) / len(kern) * 1024.0 * scale, scale
+
+    fetch, fscale = per_kernel(a.pmc_csv[0], "FETCH_SIZE")
+    write, wscale = per_kernel(a.pmc_csv[1], "WRITE_SIZE")
+    out = {"kernel": DOMINANT_KERNEL.rstrip(",") + " ...>", "workload": a.workload,
+           "kernel_source_hash": kernel_source_hash(),
+           "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+           "bytes_per_launch": fetch + write,
+           "fetch_scale": fscale, "write_scale": wscale}
+    with open(traffic_path(a.workload), "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
+def measured_traffic(workload: str):
+    """Measured bytes per launch, if taken on the current kernel source."""
+    try:
+        with open(traffic_path(workload)) as f:
+            t = json.load(f)
+    except OSError:
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
 
 
 def cpu_baseline(w, state, steps, threads):
@@ -90,6 +152,7 @@ def bench_batch(a):
     import torch
     from paper_1208_0961_amd import autotune as AT
     from paper_1208_0961_amd import batch as BT
+    from paper_1208_0961_amd import cuba as C
     from paper_1208_0961_amd import sim as S
     from paper_1208_0961_amd import workload as W
 
@@ -123,6 +186,11 @@ def bench_batch(a):
     t1 = time.perf_counter()
     batched = total_n * a.steps / (t1 - t0)
     pairs = sum(B.counters(i)["pair_tests"] for i in range(len(events))) - pairs0
+    # per-stage kernel times of one more run, without graphs (diagnostic)
+    B.set_launch(int(table.get("persistent_waves", 0)), False)
+    C.cuba_batch_timing_begin(B.b, 4 * oe + 8)
+    B.step(oe)
+    stage_times = C.cuba_batch_timing_end(B.b)
     B.close()
     del B
     torch.cuda.empty_cache()
@@ -155,12 +223,16 @@ def bench_batch(a):
            "pair_tests_per_s": pairs / (t1 - t0),
            "sequential_value": seq,
            "speedup_vs_sequential": (batched / seq) if seq else None,
+           "stage_ms_per_launch": {k: (v[0] / v[1] if v[1] else None)
+                                   for k, v in stage_times.items()},
            "tuning": table}
     print(json.dumps(out), flush=True)
 
 
 def main():
     a = parse()
+    if a.pmc_csv:
+        return write_traffic(a)
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the method's "
               "multi-GPU slab decomposition is not part of this build.", file=sys.stderr)
@@ -226,10 +298,7 @@ def main():
     step_ms = avg_ms("step") if stages["step"][1] else avg_ms("collide")
     pairs_per_step = pairs / a.steps
     achieved_tops = PHILOX_OPS_PER_PAIR * pairs_per_step / (step_ms * 1e-3) / 1e12
-    traffic = None
-    if a.traffic and os.path.exists(a.traffic):
-        with open(a.traffic) as f:
-            traffic = json.load(f).get("step_bytes_per_launch")
+    traffic = measured_traffic(a.workload)
 
     def gbs(nbytes, ms):
         return nbytes / (ms * 1e-3) / 1e9

@@ -467,10 +467,12 @@ struct cuba_batch {
   int32_t max_slots = 0;
   hipStream_t stream = nullptr;
   BatchEvent *dev_table = nullptr;  // in the caller's batch workspace
+  uint32_t *dev_item_begin = nullptr;
   std::vector<cuba_ctx *> slot_ctx;
   std::vector<int32_t> slot_cpi;
   std::vector<int32_t> table_slots;  // slots in table order
   uint32_t n_items = 0;
+  uint32_t max_cap = 0;
   bool dirty = true;
   uint32_t persistent_waves = 0;
   bool use_graphs = false;
@@ -513,6 +515,7 @@ int upload_table(cuba_batch *b) {
   std::vector<BatchEvent> host;
   b->table_slots.clear();
   uint32_t items = 0;
+  b->max_cap = 0;
   for (int32_t s = 0; s < b->max_slots; ++s) {
     cuba_ctx *c = b->slot_ctx[s];
     if (!c || c->d.n_cells == 0) continue;
@@ -530,13 +533,19 @@ int upload_table(cuba_batch *b) {
     const uint64_t ni = (e.n_cells + e.cpi - 1) / e.cpi;
     if (items + ni >= 0xFFFFFFFFull) return fail(CUBA_EINVAL, "too many work items");
     items += (uint32_t)ni;
+    if (c->d.cap > b->max_cap) b->max_cap = c->d.cap;
     host.push_back(e);
     b->table_slots.push_back(s);
   }
   b->n_items = items;
   if (!host.empty()) {
+    std::vector<uint32_t> begins(host.size());
+    for (size_t i = 0; i < host.size(); ++i) begins[i] = host[i].item_begin;
     hipError_t e = hipMemcpyAsync(b->dev_table, host.data(), host.size() * sizeof(BatchEvent),
                                   hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b->dev_item_begin, begins.data(), begins.size() * sizeof(uint32_t),
+                         hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return hip_fail(e, "batch table upload");
   }
@@ -567,7 +576,8 @@ extern "C" {
 
 size_t cuba_batch_workspace_bytes(int32_t max_slots) {
   if (max_slots < 1) return 0;
-  return align256((size_t)max_slots * sizeof(BatchEvent));
+  return align256((size_t)max_slots * sizeof(BatchEvent)) +
+         align256((size_t)max_slots * sizeof(uint32_t));
 }
 
 int cuba_batch_create(cuba_batch **out, int32_t max_slots, void *workspace,
@@ -584,6 +594,8 @@ int cuba_batch_create(cuba_batch **out, int32_t max_slots, void *workspace,
   b->max_slots = max_slots;
   b->stream = (hipStream_t)stream;
   b->dev_table = (BatchEvent *)workspace;
+  b->dev_item_begin =
+      (uint32_t *)((char *)workspace + align256((size_t)max_slots * sizeof(BatchEvent)));
   b->slot_ctx.assign(max_slots, nullptr);
   b->slot_cpi.assign(max_slots, 1);
   *out = b;
@@ -660,8 +672,8 @@ int cuba_batch_step(cuba_batch *b, int32_t nsteps) {
         hipGraphExec_t exec = nullptr;
         hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "graph capture begin");
-        launch_batch_run(b->dev_table, n_events, b->n_items, nsteps, b->persistent_waves,
-                         b->stream, nullptr, nullptr);
+        launch_batch_run(b->dev_table, b->dev_item_begin, n_events, b->n_items, nsteps,
+                         b->persistent_waves, b->max_cap, b->stream, nullptr, nullptr);
         e = hipStreamEndCapture(b->stream, &graph);
         if (e != hipSuccess) return hip_fail(e, "graph capture end");
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -672,8 +684,9 @@ int cuba_batch_step(cuba_batch *b, int32_t nsteps) {
       const hipError_t e = hipGraphLaunch(it->second, b->stream);
       if (e != hipSuccess) return hip_fail(e, "graph launch");
     } else {
-      launch_batch_run(b->dev_table, n_events, b->n_items, nsteps, b->persistent_waves,
-                       b->stream, b->timing ? batch_between : nullptr, b);
+      launch_batch_run(b->dev_table, b->dev_item_begin, n_events, b->n_items, nsteps,
+                       b->persistent_waves, b->max_cap, b->stream,
+                       b->timing ? batch_between : nullptr, b);
       const int rc = check_launch("batch run launch");
       if (rc != CUBA_OK) return rc;
     }

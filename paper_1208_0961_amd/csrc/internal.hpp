@@ -11,6 +11,7 @@
 namespace cuba {
 
 constexpr uint32_t kCellCap = 1024;  // = CUBA_MAX_CELL_OCCUPANCY
+constexpr uint32_t kSmallCap = 512;  // cell kernels with half the LDS
 constexpr uint32_t kScanTile = 2048; // counts per scan tile
 
 // Device-side error bits, accumulated until the next cuba_sync.
@@ -94,15 +95,16 @@ void launch_step(const Cells &src, const Cells &dst, bool fused, int64_t n_cells
 void launch_observe(const Cells &cur, const Geometry &g, double vol, double *cell_sums,
                     double *T00, double *T0x, hipStream_t s);
 // A run of k >= 1 steps of every event in the device table ev (n_events
-// live events, n_items work items): stream + bin, k - 1 fused steps, the
-// last collisions, then the table advance.  persistent_waves > 0 caps the
+// live events, n_items work items; item_begin[e] = ev[e].item_begin): stream + bin, k - 1 fused steps, the
+// last collisions, then the table advance.  max_cap: the largest cell
+// capacity among the events (selects the LDS size).  persistent_waves > 0 caps the
 // step grid (persistent waves taking items with a grid stride).  between
 // (may be NULL) is called before each launch with the kind of launch that
 // follows (0 stream-bin, 1 fused step, 2 collide) and with -1 after the last
 // one: a hook for stage timing.
-void launch_batch_run(BatchEvent *ev, uint32_t n_events, uint32_t n_items, int32_t k,
-                      uint32_t persistent_waves, hipStream_t s,
-                      void (*between)(void *, int), void *ctx);
+void launch_batch_run(BatchEvent *ev, const uint32_t *item_begin, uint32_t n_events,
+                      uint32_t n_items, int32_t k, uint32_t persistent_waves, uint32_t max_cap,
+                      hipStream_t s, void (*between)(void *, int), void *ctx);
 void launch_gather_by_id(const Cells &cur, int64_t n_cells, double *x, double *y,
                          double *z, double *px, double *py, double *pz, hipStream_t s);
 

@@ -29,7 +29,6 @@ namespace cuba {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr uint32_t kFiltCap = 512;  // filtered pairs held before resolving
 constexpr uint32_t kCellsPerBlock = kBlock / 64;
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
@@ -306,25 +305,27 @@ __device__ __forceinline__ void resolve_filtered(
 // order is built; after that its first half holds the filtered pairs and its
 // second half the claimed pairs.  s_mark flags (by storage index) the
 // particles whose scattering already binned them (fused steps only).
-template <bool kFused>
+template <bool kFused, uint32_t kCap>
 struct CellLds {
-  __align__(16) uint32_t buf[kCellCap];
-  uint16_t perm[kCellCap];
-  uint8_t mark[kFused ? kCellCap : 1];
+  __align__(16) uint32_t buf[kCap];
+  uint16_t perm[kCap];
+  uint8_t mark[kFused ? kCap : 1];
 };
 
 // Collisions of cell c of src at step t (one wave).  kFused: afterwards
 // stream and bin the cell's particles into dst for step t+1 and clear src's
 // count.  Starts with a barrier, so a wave may call it for several cells.
-template <bool kFused, bool kTrace>
+template <bool kFused, bool kTrace, uint32_t kCap>
 __device__ __forceinline__ void cell_step(const Cells &src, const Cells &dst, uint32_t c,
                                           uint32_t t, const PairArgs &pa,
                                           const Geometry &g, DevStatus *status,
-                                          const TraceArgs &tr, CellLds<kFused> &lds) {
-  static_assert(kFiltCap + kCellCap / 2 <= kCellCap, "LDS aliasing");
+                                          const TraceArgs &tr, CellLds<kFused, kCap> &lds) {
+  // filtered pairs and claimed pairs share the id buffer, kCap / 2 each
+  constexpr uint32_t kFilt = kCap / 2;
+  static_assert(kCap <= kCellCap && kFilt >= 256, "cell capacity");
   uint32_t *const s_id = lds.buf;
   uint32_t *const s_filt = lds.buf;
-  uint32_t *const s_claim = lds.buf + kFiltCap;
+  uint32_t *const s_claim = lds.buf + kFilt;
   uint16_t *const s_perm = lds.perm;
   uint8_t *const s_mark = lds.mark;
   __syncthreads();
@@ -383,7 +384,7 @@ __device__ __forceinline__ void cell_step(const Cells &src, const Cells &dst, ui
           nf += (uint32_t)__popcll(ma);
           if (pass_b) s_filt[nf + (uint32_t)__popcll(mb & below)] = kb;
           nf += (uint32_t)__popcll(mb);
-          if (nf > kFiltCap - 128u) {
+          if (nf > kFilt - 128u) {
             resolve_filtered<kTrace>(nf, cv, pa, st, s_perm, s_filt, s_claim, nclaim,
                                      claimed_bits, n_acc, tr, status);
             nf = 0;
@@ -398,7 +399,7 @@ __device__ __forceinline__ void cell_step(const Cells &src, const Cells &dst, ui
         if (m != 0) {
           if (pass) s_filt[nf + (uint32_t)__popcll(m & below)] = k;
           nf += (uint32_t)__popcll(m);
-          if (nf > kFiltCap - 64u) {
+          if (nf > kFilt - 64u) {
             resolve_filtered<kTrace>(nf, cv, pa, st, s_perm, s_filt, s_claim, nclaim,
                                      claimed_bits, n_acc, tr, status);
             nf = 0;
@@ -521,13 +522,13 @@ __device__ __forceinline__ void cell_step(const Cells &src, const Cells &dst, ui
   }
 }
 
-template <bool kFused, bool kTrace>
+template <bool kFused, bool kTrace, uint32_t kCap>
 __global__ __launch_bounds__(64) void k_step(Cells src, Cells dst, uint32_t t,
                                              PairArgs pa, Geometry g,
                                              DevStatus *status, TraceArgs tr) {
-  __shared__ CellLds<kFused> lds;
-  cell_step<kFused, kTrace>(src, dst, xcd_runs<8>(blockIdx.x, gridDim.x), t, pa, g,
-                            status, tr, lds);
+  __shared__ CellLds<kFused, kCap> lds;
+  cell_step<kFused, kTrace, kCap>(src, dst, xcd_runs<8>(blockIdx.x, gridDim.x), t, pa, g,
+                                  status, tr, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -539,48 +540,73 @@ __global__ __launch_bounds__(64) void k_step(Cells src, Cells dst, uint32_t t,
 // reads buffer cur ^ (j & 1) of each event and uses step index t + j - 1;
 // the run ends with k_batch_advance.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t find_event(const BatchEvent *ev, uint32_t n_events,
-                                               uint32_t item) {
-  uint32_t lo = 0, hi = n_events;  // ev[lo].item_begin <= item < ev[hi].item_begin
+// item_begin[e] is the first work item of event e (ascending, n_events
+// entries); a compact array, so the search stays in one or two cache lines.
+__device__ __forceinline__ uint32_t find_event(const uint32_t *__restrict__ item_begin,
+                                               uint32_t n_events, uint32_t item) {
+  uint32_t lo = 0, hi = n_events;  // item_begin[lo] <= item < item_begin[hi]
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) / 2;
-    if (ev[mid].item_begin <= item) lo = mid;
+    if (item_begin[mid] <= item) lo = mid;
     else hi = mid;
   }
   return lo;
 }
 
-__global__ __launch_bounds__(kBlock) void k_batch_bin(const BatchEvent *ev,
+// The event's descriptor is copied into registers once per work item: the
+// kernels store to global memory, so fields read through the table would
+// have to be reloaded after every store.
+__global__ __launch_bounds__(kBlock) void k_batch_bin(const BatchEvent *__restrict__ ev,
+                                                      const uint32_t *__restrict__ item_begin,
                                                       uint32_t n_events, uint32_t n_items) {
   const uint32_t w = threadIdx.x / 64;
   for (uint32_t item = blockIdx.x * kCellsPerBlock + w; item < n_items;
        item += gridDim.x * kCellsPerBlock) {
-    const uint32_t e = find_event(ev, n_events, item);
-    const BatchEvent &E = ev[e];
-    const uint32_t c0 = (item - E.item_begin) * E.cpi;
-    const uint32_t c1 = c0 + E.cpi < E.n_cells ? c0 + E.cpi : E.n_cells;
-    for (uint32_t c = c0; c < c1; ++c)
-      cell_stream_bin(E.buf[E.cur], E.buf[E.cur ^ 1u], c, E.g, E.status, nullptr);
+    const BatchEvent *__restrict__ E = ev + find_event(item_begin, n_events, item);
+    Cells src, dst;
+    if (E->cur == 0u) {
+      src = E->buf[0];
+      dst = E->buf[1];
+    } else {
+      src = E->buf[1];
+      dst = E->buf[0];
+    }
+    const Geometry g = E->g;
+    DevStatus *const status = E->status;
+    const uint32_t cpi = E->cpi, n_cells = E->n_cells;
+    const uint32_t c0 = (item - E->item_begin) * cpi;
+    const uint32_t c1 = c0 + cpi < n_cells ? c0 + cpi : n_cells;
+    for (uint32_t c = c0; c < c1; ++c) cell_stream_bin(src, dst, c, g, status, nullptr);
   }
 }
 
-template <bool kFused>
-__global__ __launch_bounds__(64) void k_batch_step(const BatchEvent *ev,
+template <bool kFused, uint32_t kCap>
+__global__ __launch_bounds__(64) void k_batch_step(const BatchEvent *__restrict__ ev,
+                                                   const uint32_t *__restrict__ item_begin,
                                                    uint32_t n_events, uint32_t n_items,
                                                    uint32_t j) {
-  __shared__ CellLds<kFused> lds;
+  __shared__ CellLds<kFused, kCap> lds;
   const uint32_t first = gridDim.x < n_items ? blockIdx.x
                                              : xcd_runs<8>(blockIdx.x, gridDim.x);
   for (uint32_t item = first; item < n_items; item += gridDim.x) {
-    const uint32_t e = find_event(ev, n_events, item);
-    const BatchEvent &E = ev[e];
-    const uint32_t p = E.cur ^ (j & 1u);
-    const uint32_t t = E.t + j - 1u;
-    const uint32_t c0 = (item - E.item_begin) * E.cpi;
-    const uint32_t c1 = c0 + E.cpi < E.n_cells ? c0 + E.cpi : E.n_cells;
+    const BatchEvent *__restrict__ E = ev + find_event(item_begin, n_events, item);
+    Cells src, dst;
+    if ((E->cur ^ (j & 1u)) == 0u) {
+      src = E->buf[0];
+      dst = E->buf[1];
+    } else {
+      src = E->buf[1];
+      dst = E->buf[0];
+    }
+    const Geometry g = E->g;
+    const PairArgs pa = E->pa;
+    DevStatus *const status = E->status;
+    const uint32_t t = E->t + j - 1u;
+    const uint32_t cpi = E->cpi, n_cells = E->n_cells;
+    const uint32_t c0 = (item - E->item_begin) * cpi;
+    const uint32_t c1 = c0 + cpi < n_cells ? c0 + cpi : n_cells;
     for (uint32_t c = c0; c < c1; ++c)
-      cell_step<kFused, false>(E.buf[p], E.buf[p ^ 1u], c, t, E.pa, E.g, E.status,
-                               TraceArgs{}, lds);
+      cell_step<kFused, false, kCap>(src, dst, c, t, pa, g, status, TraceArgs{}, lds);
   }
 }
 
@@ -723,15 +749,28 @@ void launch_step(const Cells &src, const Cells &dst, bool fused, int64_t n_cells
                  const TraceArgs *trace, hipStream_t s) {
   if (n_cells <= 0) return;
   const dim3 grid((unsigned)n_cells), block(64);
+  // cells of at most 512 slots use the kernels with half the LDS
+  if (src.cap <= kSmallCap) {
+    if (trace)
+      hipLaunchKernelGGL((k_step<false, true, kSmallCap>), grid, block, 0, s, src, dst, t,
+                         pa, g, status, *trace);
+    else if (fused)
+      hipLaunchKernelGGL((k_step<true, false, kSmallCap>), grid, block, 0, s, src, dst, t,
+                         pa, g, status, TraceArgs{});
+    else
+      hipLaunchKernelGGL((k_step<false, false, kSmallCap>), grid, block, 0, s, src, dst, t,
+                         pa, g, status, TraceArgs{});
+    return;
+  }
   if (trace)
-    hipLaunchKernelGGL((k_step<false, true>), grid, block, 0, s, src, dst, t, pa, g,
-                       status, *trace);
+    hipLaunchKernelGGL((k_step<false, true, kCellCap>), grid, block, 0, s, src, dst, t, pa,
+                       g, status, *trace);
   else if (fused)
-    hipLaunchKernelGGL((k_step<true, false>), grid, block, 0, s, src, dst, t, pa, g,
-                       status, TraceArgs{});
+    hipLaunchKernelGGL((k_step<true, false, kCellCap>), grid, block, 0, s, src, dst, t, pa,
+                       g, status, TraceArgs{});
   else
-    hipLaunchKernelGGL((k_step<false, false>), grid, block, 0, s, src, dst, t, pa, g,
-                       status, TraceArgs{});
+    hipLaunchKernelGGL((k_step<false, false, kCellCap>), grid, block, 0, s, src, dst, t, pa,
+                       g, status, TraceArgs{});
 }
 
 void launch_observe(const Cells &cur, const Geometry &g, double vol, double *cell_sums,
@@ -744,9 +783,9 @@ void launch_observe(const Cells &cur, const Geometry &g, double vol, double *cel
                      T0x);
 }
 
-void launch_batch_run(BatchEvent *ev, uint32_t n_events, uint32_t n_items, int32_t k,
-                      uint32_t persistent_waves, hipStream_t s,
-                      void (*between)(void *, int), void *ctx) {
+void launch_batch_run(BatchEvent *ev, const uint32_t *item_begin, uint32_t n_events,
+                      uint32_t n_items, int32_t k, uint32_t persistent_waves, uint32_t max_cap,
+                      hipStream_t s, void (*between)(void *, int), void *ctx) {
   if (n_events == 0 || n_items == 0 || k <= 0) return;
   const uint32_t step_grid =
       persistent_waves > 0 && persistent_waves < n_items ? persistent_waves : n_items;
@@ -754,15 +793,24 @@ void launch_batch_run(BatchEvent *ev, uint32_t n_events, uint32_t n_items, int32
   const uint32_t bin_grid = (bin_waves + kCellsPerBlock - 1) / kCellsPerBlock;
   if (between) between(ctx, 0);
   hipLaunchKernelGGL(k_batch_bin, dim3(bin_grid), dim3(kBlock), 0, s,
-                     (const BatchEvent *)ev, n_events, n_items);
+                     (const BatchEvent *)ev, item_begin, n_events, n_items);
+  const bool small = max_cap <= kSmallCap;
   for (int32_t j = 1; j < k; ++j) {
     if (between) between(ctx, 1);
-    hipLaunchKernelGGL((k_batch_step<true>), dim3(step_grid), dim3(64), 0, s,
-                       (const BatchEvent *)ev, n_events, n_items, (uint32_t)j);
+    if (small)
+      hipLaunchKernelGGL((k_batch_step<true, kSmallCap>), dim3(step_grid), dim3(64), 0, s,
+                         (const BatchEvent *)ev, item_begin, n_events, n_items, (uint32_t)j);
+    else
+      hipLaunchKernelGGL((k_batch_step<true, kCellCap>), dim3(step_grid), dim3(64), 0, s,
+                         (const BatchEvent *)ev, item_begin, n_events, n_items, (uint32_t)j);
   }
   if (between) between(ctx, 2);
-  hipLaunchKernelGGL((k_batch_step<false>), dim3(step_grid), dim3(64), 0, s,
-                     (const BatchEvent *)ev, n_events, n_items, (uint32_t)k);
+  if (small)
+    hipLaunchKernelGGL((k_batch_step<false, kSmallCap>), dim3(step_grid), dim3(64), 0, s,
+                       (const BatchEvent *)ev, item_begin, n_events, n_items, (uint32_t)k);
+  else
+    hipLaunchKernelGGL((k_batch_step<false, kCellCap>), dim3(step_grid), dim3(64), 0, s,
+                       (const BatchEvent *)ev, item_begin, n_events, n_items, (uint32_t)k);
   if (between) between(ctx, -1);
   hipLaunchKernelGGL(k_batch_advance, dim3((n_events + 63) / 64), dim3(64), 0, s, ev,
                      n_events, (uint32_t)k);
