@@ -1,7 +1,8 @@
 """Benchmark of the PIC Boltzmann step (arXiv:1208.0961) on one MI355X.
 
 A step is the whole per-time-step update: streaming, wall reflection,
-binning (count, scan, scatter), the pair tests with claims and kinematics,
+binning (slot atomics into fixed-capacity cells), the pair tests with
+claims and kinematics,
 and the T00/T0x profiles every 50 steps.  The default workload is the 3-D
 binned Riemann tube: 10 x 2 x 2 fm, 100 x 10 x 10 cells, r_test = 2500,
 1 020 851 test particles, sigma = 0.4 fm^2, dt = 0.02 fm/c, FP64.  Inputs
@@ -56,6 +57,9 @@ def parse():
                     help="batch: ignore a stored tuning table")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batch: skip the one-at-a-time comparison")
+    ap.add_argument("--lanes", type=int, default=None, choices=[0, 8, 16, 32, 64],
+                    help="plain workloads: lanes per cell of the cell kernels "
+                         "(default: the library's choice from the mean occupancy)")
     ap.add_argument("--cpu-steps", type=int, default=None,
                     help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--cpu-threads", type=int, default=None)
@@ -255,9 +259,10 @@ def main():
         return serve.bench(a)
     w = W.ALIASES[a.workload]
     state = W.riemann_state(w)
-    sim = S.Sim(w.params(), state)
-    print(f"# {w.name}: {w.n} particles, {w.n_cells} cells; warmup {a.warmup}",
-          file=sys.stderr, flush=True)
+    sim = S.Sim(w.params(), state, cell_lanes=a.lanes)
+    lanes = sim.cell_lanes
+    print(f"# {w.name}: {w.n} particles, {w.n_cells} cells, {lanes} lanes per "
+          f"cell; warmup {a.warmup}", file=sys.stderr, flush=True)
     sim.step(a.warmup)
     sim.sync()
     c0 = C.cuba_counters(sim.ctx)
@@ -338,7 +343,8 @@ def main():
         "data": "synthetic: seeded thermal Riemann gas (T 0.40 / 0.32 GeV), no dataset",
         "config": {"workload": w.name, "n_particles": w.n, "cells": list(w.cells),
                    "box_fm": list(w.box), "r_test": w.r_test, "sigma_fm2": w.sigma,
-                   "dt_fm": w.dt, "observe_every": w.observe_every},
+                   "dt_fm": w.dt, "observe_every": w.observe_every,
+                   "cell_lanes": lanes},
         "pair_tests_per_s": pairs / elapsed,
         "candidates_per_step": cand / a.steps,
         "scatterings_per_step": claims / a.steps,

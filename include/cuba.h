@@ -159,6 +159,18 @@ int cuba_trace_step(cuba_ctx *ctx, const cuba_trace *trace);
  * since the last cuba_sync (CUBA_ERANGE, CUBA_ENOMEM) or CUBA_EDEVICE. */
 int cuba_sync(cuba_ctx *ctx);
 
+/* Lanes per cell of the collision and binning kernels (a launch shape; the
+ * results are bit-identical for every setting).  0: one wave64 per cell,
+ * whatever its occupancy.  8, 16, 32 or 64: each wave takes 64 / lanes
+ * consecutive cells with one particle per lane, which serves sparse cells
+ * without a mostly idle wave each; cells holding more particles than lanes
+ * are then stepped by the whole wave, in a second launch.  cuba_init
+ * chooses from the mean occupancy n / cells: 8 up to 4, 16 up to 11, 32 up
+ * to 24, else 0.  Errors: CUBA_EINVAL for NULL or any other value.  For an event in
+ * a batch use cuba_batch_set_cell_lanes. */
+int cuba_set_cell_lanes(cuba_ctx *ctx, int32_t lanes);
+int cuba_get_cell_lanes(const cuba_ctx *ctx, int32_t *lanes);
+
 /* Index of the next step, number of particles, number of cells. */
 int cuba_info(const cuba_ctx *ctx, uint32_t *next_step, int64_t *n,
               int64_t *n_cells);
@@ -228,14 +240,20 @@ int cuba_batch_retire(cuba_batch *b, int32_t slot);
 /* The context of an occupied slot, or NULL.  Owned by the batch. */
 cuba_ctx *cuba_batch_slot(cuba_batch *b, int32_t slot);
 
-/* Cells per work item of a slot's event (default: about 64 particles per
- * item, at most 64 cells); set by the autotuner. */
+/* Cells per binning work item of a slot's event (default: about 64
+ * particles per item, at most 64 cells; 64 cells for events with lanes per
+ * cell > 0); set by the autotuner.  The collision kernels take fixed units:
+ * a cell per wave, or 64 / lanes cells per wave with lanes per cell > 0. */
 int cuba_batch_set_cells_per_item(cuba_batch *b, int32_t slot, int32_t cells);
 
-/* Launch shape: persistent_waves > 0 runs the step kernels on that many
- * persistent waves taking work items with a grid stride (0: one workgroup
- * per item); use_graphs != 0 captures each run of n steps as a hipGraph
- * (cached per n, rebuilt after admissions and retirements). */
+/* Lanes per cell of a slot's event (as cuba_set_cell_lanes; the default is
+ * cuba_init's choice); set by the autotuner. */
+int cuba_batch_set_cell_lanes(cuba_batch *b, int32_t slot, int32_t lanes);
+
+/* Launch shape: persistent_waves > 0 runs the binning kernel on that many
+ * persistent waves taking work items with a grid stride (0: one wave per
+ * item); use_graphs != 0 captures each run of n steps as a hipGraph (cached
+ * per n, rebuilt after admissions, retirements and setting changes). */
 int cuba_batch_set_launch(cuba_batch *b, int32_t persistent_waves,
                           int32_t use_graphs);
 

@@ -85,6 +85,12 @@ class Batch:
     def set_cells_per_item(self, slot: int, cells: int) -> None:
         C.cuba_batch_set_cells_per_item(self.b, slot, cells)
 
+    def set_cell_lanes(self, slot: int, lanes: int) -> None:
+        C.cuba_batch_set_cell_lanes(self.b, slot, lanes)
+
+    def cell_lanes(self, slot: int) -> int:
+        return C.cuba_get_cell_lanes(self.ctx(slot))
+
     def set_launch(self, persistent_waves: int = 0, use_graphs: bool = False) -> None:
         C.cuba_batch_set_launch(self.b, persistent_waves, use_graphs)
 

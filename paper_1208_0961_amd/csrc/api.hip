@@ -112,6 +112,17 @@ int derive(const cuba_params *p, Derived &d) {
   return CUBA_OK;
 }
 
+// Lanes per cell from the mean occupancy: small-cell groups while a group
+// of that many lanes holds the typical cell with room for its fluctuations,
+// one wave per cell beyond.
+uint32_t default_lanes(int64_t n, int64_t n_cells) {
+  const double mean = n_cells > 0 ? (double)n / (double)n_cells : 0.0;
+  if (mean <= 4.0) return 8;
+  if (mean <= 11.0) return 16;
+  if (mean <= 24.0) return 32;
+  return 0;
+}
+
 // Pairs can only be accepted when the Philox high word w1 is below this:
 // u >= w1 2^-32 and P22 <= 2 K (1 + 13 eps) < 2 K (1 + 2^-30).
 uint64_t w1_limit(double kfac) {
@@ -134,6 +145,7 @@ struct cuba_ctx {
   PairArgs pa;
   int64_t n;
   uint32_t next_step;
+  uint32_t lanes;  // lanes per cell of the cell kernels (valid_cell_lanes)
   hipStream_t stream;
   DevStatus *status;
   Cells buf[2];
@@ -187,13 +199,15 @@ void drop_timing(cuba_ctx *c) {
 int run_steps(cuba_ctx *c, int32_t nsteps, const TraceArgs *trace_in) {
   if (nsteps <= 0) return CUBA_OK;
   stage(c, kStageBin, [&] {
-    launch_stream_bin(c->buf[c->cur], c->buf[c->cur ^ 1], c->d.n_cells, c->d.g, c->status,
+    launch_stream_bin(c->buf[c->cur], c->buf[c->cur ^ 1], c->d.n_cells, c->lanes, c->d.g,
+                      c->status,
                       trace_in ? trace_in->cell : nullptr, c->stream);
   });
   c->cur ^= 1;
   for (int32_t s = 1; s < nsteps; ++s) {
     stage(c, kStageStep, [&] {
-      launch_step(c->buf[c->cur], c->buf[c->cur ^ 1], true, c->d.n_cells, c->next_step,
+      launch_step(c->buf[c->cur], c->buf[c->cur ^ 1], true, c->d.n_cells, c->lanes,
+                  c->next_step,
                   c->pa, c->d.g, c->status, nullptr, c->stream);
     });
     c->cur ^= 1;
@@ -208,7 +222,8 @@ int run_steps(cuba_ctx *c, int32_t nsteps, const TraceArgs *trace_in) {
     });
   }
   stage(c, kStageCollide, [&] {
-    launch_step(c->buf[c->cur], c->buf[c->cur ^ 1], false, c->d.n_cells, c->next_step,
+    launch_step(c->buf[c->cur], c->buf[c->cur ^ 1], false, c->d.n_cells, c->lanes,
+                c->next_step,
                 c->pa, c->d.g, c->status, trace_in ? &tr : nullptr, c->stream);
   });
   c->next_step += 1;
@@ -255,6 +270,7 @@ int cuba_init(cuba_ctx **out, const cuba_params *params, int64_t n, const double
   c->pa.key1 = (uint32_t)(params->seed >> 32);
   c->n = n;
   c->next_step = params->step0;
+  c->lanes = default_lanes(n, d.n_cells);
   c->stream = (hipStream_t)stream;
   char *ws = (char *)workspace;
   c->status = (DevStatus *)(ws + L.status);
@@ -305,6 +321,19 @@ int cuba_init(cuba_ctx **out, const cuba_params *params, int64_t n, const double
                                  std::to_string(d.cap) + ")");
   }
   *out = c;
+  return CUBA_OK;
+}
+
+int cuba_set_cell_lanes(cuba_ctx *c, int32_t lanes) {
+  if (!c) return fail(CUBA_EINVAL, "ctx is NULL");
+  if (!valid_cell_lanes(lanes)) return fail(CUBA_EINVAL, "lanes must be 0, 8, 16, 32 or 64");
+  c->lanes = (uint32_t)lanes;
+  return CUBA_OK;
+}
+
+int cuba_get_cell_lanes(const cuba_ctx *c, int32_t *lanes) {
+  if (!c || !lanes) return fail(CUBA_EINVAL, "NULL argument");
+  *lanes = (int32_t)c->lanes;
   return CUBA_OK;
 }
 
@@ -467,11 +496,11 @@ struct cuba_batch {
   int32_t max_slots = 0;
   hipStream_t stream = nullptr;
   BatchEvent *dev_table = nullptr;  // in the caller's batch workspace
-  uint32_t *dev_item_begin = nullptr;
+  uint32_t *dev_begin = nullptr;  // 4 x max_slots: first unit per event of each work space
   std::vector<cuba_ctx *> slot_ctx;
   std::vector<int32_t> slot_cpi;
   std::vector<int32_t> table_slots;  // slots in table order
-  uint32_t n_items = 0;
+  BatchSpaces spaces{};  // unit counts of the work spaces (device begins in dev_begin)
   uint32_t max_cap = 0;
   bool dirty = true;
   uint32_t persistent_waves = 0;
@@ -500,9 +529,11 @@ void drop_batch_timing(cuba_batch *b) {
   b->timing_cap = 0;
 }
 
-// Default cells per work item: enough cells that an item holds about 64
-// particles (a full wave), at most 64 cells.
+// Default cells per binning item: enough cells that an item holds about 64
+// particles (a full wave), at most 64 cells; events with lanes per cell > 0
+// bin 64 cells per item (in groups of 64 / lanes cells).
 int32_t default_cpi(const cuba_ctx *c) {
+  if (c->lanes > 0) return 64;
   const double mean = c->d.n_cells > 0 ? (double)c->n / (double)c->d.n_cells : 0.0;
   int32_t cpi = mean > 0.0 ? (int32_t)(64.0 / mean) : 64;
   if (cpi < 1) cpi = 1;
@@ -510,11 +541,12 @@ int32_t default_cpi(const cuba_ctx *c) {
   return cpi;
 }
 
-// Rebuilds the device table from the live slots (in slot order).
+// Rebuilds the device table and the work spaces from the live slots (in
+// slot order).
 int upload_table(cuba_batch *b) {
   std::vector<BatchEvent> host;
   b->table_slots.clear();
-  uint32_t items = 0;
+  uint64_t items = 0, chunks = 0, scans = 0, cells = 0;
   b->max_cap = 0;
   for (int32_t s = 0; s < b->max_slots; ++s) {
     cuba_ctx *c = b->slot_ctx[s];
@@ -527,24 +559,50 @@ int upload_table(cuba_batch *b) {
     e.status = c->status;
     e.n_cells = (uint32_t)c->d.n_cells;
     e.cpi = (uint32_t)b->slot_cpi[s];
-    e.item_begin = items;
     e.cur = (uint32_t)c->cur;
     e.t = c->next_step;
-    const uint64_t ni = (e.n_cells + e.cpi - 1) / e.cpi;
-    if (items + ni >= 0xFFFFFFFFull) return fail(CUBA_EINVAL, "too many work items");
-    items += (uint32_t)ni;
+    e.lanes = c->lanes;
+    e.item_begin = (uint32_t)items;
+    e.chunk_begin = (uint32_t)chunks;
+    e.scan_begin = (uint32_t)scans;
+    e.cell_begin = (uint32_t)cells;
+    items += (e.n_cells + e.cpi - 1) / e.cpi;
+    if (c->lanes > 0) {
+      const uint64_t per = 64 / c->lanes;
+      chunks += (e.n_cells + per - 1) / per;
+      scans += (e.n_cells + 63) / 64;
+    } else {
+      cells += e.n_cells;
+    }
+    // grid sizes stay below 2^31 workgroups
+    if (items >= 0x80000000ull || chunks >= 0x80000000ull || cells >= 0x80000000ull)
+      return fail(CUBA_EINVAL, "too many cells in the batch for one launch");
     if (c->d.cap > b->max_cap) b->max_cap = c->d.cap;
     host.push_back(e);
     b->table_slots.push_back(s);
   }
-  b->n_items = items;
-  if (!host.empty()) {
-    std::vector<uint32_t> begins(host.size());
-    for (size_t i = 0; i < host.size(); ++i) begins[i] = host[i].item_begin;
-    hipError_t e = hipMemcpyAsync(b->dev_table, host.data(), host.size() * sizeof(BatchEvent),
+  const size_t ne = host.size();
+  const size_t stride = (size_t)b->max_slots;
+  b->spaces.item_begin = b->dev_begin;
+  b->spaces.chunk_begin = b->dev_begin + stride;
+  b->spaces.scan_begin = b->dev_begin + 2 * stride;
+  b->spaces.cell_begin = b->dev_begin + 3 * stride;
+  b->spaces.n_items = (uint32_t)items;
+  b->spaces.n_chunks = (uint32_t)chunks;
+  b->spaces.n_scans = (uint32_t)scans;
+  b->spaces.n_cells = (uint32_t)cells;
+  if (ne > 0) {
+    std::vector<uint32_t> begins(4 * stride, 0u);
+    for (size_t i = 0; i < ne; ++i) {
+      begins[i] = host[i].item_begin;
+      begins[stride + i] = host[i].chunk_begin;
+      begins[2 * stride + i] = host[i].scan_begin;
+      begins[3 * stride + i] = host[i].cell_begin;
+    }
+    hipError_t e = hipMemcpyAsync(b->dev_table, host.data(), ne * sizeof(BatchEvent),
                                   hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(b->dev_item_begin, begins.data(), begins.size() * sizeof(uint32_t),
+      e = hipMemcpyAsync(b->dev_begin, begins.data(), begins.size() * sizeof(uint32_t),
                          hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return hip_fail(e, "batch table upload");
@@ -577,7 +635,7 @@ extern "C" {
 size_t cuba_batch_workspace_bytes(int32_t max_slots) {
   if (max_slots < 1) return 0;
   return align256((size_t)max_slots * sizeof(BatchEvent)) +
-         align256((size_t)max_slots * sizeof(uint32_t));
+         align256(4 * (size_t)max_slots * sizeof(uint32_t));
 }
 
 int cuba_batch_create(cuba_batch **out, int32_t max_slots, void *workspace,
@@ -594,7 +652,7 @@ int cuba_batch_create(cuba_batch **out, int32_t max_slots, void *workspace,
   b->max_slots = max_slots;
   b->stream = (hipStream_t)stream;
   b->dev_table = (BatchEvent *)workspace;
-  b->dev_item_begin =
+  b->dev_begin =
       (uint32_t *)((char *)workspace + align256((size_t)max_slots * sizeof(BatchEvent)));
   b->slot_ctx.assign(max_slots, nullptr);
   b->slot_cpi.assign(max_slots, 1);
@@ -645,6 +703,15 @@ int cuba_batch_set_cells_per_item(cuba_batch *b, int32_t slot, int32_t cells) {
   return CUBA_OK;
 }
 
+int cuba_batch_set_cell_lanes(cuba_batch *b, int32_t slot, int32_t lanes) {
+  if (!b || slot < 0 || slot >= b->max_slots || !b->slot_ctx[slot])
+    return fail(CUBA_EINVAL, "slot is not occupied");
+  if (!valid_cell_lanes(lanes)) return fail(CUBA_EINVAL, "lanes must be 0, 8, 16, 32 or 64");
+  b->slot_ctx[slot]->lanes = (uint32_t)lanes;
+  b->dirty = true;
+  return CUBA_OK;
+}
+
 int cuba_batch_set_launch(cuba_batch *b, int32_t persistent_waves, int32_t use_graphs) {
   if (!b || persistent_waves < 0) return fail(CUBA_EINVAL, "bad launch settings");
   if (use_graphs && b->stream == nullptr)
@@ -672,8 +739,8 @@ int cuba_batch_step(cuba_batch *b, int32_t nsteps) {
         hipGraphExec_t exec = nullptr;
         hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "graph capture begin");
-        launch_batch_run(b->dev_table, b->dev_item_begin, n_events, b->n_items, nsteps,
-                         b->persistent_waves, b->max_cap, b->stream, nullptr, nullptr);
+        launch_batch_run(b->dev_table, b->spaces, n_events, nsteps, b->persistent_waves,
+                         b->max_cap, b->stream, nullptr, nullptr);
         e = hipStreamEndCapture(b->stream, &graph);
         if (e != hipSuccess) return hip_fail(e, "graph capture end");
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -684,9 +751,8 @@ int cuba_batch_step(cuba_batch *b, int32_t nsteps) {
       const hipError_t e = hipGraphLaunch(it->second, b->stream);
       if (e != hipSuccess) return hip_fail(e, "graph launch");
     } else {
-      launch_batch_run(b->dev_table, b->dev_item_begin, n_events, b->n_items, nsteps,
-                       b->persistent_waves, b->max_cap, b->stream,
-                       b->timing ? batch_between : nullptr, b);
+      launch_batch_run(b->dev_table, b->spaces, n_events, nsteps, b->persistent_waves,
+                       b->max_cap, b->stream, b->timing ? batch_between : nullptr, b);
       const int rc = check_launch("batch run launch");
       if (rc != CUBA_OK) return rc;
     }

@@ -75,8 +75,26 @@ struct BatchEvent {
   uint32_t item_begin;  // first work item of this event
   uint32_t cur;         // buffer holding the state at the start of a run
   uint32_t t;           // step index of the next step
+  uint32_t lanes;       // lanes per cell (0: one wave per cell; 8, 16, 32, 64)
+  uint32_t chunk_begin; // first small-cell chunk (64 / lanes cells), if lanes > 0
+  uint32_t scan_begin;  // first oversize-cell scan unit (64 cells), if lanes > 0
+  uint32_t cell_begin;  // first unit of the one-wave-per-cell space, if lanes = 0
   uint32_t pad[3];
 };
+
+// The work spaces of a batch run (see launch_batch_run): unit counts and,
+// per event in table order, the first unit of each space (device arrays).
+struct BatchSpaces {
+  const uint32_t *item_begin, *chunk_begin, *scan_begin, *cell_begin;
+  uint32_t n_items, n_chunks, n_scans, n_cells;
+};
+
+// Lanes-per-cell settings of the cell kernels: 0 runs one wave per cell;
+// 8, 16, 32 and 64 run 64 / lanes small cells per wave, one particle per
+// lane, and step larger cells with the whole wave.
+inline bool valid_cell_lanes(int32_t v) {
+  return v == 0 || v == 8 || v == 16 || v == 32 || v == 64;
+}
 
 // Launchers (kernels.hip).  All asynchronous on stream s.
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s);
@@ -84,27 +102,30 @@ void launch_init_bin(const double *x, const double *y, const double *z,
                      const double *px, const double *py, const double *pz,
                      const Cells &dst, int64_t n, const Geometry &g, DevStatus *st,
                      hipStream_t s);
-void launch_stream_bin(const Cells &src, const Cells &dst, int64_t n_cells,
+void launch_stream_bin(const Cells &src, const Cells &dst, int64_t n_cells, uint32_t lanes,
                        const Geometry &g, DevStatus *status, uint32_t *trace_cell,
                        hipStream_t s);
 void launch_offsets(const Cells &cur, uint32_t *offsets, uint32_t *tile_sums,
                     int64_t n_cells, hipStream_t s);
 void launch_step(const Cells &src, const Cells &dst, bool fused, int64_t n_cells,
-                 uint32_t t, const PairArgs &pa, const Geometry &g, DevStatus *status,
+                 uint32_t lanes, uint32_t t, const PairArgs &pa, const Geometry &g, DevStatus *status,
                  const TraceArgs *trace, hipStream_t s);
 void launch_observe(const Cells &cur, const Geometry &g, double vol, double *cell_sums,
                     double *T00, double *T0x, hipStream_t s);
 // A run of k >= 1 steps of every event in the device table ev (n_events
-// live events, n_items work items; item_begin[e] = ev[e].item_begin): stream + bin, k - 1 fused steps, the
-// last collisions, then the table advance.  max_cap: the largest cell
-// capacity among the events (selects the LDS size).  persistent_waves > 0 caps the
-// step grid (persistent waves taking items with a grid stride).  between
-// (may be NULL) is called before each launch with the kind of launch that
-// follows (0 stream-bin, 1 fused step, 2 collide) and with -1 after the last
+// live events): stream + bin, k - 1 fused steps, the last collisions, then
+// the table advance.  The work spaces: items of cells_per_item cells for the
+// binning (every event); for events with lanes per cell > 0, small-cell
+// chunks of 64 / lanes cells and scan units of 64 cells for their oversize
+// cells; for events with lanes = 0, one unit per cell.  max_cap: the largest
+// cell capacity among the events (selects the LDS size).  persistent_waves
+// > 0 caps the binning grid (persistent waves taking items with a grid
+// stride).  between (may be NULL) is called before each step of the run with
+// its kind (0 stream-bin, 1 fused step, 2 collide) and with -1 after the last
 // one: a hook for stage timing.
-void launch_batch_run(BatchEvent *ev, const uint32_t *item_begin, uint32_t n_events,
-                      uint32_t n_items, int32_t k, uint32_t persistent_waves, uint32_t max_cap,
-                      hipStream_t s, void (*between)(void *, int), void *ctx);
+void launch_batch_run(BatchEvent *ev, const BatchSpaces &spaces, uint32_t n_events, int32_t k,
+                      uint32_t persistent_waves, uint32_t max_cap, hipStream_t s,
+                      void (*between)(void *, int), void *ctx);
 void launch_gather_by_id(const Cells &cur, int64_t n_cells, double *x, double *y,
                          double *z, double *px, double *py, double *pz, hipStream_t s);
 

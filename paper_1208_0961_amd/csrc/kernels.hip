@@ -22,6 +22,8 @@
 // step, which leaves the state binned and collided (positions of step t+n-1).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace cuba {
@@ -138,16 +140,22 @@ __global__ __launch_bounds__(kBlock) void k_init_bin(
   append(dst, cell, active, a, b, c, qa, qb, qc, (uint32_t)i, status);
 }
 
-// Stream + reflect + bin the particles of source cell c (one wave).  Clears
-// the source count, so the source buffer can receive the next binning.
-__device__ __forceinline__ void cell_stream_bin(const Cells &src, const Cells &dst,
-                                                uint32_t c, const Geometry &g,
-                                                DevStatus *status, uint32_t *trace_cell) {
+// Stream + reflect + bin the particles of the source cells c0 .. c_end - 1
+// (at most 64 / G of them), G lanes per cell; G = 64 is one wave per cell.
+// Clears the source counts, so the source buffer can receive the next
+// binning.
+template <uint32_t G>
+__device__ __forceinline__ void cells_stream_bin(const Cells &src, const Cells &dst,
+                                                 uint32_t c0, uint32_t c_end,
+                                                 const Geometry &g, DevStatus *status,
+                                                 uint32_t *trace_cell) {
   const uint32_t lane = lane_id();
-  const uint32_t n = occupancy(src, c);
+  const uint32_t c = c0 + lane / G, gl = lane % G;
+  const bool in_range = c < c_end;
+  const uint32_t n = in_range ? occupancy(src, c) : 0u;
   const size_t base = (size_t)c * src.cap;
-  for (uint32_t j0 = 0; j0 < n; j0 += 64) {
-    const uint32_t j = j0 + lane;
+  for (uint32_t j0 = 0; __ballot(j0 < n) != 0; j0 += G) {
+    const uint32_t j = j0 + gl;
     const bool active = j < n;
     double x = 0, y = 0, z = 0, px = 0, py = 0, pz = 0;
     uint32_t id = 0, c2 = 0;
@@ -165,18 +173,21 @@ __device__ __forceinline__ void cell_stream_bin(const Cells &src, const Cells &d
     }
     append(dst, c2, active, x, y, z, px, py, pz, id, status);
   }
-  if (lane == 0) src.count[c] = 0u;
+  if (in_range && gl == 0) src.count[c] = 0u;
 }
 
-// One wave per source cell, four cells per block.
+// Four waves per block; each wave takes 64 / G consecutive source cells.
+template <uint32_t G>
 __global__ __launch_bounds__(kBlock) void k_stream_bin(Cells src, Cells dst,
                                                        uint32_t n_cells, Geometry g,
                                                        DevStatus *status,
                                                        uint32_t *trace_cell) {
-  const uint32_t c = xcd_runs<2>(blockIdx.x, gridDim.x) * kCellsPerBlock +
-                     threadIdx.x / 64;
-  if (c >= n_cells) return;
-  cell_stream_bin(src, dst, c, g, status, trace_cell);
+  constexpr uint32_t kPer = 64 / G;
+  const uint32_t c0 =
+      (xcd_runs<2>(blockIdx.x, gridDim.x) * kCellsPerBlock + threadIdx.x / 64) * kPer;
+  if (c0 >= n_cells) return;
+  const uint32_t c_end = c0 + kPer < n_cells ? c0 + kPer : n_cells;
+  cells_stream_bin<G>(src, dst, c0, c_end, g, status, trace_cell);
 }
 
 // Exclusive scan of the counts into compact offsets (trace only; the counts
@@ -522,6 +533,250 @@ __device__ __forceinline__ void cell_step(const Cells &src, const Cells &dst, ui
   }
 }
 
+// ---------------------------------------------------------------------------
+// Small cells: one wave takes 64 / G consecutive cells, G lanes per cell and
+// one particle per lane.  A lane loads its particle once and keeps it in
+// registers through collisions, streaming and binning, so a sparse cell
+// costs one load round trip and one slot atomic instead of a wave of its own
+// with several dependent round trips.
+// ---------------------------------------------------------------------------
+struct SmallLds {
+  __align__(16) uint32_t id[64];  // by lane (the cell's storage order)
+  double x[64], y[64], z[64];     // by lane
+  double px[64], py[64], pz[64];  // by group and canonical rank
+};
+
+template <uint32_t G>
+using ClaimMask = typename std::conditional<(G == 64), uint64_t, uint32_t>::type;
+
+// Collisions of the cells c0 .. c_end - 1 (at most 64 / G) of src at step t.
+// The canonical rank of each particle is counted over its cell's ids in
+// LDS, where the momenta are then stored in canonical order (and the
+// positions by lane, so that no particle state stays live in registers
+// through the pair loop).  Pairs k = gl, gl + G, ... of each cell are tested
+// as in cell_step (Philox w1 filter, then the exact Eq. (3) test in the same
+// lane); a cell's accepted pairs of one round appear in its bits of the
+// wave's ballot in increasing k, so the greedy claim walks those bits in
+// order, with the cell's claimed set kept identically by all its lanes.
+// Both lanes of a claimed pair evaluate its kinematics (same inputs, same
+// code, hence the same result) and keep their own half.  kFused: every lane
+// then streams and bins its particle into dst for step t+1.  Cells holding
+// more than G particles are left alone; the result has bit grp G set for
+// each such cell c0 + grp.
+template <bool kFused, bool kTrace, uint32_t G>
+__device__ __forceinline__ uint64_t small_cells_step(const Cells &src, const Cells &dst,
+                                                     uint32_t c0, uint32_t c_end,
+                                                     uint32_t t, const PairArgs &pa,
+                                                     const Geometry &g, DevStatus *status,
+                                                     const TraceArgs &tr, SmallLds &lds) {
+  static_assert(G == 8 || G == 16 || G == 32 || G == 64, "lanes per cell");
+  constexpr uint32_t kNone = 0xFFFFFFFFu;
+  const uint32_t lane = lane_id();
+  const uint32_t grp = lane / G, gl = lane % G;
+  const uint32_t c = c0 + grp;
+  const bool in_range = c < c_end;
+  const uint32_t n = in_range ? occupancy(src, c) : 0u;
+  const bool small = in_range && n <= G;
+  const bool mine = small && gl < n;
+  const size_t o = (size_t)c * src.cap + gl;
+  __syncthreads();  // a previous call's readers of lds are done
+  {
+    uint32_t id = kNone;  // ids are below 2^32 - 1, so kNone ranks after all
+    if (mine) {
+      lds.x[lane] = src.st.x[o];
+      lds.y[lane] = src.st.y[o];
+      lds.z[lane] = src.st.z[o];
+      id = src.st.id[o];
+    }
+    lds.id[lane] = id;
+  }
+  double qx = 0, qy = 0, qz = 0;
+  if (mine) {
+    qx = src.st.px[o];
+    qy = src.st.py[o];
+    qz = src.st.pz[o];
+  }
+  __syncthreads();
+  uint32_t r = 0;
+  if (mine) {
+    const uint32_t id = lds.id[lane];
+    const uint4 *q4 = reinterpret_cast<const uint4 *>(lds.id + grp * G);
+#pragma unroll
+    for (uint32_t m = 0; m < G / 4; ++m) {
+      const uint4 q = q4[m];
+      r += (q.x < id) + (q.y < id) + (q.z < id) + (q.w < id);
+    }
+    lds.px[grp * G + r] = qx;
+    lds.py[grp * G + r] = qy;
+    lds.pz[grp * G + r] = qz;
+    if (kTrace && tr.perm) tr.perm[tr.offsets[c] + r] = id;
+  }
+  __syncthreads();
+
+  const double *const spx = lds.px + grp * G;
+  const double *const spy = lds.py + grp * G;
+  const double *const spz = lds.pz + grp * G;
+  const uint32_t npairs = small ? n * (n - 1u) / 2u : 0u;
+  ClaimMask<G> claimed = 0;  // the cell's claimed canonical indices
+  uint32_t partner = kNone, kpair = 0, n_acc = 0;
+  if (pa.any) {
+    for (uint32_t k0 = 0; __ballot(k0 < npairs) != 0; k0 += G) {
+      const uint32_t k = k0 + gl;
+      bool acc = false;
+      if (k < npairs && philox10_w1(k, c, t, 0u, pa.key0, pa.key1) <= pa.w1_max) {
+        const Words4 w = philox10(k, c, t, 0u, pa.key0, pa.key1);
+        uint32_t a, b;
+        pair_of_index(k, n, a, b);
+        acc = uniform53(w.w0, w.w1) <
+              p22(spx[a], spy[a], spz[a], spx[b], spy[b], spz[b], pa.kfac);
+        if (kTrace && acc && tr.cand) {
+          const uint32_t slot = atomicAdd(&tr.counts[0], 1u);
+          if (slot < tr.cand_cap) {
+            tr.cand[3 * (size_t)slot + 0] = c;
+            tr.cand[3 * (size_t)slot + 1] = a;
+            tr.cand[3 * (size_t)slot + 2] = b;
+          } else {
+            atomicOr(&status->err, kErrTrace);
+          }
+        }
+      }
+      n_acc += acc ? 1u : 0u;
+      uint64_t seg = __ballot(acc);
+      if (G < 64) seg = (seg >> (grp * G)) & ((1ull << (G % 64)) - 1ull);
+      while (seg != 0) {
+        const uint32_t kk = k0 + (uint32_t)__builtin_ctzll(seg);
+        seg &= seg - 1ull;
+        uint32_t a, b;
+        pair_of_index(kk, n, a, b);
+        const ClaimMask<G> ab = ((ClaimMask<G>)1 << a) | ((ClaimMask<G>)1 << b);
+        if ((claimed & ab) == 0) {
+          claimed |= ab;
+          if (mine && (r == a || r == b)) {
+            partner = r == a ? b : a;
+            kpair = kk;
+          }
+          if (kTrace && tr.claim && gl == 0) {
+            const uint32_t slot = atomicAdd(&tr.counts[1], 1u);
+            if (slot < tr.claim_cap) {
+              tr.claim[3 * (size_t)slot + 0] = c;
+              tr.claim[3 * (size_t)slot + 1] = a;
+              tr.claim[3 * (size_t)slot + 2] = b;
+            } else {
+              atomicOr(&status->err, kErrTrace);
+            }
+          }
+        }
+      }
+    }
+  }
+
+  // work counters of the wave's cells, in one slot
+  const bool scat = partner != kNone;
+  {
+    uint32_t cnt_pairs = small && gl == 0 ? npairs : 0u;
+    uint32_t cnt_claims = scat && r < partner ? 1u : 0u;
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) {
+      cnt_pairs += __shfl_down(cnt_pairs, s);
+      n_acc += __shfl_down(n_acc, s);
+      cnt_claims += __shfl_down(cnt_claims, s);
+    }
+    if (lane == 0 && cnt_pairs != 0) {
+      const uint32_t slot = c0 % kCounterSlots;
+      atomicAdd(&status->pairs[slot], (unsigned long long)cnt_pairs);
+      atomicAdd(&status->cand[slot], (unsigned long long)n_acc);
+      atomicAdd(&status->claims[slot], (unsigned long long)cnt_claims);
+    }
+  }
+
+  double px = 0, py = 0, pz = 0;
+  if (mine) {
+    px = spx[r];
+    py = spy[r];
+    pz = spz[r];
+  }
+  if (scat) {
+    const bool lo = r < partner;
+    const uint32_t a = lo ? r : partner, b = lo ? partner : r;
+    const Words4 w = philox10(kpair, c, t, 1u, pa.key0, pa.key1);
+    double ax = spx[a], ay = spy[a], az = spz[a];
+    double bx = spx[b], by = spy[b], bz = spz[b];
+    scatter_pair(ax, ay, az, bx, by, bz, uniform53(w.w0, w.w1), uniform53(w.w2, w.w3));
+    px = lo ? ax : bx;
+    py = lo ? ay : by;
+    pz = lo ? az : bz;
+    if (!kFused) {
+      src.st.px[o] = px;
+      src.st.py[o] = py;
+      src.st.pz[o] = pz;
+    }
+  }
+
+  if (kFused) {
+    double x = 0, y = 0, z = 0;
+    uint32_t id = 0, c2 = 0;
+    if (mine) {
+      x = lds.x[lane];
+      y = lds.y[lane];
+      z = lds.z[lane];
+      id = lds.id[lane];
+      advance<true>(g, x, y, z, px, py, pz);
+      c2 = cell_id(g, x, y, z);
+    }
+    append(dst, c2, mine, x, y, z, px, py, pz, id, status);
+    if (small && gl == 0) src.count[c] = 0u;
+  }
+  return __ballot(in_range && !small && gl == 0);
+}
+
+// The cells among c0 .. c_end - 1 (at most 64) holding more than `lanes`
+// particles, stepped one after another by the whole wave: the cells that a
+// small-cell launch with that many lanes per cell left alone (lanes = 0:
+// every non-empty cell).  A separate launch, so that each kernel keeps the
+// registers of its own path (the small-cell kernel runs at twice the
+// occupancy of the wave-per-cell code).
+template <bool kFused, bool kTrace, uint32_t kCap>
+__device__ __forceinline__ void large_cells_step(const Cells &src, const Cells &dst,
+                                                 uint32_t c0, uint32_t c_end, uint32_t lanes,
+                                                 uint32_t t, const PairArgs &pa,
+                                                 const Geometry &g, DevStatus *status,
+                                                 const TraceArgs &tr,
+                                                 CellLds<kFused, kCap> &lds) {
+  const uint32_t c = c0 + lane_id();
+  const uint32_t n = c < c_end ? occupancy(src, c) : 0u;
+  uint64_t big = __ballot(n > lanes);
+  while (big != 0) {
+    const uint32_t l = (uint32_t)__builtin_ctzll(big);
+    big &= big - 1ull;
+    cell_step<kFused, kTrace, kCap>(src, dst, c0 + l, t, pa, g, status, tr, lds);
+  }
+}
+
+template <bool kFused, bool kTrace, uint32_t G>
+__global__ __launch_bounds__(64) void k_step_small(Cells src, Cells dst, uint32_t n_cells,
+                                                   uint32_t t, PairArgs pa, Geometry g,
+                                                   DevStatus *status, TraceArgs tr) {
+  __shared__ SmallLds lds;
+  constexpr uint32_t kPer = 64 / G;
+  const uint32_t c0 = xcd_runs<8>(blockIdx.x, gridDim.x) * kPer;
+  const uint32_t c_end = c0 + kPer < n_cells ? c0 + kPer : n_cells;
+  (void)small_cells_step<kFused, kTrace, G>(src, dst, c0, c_end, t, pa, g, status, tr, lds);
+}
+
+// One wave per 64 consecutive cells: the cells holding more than `lanes`
+// particles.
+template <bool kFused, bool kTrace, uint32_t kCap>
+__global__ __launch_bounds__(64) void k_step_large(Cells src, Cells dst, uint32_t n_cells,
+                                                   uint32_t lanes, uint32_t t, PairArgs pa,
+                                                   Geometry g, DevStatus *status,
+                                                   TraceArgs tr) {
+  __shared__ CellLds<kFused, kCap> lds;
+  const uint32_t c0 = blockIdx.x * 64u;
+  const uint32_t c_end = c0 + 64u < n_cells ? c0 + 64u : n_cells;
+  large_cells_step<kFused, kTrace, kCap>(src, dst, c0, c_end, lanes, t, pa, g, status, tr,
+                                         lds);
+}
+
 template <bool kFused, bool kTrace, uint32_t kCap>
 __global__ __launch_bounds__(64) void k_step(Cells src, Cells dst, uint32_t t,
                                              PairArgs pa, Geometry g,
@@ -532,34 +787,75 @@ __global__ __launch_bounds__(64) void k_step(Cells src, Cells dst, uint32_t t,
 }
 
 // ---------------------------------------------------------------------------
-// Batched steps: all live events of a batch advance together.  Work item i
-// is a run of cpi consecutive cells of one event (events are laid out one
-// after another in item space); a wave takes items with a grid stride, so a
-// grid smaller than the item count is a persistent launch.  Within a run of
-// k steps, launch j (0: stream + bin, 1..k-1: fused, k: collisions only)
-// reads buffer cur ^ (j & 1) of each event and uses step index t + j - 1;
-// the run ends with k_batch_advance.
+// Batched steps: all live events of a batch advance together.  Each kernel
+// has a work space in which the events are laid out one after another
+// (space_begin[e] = the first unit of event e, ascending from 0):
+//   items   cpi consecutive cells, for the binning (every event); a wave
+//           takes items with a grid stride, so a grid smaller than the item
+//           count is a persistent launch;
+//   chunks  64 / lanes cells, one wave each, for the small cells of events
+//           with lanes per cell > 0;
+//   scans   64 cells, one wave each, stepping the cells of those events that
+//           hold more particles than the event's lanes per cell;
+//   cells   one cell per wave, for events stepped one wave per cell.
+// The step kernels have no loop over units: a loop keeps the descriptor and
+// lane constants live across iterations, which costs registers and with
+// them the occupancy that hides memory latency.  Within a run of k steps,
+// launch j (0: stream + bin, 1..k-1: fused, k: collisions only) reads buffer
+// cur ^ (j & 1) of each event and uses step index t + j - 1; the run ends
+// with k_batch_advance.
 // ---------------------------------------------------------------------------
-// item_begin[e] is the first work item of event e (ascending, n_events
-// entries); a compact array, so the search stays in one or two cache lines.
-__device__ __forceinline__ uint32_t find_event(const uint32_t *__restrict__ item_begin,
-                                               uint32_t n_events, uint32_t item) {
-  uint32_t lo = 0, hi = n_events;  // item_begin[lo] <= item < item_begin[hi]
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) / 2;
-    if (item_begin[mid] <= item) lo = mid;
-    else hi = mid;
+// The event of `unit` in a work space: the number of entries of begin[]
+// that are <= unit, minus one (begin[] is ascending from 0; an event with
+// no units has the begin of the next one, so it is never the answer).  The
+// lanes load 64 entries at a time, all loads independent, and a ballot
+// counts them.  `unit` must be the same in every lane of the wave.
+__device__ __forceinline__ uint32_t find_event(const uint32_t *__restrict__ begin,
+                                               uint32_t n_events, uint32_t unit) {
+  const uint32_t lane = lane_id();
+  uint32_t count = 0;
+#pragma unroll 4
+  for (uint32_t e0 = 0; e0 < n_events; e0 += 64) {
+    const uint32_t e = e0 + lane;
+    const bool le = e < n_events && begin[e] <= unit;
+    count += (uint32_t)__popcll(__ballot(le));
   }
-  return lo;
+  return count - 1u;
 }
 
-// The event's descriptor is copied into registers once per work item: the
+// The event's fields for launch j of a run, loaded once into registers (the
 // kernels store to global memory, so fields read through the table would
-// have to be reloaded after every store.
+// be reloaded after every store).
+struct EventView {
+  Cells src, dst;
+  Geometry g;
+  PairArgs pa;
+  DevStatus *status;
+  uint32_t t, lanes, n_cells;
+};
+
+__device__ __forceinline__ EventView event_view(const BatchEvent *__restrict__ E, uint32_t j) {
+  EventView v;
+  if ((E->cur ^ (j & 1u)) == 0u) {
+    v.src = E->buf[0];
+    v.dst = E->buf[1];
+  } else {
+    v.src = E->buf[1];
+    v.dst = E->buf[0];
+  }
+  v.g = E->g;
+  v.pa = E->pa;
+  v.status = E->status;
+  v.t = E->t + j - 1u;
+  v.lanes = E->lanes;
+  v.n_cells = E->n_cells;
+  return v;
+}
+
 __global__ __launch_bounds__(kBlock) void k_batch_bin(const BatchEvent *__restrict__ ev,
                                                       const uint32_t *__restrict__ item_begin,
                                                       uint32_t n_events, uint32_t n_items) {
-  const uint32_t w = threadIdx.x / 64;
+  const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);  // wave-uniform
   for (uint32_t item = blockIdx.x * kCellsPerBlock + w; item < n_items;
        item += gridDim.x * kCellsPerBlock) {
     const BatchEvent *__restrict__ E = ev + find_event(item_begin, n_events, item);
@@ -573,41 +869,82 @@ __global__ __launch_bounds__(kBlock) void k_batch_bin(const BatchEvent *__restri
     }
     const Geometry g = E->g;
     DevStatus *const status = E->status;
-    const uint32_t cpi = E->cpi, n_cells = E->n_cells;
+    const uint32_t cpi = E->cpi, n_cells = E->n_cells, lanes = E->lanes;
     const uint32_t c0 = (item - E->item_begin) * cpi;
     const uint32_t c1 = c0 + cpi < n_cells ? c0 + cpi : n_cells;
-    for (uint32_t c = c0; c < c1; ++c) cell_stream_bin(src, dst, c, g, status, nullptr);
+    switch (lanes) {
+      case 8:
+        for (uint32_t c = c0; c < c1; c += 8) cells_stream_bin<8>(src, dst, c, c1, g, status, nullptr);
+        break;
+      case 16:
+        for (uint32_t c = c0; c < c1; c += 4) cells_stream_bin<16>(src, dst, c, c1, g, status, nullptr);
+        break;
+      case 32:
+        for (uint32_t c = c0; c < c1; c += 2) cells_stream_bin<32>(src, dst, c, c1, g, status, nullptr);
+        break;
+      default:
+        for (uint32_t c = c0; c < c1; ++c) cells_stream_bin<64>(src, dst, c, c + 1, g, status, nullptr);
+    }
   }
 }
 
-template <bool kFused, uint32_t kCap>
-__global__ __launch_bounds__(64) void k_batch_step(const BatchEvent *__restrict__ ev,
-                                                   const uint32_t *__restrict__ item_begin,
-                                                   uint32_t n_events, uint32_t n_items,
-                                                   uint32_t j) {
-  __shared__ CellLds<kFused, kCap> lds;
-  const uint32_t first = gridDim.x < n_items ? blockIdx.x
-                                             : xcd_runs<8>(blockIdx.x, gridDim.x);
-  for (uint32_t item = first; item < n_items; item += gridDim.x) {
-    const BatchEvent *__restrict__ E = ev + find_event(item_begin, n_events, item);
-    Cells src, dst;
-    if ((E->cur ^ (j & 1u)) == 0u) {
-      src = E->buf[0];
-      dst = E->buf[1];
-    } else {
-      src = E->buf[1];
-      dst = E->buf[0];
-    }
-    const Geometry g = E->g;
-    const PairArgs pa = E->pa;
-    DevStatus *const status = E->status;
-    const uint32_t t = E->t + j - 1u;
-    const uint32_t cpi = E->cpi, n_cells = E->n_cells;
-    const uint32_t c0 = (item - E->item_begin) * cpi;
-    const uint32_t c1 = c0 + cpi < n_cells ? c0 + cpi : n_cells;
-    for (uint32_t c = c0; c < c1; ++c)
-      cell_step<kFused, false, kCap>(src, dst, c, t, pa, g, status, TraceArgs{}, lds);
+// Small cells: one wave per chunk of 64 / lanes cells.
+template <bool kFused>
+__global__ __launch_bounds__(64) void k_batch_step_small(const BatchEvent *__restrict__ ev,
+                                                         const uint32_t *__restrict__ chunk_begin,
+                                                         uint32_t n_events, uint32_t j) {
+  __shared__ SmallLds lds;
+  const uint32_t chunk = xcd_runs<8>(blockIdx.x, gridDim.x);
+  const BatchEvent *__restrict__ E = ev + find_event(chunk_begin, n_events, chunk);
+  const EventView v = event_view(E, j);
+  const uint32_t per = 64u / v.lanes;
+  const uint32_t c0 = (chunk - E->chunk_begin) * per;
+  const uint32_t c1 = c0 + per < v.n_cells ? c0 + per : v.n_cells;
+  const TraceArgs none{};
+  switch (v.lanes) {
+    case 8:
+      small_cells_step<kFused, false, 8>(v.src, v.dst, c0, c1, v.t, v.pa, v.g, v.status, none, lds);
+      break;
+    case 16:
+      small_cells_step<kFused, false, 16>(v.src, v.dst, c0, c1, v.t, v.pa, v.g, v.status, none, lds);
+      break;
+    case 32:
+      small_cells_step<kFused, false, 32>(v.src, v.dst, c0, c1, v.t, v.pa, v.g, v.status, none, lds);
+      break;
+    default:
+      small_cells_step<kFused, false, 64>(v.src, v.dst, c0, c1, v.t, v.pa, v.g, v.status, none, lds);
   }
+}
+
+// The cells of 64 consecutive cells of a small-cell event holding more than
+// its lanes per cell (rare), by the whole wave.
+template <bool kFused, uint32_t kCap>
+__global__ __launch_bounds__(64) void k_batch_step_scan(const BatchEvent *__restrict__ ev,
+                                                        const uint32_t *__restrict__ scan_begin,
+                                                        uint32_t n_events, uint32_t j) {
+  __shared__ CellLds<kFused, kCap> lds;
+  const uint32_t unit = blockIdx.x;
+  const BatchEvent *__restrict__ E = ev + find_event(scan_begin, n_events, unit);
+  const EventView v = event_view(E, j);
+  const uint32_t c0 = (unit - E->scan_begin) * 64u;
+  const uint32_t c1 = c0 + 64u < v.n_cells ? c0 + 64u : v.n_cells;
+  large_cells_step<kFused, false, kCap>(v.src, v.dst, c0, c1, v.lanes, v.t, v.pa, v.g,
+                                        v.status, TraceArgs{}, lds);
+}
+
+// One wave per cell of the events stepped one wave per cell.  Held to the
+// register budget of 5 waves per SIMD, as the plain kernel (it fits without
+// scratch; the event lookup would otherwise push it 1 register over).
+template <bool kFused, uint32_t kCap>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_batch_step_cells(const BatchEvent *__restrict__ ev,
+                                                         const uint32_t *__restrict__ cell_begin,
+                                                         uint32_t n_events, uint32_t j) {
+  __shared__ CellLds<kFused, kCap> lds;
+  const uint32_t unit = xcd_runs<8>(blockIdx.x, gridDim.x);
+  const BatchEvent *__restrict__ E = ev + find_event(cell_begin, n_events, unit);
+  const EventView v = event_view(E, j);
+  cell_step<kFused, false, kCap>(v.src, v.dst, unit - E->cell_begin, v.t, v.pa, v.g, v.status,
+                                 TraceArgs{}, lds);
 }
 
 // End of a run of k steps: every event moved k buffers and k step indices.
@@ -727,12 +1064,27 @@ void launch_init_bin(const double *x, const double *y, const double *z,
                      pz, dst, n, g, st);
 }
 
-void launch_stream_bin(const Cells &src, const Cells &dst, int64_t n_cells,
+void launch_stream_bin(const Cells &src, const Cells &dst, int64_t n_cells, uint32_t lanes,
                        const Geometry &g, DevStatus *status, uint32_t *trace_cell,
                        hipStream_t s) {
   if (n_cells <= 0) return;
-  hipLaunchKernelGGL(k_stream_bin, dim3(cell_blocks(n_cells)), dim3(kBlock), 0, s, src,
-                     dst, (uint32_t)n_cells, g, status, trace_cell);
+  const uint32_t G = lanes == 0 ? 64u : lanes;
+  const int64_t waves = (n_cells + 64 / G - 1) / (64 / G);
+  const dim3 grid(cell_blocks(waves)), block(kBlock);
+  const uint32_t nc = (uint32_t)n_cells;
+  switch (G) {
+    case 8:
+      hipLaunchKernelGGL(k_stream_bin<8>, grid, block, 0, s, src, dst, nc, g, status, trace_cell);
+      break;
+    case 16:
+      hipLaunchKernelGGL(k_stream_bin<16>, grid, block, 0, s, src, dst, nc, g, status, trace_cell);
+      break;
+    case 32:
+      hipLaunchKernelGGL(k_stream_bin<32>, grid, block, 0, s, src, dst, nc, g, status, trace_cell);
+      break;
+    default:
+      hipLaunchKernelGGL(k_stream_bin<64>, grid, block, 0, s, src, dst, nc, g, status, trace_cell);
+  }
 }
 
 void launch_offsets(const Cells &cur, uint32_t *offsets, uint32_t *tile_sums,
@@ -744,33 +1096,68 @@ void launch_offsets(const Cells &cur, uint32_t *offsets, uint32_t *tile_sums,
                      (const uint32_t *)tile_sums, n_cells);
 }
 
-void launch_step(const Cells &src, const Cells &dst, bool fused, int64_t n_cells,
-                 uint32_t t, const PairArgs &pa, const Geometry &g, DevStatus *status,
-                 const TraceArgs *trace, hipStream_t s) {
-  if (n_cells <= 0) return;
-  const dim3 grid((unsigned)n_cells), block(64);
-  // cells of at most 512 slots use the kernels with half the LDS
-  if (src.cap <= kSmallCap) {
-    if (trace)
-      hipLaunchKernelGGL((k_step<false, true, kSmallCap>), grid, block, 0, s, src, dst, t,
-                         pa, g, status, *trace);
-    else if (fused)
-      hipLaunchKernelGGL((k_step<true, false, kSmallCap>), grid, block, 0, s, src, dst, t,
-                         pa, g, status, TraceArgs{});
-    else
-      hipLaunchKernelGGL((k_step<false, false, kSmallCap>), grid, block, 0, s, src, dst, t,
-                         pa, g, status, TraceArgs{});
+namespace {
+
+template <bool kFused, bool kTrace, uint32_t kCap>
+void launch_step_cap(const Cells &src, const Cells &dst, uint32_t n_cells, uint32_t lanes,
+                     uint32_t t, const PairArgs &pa, const Geometry &g, DevStatus *status,
+                     const TraceArgs &tr, hipStream_t s) {
+  const dim3 block(64);
+  if (lanes == 0) {
+    hipLaunchKernelGGL((k_step<kFused, kTrace, kCap>), dim3(n_cells), block, 0, s, src, dst,
+                       t, pa, g, status, tr);
     return;
   }
+  // the small cells, then the cells the small-cell kernel left alone
+  const dim3 grid((n_cells + 64 / lanes - 1) / (64 / lanes));
+  switch (lanes) {
+    case 8:
+      hipLaunchKernelGGL((k_step_small<kFused, kTrace, 8>), grid, block, 0, s, src, dst,
+                         n_cells, t, pa, g, status, tr);
+      break;
+    case 16:
+      hipLaunchKernelGGL((k_step_small<kFused, kTrace, 16>), grid, block, 0, s, src, dst,
+                         n_cells, t, pa, g, status, tr);
+      break;
+    case 32:
+      hipLaunchKernelGGL((k_step_small<kFused, kTrace, 32>), grid, block, 0, s, src, dst,
+                         n_cells, t, pa, g, status, tr);
+      break;
+    default:
+      hipLaunchKernelGGL((k_step_small<kFused, kTrace, 64>), grid, block, 0, s, src, dst,
+                         n_cells, t, pa, g, status, tr);
+  }
+  hipLaunchKernelGGL((k_step_large<kFused, kTrace, kCap>), dim3((n_cells + 63) / 64), block,
+                     0, s, src, dst, n_cells, lanes, t, pa, g, status, tr);
+}
+
+template <uint32_t kCap>
+void launch_step_any(const Cells &src, const Cells &dst, bool fused, uint32_t n_cells,
+                     uint32_t lanes, uint32_t t, const PairArgs &pa, const Geometry &g,
+                     DevStatus *status, const TraceArgs *trace, hipStream_t s) {
   if (trace)
-    hipLaunchKernelGGL((k_step<false, true, kCellCap>), grid, block, 0, s, src, dst, t, pa,
-                       g, status, *trace);
+    launch_step_cap<false, true, kCap>(src, dst, n_cells, lanes, t, pa, g, status, *trace, s);
   else if (fused)
-    hipLaunchKernelGGL((k_step<true, false, kCellCap>), grid, block, 0, s, src, dst, t, pa,
-                       g, status, TraceArgs{});
+    launch_step_cap<true, false, kCap>(src, dst, n_cells, lanes, t, pa, g, status,
+                                       TraceArgs{}, s);
   else
-    hipLaunchKernelGGL((k_step<false, false, kCellCap>), grid, block, 0, s, src, dst, t, pa,
-                       g, status, TraceArgs{});
+    launch_step_cap<false, false, kCap>(src, dst, n_cells, lanes, t, pa, g, status,
+                                        TraceArgs{}, s);
+}
+
+}  // namespace
+
+void launch_step(const Cells &src, const Cells &dst, bool fused, int64_t n_cells,
+                 uint32_t lanes, uint32_t t, const PairArgs &pa, const Geometry &g,
+                 DevStatus *status, const TraceArgs *trace, hipStream_t s) {
+  if (n_cells <= 0) return;
+  // cells of at most 512 slots use the kernels with half the LDS
+  if (src.cap <= kSmallCap)
+    launch_step_any<kSmallCap>(src, dst, fused, (uint32_t)n_cells, lanes, t, pa, g, status,
+                               trace, s);
+  else
+    launch_step_any<kCellCap>(src, dst, fused, (uint32_t)n_cells, lanes, t, pa, g, status,
+                              trace, s);
 }
 
 void launch_observe(const Cells &cur, const Geometry &g, double vol, double *cell_sums,
@@ -783,34 +1170,46 @@ void launch_observe(const Cells &cur, const Geometry &g, double vol, double *cel
                      T0x);
 }
 
-void launch_batch_run(BatchEvent *ev, const uint32_t *item_begin, uint32_t n_events,
-                      uint32_t n_items, int32_t k, uint32_t persistent_waves, uint32_t max_cap,
-                      hipStream_t s, void (*between)(void *, int), void *ctx) {
-  if (n_events == 0 || n_items == 0 || k <= 0) return;
-  const uint32_t step_grid =
-      persistent_waves > 0 && persistent_waves < n_items ? persistent_waves : n_items;
-  const uint32_t bin_waves = step_grid;
+void launch_batch_run(BatchEvent *ev, const BatchSpaces &sp, uint32_t n_events, int32_t k,
+                      uint32_t persistent_waves, uint32_t max_cap, hipStream_t s,
+                      void (*between)(void *, int), void *ctx) {
+  if (n_events == 0 || sp.n_items == 0 || k <= 0) return;
+  const uint32_t bin_waves =
+      persistent_waves > 0 && persistent_waves < sp.n_items ? persistent_waves : sp.n_items;
   const uint32_t bin_grid = (bin_waves + kCellsPerBlock - 1) / kCellsPerBlock;
+  const BatchEvent *cev = ev;
+  const dim3 wave(64);
   if (between) between(ctx, 0);
-  hipLaunchKernelGGL(k_batch_bin, dim3(bin_grid), dim3(kBlock), 0, s,
-                     (const BatchEvent *)ev, item_begin, n_events, n_items);
-  const bool small = max_cap <= kSmallCap;
+  hipLaunchKernelGGL(k_batch_bin, dim3(bin_grid), dim3(kBlock), 0, s, cev, sp.item_begin,
+                     n_events, sp.n_items);
+  // launch j: the small cells, the oversize cells of small-cell events, and
+  // the cells of events stepped one wave per cell (each kernel if it has work)
+  auto step = [&](auto fused, auto cap, uint32_t j) {
+    constexpr bool kF = decltype(fused)::value;
+    constexpr uint32_t kC = decltype(cap)::value;
+    if (sp.n_chunks > 0)
+      hipLaunchKernelGGL((k_batch_step_small<kF>), dim3(sp.n_chunks), wave, 0, s, cev,
+                         sp.chunk_begin, n_events, j);
+    if (sp.n_scans > 0)
+      hipLaunchKernelGGL((k_batch_step_scan<kF, kC>), dim3(sp.n_scans), wave, 0, s, cev,
+                         sp.scan_begin, n_events, j);
+    if (sp.n_cells > 0)
+      hipLaunchKernelGGL((k_batch_step_cells<kF, kC>), dim3(sp.n_cells), wave, 0, s, cev,
+                         sp.cell_begin, n_events, j);
+  };
+  using Fused = std::integral_constant<bool, true>;
+  using Last = std::integral_constant<bool, false>;
+  using Small = std::integral_constant<uint32_t, kSmallCap>;
+  using Large = std::integral_constant<uint32_t, kCellCap>;
+  const bool small_lds = max_cap <= kSmallCap;
   for (int32_t j = 1; j < k; ++j) {
     if (between) between(ctx, 1);
-    if (small)
-      hipLaunchKernelGGL((k_batch_step<true, kSmallCap>), dim3(step_grid), dim3(64), 0, s,
-                         (const BatchEvent *)ev, item_begin, n_events, n_items, (uint32_t)j);
-    else
-      hipLaunchKernelGGL((k_batch_step<true, kCellCap>), dim3(step_grid), dim3(64), 0, s,
-                         (const BatchEvent *)ev, item_begin, n_events, n_items, (uint32_t)j);
+    if (small_lds) step(Fused{}, Small{}, (uint32_t)j);
+    else step(Fused{}, Large{}, (uint32_t)j);
   }
   if (between) between(ctx, 2);
-  if (small)
-    hipLaunchKernelGGL((k_batch_step<false, kSmallCap>), dim3(step_grid), dim3(64), 0, s,
-                       (const BatchEvent *)ev, item_begin, n_events, n_items, (uint32_t)k);
-  else
-    hipLaunchKernelGGL((k_batch_step<false, kCellCap>), dim3(step_grid), dim3(64), 0, s,
-                       (const BatchEvent *)ev, item_begin, n_events, n_items, (uint32_t)k);
+  if (small_lds) step(Last{}, Small{}, (uint32_t)k);
+  else step(Last{}, Large{}, (uint32_t)k);
   if (between) between(ctx, -1);
   hipLaunchKernelGGL(k_batch_advance, dim3((n_events + 63) / 64), dim3(64), 0, s, ev,
                      n_events, (uint32_t)k);

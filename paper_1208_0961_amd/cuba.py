@@ -71,6 +71,10 @@ def _load() -> ctypes.CDLL:
     L.cuba_trace_step.restype = ctypes.c_int
     L.cuba_sync.argtypes = [vp]
     L.cuba_sync.restype = ctypes.c_int
+    L.cuba_set_cell_lanes.argtypes = [vp, i32]
+    L.cuba_set_cell_lanes.restype = ctypes.c_int
+    L.cuba_get_cell_lanes.argtypes = [vp, ctypes.POINTER(i32)]
+    L.cuba_get_cell_lanes.restype = ctypes.c_int
     L.cuba_info.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(i64),
                             ctypes.POINTER(i64)]
     L.cuba_info.restype = ctypes.c_int
@@ -93,6 +97,8 @@ def _load() -> ctypes.CDLL:
     L.cuba_batch_slot.restype = vp
     L.cuba_batch_set_cells_per_item.argtypes = [vp, i32, i32]
     L.cuba_batch_set_cells_per_item.restype = ctypes.c_int
+    L.cuba_batch_set_cell_lanes.argtypes = [vp, i32, i32]
+    L.cuba_batch_set_cell_lanes.restype = ctypes.c_int
     L.cuba_batch_set_launch.argtypes = [vp, i32, i32]
     L.cuba_batch_set_launch.restype = ctypes.c_int
     L.cuba_batch_step.argtypes = [vp, i32]
@@ -181,6 +187,19 @@ def cuba_sync(ctx: int) -> None:
     _check(_lib.cuba_sync(ctx), "cuba_sync")
 
 
+CELL_LANES = (0, 8, 16, 32, 64)
+
+
+def cuba_set_cell_lanes(ctx: int, lanes: int) -> None:
+    _check(_lib.cuba_set_cell_lanes(ctx, int(lanes)), "cuba_set_cell_lanes")
+
+
+def cuba_get_cell_lanes(ctx: int) -> int:
+    v = ctypes.c_int32()
+    _check(_lib.cuba_get_cell_lanes(ctx, ctypes.byref(v)), "cuba_get_cell_lanes")
+    return int(v.value)
+
+
 def cuba_info(ctx: int):
     t = ctypes.c_uint32()
     n = ctypes.c_int64()
@@ -246,6 +265,11 @@ def cuba_batch_slot(b: int, slot: int):
 def cuba_batch_set_cells_per_item(b: int, slot: int, cells: int) -> None:
     _check(_lib.cuba_batch_set_cells_per_item(b, int(slot), int(cells)),
            "cuba_batch_set_cells_per_item")
+
+
+def cuba_batch_set_cell_lanes(b: int, slot: int, lanes: int) -> None:
+    _check(_lib.cuba_batch_set_cell_lanes(b, int(slot), int(lanes)),
+           "cuba_batch_set_cell_lanes")
 
 
 def cuba_batch_set_launch(b: int, persistent_waves: int, use_graphs: bool) -> None:

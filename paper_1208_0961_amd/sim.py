@@ -24,7 +24,8 @@ def suggest_cell_capacity(params: dict, state, headroom: float = 2.0, margin: in
         return 64
     box = np.asarray(params["box"], np.float64)
     cells = np.asarray(params["cells"], np.int64)
-    r = [np.asarray(state[d], np.float64) for d in range(3)]
+    r = [state[d].detach().cpu().numpy() if isinstance(state[d], torch.Tensor)
+         else np.asarray(state[d], np.float64) for d in range(3)]
     ok = np.isfinite(r[0]) & np.isfinite(r[1]) & np.isfinite(r[2])
     if not ok.any():
         return 64
@@ -42,10 +43,12 @@ class Sim:
     params: dict with box, cells, sigma, r_test, dt, seed and optionally
     step0 and cell_capacity (default: suggest_cell_capacity of the initial
     state).  state: six arrays (x, y, z, px, py, pz) indexed by particle id.
+    cell_lanes: lanes per cell of the cell kernels (None: the library's
+    choice from the mean occupancy; see cuba_set_cell_lanes).
     """
 
     def __init__(self, params: dict, state, device: str | torch.device = "cuda",
-                 stream: torch.cuda.Stream | None = None):
+                 stream: torch.cuda.Stream | None = None, cell_lanes: int | None = None):
         self.device = torch.device(device)
         self.params = dict(params)
         if not self.params.get("cell_capacity"):
@@ -69,6 +72,16 @@ class Sim:
                                    self.stream.cuda_stream)
             # the inputs are copied on the stream; keep them until it passes
             self._inputs = arrs
+        if cell_lanes is not None:
+            C.cuba_set_cell_lanes(self.ctx, cell_lanes)
+
+    @property
+    def cell_lanes(self) -> int:
+        return C.cuba_get_cell_lanes(self.ctx)
+
+    @cell_lanes.setter
+    def cell_lanes(self, lanes: int) -> None:
+        C.cuba_set_cell_lanes(self.ctx, lanes)
 
     # -- stepping -------------------------------------------------------------
     def step(self, nsteps: int = 1) -> None:

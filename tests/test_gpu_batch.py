@@ -131,3 +131,27 @@ def test_batch_reports_the_failing_slot(mods):
         B.sync()
     assert e.value.code == C.CUBA_ERANGE and e.value.slot == 2
     B.close()
+
+
+def test_batch_mixed_lanes_per_cell(mods):
+    """Events stepped with different lanes-per-cell settings in one batch,
+    with items that end inside a group of cells, equal the events run alone
+    (with the library's default setting)."""
+    batch, sim = mods
+    evs = small_events()
+    states = [W.riemann_state(w, seed=40 + i) for i, w in enumerate(evs)]
+    settings = [(0, 5), (8, 3), (16, 7), (32, 5), (64, 2)]
+    B = batch.Batch(len(evs), use_graphs=True)
+    for i, ((lanes, cpi), w, st) in enumerate(zip(settings, evs, states)):
+        B.admit(i, w.params(), st)
+        B.set_cell_lanes(i, lanes)
+        B.set_cells_per_item(i, cpi)
+        assert B.cell_lanes(i) == lanes
+    say(f"[batch] lanes/cpi {settings}")
+    for k in (6, 1, 6):
+        B.step(k)
+        B.observe(0)
+    B.sync()
+    for i, (w, st) in enumerate(zip(evs, states)):
+        assert_same(B.get_state(i), alone(sim, w, st, 13), w.name)
+    B.close()

@@ -46,13 +46,14 @@ def _rows(a):
     return a[np.lexsort((a[:, 2], a[:, 1], a[:, 0]))]
 
 
-def compare_step(orc, lib, params, state, t, label=""):
+def compare_step(orc, lib, params, state, t, label="", lanes=None):
     """Run step t from state on both sides; assert the parity contract.
+    lanes: the GPU context's lanes-per-cell setting (None: its default).
     Returns the GPU state after the step (id order) and the GPU trace."""
-    say(f"[parity] {label} n={len(state[0])} t={t}")
+    say(f"[parity] {label} n={len(state[0])} t={t} lanes={lanes}")
     st = orc.State(*state)
     tr_o = orc.step(_orc_params(orc, params), st, t & 0xFFFFFFFF, trace=True)
-    sim = lib.Sim({**params, "step0": t}, state)
+    sim = lib.Sim({**params, "step0": t}, state, cell_lanes=lanes)
     tr_g = sim.trace_step(cand_cap=len(tr_o["cand"]) + 1024)
     gs = sim.get_state()
     sim.close()

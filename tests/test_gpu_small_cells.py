@@ -1,0 +1,147 @@
+"""Parity of the small-cell kernels (several cells per wave, one particle per
+lane, larger cells stepped by the whole wave) with the CPU oracle, for every
+lanes-per-cell setting.
+
+cuba_trace_step runs the collision kernel of the context's setting, so the
+trace comparison checks that kernel's decisions (cells, canonical order,
+candidate and claimed pairs) bit for bit.  The fused kernel (collisions of
+step t, then streaming and binning of step t+1) is checked by running
+n - 1 and n steps from the same state: one oracle step from the first
+result must reproduce the second.
+"""
+import numpy as np
+import pytest
+
+from paper_1208_0961_amd import workload as W
+from test_gpu_parity import compare_step, _cells_box, _orc_params, _rows, say, lib  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+LANES = (8, 16, 32, 64)
+
+
+def sparse_workload(mean_scale=1.0, seed=31):
+    """A 10 x 1 x 1 fm Riemann tube, 100 x 5 x 5 cells, about 3.8 / 1.9
+    particles per cell on the two sides (scaled by mean_scale), K = 0.09."""
+    return W.Workload("sparse", (10.0, 1.0, 1.0), (100, 5, 5), 50.0 * mean_scale,
+                      0.9 * mean_scale, 0.02, 0.45, 0.36, seed=seed)
+
+
+@pytest.mark.parametrize("lanes", LANES)
+def test_small_cells_trace_parity_sparse(orc, lib, lanes):  # noqa: F811
+    w = sparse_workload()
+    state = W.riemann_state(w, seed=5)
+    n_claim = 0
+    for t in range(3):
+        state, tr = compare_step(orc, lib, w.params(), state, t, "sparse", lanes=lanes)
+        n_claim += len(tr["claim"])
+    assert n_claim > 300
+
+
+@pytest.mark.parametrize("lanes", LANES)
+def test_small_cells_trace_parity_ragged(orc, lib, lanes):  # noqa: F811
+    # occupancies on both sides of every group size, the 64-lane limit, and
+    # cells the whole wave must take over
+    occ = ([0, 1, 2, 3, 7, 8, 9, 15, 16, 17, 31, 32, 33, 63, 64, 65, 100, 300]
+           + [2] * 20 + [5] * 16 + [12] * 10)
+    state = _cells_box(occ)
+    params = dict(box=(1.0, 1.0, 1.0), cells=(4, 4, 4), sigma=2.0, r_test=1.0,
+                  dt=0.001, seed=777)
+    for t in range(2):
+        state, tr = compare_step(orc, lib, params, state, t, "ragged", lanes=lanes)
+    assert len(tr["claim"]) > 50
+
+
+@pytest.mark.parametrize("lanes", LANES)
+def test_small_cells_every_pair_passes_filter(orc, lib, lanes):  # noqa: F811
+    # 2K = 1: the w1 filter passes every pair, so every pair takes the exact
+    # test and many claims compete inside each cell
+    occ = [lanes, lanes - 1, 3, 2] * 2
+    state = _cells_box(occ, m=2)
+    V = 1.0 / 8.0
+    params = dict(box=(1.0, 1.0, 1.0), cells=(2, 2, 2), sigma=0.5 * V / 0.001,
+                  r_test=1.0, dt=0.001, seed=4242)
+    _, tr = compare_step(orc, lib, params, state, 9, "K=1/2", lanes=lanes)
+    assert len(tr["claim"]) >= lanes // 2
+
+
+def _fused_step_check(orc, lib, params, state, nsteps, lanes, label):  # noqa: F811
+    """GPU runs of nsteps - 1 and nsteps steps from state (the later steps of
+    a run use the fused kernel); one oracle step from the first result must
+    give the second (positions and unscattered momenta bit-exact, scattered
+    momenta within 1e-12 of the pair energy)."""
+    say(f"[fused] {label} lanes={lanes} nsteps={nsteps}")
+    a = lib.Sim(params, state, cell_lanes=lanes)
+    a.step(nsteps - 1)
+    prev = a.get_state()
+    a.close()
+    b = lib.Sim(params, state, cell_lanes=lanes)
+    b.step(nsteps)
+    got = b.get_state()
+    b.close()
+    st = orc.State(*prev)
+    t = (params.get("step0", 0) + nsteps - 1) & 0xFFFFFFFF
+    tr = orc.step(_orc_params(orc, params), st, t, trace=True)
+    for d in range(3):
+        assert np.array_equal(got[d], st[d]), f"positions differ on axis {d}"
+    scattered = np.zeros(len(state[0]), bool)
+    pair_e = np.zeros(len(state[0]))
+    offs = tr["offsets"].astype(np.int64)
+    E = np.sqrt(st[3] ** 2 + st[4] ** 2 + st[5] ** 2)
+    for c, i, j in _rows(tr["claim"]):
+        ia = tr["perm"][offs[c] + i]
+        ib = tr["perm"][offs[c] + j]
+        scattered[[ia, ib]] = True
+        pair_e[[ia, ib]] = E[ia] + E[ib]
+    for d in range(3, 6):
+        assert np.array_equal(got[d][~scattered], st[d][~scattered]), "unscattered p differs"
+        assert np.all(np.abs(got[d][scattered] - st[d][scattered]) <= 1e-12 * pair_e[scattered])
+    return len(tr["claim"])
+
+
+@pytest.mark.parametrize("lanes", (0,) + LANES)
+def test_fused_small_cell_steps_match_oracle(orc, lib, lanes):  # noqa: F811
+    w = sparse_workload(seed=11)
+    state = W.riemann_state(w, seed=12)
+    assert _fused_step_check(orc, lib, w.params(), state, 4, lanes, "sparse") > 50
+    occ = [0, 1, 2, 3, 9, 17, 33, 65, 120] + [4] * 55
+    state = _cells_box(occ, seed=8)
+    params = dict(box=(1.0, 1.0, 1.0), cells=(4, 4, 4), sigma=2.0, r_test=1.0,
+                  dt=0.001, seed=3)
+    assert _fused_step_check(orc, lib, params, state, 3, lanes, "ragged") > 20
+
+
+def test_lanes_settings_agree_bit_for_bit(lib):  # noqa: F811
+    """Every setting runs the same decisions and the same arithmetic: after
+    30 steps the states are identical, and so are the work counters."""
+    from paper_1208_0961_amd import cuba as C
+    w = sparse_workload(mean_scale=2.0, seed=21)
+    state = W.riemann_state(w, seed=22)
+    ref = None
+    for lanes in (0,) + LANES:
+        s = lib.Sim(w.params(), state, cell_lanes=lanes)
+        assert s.cell_lanes == lanes
+        s.step(13)
+        s.step(17)
+        out = s.get_state()
+        cnt = C.cuba_counters(s.ctx)
+        s.close()
+        if ref is None:
+            ref = (out, cnt)
+            assert cnt["claims"] > 1000
+            continue
+        for d in range(6):
+            assert np.array_equal(out[d], ref[0][d]), f"lanes={lanes}: array {d}"
+        assert cnt == ref[1], f"lanes={lanes}: counters {cnt} vs {ref[1]}"
+
+
+def test_lanes_setting_is_validated(lib):  # noqa: F811
+    from paper_1208_0961_amd import cuba as C
+    w = sparse_workload()
+    s = lib.Sim(w.params(), W.riemann_state(w))
+    assert s.cell_lanes in (0,) + LANES
+    for bad in (-1, 1, 4, 12, 128):
+        with pytest.raises(C.CubaError) as e:
+            s.cell_lanes = bad
+        assert e.value.code == C.CUBA_EINVAL
+    s.close()

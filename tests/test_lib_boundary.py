@@ -94,3 +94,24 @@ def test_init_rejects_before_touching_the_device(C):
     assert rc == C.CUBA_ENOMEM
     for code in (0, -1, -2, -3, -4):
         assert C.cuba_strerror(code).startswith("CUBA_")
+
+
+def test_lanes_and_batch_arguments_checked_on_the_host(C):
+    L = C._lib
+    out = ctypes.c_int32()
+    assert L.cuba_set_cell_lanes(None, 8) == C.CUBA_EINVAL
+    assert L.cuba_get_cell_lanes(None, ctypes.byref(out)) == C.CUBA_EINVAL
+    assert L.cuba_batch_set_cell_lanes(None, 0, 8) == C.CUBA_EINVAL
+    # batch table: the event descriptors plus four work-space index arrays,
+    # 256-byte aligned pieces, growing with the slot count
+    assert C.cuba_batch_workspace_bytes(0) == 0
+    prev = 0
+    for slots in (1, 2, 64, 65, 1000):
+        nb = C.cuba_batch_workspace_bytes(slots)
+        assert nb % 256 == 0 and nb > prev and nb >= slots * (200 + 16)
+        prev = nb
+    b = ctypes.c_void_p()
+    rc = L.cuba_batch_create(ctypes.byref(b), 4, 8, 1 << 20, None)
+    assert rc == C.CUBA_EINVAL and b.value is None
+    rc = L.cuba_batch_create(ctypes.byref(b), 4, 256, 16, None)
+    assert rc == C.CUBA_ENOMEM and b.value is None
