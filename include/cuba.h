@@ -164,9 +164,10 @@ int cuba_sync(cuba_ctx *ctx);
  * whatever its occupancy.  8, 16, 32 or 64: each wave takes 64 / lanes
  * consecutive cells with one particle per lane, which serves sparse cells
  * without a mostly idle wave each; cells holding more particles than lanes
- * are then stepped by the whole wave, in a second launch.  cuba_init
- * chooses from the mean occupancy n / cells: 8 up to 4, 16 up to 11, 32 up
- * to 24, else 0.  Errors: CUBA_EINVAL for NULL or any other value.  For an event in
+ * are stepped by the whole wave in a second kernel.  cuba_init chooses
+ * from the initial occupancy: 0 below 16384 cells (launch-bound steps),
+ * else the smallest of 8, 16, 32, 64 that all but 0.2 % of the cells fit,
+ * else 0.  Errors: CUBA_EINVAL for NULL or any other value.  For an event in
  * a batch use cuba_batch_set_cell_lanes. */
 int cuba_set_cell_lanes(cuba_ctx *ctx, int32_t lanes);
 int cuba_get_cell_lanes(const cuba_ctx *ctx, int32_t *lanes);
@@ -221,7 +222,10 @@ size_t cuba_batch_workspace_bytes(int32_t max_slots);
 
 /* Creates a batch.  workspace: device memory of ws_bytes >=
  * cuba_batch_workspace_bytes(max_slots), 256-byte aligned, owned by the
- * caller.  stream: hipStream_t (must not be NULL if graphs are enabled). */
+ * caller.  stream: hipStream_t (must not be NULL if graphs are enabled).
+ * The batch also creates one stream of its own (default priority), on which
+ * the kernels of a step that are independent of the small-cell kernel run
+ * concurrently, joined back into `stream` before the next step. */
 int cuba_batch_create(cuba_batch **out, int32_t max_slots, void *workspace,
                       size_t ws_bytes, void *stream);
 

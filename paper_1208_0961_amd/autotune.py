@@ -1,5 +1,5 @@
-"""Autotuner for batched steps: lanes per cell and cells per work item by
-occupancy class, and the launch shape (one workgroup per item, or a
+"""Autotuner for batched steps: lanes per cell and cells per binning item
+by occupancy class, and the binning launch shape (one wave per item, or a
 persistent grid).
 
 Tuning runs on a probe batch of representative events with fresh states, so
@@ -21,8 +21,10 @@ from .batch import Batch
 # classes of mean particles per cell (upper bounds)
 OCC_BOUNDS = (2.0, 8.0, 32.0, 128.0, math.inf)
 CPI_CANDIDATES = (1, 2, 4, 8, 16, 32, 64)
-# lanes-per-cell settings worth trying per occupancy class (0: one wave per cell)
-LANES_CANDIDATES = {0: (8, 16, 0), 1: (16, 32, 8, 0), 2: (32, 64, 0), 3: (64, 0), 4: (0,)}
+# lanes-per-cell settings tried per class; AUTO keeps each event's own
+# library default (chosen at admission from its occupancy histogram)
+AUTO = -1
+LANES_CANDIDATES = (AUTO, 0, 8, 16, 32, 64)
 PERSISTENT_CANDIDATES = (0, 256 * 16, 256 * 32)
 DEFAULT_TABLE = os.path.join(os.path.expanduser("~"), ".cache", "cuba_mi355x", "tuning.json")
 
@@ -40,20 +42,6 @@ def heuristic_cpi(mean_occupancy: float) -> int:
     return max(1, min(64, int(64.0 / mean_occupancy)))
 
 
-def heuristic_lanes(mean_occupancy: float) -> int:
-    """Lanes per cell for a class: groups that hold the typical cell."""
-    for ub, lanes in ((2.0, 8), (5.0, 16), (14.0, 32), (36.0, 64)):
-        if mean_occupancy <= ub:
-            return lanes
-    return 0
-
-
-def cpi_candidates(lanes: int) -> list:
-    """Cells per item, in whole groups of 64 / lanes cells."""
-    per = 64 // lanes if lanes else 1
-    return sorted({-(-c // per) * per for c in CPI_CANDIDATES})
-
-
 def _time_run(B: Batch, steps: int, repeats: int) -> float:
     B.step(steps)                       # warm (and graph capture if enabled)
     B.sync()
@@ -69,53 +57,63 @@ def _time_run(B: Batch, steps: int, repeats: int) -> float:
     return best
 
 
-def tune(events: list, per_class: int = 3, steps: int = 3, repeats: int = 2,
+def _probe_batch(ws: list, device: str, seed: int) -> Batch:
+    B = Batch(len(ws), device=device)
+    for slot, w in enumerate(ws):
+        state = W.riemann_state_torch(w, seed + slot, device=device)
+        B.admit(slot, {**w.params(), "cell_capacity": W.capacity_for(w)}, state)
+    return B
+
+
+def tune(events: list, per_class: int = 3, steps: int = 8, repeats: int = 3,
          device: str = "cuda", seed: int = 9) -> dict:
-    """Tunes on up to per_class probe events of each occupancy class present
-    in `events` (Workloads).  Returns the tuning table."""
+    """Tunes each occupancy class present in `events` (Workloads) on a probe
+    batch of up to per_class of its events (the smallest, median and
+    largest), so that a setting's effect is timed on the work it changes:
+    first lanes per cell, then cells per binning item; then the binning
+    launch shape on all probe events together.  Returns the tuning table."""
     by_class: dict[int, list] = {}
     for w in events:
         by_class.setdefault(occupancy_class(W.max_mean_occupancy(w)), []).append(w)
-    probes = []
+    picks = {}
     for k in sorted(by_class):
         ws = sorted(by_class[k], key=lambda w: w.n)
-        # the smallest, median and largest event of the class
-        pick = [ws[0], ws[len(ws) // 2], ws[-1]][:per_class]
-        probes += [(k, w) for w in pick]
-    B = Batch(len(probes), device=device)
-    for slot, (k, w) in enumerate(probes):
-        state = W.riemann_state_torch(w, seed + slot, device=device)
-        B.admit(slot, {**w.params(), "cell_capacity": W.capacity_for(w)}, state)
-    lanes = {k: heuristic_lanes(W.max_mean_occupancy(by_class[k][0])) for k in by_class}
-    cpi = {k: cpi_candidates(lanes[k])[0] if lanes[k] else
-           heuristic_cpi(W.max_mean_occupancy(by_class[k][0])) for k in by_class}
-
-    def apply_settings():
-        for slot, (k, w) in enumerate(probes):
-            B.set_cell_lanes(slot, lanes[k])
-            B.set_cells_per_item(slot, cpi[k])
-
+        picks[k] = [ws[0], ws[len(ws) // 2], ws[-1]][:per_class]
     t0 = time.perf_counter()
-    for k in sorted(by_class):
-        # lanes per cell (each with its smallest whole-group item), then cells per item
-        best_t, best = math.inf, (lanes[k], cpi[k])
-        for g in LANES_CANDIDATES[k]:
-            lanes[k] = g
-            cpi[k] = (cpi_candidates(g)[0] if g else
-                      heuristic_cpi(W.max_mean_occupancy(by_class[k][0])))
-            apply_settings()
+    lanes, cpi = {}, {}
+    for k in sorted(picks):
+        B = _probe_batch(picks[k], device, seed)
+        own = {slot: B.cell_lanes(slot) for slot in range(len(picks[k]))}
+
+        def apply_settings(g, c):
+            for slot, w in enumerate(picks[k]):
+                gl = own[slot] if g == AUTO else g
+                B.set_cell_lanes(slot, gl)
+                if c is None:   # default binning item for the lanes setting
+                    c_slot = 64 if gl > 0 else heuristic_cpi(W.max_mean_occupancy(w))
+                else:
+                    c_slot = c
+                B.set_cells_per_item(slot, c_slot)
+
+        best_t, best = math.inf, (AUTO, None)
+        for g in LANES_CANDIDATES:
+            apply_settings(g, None)
             dt = _time_run(B, steps, repeats)
             if dt < best_t:
-                best_t, best = dt, (g, cpi[k])
-        lanes[k] = best[0]
-        for c in cpi_candidates(lanes[k]):
-            cpi[k] = c
-            apply_settings()
+                best_t, best = dt, (g, None)
+        for c in CPI_CANDIDATES:
+            apply_settings(best[0], c)
             dt = _time_run(B, steps, repeats)
             if dt < best_t:
-                best_t, best = dt, (lanes[k], c)
+                best_t, best = dt, (best[0], c)
         lanes[k], cpi[k] = best
-    apply_settings()
+        B.close()
+    # the binning launch shape, all classes together
+    probes = [w for k in sorted(picks) for w in picks[k]]
+    B = _probe_batch(probes, device, seed)
+    apply(B, {"cells_per_item": {str(k): v for k, v in cpi.items()},
+              "cell_lanes": {str(k): v for k, v in lanes.items()}},
+          dict(enumerate(probes)), use_graphs=False)
     best_t, best_p = math.inf, 0
     for pw in PERSISTENT_CANDIDATES:
         B.set_launch(pw, False)
@@ -144,15 +142,22 @@ def load(path: str = DEFAULT_TABLE) -> dict | None:
 
 
 def apply(B: Batch, table: dict, events_by_slot: dict, use_graphs: bool = True) -> None:
-    """Sets each slot's lanes per cell and cells per item from its occupancy
-    class and the batch's launch shape from the table."""
+    """Sets each slot's lanes per cell and cells per binning item from its
+    occupancy class (AUTO or no entry: the event's own library default) and
+    the batch's launch shape from the table."""
     for slot, w in events_by_slot.items():
-        m = W.max_mean_occupancy(w)
-        k = occupancy_class(m)
-        g = table.get("cell_lanes", {}).get(str(k))
-        g = int(g) if g is not None else heuristic_lanes(m)
-        c = table["cells_per_item"].get(str(k))
-        c = int(c) if c else heuristic_cpi(m)
-        B.set_cell_lanes(slot, g)
-        B.set_cells_per_item(slot, c)
+        settings_for(B, slot, w, table)
     B.set_launch(int(table.get("persistent_waves", 0)), use_graphs)
+
+
+def settings_for(B: Batch, slot: int, w, table: dict) -> None:
+    """Applies the table's class settings to one admitted event."""
+    m = W.max_mean_occupancy(w)
+    k = str(occupancy_class(m))
+    g = table.get("cell_lanes", {}).get(k)
+    if g is not None and int(g) != AUTO:
+        B.set_cell_lanes(slot, int(g))
+    c = table.get("cells_per_item", {}).get(k)
+    if c is None:
+        c = 64 if B.cell_lanes(slot) > 0 else heuristic_cpi(m)
+    B.set_cells_per_item(slot, int(c))

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -112,15 +113,37 @@ int derive(const cuba_params *p, Derived &d) {
   return CUBA_OK;
 }
 
-// Lanes per cell from the mean occupancy: small-cell groups while a group
-// of that many lanes holds the typical cell with room for its fluctuations,
-// one wave per cell beyond.
-uint32_t default_lanes(int64_t n, int64_t n_cells) {
-  const double mean = n_cells > 0 ? (double)n / (double)n_cells : 0.0;
-  if (mean <= 4.0) return 8;
-  if (mean <= 11.0) return 16;
-  if (mean <= 24.0) return 32;
+// Lanes per cell from the occupancy at init: the smallest group that all
+// but a small fraction of the cells fit (oversize cells cost a second
+// kernel), else one wave per cell; one wave per cell also for boxes of
+// fewer cells than a few waves per SIMD, whose steps are bound by launch
+// latency, which the second kernel adds to.  over[k] = cells holding more
+// than 8 << k particles.
+constexpr double kOversizeFraction = 2e-3;
+constexpr int64_t kSmallCellsMinCells = 16384;
+uint32_t default_lanes(const uint32_t over[4], int64_t n_cells) {
+  if (n_cells < kSmallCellsMinCells) return 0;
+  const double limit = kOversizeFraction * (double)n_cells;
+  for (uint32_t k = 0; k < 4; ++k)
+    if ((double)over[k] <= limit) return 8u << k;
   return 0;
+}
+
+void destroy_side(SideStream &sd) {
+  if (sd.fork) (void)hipEventDestroy(sd.fork);
+  if (sd.join) (void)hipEventDestroy(sd.join);
+  if (sd.stream) (void)hipStreamDestroy(sd.stream);
+  sd = SideStream{};
+}
+
+// A non-blocking stream of default priority and two timing-free events.
+hipError_t create_side(SideStream &sd) {
+  sd = SideStream{};
+  hipError_t e = hipStreamCreateWithFlags(&sd.stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&sd.join, hipEventDisableTiming);
+  if (e != hipSuccess) destroy_side(sd);
+  return e;
 }
 
 // Pairs can only be accepted when the Philox high word w1 is below this:
@@ -198,6 +221,10 @@ void drop_timing(cuba_ctx *c) {
 // and the compact offsets are built before the collisions.
 int run_steps(cuba_ctx *c, int32_t nsteps, const TraceArgs *trace_in) {
   if (nsteps <= 0) return CUBA_OK;
+  // the oversize-cell kernel follows the small-cell kernel on the same
+  // stream: a fork to a second stream and back costs more per step than
+  // the overlap gains for a single event (measured on MI355X)
+  const SideStream *side = nullptr;
   stage(c, kStageBin, [&] {
     launch_stream_bin(c->buf[c->cur], c->buf[c->cur ^ 1], c->d.n_cells, c->lanes, c->d.g,
                       c->status,
@@ -207,8 +234,7 @@ int run_steps(cuba_ctx *c, int32_t nsteps, const TraceArgs *trace_in) {
   for (int32_t s = 1; s < nsteps; ++s) {
     stage(c, kStageStep, [&] {
       launch_step(c->buf[c->cur], c->buf[c->cur ^ 1], true, c->d.n_cells, c->lanes,
-                  c->next_step,
-                  c->pa, c->d.g, c->status, nullptr, c->stream);
+                  c->next_step, c->pa, c->d.g, c->status, nullptr, c->stream, side);
     });
     c->cur ^= 1;
     c->next_step += 1;
@@ -223,8 +249,8 @@ int run_steps(cuba_ctx *c, int32_t nsteps, const TraceArgs *trace_in) {
   }
   stage(c, kStageCollide, [&] {
     launch_step(c->buf[c->cur], c->buf[c->cur ^ 1], false, c->d.n_cells, c->lanes,
-                c->next_step,
-                c->pa, c->d.g, c->status, trace_in ? &tr : nullptr, c->stream);
+                c->next_step, c->pa, c->d.g, c->status, trace_in ? &tr : nullptr, c->stream,
+                side);
   });
   c->next_step += 1;
   return check_launch("step launch");
@@ -270,7 +296,6 @@ int cuba_init(cuba_ctx **out, const cuba_params *params, int64_t n, const double
   c->pa.key1 = (uint32_t)(params->seed >> 32);
   c->n = n;
   c->next_step = params->step0;
-  c->lanes = default_lanes(n, d.n_cells);
   c->stream = (hipStream_t)stream;
   char *ws = (char *)workspace;
   c->status = (DevStatus *)(ws + L.status);
@@ -297,19 +322,23 @@ int cuba_init(cuba_ctx **out, const cuba_params *params, int64_t n, const double
   launch_fill_u32(c->buf[0].count, 0u, d.n_cells, c->stream);
   launch_fill_u32(c->buf[1].count, 0u, d.n_cells, c->stream);
   launch_init_bin(x, y, z, px, py, pz, c->buf[0], n, d.g, c->status, c->stream);
+  launch_occupancy_over(c->buf[0], d.n_cells, c->status, c->stream);
   rc = check_launch("init launch");
   if (rc != CUBA_OK) {
     delete c;
     return rc;
   }
-  uint32_t err = 0;
-  hipError_t e = hipMemcpyAsync(&err, &c->status->err, sizeof(err),
-                                hipMemcpyDeviceToHost, c->stream);
+  uint32_t head[5] = {0, 0, 0, 0, 0};  // err, over[4]
+  static_assert(offsetof(DevStatus, over) == sizeof(uint32_t), "status layout");
+  hipError_t e = hipMemcpyAsync(head, &c->status->err, sizeof(head), hipMemcpyDeviceToHost,
+                                c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     delete c;
     return hip_fail(e, "init check");
   }
+  const uint32_t err = head[0];
+  c->lanes = default_lanes(head + 1, d.n_cells);
   if (err & kErrRange) {
     delete c;
     return fail(CUBA_ERANGE,
@@ -501,6 +530,7 @@ struct cuba_batch {
   std::vector<int32_t> slot_cpi;
   std::vector<int32_t> table_slots;  // slots in table order
   BatchSpaces spaces{};  // unit counts of the work spaces (device begins in dev_begin)
+  SideStream side{};     // library-owned stream for concurrent kernels of a step
   uint32_t max_cap = 0;
   bool dirty = true;
   uint32_t persistent_waves = 0;
@@ -656,6 +686,11 @@ int cuba_batch_create(cuba_batch **out, int32_t max_slots, void *workspace,
       (uint32_t *)((char *)workspace + align256((size_t)max_slots * sizeof(BatchEvent)));
   b->slot_ctx.assign(max_slots, nullptr);
   b->slot_cpi.assign(max_slots, 1);
+  const hipError_t e = create_side(b->side);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(e, "batch side stream");
+  }
   *out = b;
   return CUBA_OK;
 }
@@ -740,7 +775,7 @@ int cuba_batch_step(cuba_batch *b, int32_t nsteps) {
         hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "graph capture begin");
         launch_batch_run(b->dev_table, b->spaces, n_events, nsteps, b->persistent_waves,
-                         b->max_cap, b->stream, nullptr, nullptr);
+                         b->max_cap, b->stream, &b->side, nullptr, nullptr);
         e = hipStreamEndCapture(b->stream, &graph);
         if (e != hipSuccess) return hip_fail(e, "graph capture end");
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -752,7 +787,7 @@ int cuba_batch_step(cuba_batch *b, int32_t nsteps) {
       if (e != hipSuccess) return hip_fail(e, "graph launch");
     } else {
       launch_batch_run(b->dev_table, b->spaces, n_events, nsteps, b->persistent_waves,
-                       b->max_cap, b->stream, b->timing ? batch_between : nullptr, b);
+                       b->max_cap, b->stream, &b->side, b->timing ? batch_between : nullptr, b);
       const int rc = check_launch("batch run launch");
       if (rc != CUBA_OK) return rc;
     }
@@ -829,9 +864,11 @@ int cuba_batch_timing_end(cuba_batch *b, double stage_ms[CUBA_NUM_STAGES],
 void cuba_batch_destroy(cuba_batch *b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->stream);
+  (void)hipStreamSynchronize(b->side.stream);
   drop_graphs(b);
   drop_batch_timing(b);
   for (cuba_ctx *c : b->slot_ctx) cuba_destroy(c);
+  destroy_side(b->side);
   delete b;
 }
 

@@ -40,7 +40,8 @@ struct Cells {
 constexpr uint32_t kCounterSlots = 256;
 struct DevStatus {
   uint32_t err;
-  uint32_t pad[63];
+  uint32_t over[4];  // cells holding more than 8, 16, 32, 64 particles (filled at init)
+  uint32_t pad[59];
   unsigned long long pairs[kCounterSlots];   // pair tests
   unsigned long long cand[kCounterSlots];    // pairs with u < P22
   unsigned long long claims[kCounterSlots];  // scatterings
@@ -96,6 +97,13 @@ inline bool valid_cell_lanes(int32_t v) {
   return v == 0 || v == 8 || v == 16 || v == 32 || v == 64;
 }
 
+// A second stream on which a step runs work that is independent of the
+// work on the main stream (fork: main -> side, join: side -> main).
+struct SideStream {
+  hipStream_t stream;
+  hipEvent_t fork, join;
+};
+
 // Launchers (kernels.hip).  All asynchronous on stream s.
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s);
 void launch_init_bin(const double *x, const double *y, const double *z,
@@ -107,9 +115,15 @@ void launch_stream_bin(const Cells &src, const Cells &dst, int64_t n_cells, uint
                        hipStream_t s);
 void launch_offsets(const Cells &cur, uint32_t *offsets, uint32_t *tile_sums,
                     int64_t n_cells, hipStream_t s);
+// One collision launch (fused: then streaming + binning of the next step).
+// lanes > 0: the small-cell kernel on s and, concurrently on side (if not
+// NULL; else after it on s), the kernel for the cells it leaves alone.
 void launch_step(const Cells &src, const Cells &dst, bool fused, int64_t n_cells,
                  uint32_t lanes, uint32_t t, const PairArgs &pa, const Geometry &g, DevStatus *status,
-                 const TraceArgs *trace, hipStream_t s);
+                 const TraceArgs *trace, hipStream_t s, const SideStream *side);
+// Counts the cells of cur holding more than 8, 16, 32 and 64 particles into
+// status->over (which must be zero).
+void launch_occupancy_over(const Cells &cur, int64_t n_cells, DevStatus *status, hipStream_t s);
 void launch_observe(const Cells &cur, const Geometry &g, double vol, double *cell_sums,
                     double *T00, double *T0x, hipStream_t s);
 // A run of k >= 1 steps of every event in the device table ev (n_events
@@ -120,12 +134,14 @@ void launch_observe(const Cells &cur, const Geometry &g, double vol, double *cel
 // cells; for events with lanes = 0, one unit per cell.  max_cap: the largest
 // cell capacity among the events (selects the LDS size).  persistent_waves
 // > 0 caps the binning grid (persistent waves taking items with a grid
-// stride).  between (may be NULL) is called before each step of the run with
+// stride).  Each step runs the small-cell chunks on s and, concurrently on
+// side (if not NULL), the one-wave-per-cell events and the oversize cells.
+// between (may be NULL) is called before each step of the run with
 // its kind (0 stream-bin, 1 fused step, 2 collide) and with -1 after the last
 // one: a hook for stage timing.
 void launch_batch_run(BatchEvent *ev, const BatchSpaces &spaces, uint32_t n_events, int32_t k,
                       uint32_t persistent_waves, uint32_t max_cap, hipStream_t s,
-                      void (*between)(void *, int), void *ctx);
+                      const SideStream *side, void (*between)(void *, int), void *ctx);
 void launch_gather_by_id(const Cells &cur, int64_t n_cells, double *x, double *y,
                          double *z, double *px, double *py, double *pz, hipStream_t s);
 

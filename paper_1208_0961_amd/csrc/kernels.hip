@@ -47,7 +47,7 @@ __device__ __forceinline__ uint32_t aggregated_fetch_add(uint32_t *ctr, uint32_t
   uint64_t todo = __ballot(active);
   while (todo != 0) {
     const int l = __builtin_ctzll(todo);
-    const uint32_t lkey = __shfl(key, l);
+    const uint32_t lkey = (uint32_t)__builtin_amdgcn_readlane((int)key, l);
     const uint64_t group = __ballot(active && key == lkey);
     if (active && key == lkey) {
       leader = (uint32_t)l;
@@ -101,6 +101,79 @@ __device__ __forceinline__ void append(const Cells &dst, uint32_t c2, bool activ
   }
 }
 
+// One particle in registers.
+struct Particle {
+  double x, y, z, px, py, pz;
+  uint32_t id;
+};
+
+__device__ __forceinline__ Particle load_particle(const SoA &st, size_t o) {
+  return Particle{st.x[o], st.y[o], st.z[o], st.px[o], st.py[o], st.pz[o], st.id[o]};
+}
+
+__device__ __forceinline__ void store_particle(const Cells &dst, uint32_t c2, uint32_t slot,
+                                               const Particle &q, DevStatus *status) {
+  if (slot < dst.cap) {
+    const size_t o = (size_t)c2 * dst.cap + slot;
+    dst.st.x[o] = q.x;
+    dst.st.y[o] = q.y;
+    dst.st.z[o] = q.z;
+    dst.st.px[o] = q.px;
+    dst.st.py[o] = q.py;
+    dst.st.pz[o] = q.pz;
+    dst.st.id[o] = q.id;
+  } else {
+    atomicOr(&status->err, kErrCapacity);
+  }
+}
+
+// Appends two particles per lane (a and b, up to 128 per wave) to cells ca
+// and cb of dst: the 128 keys are grouped by ballots (ALU only), the group's
+// leader (its lowest lane, among the a particles first) adds the group size
+// to the cell's count, and all leaders' atomics are in flight together, so
+// the wave waits for one round trip for both halves.  A lane may lead one
+// group through its a particle and one through its b particle.
+__device__ __forceinline__ void append_two(const Cells &dst, uint32_t ca, bool act_a,
+                                           const Particle &qa, uint32_t cb, bool act_b,
+                                           const Particle &qb, DevStatus *status) {
+  const uint32_t lane = lane_id();
+  const uint64_t below = (1ull << lane) - 1ull;
+  uint32_t lead_a = lane, lead_b = lane, sel_a = 0, sel_b = 0, rank_a = 0, rank_b = 0;
+  uint32_t size_via_a = 0, size_via_b = 0;
+  uint64_t todo_a = __ballot(act_a), todo_b = __ballot(act_b);
+  while ((todo_a | todo_b) != 0) {
+    const bool from_a = todo_a != 0;
+    const int l = __builtin_ctzll(from_a ? todo_a : todo_b);
+    const uint32_t key = (uint32_t)__builtin_amdgcn_readlane((int)(from_a ? ca : cb), l);
+    const bool in_a = act_a && ca == key, in_b = act_b && cb == key;
+    const uint64_t ma = __ballot(in_a), mb = __ballot(in_b);
+    const uint32_t na = (uint32_t)__popcll(ma);
+    if (in_a) {
+      lead_a = (uint32_t)l;
+      sel_a = from_a ? 0u : 1u;
+      rank_a = (uint32_t)__popcll(ma & below);
+    }
+    if (in_b) {
+      lead_b = (uint32_t)l;
+      sel_b = from_a ? 0u : 1u;
+      rank_b = na + (uint32_t)__popcll(mb & below);
+    }
+    if (lane == (uint32_t)l) {
+      if (from_a) size_via_a = na + (uint32_t)__popcll(mb);
+      else size_via_b = (uint32_t)__popcll(mb);
+    }
+    todo_a &= ~ma;
+    todo_b &= ~mb;
+  }
+  uint32_t base0 = 0, base1 = 0;
+  if (size_via_a != 0) base0 = atomicAdd(&dst.count[ca], size_via_a);
+  if (size_via_b != 0) base1 = atomicAdd(&dst.count[cb], size_via_b);
+  const uint32_t a0 = __shfl(base0, (int)lead_a), a1 = __shfl(base1, (int)lead_a);
+  const uint32_t b0 = __shfl(base0, (int)lead_b), b1 = __shfl(base1, (int)lead_b);
+  if (act_a) store_particle(dst, ca, (sel_a ? a1 : a0) + rank_a, qa, status);
+  if (act_b) store_particle(dst, cb, (sel_b ? b1 : b0) + rank_b, qb, status);
+}
+
 __device__ __forceinline__ uint32_t occupancy(const Cells &c, uint32_t cell) {
   const uint32_t n = c.count[cell];
   return n < c.cap ? n : c.cap;
@@ -140,6 +213,20 @@ __global__ __launch_bounds__(kBlock) void k_init_bin(
   append(dst, cell, active, a, b, c, qa, qb, qc, (uint32_t)i, status);
 }
 
+// Cells holding more than 8, 16, 32, 64 particles (ballot counts, one
+// atomic per wave and threshold).
+__global__ __launch_bounds__(kBlock) void k_occupancy_over(Cells cur, uint32_t n_cells,
+                                                           uint32_t *over) {
+  const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t n = c < n_cells ? occupancy(cur, c) : 0u;
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (uint32_t k = 0; k < 4; ++k) {
+    const uint32_t cnt = (uint32_t)__popcll(__ballot(n > (8u << k)));
+    if (lane == 0 && cnt != 0) atomicAdd(&over[k], cnt);
+  }
+}
+
 // Stream + reflect + bin the particles of the source cells c0 .. c_end - 1
 // (at most 64 / G of them), G lanes per cell; G = 64 is one wave per cell.
 // Clears the source counts, so the source buffer can receive the next
@@ -154,6 +241,30 @@ __device__ __forceinline__ void cells_stream_bin(const Cells &src, const Cells &
   const bool in_range = c < c_end;
   const uint32_t n = in_range ? occupancy(src, c) : 0u;
   const size_t base = (size_t)c * src.cap;
+  if (G == 64) {
+    // one cell: 128 particles per round, both halves' atomics in flight together
+    for (uint32_t j0 = 0; j0 < n; j0 += 128) {
+      const uint32_t ja = j0 + lane, jb = j0 + 64 + lane;
+      const bool act_a = ja < n, act_b = jb < n;
+      Particle qa{}, qb{};
+      if (act_a) qa = load_particle(src.st, base + ja);
+      if (act_b) qb = load_particle(src.st, base + jb);
+      uint32_t ca = 0, cb = 0;
+      if (act_a) {
+        advance<true>(g, qa.x, qa.y, qa.z, qa.px, qa.py, qa.pz);
+        ca = cell_id(g, qa.x, qa.y, qa.z);
+        if (trace_cell) trace_cell[qa.id] = ca;
+      }
+      if (act_b) {
+        advance<true>(g, qb.x, qb.y, qb.z, qb.px, qb.py, qb.pz);
+        cb = cell_id(g, qb.x, qb.y, qb.z);
+        if (trace_cell) trace_cell[qb.id] = cb;
+      }
+      append_two(dst, ca, act_a, qa, cb, act_b, qb, status);
+    }
+    if (in_range && gl == 0) src.count[c] = 0u;
+    return;
+  }
   for (uint32_t j0 = 0; __ballot(j0 < n) != 0; j0 += G) {
     const uint32_t j = j0 + gl;
     const bool active = j < n;
@@ -1098,17 +1209,33 @@ void launch_offsets(const Cells &cur, uint32_t *offsets, uint32_t *tile_sums,
 
 namespace {
 
+// fork: work queued on s so far precedes the work then queued on side
+void fork(hipStream_t s, const SideStream *side) {
+  if (!side) return;
+  (void)hipEventRecord(side->fork, s);
+  (void)hipStreamWaitEvent(side->stream, side->fork, 0);
+}
+
+// join: the work queued on side precedes the work then queued on s
+void join(hipStream_t s, const SideStream *side) {
+  if (!side) return;
+  (void)hipEventRecord(side->join, side->stream);
+  (void)hipStreamWaitEvent(s, side->join, 0);
+}
+
 template <bool kFused, bool kTrace, uint32_t kCap>
 void launch_step_cap(const Cells &src, const Cells &dst, uint32_t n_cells, uint32_t lanes,
                      uint32_t t, const PairArgs &pa, const Geometry &g, DevStatus *status,
-                     const TraceArgs &tr, hipStream_t s) {
+                     const TraceArgs &tr, hipStream_t s, const SideStream *side) {
   const dim3 block(64);
   if (lanes == 0) {
     hipLaunchKernelGGL((k_step<kFused, kTrace, kCap>), dim3(n_cells), block, 0, s, src, dst,
                        t, pa, g, status, tr);
     return;
   }
-  // the small cells, then the cells the small-cell kernel left alone
+  // the small cells and, concurrently, the cells the small-cell kernel
+  // leaves alone (disjoint cells; both append to dst through atomics)
+  fork(s, side);
   const dim3 grid((n_cells + 64 / lanes - 1) / (64 / lanes));
   switch (lanes) {
     case 8:
@@ -1128,36 +1255,47 @@ void launch_step_cap(const Cells &src, const Cells &dst, uint32_t n_cells, uint3
                          n_cells, t, pa, g, status, tr);
   }
   hipLaunchKernelGGL((k_step_large<kFused, kTrace, kCap>), dim3((n_cells + 63) / 64), block,
-                     0, s, src, dst, n_cells, lanes, t, pa, g, status, tr);
+                     0, side ? side->stream : s, src, dst, n_cells, lanes, t, pa, g, status, tr);
+  join(s, side);
 }
 
 template <uint32_t kCap>
 void launch_step_any(const Cells &src, const Cells &dst, bool fused, uint32_t n_cells,
                      uint32_t lanes, uint32_t t, const PairArgs &pa, const Geometry &g,
-                     DevStatus *status, const TraceArgs *trace, hipStream_t s) {
+                     DevStatus *status, const TraceArgs *trace, hipStream_t s,
+                     const SideStream *side) {
   if (trace)
-    launch_step_cap<false, true, kCap>(src, dst, n_cells, lanes, t, pa, g, status, *trace, s);
+    launch_step_cap<false, true, kCap>(src, dst, n_cells, lanes, t, pa, g, status, *trace, s,
+                                       side);
   else if (fused)
     launch_step_cap<true, false, kCap>(src, dst, n_cells, lanes, t, pa, g, status,
-                                       TraceArgs{}, s);
+                                       TraceArgs{}, s, side);
   else
     launch_step_cap<false, false, kCap>(src, dst, n_cells, lanes, t, pa, g, status,
-                                        TraceArgs{}, s);
+                                        TraceArgs{}, s, side);
 }
 
 }  // namespace
 
 void launch_step(const Cells &src, const Cells &dst, bool fused, int64_t n_cells,
                  uint32_t lanes, uint32_t t, const PairArgs &pa, const Geometry &g,
-                 DevStatus *status, const TraceArgs *trace, hipStream_t s) {
+                 DevStatus *status, const TraceArgs *trace, hipStream_t s,
+                 const SideStream *side) {
   if (n_cells <= 0) return;
   // cells of at most 512 slots use the kernels with half the LDS
   if (src.cap <= kSmallCap)
     launch_step_any<kSmallCap>(src, dst, fused, (uint32_t)n_cells, lanes, t, pa, g, status,
-                               trace, s);
+                               trace, s, side);
   else
     launch_step_any<kCellCap>(src, dst, fused, (uint32_t)n_cells, lanes, t, pa, g, status,
-                              trace, s);
+                              trace, s, side);
+}
+
+void launch_occupancy_over(const Cells &cur, int64_t n_cells, DevStatus *status,
+                           hipStream_t s) {
+  if (n_cells <= 0) return;
+  hipLaunchKernelGGL(k_occupancy_over, dim3(grid_for(n_cells)), dim3(kBlock), 0, s, cur,
+                     (uint32_t)n_cells, status->over);
 }
 
 void launch_observe(const Cells &cur, const Geometry &g, double vol, double *cell_sums,
@@ -1172,7 +1310,7 @@ void launch_observe(const Cells &cur, const Geometry &g, double vol, double *cel
 
 void launch_batch_run(BatchEvent *ev, const BatchSpaces &sp, uint32_t n_events, int32_t k,
                       uint32_t persistent_waves, uint32_t max_cap, hipStream_t s,
-                      void (*between)(void *, int), void *ctx) {
+                      const SideStream *side, void (*between)(void *, int), void *ctx) {
   if (n_events == 0 || sp.n_items == 0 || k <= 0) return;
   const uint32_t bin_waves =
       persistent_waves > 0 && persistent_waves < sp.n_items ? persistent_waves : sp.n_items;
@@ -1182,20 +1320,26 @@ void launch_batch_run(BatchEvent *ev, const BatchSpaces &sp, uint32_t n_events, 
   if (between) between(ctx, 0);
   hipLaunchKernelGGL(k_batch_bin, dim3(bin_grid), dim3(kBlock), 0, s, cev, sp.item_begin,
                      n_events, sp.n_items);
-  // launch j: the small cells, the oversize cells of small-cell events, and
-  // the cells of events stepped one wave per cell (each kernel if it has work)
+  // launch j: the small cells on s; concurrently on the side stream the
+  // cells of events stepped one wave per cell, then the oversize cells of
+  // small-cell events (all disjoint cells; appends go through atomics)
   auto step = [&](auto fused, auto cap, uint32_t j) {
     constexpr bool kF = decltype(fused)::value;
     constexpr uint32_t kC = decltype(cap)::value;
+    const bool both = sp.n_chunks > 0 && (sp.n_cells > 0 || sp.n_scans > 0);
+    const SideStream *sd = both ? side : nullptr;
+    const hipStream_t s2 = sd ? sd->stream : s;
+    fork(s, sd);
     if (sp.n_chunks > 0)
       hipLaunchKernelGGL((k_batch_step_small<kF>), dim3(sp.n_chunks), wave, 0, s, cev,
                          sp.chunk_begin, n_events, j);
-    if (sp.n_scans > 0)
-      hipLaunchKernelGGL((k_batch_step_scan<kF, kC>), dim3(sp.n_scans), wave, 0, s, cev,
-                         sp.scan_begin, n_events, j);
     if (sp.n_cells > 0)
-      hipLaunchKernelGGL((k_batch_step_cells<kF, kC>), dim3(sp.n_cells), wave, 0, s, cev,
+      hipLaunchKernelGGL((k_batch_step_cells<kF, kC>), dim3(sp.n_cells), wave, 0, s2, cev,
                          sp.cell_begin, n_events, j);
+    if (sp.n_scans > 0)
+      hipLaunchKernelGGL((k_batch_step_scan<kF, kC>), dim3(sp.n_scans), wave, 0, s2, cev,
+                         sp.scan_begin, n_events, j);
+    join(s, sd);
   };
   using Fused = std::integral_constant<bool, true>;
   using Last = std::integral_constant<bool, false>;

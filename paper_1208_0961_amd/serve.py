@@ -101,13 +101,7 @@ class Server:
         self.B.admit(slot, {**req.work.params(), "cell_capacity": W.capacity_for(req.work)},
                      state)
         if self.tuning:
-            m = W.max_mean_occupancy(req.work)
-            k = AT.occupancy_class(m)
-            g = self.tuning.get("cell_lanes", {}).get(str(k))
-            self.B.set_cell_lanes(slot, int(g) if g is not None else AT.heuristic_lanes(m))
-            c = self.tuning["cells_per_item"].get(str(k))
-            if c:
-                self.B.set_cells_per_item(slot, int(c))
+            AT.settings_for(self.B, slot, req.work, self.tuning)
 
     def run(self, requests: list[Request], realtime: bool = True) -> list[Result]:
         """Serves the requests; with realtime, a request is only admitted once
