@@ -38,7 +38,14 @@ struct Layout {
   size_t soa[2][7];  // x y z px py pz id, for the two buffers (C x cap slots)
   size_t count[2];   // per-cell occupancy of the two buffers
   size_t offsets, tile_sums, cell_sums;
+  size_t consts;  // device copies of the two buffer descriptors and the geometry
   size_t total;
+};
+
+// The descriptors the kernels read from device memory.
+struct DeviceConsts {
+  Cells buf[2];
+  Geometry g;
 };
 
 Layout make_layout(int64_t n_cells, uint32_t cap) {
@@ -61,6 +68,7 @@ Layout make_layout(int64_t n_cells, uint32_t cap) {
   L.offsets = take((cc + 1) * sizeof(uint32_t));
   L.tile_sums = take(tiles * sizeof(uint32_t));
   L.cell_sums = take(cc * 2 * sizeof(double));
+  L.consts = take(sizeof(DeviceConsts));
   L.total = off;
   return L;
 }
@@ -175,6 +183,7 @@ struct cuba_ctx {
   int cur;
   uint32_t *offsets, *tile_sums;
   double *cell_sums;
+  DeviceConsts *consts;  // in the workspace
   // stage timing (cuba_timing_begin / cuba_timing_end)
   bool timing = false;
   size_t timing_cap = 0;
@@ -215,6 +224,11 @@ void drop_timing(cuba_ctx *c) {
   c->timing_cap = 0;
 }
 
+// Device copies of the current step's destination descriptor and geometry.
+StepDevice step_device(const cuba_ctx *c) {
+  return StepDevice{&c->consts->buf[c->cur ^ 1], &c->consts->g};
+}
+
 // nsteps steps: stream + bin into the other buffer, then nsteps - 1 fused
 // steps (collide, then stream + bin into the other buffer), then the last
 // collisions in place.  With a trace (nsteps = 1) the binning records cells
@@ -234,7 +248,8 @@ int run_steps(cuba_ctx *c, int32_t nsteps, const TraceArgs *trace_in) {
   for (int32_t s = 1; s < nsteps; ++s) {
     stage(c, kStageStep, [&] {
       launch_step(c->buf[c->cur], c->buf[c->cur ^ 1], true, c->d.n_cells, c->lanes,
-                  c->next_step, c->pa, c->d.g, c->status, nullptr, c->stream, side);
+                  c->next_step, c->pa, c->d.g, c->status, nullptr, c->stream, side,
+                  step_device(c));
     });
     c->cur ^= 1;
     c->next_step += 1;
@@ -250,7 +265,7 @@ int run_steps(cuba_ctx *c, int32_t nsteps, const TraceArgs *trace_in) {
   stage(c, kStageCollide, [&] {
     launch_step(c->buf[c->cur], c->buf[c->cur ^ 1], false, c->d.n_cells, c->lanes,
                 c->next_step, c->pa, c->d.g, c->status, trace_in ? &tr : nullptr, c->stream,
-                side);
+                side, step_device(c));
   });
   c->next_step += 1;
   return check_launch("step launch");
@@ -314,13 +329,23 @@ int cuba_init(cuba_ctx **out, const cuba_params *params, int64_t n, const double
   c->offsets = (uint32_t *)(ws + L.offsets);
   c->tile_sums = (uint32_t *)(ws + L.tile_sums);
   c->cell_sums = (double *)(ws + L.cell_sums);
+  c->consts = (DeviceConsts *)(ws + L.consts);
   c->cur = 0;
+  DeviceConsts hc{};
+  hc.buf[0] = c->buf[0];
+  hc.buf[1] = c->buf[1];
+  hc.g = d.g;
 
   // clear status and counts, then check and bin the particles
   launch_fill_u32((uint32_t *)c->status, 0u, sizeof(DevStatus) / sizeof(uint32_t),
                   c->stream);
   launch_fill_u32(c->buf[0].count, 0u, d.n_cells, c->stream);
   launch_fill_u32(c->buf[1].count, 0u, d.n_cells, c->stream);
+  hipError_t e = hipMemcpyAsync(c->consts, &hc, sizeof(hc), hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "init constants");
+  }
   launch_init_bin(x, y, z, px, py, pz, c->buf[0], n, d.g, c->status, c->stream);
   launch_occupancy_over(c->buf[0], d.n_cells, c->status, c->stream);
   rc = check_launch("init launch");
@@ -330,8 +355,7 @@ int cuba_init(cuba_ctx **out, const cuba_params *params, int64_t n, const double
   }
   uint32_t head[5] = {0, 0, 0, 0, 0};  // err, over[4]
   static_assert(offsetof(DevStatus, over) == sizeof(uint32_t), "status layout");
-  hipError_t e = hipMemcpyAsync(head, &c->status->err, sizeof(head), hipMemcpyDeviceToHost,
-                                c->stream);
+  e = hipMemcpyAsync(head, &c->status->err, sizeof(head), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     delete c;

@@ -888,12 +888,17 @@ __global__ __launch_bounds__(64) void k_step_large(Cells src, Cells dst, uint32_
                                          lds);
 }
 
+// dst and g are read from device memory where the binning uses them: as
+// kernel arguments they would be loaded at entry and held through the pair
+// loop, which spills scalar registers into vector lanes and reloads them in
+// the loop.
 template <bool kFused, bool kTrace, uint32_t kCap>
-__global__ __launch_bounds__(64) void k_step(Cells src, Cells dst, uint32_t t,
-                                             PairArgs pa, Geometry g,
+__global__ __launch_bounds__(64) void k_step(Cells src, const Cells *__restrict__ dstp,
+                                             uint32_t t, PairArgs pa,
+                                             const Geometry *__restrict__ gp,
                                              DevStatus *status, TraceArgs tr) {
   __shared__ CellLds<kFused, kCap> lds;
-  cell_step<kFused, kTrace, kCap>(src, dst, xcd_runs<8>(blockIdx.x, gridDim.x), t, pa, g,
+  cell_step<kFused, kTrace, kCap>(src, *dstp, xcd_runs<8>(blockIdx.x, gridDim.x), t, pa, *gp,
                                   status, tr, lds);
 }
 
@@ -1053,9 +1058,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
   __shared__ CellLds<kFused, kCap> lds;
   const uint32_t unit = xcd_runs<8>(blockIdx.x, gridDim.x);
   const BatchEvent *__restrict__ E = ev + find_event(cell_begin, n_events, unit);
-  const EventView v = event_view(E, j);
-  cell_step<kFused, false, kCap>(v.src, v.dst, unit - E->cell_begin, v.t, v.pa, v.g, v.status,
-                                 TraceArgs{}, lds);
+  // dst and g by reference into the table, read where the binning uses
+  // them (see k_step)
+  const uint32_t s = (E->cur ^ (j & 1u)) & 1u;
+  const Cells src = E->buf[s];
+  const PairArgs pa = E->pa;
+  cell_step<kFused, false, kCap>(src, E->buf[s ^ 1u], unit - E->cell_begin, E->t + j - 1u, pa,
+                                 E->g, E->status, TraceArgs{}, lds);
 }
 
 // End of a run of k steps: every event moved k buffers and k step indices.
@@ -1226,11 +1235,12 @@ void join(hipStream_t s, const SideStream *side) {
 template <bool kFused, bool kTrace, uint32_t kCap>
 void launch_step_cap(const Cells &src, const Cells &dst, uint32_t n_cells, uint32_t lanes,
                      uint32_t t, const PairArgs &pa, const Geometry &g, DevStatus *status,
-                     const TraceArgs &tr, hipStream_t s, const SideStream *side) {
+                     const TraceArgs &tr, hipStream_t s, const SideStream *side,
+                     const StepDevice &dev) {
   const dim3 block(64);
   if (lanes == 0) {
-    hipLaunchKernelGGL((k_step<kFused, kTrace, kCap>), dim3(n_cells), block, 0, s, src, dst,
-                       t, pa, g, status, tr);
+    hipLaunchKernelGGL((k_step<kFused, kTrace, kCap>), dim3(n_cells), block, 0, s, src,
+                       dev.dst, t, pa, dev.g, status, tr);
     return;
   }
   // the small cells and, concurrently, the cells the small-cell kernel
@@ -1263,16 +1273,16 @@ template <uint32_t kCap>
 void launch_step_any(const Cells &src, const Cells &dst, bool fused, uint32_t n_cells,
                      uint32_t lanes, uint32_t t, const PairArgs &pa, const Geometry &g,
                      DevStatus *status, const TraceArgs *trace, hipStream_t s,
-                     const SideStream *side) {
+                     const SideStream *side, const StepDevice &dev) {
   if (trace)
     launch_step_cap<false, true, kCap>(src, dst, n_cells, lanes, t, pa, g, status, *trace, s,
-                                       side);
+                                       side, dev);
   else if (fused)
     launch_step_cap<true, false, kCap>(src, dst, n_cells, lanes, t, pa, g, status,
-                                       TraceArgs{}, s, side);
+                                       TraceArgs{}, s, side, dev);
   else
     launch_step_cap<false, false, kCap>(src, dst, n_cells, lanes, t, pa, g, status,
-                                        TraceArgs{}, s, side);
+                                        TraceArgs{}, s, side, dev);
 }
 
 }  // namespace
@@ -1280,15 +1290,15 @@ void launch_step_any(const Cells &src, const Cells &dst, bool fused, uint32_t n_
 void launch_step(const Cells &src, const Cells &dst, bool fused, int64_t n_cells,
                  uint32_t lanes, uint32_t t, const PairArgs &pa, const Geometry &g,
                  DevStatus *status, const TraceArgs *trace, hipStream_t s,
-                 const SideStream *side) {
+                 const SideStream *side, const StepDevice &dev) {
   if (n_cells <= 0) return;
   // cells of at most 512 slots use the kernels with half the LDS
   if (src.cap <= kSmallCap)
     launch_step_any<kSmallCap>(src, dst, fused, (uint32_t)n_cells, lanes, t, pa, g, status,
-                               trace, s, side);
+                               trace, s, side, dev);
   else
     launch_step_any<kCellCap>(src, dst, fused, (uint32_t)n_cells, lanes, t, pa, g, status,
-                              trace, s, side);
+                              trace, s, side, dev);
 }
 
 void launch_occupancy_over(const Cells &cur, int64_t n_cells, DevStatus *status,
