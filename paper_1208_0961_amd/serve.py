@@ -209,6 +209,13 @@ def bench(a):
     from . import autotune as AT
     n_req = int(a.requests)
     tuning = AT.load()
+    # untimed warm-up of both paths (first launches load code objects and
+    # grow the allocator's pools)
+    warm = request_stream(16, 0.0, seed=56)
+    srv = Server(tuning=tuning, use_graphs=False)
+    srv.run(warm, realtime=False)
+    srv.close()
+    run_alone(warm[0])
     # capacity: a closed batch of 64 requests all present at t = 0
     probe = request_stream(64, 0.0, seed=55)
     srv = Server(tuning=tuning, use_graphs=False)
