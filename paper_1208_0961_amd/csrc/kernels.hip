@@ -13,9 +13,10 @@
 //                  rank counting, all n(n-1)/2 pair tests over the lanes with
 //                  a Philox block each, ballot compaction of the pairs that
 //                  can pass, exact Eq. (3) test on those, greedy claim in
-//                  pair order, CM kinematics.  With F (fused) the same wave
-//                  then streams and bins its particles for step t+1, so the
-//                  binning traffic overlaps the ALU-bound pair tests.
+//                  pair order, CM kinematics (written back in place).  With
+//                  F (fused) the same wave then streams and bins its
+//                  particles for step t+1, so the binning traffic overlaps
+//                  the ALU-bound pair tests.
 //   observe        per-cell sums of E and p_x, then fixed-order slab sums.
 //   gather         state export by id.
 // A run of n steps is one stream_bin, n-1 fused steps and one collide-only
@@ -423,15 +424,13 @@ __device__ __forceinline__ void resolve_filtered(
   __syncthreads();
 }
 
-// LDS of one wave's cell: s_buf holds the cell's ids while the canonical
+// LDS of one wave's cell: buf holds the cell's ids while the canonical
 // order is built; after that its first half holds the filtered pairs and its
-// second half the claimed pairs.  s_mark flags (by storage index) the
-// particles whose scattering already binned them (fused steps only).
+// second half the claimed pairs.
 template <bool kFused, uint32_t kCap>
 struct CellLds {
   __align__(16) uint32_t buf[kCap];
   uint16_t perm[kCap];
-  uint8_t mark[kFused ? kCap : 1];
 };
 
 // Collisions of cell c of src at step t (one wave).  kFused: afterwards
@@ -449,7 +448,6 @@ __device__ __forceinline__ void cell_step(const Cells &src, const Cells &dst, ui
   uint32_t *const s_filt = lds.buf;
   uint32_t *const s_claim = lds.buf + kFilt;
   uint16_t *const s_perm = lds.perm;
-  uint8_t *const s_mark = lds.mark;
   __syncthreads();
 
   const uint32_t lane = lane_id();
@@ -467,21 +465,41 @@ __device__ __forceinline__ void cell_step(const Cells &src, const Cells &dst, ui
     const uint32_t n4 = (n + 3u) & ~3u;
     for (uint32_t j = lane; j < n4; j += 64)
       s_id[j] = j < n ? st.id[cv.base + j] : 0xFFFFFFFFu;
-    if (kFused)
-      for (uint32_t j = lane; j < n; j += 64) s_mark[j] = 0;
     __syncthreads();
 
-    // canonical order: the rank of each id among the cell's ids
+    // canonical order: the rank of each id among the cell's ids; two
+    // particles per lane while at least 65 remain (one pass over the ids
+    // serves both), then one
     const uint4 *s_id4 = reinterpret_cast<const uint4 *>(s_id);
-    for (uint32_t j = lane; j < n; j += 64) {
-      const uint32_t me = s_id[j];
-      uint32_t r = 0;
+    uint32_t j0 = 0;
+    for (; j0 + 64u < n; j0 += 128u) {
+      const uint32_t ja = j0 + lane, jb = j0 + 64u + lane;
+      const uint32_t mea = s_id[ja], meb = jb < n ? s_id[jb] : 0u;
+      uint32_t ra = 0, rb = 0;
       for (uint32_t m = 0; m < n4 / 4; ++m) {
         const uint4 q = s_id4[m];
-        r += (q.x < me) + (q.y < me) + (q.z < me) + (q.w < me);
+        ra += (q.x < mea) + (q.y < mea) + (q.z < mea) + (q.w < mea);
+        rb += (q.x < meb) + (q.y < meb) + (q.z < meb) + (q.w < meb);
       }
-      s_perm[r] = (uint16_t)j;
-      if (kTrace && tr.perm) tr.perm[tr.offsets[cv.c] + r] = me;
+      s_perm[ra] = (uint16_t)ja;
+      if (kTrace && tr.perm) tr.perm[tr.offsets[cv.c] + ra] = mea;
+      if (jb < n) {
+        s_perm[rb] = (uint16_t)jb;
+        if (kTrace && tr.perm) tr.perm[tr.offsets[cv.c] + rb] = meb;
+      }
+    }
+    if (j0 < n) {
+      const uint32_t j = j0 + lane;
+      if (j < n) {
+        const uint32_t me = s_id[j];
+        uint32_t r = 0;
+        for (uint32_t m = 0; m < n4 / 4; ++m) {
+          const uint4 q = s_id4[m];
+          r += (q.x < me) + (q.y < me) + (q.z < me) + (q.w < me);
+        }
+        s_perm[r] = (uint16_t)j;
+        if (kTrace && tr.perm) tr.perm[tr.offsets[cv.c] + r] = me;
+      }
     }
     __syncthreads();
 
@@ -544,8 +562,8 @@ __device__ __forceinline__ void cell_step(const Cells &src, const Cells &dst, ui
       atomicAdd(&status->claims[slot], (unsigned long long)nclaim);
     }
 
-    // kinematics of the claimed pairs (disjoint: one writer per particle).
-    // Fused: the lane that scattered a pair also streams and bins it.
+    // kinematics of the claimed pairs (disjoint: one writer per particle),
+    // written back in place; a fused step then bins every particle
     for (uint32_t i0 = 0; i0 < nclaim; i0 += 64) {
       const uint32_t i = i0 + lane;
       const bool active = i < nclaim;
@@ -568,14 +586,12 @@ __device__ __forceinline__ void cell_step(const Cells &src, const Cells &dst, ui
         by = st.py[ib];
         bz = st.pz[ib];
         scatter_pair(ax, ay, az, bx, by, bz, uc, uphi);
-        if (!kFused) {
-          st.px[ia] = ax;
-          st.py[ia] = ay;
-          st.pz[ia] = az;
-          st.px[ib] = bx;
-          st.py[ib] = by;
-          st.pz[ib] = bz;
-        }
+        st.px[ia] = ax;
+        st.py[ia] = ay;
+        st.pz[ia] = az;
+        st.px[ib] = bx;
+        st.py[ib] = by;
+        st.pz[ib] = bz;
         if (kTrace && tr.claim) {
           const uint32_t slot = atomicAdd(&tr.counts[1], 1u);
           if (slot < tr.claim_cap) {
@@ -587,32 +603,6 @@ __device__ __forceinline__ void cell_step(const Cells &src, const Cells &dst, ui
           }
         }
       }
-      if (kFused) {
-        double x = 0, y = 0, z = 0;
-        uint32_t id = 0, c2 = 0;
-        if (active) {
-          const size_t ia = cv.base + ja;
-          x = st.x[ia];
-          y = st.y[ia];
-          z = st.z[ia];
-          id = st.id[ia];
-          s_mark[ja] = 1;
-          advance<true>(g, x, y, z, ax, ay, az);
-          c2 = cell_id(g, x, y, z);
-        }
-        append(dst, c2, active, x, y, z, ax, ay, az, id, status);
-        if (active) {
-          const size_t ib = cv.base + jb;
-          x = st.x[ib];
-          y = st.y[ib];
-          z = st.z[ib];
-          id = st.id[ib];
-          s_mark[jb] = 1;
-          advance<true>(g, x, y, z, bx, by, bz);
-          c2 = cell_id(g, x, y, z);
-        }
-        append(dst, c2, active, x, y, z, bx, by, bz, id, status);
-      }
     }
     if (kFused) __syncthreads();
   } else if (kTrace && n == 1 && lane == 0 && tr.perm) {
@@ -620,10 +610,11 @@ __device__ __forceinline__ void cell_step(const Cells &src, const Cells &dst, ui
   }
 
   if (kFused) {
-    // stream and bin the particles that did not scatter
+    // stream and bin every particle (scattered momenta were written back
+    // in place; the barrier above makes them visible to all lanes)
     for (uint32_t j0 = 0; j0 < n; j0 += 64) {
       const uint32_t j = j0 + lane;
-      const bool active = j < n && (n < 2 || nclaim == 0 || s_mark[j] == 0);
+      const bool active = j < n;
       double x = 0, y = 0, z = 0, px = 0, py = 0, pz = 0;
       uint32_t id = 0, c2 = 0;
       if (active) {
