@@ -424,6 +424,23 @@ __device__ __forceinline__ void resolve_filtered(
   __syncthreads();
 }
 
+// Cells of more than kBucketRankMin particles rank their ids through
+// kRankBuckets buckets by value; smaller cells count all ids.
+constexpr uint32_t kRankBuckets = 256;
+constexpr uint32_t kBucketRankMin = 48;
+
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
+  return v;
+}
+
 // LDS of one wave's cell: buf holds the cell's ids while the canonical
 // order is built; after that its first half holds the filtered pairs and its
 // second half the claimed pairs.
@@ -431,6 +448,8 @@ template <bool kFused, uint32_t kCap>
 struct CellLds {
   __align__(16) uint32_t buf[kCap];
   uint16_t perm[kCap];
+  __align__(16) uint32_t bkt[kRankBuckets + 4];  // bucket ends, then starts
+  uint32_t sorted[kCap];                         // ids in bucket order
 };
 
 // Collisions of cell c of src at step t (one wave).  kFused: afterwards
@@ -467,37 +486,75 @@ __device__ __forceinline__ void cell_step(const Cells &src, const Cells &dst, ui
       s_id[j] = j < n ? st.id[cv.base + j] : 0xFFFFFFFFu;
     __syncthreads();
 
-    // canonical order: the rank of each id among the cell's ids; two
-    // particles per lane while at least 65 remain (one pass over the ids
-    // serves both), then one
-    const uint4 *s_id4 = reinterpret_cast<const uint4 *>(s_id);
-    uint32_t j0 = 0;
-    for (; j0 + 64u < n; j0 += 128u) {
-      const uint32_t ja = j0 + lane, jb = j0 + 64u + lane;
-      const uint32_t mea = s_id[ja], meb = jb < n ? s_id[jb] : 0u;
-      uint32_t ra = 0, rb = 0;
-      for (uint32_t m = 0; m < n4 / 4; ++m) {
-        const uint4 q = s_id4[m];
-        ra += (q.x < mea) + (q.y < mea) + (q.z < mea) + (q.w < mea);
-        rb += (q.x < meb) + (q.y < meb) + (q.z < meb) + (q.w < meb);
+    // canonical order: the rank of each id among the cell's ids
+    if (n > kBucketRankMin) {
+      // Counting by buckets of the id value (monotone in the id, so the
+      // rank is exact whatever the ids): the bucket's start plus the number
+      // of smaller ids in the same bucket.  Bucket b holds the ids with
+      // (id - lo) >> shift == b, shift chosen so that b < kRankBuckets.
+      uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+      for (uint32_t j = lane; j < n; j += 64) {
+        const uint32_t v = s_id[j];
+        lo = min(lo, v);
+        hi = max(hi, v);
       }
-      s_perm[ra] = (uint16_t)ja;
-      if (kTrace && tr.perm) tr.perm[tr.offsets[cv.c] + ra] = mea;
-      if (jb < n) {
-        s_perm[rb] = (uint16_t)jb;
-        if (kTrace && tr.perm) tr.perm[tr.offsets[cv.c] + rb] = meb;
+      lo = wave_min(lo);
+      hi = wave_max(hi);
+      const uint32_t bits = 32u - (uint32_t)__builtin_clz(hi - lo);  // hi > lo: ids differ
+      const uint32_t shift = bits > 8u ? bits - 8u : 0u;
+      uint32_t *const s_bkt = lds.bkt;
+      uint32_t *const s_sorted = lds.sorted;
+      for (uint32_t b = lane; b < kRankBuckets; b += 64) s_bkt[b] = 0u;
+      if (lane == 0) s_bkt[kRankBuckets] = n;
+      __syncthreads();
+      for (uint32_t j = lane; j < n; j += 64) atomicAdd(&s_bkt[(s_id[j] - lo) >> shift], 1u);
+      __syncthreads();
+      {  // inclusive scan of the counts: s_bkt[b] = end of bucket b
+        uint4 q = reinterpret_cast<uint4 *>(s_bkt)[lane];
+        q.y += q.x;
+        q.z += q.y;
+        q.w += q.z;
+        uint32_t incl = q.w;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const uint32_t up = (uint32_t)__shfl_up((int)incl, o);
+          if ((int)lane >= o) incl += up;
+        }
+        const uint32_t excl = incl - q.w;
+        q.x += excl;
+        q.y += excl;
+        q.z += excl;
+        q.w += excl;
+        reinterpret_cast<uint4 *>(s_bkt)[lane] = q;
       }
-    }
-    if (j0 < n) {
-      const uint32_t j = j0 + lane;
-      if (j < n) {
-        const uint32_t me = s_id[j];
+      __syncthreads();
+      // each bucket filled from its end: afterwards s_bkt[b] is its start
+      for (uint32_t j = lane; j < n; j += 64) {
+        const uint32_t v = s_id[j];
+        const uint32_t pos = atomicSub(&s_bkt[(v - lo) >> shift], 1u) - 1u;
+        s_sorted[pos] = v;
+      }
+      __syncthreads();
+      for (uint32_t j = lane; j < n; j += 64) {
+        const uint32_t me = s_id[j], b = (me - lo) >> shift;
+        const uint32_t p1 = s_bkt[b + 1];
+        uint32_t r = s_bkt[b];
+        for (uint32_t p = r; p < p1; ++p) r += s_sorted[p] < me ? 1u : 0u;
+        s_perm[r] = (uint16_t)j;
+        if (kTrace && tr.perm) tr.perm[tr.offsets[cv.c] + r] = me;
+      }
+    } else {
+      // at most kBucketRankMin < 64 particles: one per lane, counting all ids
+      const uint4 *s_id4 = reinterpret_cast<const uint4 *>(s_id);
+      static_assert(kBucketRankMin < 64, "one particle per lane");
+      if (lane < n) {
+        const uint32_t me = s_id[lane];
         uint32_t r = 0;
         for (uint32_t m = 0; m < n4 / 4; ++m) {
           const uint4 q = s_id4[m];
           r += (q.x < me) + (q.y < me) + (q.z < me) + (q.w < me);
         }
-        s_perm[r] = (uint16_t)j;
+        s_perm[r] = (uint16_t)lane;
         if (kTrace && tr.perm) tr.perm[tr.offsets[cv.c] + r] = me;
       }
     }

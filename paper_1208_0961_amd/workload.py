@@ -184,9 +184,12 @@ def max_mean_occupancy(w: Workload) -> float:
     return w.r_test * gluon_density(w.T_left) * vcell
 
 
-def capacity_for(w: Workload, headroom: float = 2.0, margin: int = 32) -> int:
+def capacity_for(w: Workload, headroom: float = 1.5, margin: int = 32) -> int:
     """Cell capacity from the expected occupancy (mean + 5 sigma on the
-    denser side), as suggest_cell_capacity would choose from a sample."""
+    denser side) with headroom for the flow (a cell that overflows is
+    reported as an error at the next sync).  1.5x keeps the densest ensemble
+    events at <= 512 slots, the limit of the kernels with the smaller LDS
+    footprint."""
     m = max_mean_occupancy(w)
     occ = m + 5.0 * math.sqrt(m) + 2.0
     cap = int(math.ceil((headroom * occ + margin) / 32.0)) * 32
