@@ -549,13 +549,12 @@ struct cuba_batch {
   int32_t max_slots = 0;
   hipStream_t stream = nullptr;
   BatchEvent *dev_table = nullptr;  // in the caller's batch workspace
-  uint32_t *dev_begin = nullptr;  // 4 x max_slots: first unit per event of each work space
+  uint32_t *dev_begin = nullptr;  // kSpaces x max_slots: first unit per event of each work space
   std::vector<cuba_ctx *> slot_ctx;
   std::vector<int32_t> slot_cpi;
   std::vector<int32_t> table_slots;  // slots in table order
   BatchSpaces spaces{};  // unit counts of the work spaces (device begins in dev_begin)
   SideStream side{};     // library-owned stream for concurrent kernels of a step
-  uint32_t max_cap = 0;
   bool dirty = true;
   uint32_t persistent_waves = 0;
   bool use_graphs = false;
@@ -595,13 +594,18 @@ int32_t default_cpi(const cuba_ctx *c) {
   return cpi;
 }
 
+// Work spaces of a batch: binning items, small-cell chunks, oversize scans,
+// and the one-wave-per-cell spaces of small and large cell capacity.
+constexpr int kSpaces = 5;
+
 // Rebuilds the device table and the work spaces from the live slots (in
 // slot order).
 int upload_table(cuba_batch *b) {
   std::vector<BatchEvent> host;
   b->table_slots.clear();
-  uint64_t items = 0, chunks = 0, scans = 0, cells = 0;
-  b->max_cap = 0;
+  uint64_t items = 0, chunks = 0, scans = 0, cells[2] = {0, 0};
+  bool scan_large = false;
+  std::vector<int> cell_space;
   for (int32_t s = 0; s < b->max_slots; ++s) {
     cuba_ctx *c = b->slot_ctx[s];
     if (!c || c->d.n_cells == 0) continue;
@@ -616,22 +620,25 @@ int upload_table(cuba_batch *b) {
     e.cur = (uint32_t)c->cur;
     e.t = c->next_step;
     e.lanes = c->lanes;
+    const int space = c->d.cap <= kSmallCap ? 0 : 1;
     e.item_begin = (uint32_t)items;
     e.chunk_begin = (uint32_t)chunks;
     e.scan_begin = (uint32_t)scans;
-    e.cell_begin = (uint32_t)cells;
+    e.cell_begin = (uint32_t)cells[space];
     items += (e.n_cells + e.cpi - 1) / e.cpi;
     if (c->lanes > 0) {
       const uint64_t per = 64 / c->lanes;
       chunks += (e.n_cells + per - 1) / per;
       scans += (e.n_cells + 63) / 64;
+      if (space == 1) scan_large = true;
     } else {
-      cells += e.n_cells;
+      cells[space] += e.n_cells;
     }
     // grid sizes stay below 2^31 workgroups
-    if (items >= 0x80000000ull || chunks >= 0x80000000ull || cells >= 0x80000000ull)
+    if (items >= 0x80000000ull || chunks >= 0x80000000ull || cells[0] >= 0x80000000ull ||
+        cells[1] >= 0x80000000ull)
       return fail(CUBA_EINVAL, "too many cells in the batch for one launch");
-    if (c->d.cap > b->max_cap) b->max_cap = c->d.cap;
+    cell_space.push_back(c->lanes > 0 ? -1 : space);
     host.push_back(e);
     b->table_slots.push_back(s);
   }
@@ -640,18 +647,27 @@ int upload_table(cuba_batch *b) {
   b->spaces.item_begin = b->dev_begin;
   b->spaces.chunk_begin = b->dev_begin + stride;
   b->spaces.scan_begin = b->dev_begin + 2 * stride;
-  b->spaces.cell_begin = b->dev_begin + 3 * stride;
+  b->spaces.cell_begin[0] = b->dev_begin + 3 * stride;
+  b->spaces.cell_begin[1] = b->dev_begin + 4 * stride;
   b->spaces.n_items = (uint32_t)items;
   b->spaces.n_chunks = (uint32_t)chunks;
   b->spaces.n_scans = (uint32_t)scans;
-  b->spaces.n_cells = (uint32_t)cells;
+  b->spaces.n_cells[0] = (uint32_t)cells[0];
+  b->spaces.n_cells[1] = (uint32_t)cells[1];
+  b->spaces.scan_large = scan_large;
   if (ne > 0) {
-    std::vector<uint32_t> begins(4 * stride, 0u);
+    // an event outside a cells space gets that space's running total (the
+    // next event's begin), so the lookup never lands on it
+    std::vector<uint32_t> begins(kSpaces * stride, 0u);
+    uint32_t run[2] = {0, 0};
     for (size_t i = 0; i < ne; ++i) {
       begins[i] = host[i].item_begin;
       begins[stride + i] = host[i].chunk_begin;
       begins[2 * stride + i] = host[i].scan_begin;
-      begins[3 * stride + i] = host[i].cell_begin;
+      for (int sp = 0; sp < 2; ++sp) {
+        begins[(3 + sp) * stride + i] = run[sp];
+        if (cell_space[i] == sp) run[sp] += host[i].n_cells;
+      }
     }
     hipError_t e = hipMemcpyAsync(b->dev_table, host.data(), ne * sizeof(BatchEvent),
                                   hipMemcpyHostToDevice, b->stream);
@@ -689,7 +705,7 @@ extern "C" {
 size_t cuba_batch_workspace_bytes(int32_t max_slots) {
   if (max_slots < 1) return 0;
   return align256((size_t)max_slots * sizeof(BatchEvent)) +
-         align256(4 * (size_t)max_slots * sizeof(uint32_t));
+         align256((size_t)kSpaces * max_slots * sizeof(uint32_t));
 }
 
 int cuba_batch_create(cuba_batch **out, int32_t max_slots, void *workspace,
@@ -799,7 +815,7 @@ int cuba_batch_step(cuba_batch *b, int32_t nsteps) {
         hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "graph capture begin");
         launch_batch_run(b->dev_table, b->spaces, n_events, nsteps, b->persistent_waves,
-                         b->max_cap, b->stream, &b->side, nullptr, nullptr);
+                         b->stream, &b->side, nullptr, nullptr);
         e = hipStreamEndCapture(b->stream, &graph);
         if (e != hipSuccess) return hip_fail(e, "graph capture end");
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -811,7 +827,7 @@ int cuba_batch_step(cuba_batch *b, int32_t nsteps) {
       if (e != hipSuccess) return hip_fail(e, "graph launch");
     } else {
       launch_batch_run(b->dev_table, b->spaces, n_events, nsteps, b->persistent_waves,
-                       b->max_cap, b->stream, &b->side, b->timing ? batch_between : nullptr, b);
+                       b->stream, &b->side, b->timing ? batch_between : nullptr, b);
       const int rc = check_launch("batch run launch");
       if (rc != CUBA_OK) return rc;
     }

@@ -79,15 +79,17 @@ struct BatchEvent {
   uint32_t lanes;       // lanes per cell (0: one wave per cell; 8, 16, 32, 64)
   uint32_t chunk_begin; // first small-cell chunk (64 / lanes cells), if lanes > 0
   uint32_t scan_begin;  // first oversize-cell scan unit (64 cells), if lanes > 0
-  uint32_t cell_begin;  // first unit of the one-wave-per-cell space, if lanes = 0
+  uint32_t cell_begin;  // first unit in its one-wave-per-cell space, if lanes = 0
+                        // (space 0: cell capacity <= kSmallCap, space 1: larger)
   uint32_t pad[3];
 };
 
 // The work spaces of a batch run (see launch_batch_run): unit counts and,
 // per event in table order, the first unit of each space (device arrays).
 struct BatchSpaces {
-  const uint32_t *item_begin, *chunk_begin, *scan_begin, *cell_begin;
-  uint32_t n_items, n_chunks, n_scans, n_cells;
+  const uint32_t *item_begin, *chunk_begin, *scan_begin, *cell_begin[2];
+  uint32_t n_items, n_chunks, n_scans, n_cells[2];
+  bool scan_large;  // some small-cell event has a cell capacity > kSmallCap
 };
 
 // Lanes-per-cell settings of the cell kernels: 0 runs one wave per cell;
@@ -140,8 +142,10 @@ void launch_observe(const Cells &cur, const Geometry &g, double vol, double *cel
 // the table advance.  The work spaces: items of cells_per_item cells for the
 // binning (every event); for events with lanes per cell > 0, small-cell
 // chunks of 64 / lanes cells and scan units of 64 cells for their oversize
-// cells; for events with lanes = 0, one unit per cell.  max_cap: the largest
-// cell capacity among the events (selects the LDS size).  persistent_waves
+// cells; for events with lanes = 0, one unit per cell, in two spaces by cell
+// capacity (<= kSmallCap and larger), each stepped by the kernel with the
+// LDS for its capacity, so that one large event does not lower the
+// occupancy of all the others.  persistent_waves
 // > 0 caps the binning grid (persistent waves taking items with a grid
 // stride).  Each step runs the small-cell chunks on s and, concurrently on
 // side (if not NULL), the one-wave-per-cell events and the oversize cells.
@@ -149,8 +153,8 @@ void launch_observe(const Cells &cur, const Geometry &g, double vol, double *cel
 // its kind (0 stream-bin, 1 fused step, 2 collide) and with -1 after the last
 // one: a hook for stage timing.
 void launch_batch_run(BatchEvent *ev, const BatchSpaces &spaces, uint32_t n_events, int32_t k,
-                      uint32_t persistent_waves, uint32_t max_cap, hipStream_t s,
-                      const SideStream *side, void (*between)(void *, int), void *ctx);
+                      uint32_t persistent_waves, hipStream_t s, const SideStream *side,
+                      void (*between)(void *, int), void *ctx);
 void launch_gather_by_id(const Cells &cur, int64_t n_cells, double *x, double *y,
                          double *z, double *px, double *py, double *pz, hipStream_t s);
 

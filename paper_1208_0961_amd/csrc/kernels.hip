@@ -1367,8 +1367,8 @@ void launch_observe(const Cells &cur, const Geometry &g, double vol, double *cel
 }
 
 void launch_batch_run(BatchEvent *ev, const BatchSpaces &sp, uint32_t n_events, int32_t k,
-                      uint32_t persistent_waves, uint32_t max_cap, hipStream_t s,
-                      const SideStream *side, void (*between)(void *, int), void *ctx) {
+                      uint32_t persistent_waves, hipStream_t s, const SideStream *side,
+                      void (*between)(void *, int), void *ctx) {
   if (n_events == 0 || sp.n_items == 0 || k <= 0) return;
   const uint32_t bin_waves =
       persistent_waves > 0 && persistent_waves < sp.n_items ? persistent_waves : sp.n_items;
@@ -1381,37 +1381,40 @@ void launch_batch_run(BatchEvent *ev, const BatchSpaces &sp, uint32_t n_events, 
   // launch j: the small cells on s; concurrently on the side stream the
   // cells of events stepped one wave per cell, then the oversize cells of
   // small-cell events (all disjoint cells; appends go through atomics)
-  auto step = [&](auto fused, auto cap, uint32_t j) {
+  auto step = [&](auto fused, uint32_t j) {
     constexpr bool kF = decltype(fused)::value;
-    constexpr uint32_t kC = decltype(cap)::value;
-    const bool both = sp.n_chunks > 0 && (sp.n_cells > 0 || sp.n_scans > 0);
+    const bool both =
+        sp.n_chunks > 0 && (sp.n_cells[0] > 0 || sp.n_cells[1] > 0 || sp.n_scans > 0);
     const SideStream *sd = both ? side : nullptr;
     const hipStream_t s2 = sd ? sd->stream : s;
     fork(s, sd);
     if (sp.n_chunks > 0)
       hipLaunchKernelGGL((k_batch_step_small<kF>), dim3(sp.n_chunks), wave, 0, s, cev,
                          sp.chunk_begin, n_events, j);
-    if (sp.n_cells > 0)
-      hipLaunchKernelGGL((k_batch_step_cells<kF, kC>), dim3(sp.n_cells), wave, 0, s2, cev,
-                         sp.cell_begin, n_events, j);
-    if (sp.n_scans > 0)
-      hipLaunchKernelGGL((k_batch_step_scan<kF, kC>), dim3(sp.n_scans), wave, 0, s2, cev,
-                         sp.scan_begin, n_events, j);
+    if (sp.n_cells[0] > 0)
+      hipLaunchKernelGGL((k_batch_step_cells<kF, kSmallCap>), dim3(sp.n_cells[0]), wave, 0, s2,
+                         cev, sp.cell_begin[0], n_events, j);
+    if (sp.n_cells[1] > 0)
+      hipLaunchKernelGGL((k_batch_step_cells<kF, kCellCap>), dim3(sp.n_cells[1]), wave, 0, s2,
+                         cev, sp.cell_begin[1], n_events, j);
+    if (sp.n_scans > 0) {
+      if (sp.scan_large)
+        hipLaunchKernelGGL((k_batch_step_scan<kF, kCellCap>), dim3(sp.n_scans), wave, 0, s2,
+                           cev, sp.scan_begin, n_events, j);
+      else
+        hipLaunchKernelGGL((k_batch_step_scan<kF, kSmallCap>), dim3(sp.n_scans), wave, 0, s2,
+                           cev, sp.scan_begin, n_events, j);
+    }
     join(s, sd);
   };
   using Fused = std::integral_constant<bool, true>;
   using Last = std::integral_constant<bool, false>;
-  using Small = std::integral_constant<uint32_t, kSmallCap>;
-  using Large = std::integral_constant<uint32_t, kCellCap>;
-  const bool small_lds = max_cap <= kSmallCap;
   for (int32_t j = 1; j < k; ++j) {
     if (between) between(ctx, 1);
-    if (small_lds) step(Fused{}, Small{}, (uint32_t)j);
-    else step(Fused{}, Large{}, (uint32_t)j);
+    step(Fused{}, (uint32_t)j);
   }
   if (between) between(ctx, 2);
-  if (small_lds) step(Last{}, Small{}, (uint32_t)k);
-  else step(Last{}, Large{}, (uint32_t)k);
+  step(Last{}, (uint32_t)k);
   if (between) between(ctx, -1);
   hipLaunchKernelGGL(k_batch_advance, dim3((n_events + 63) / 64), dim3(64), 0, s, ev,
                      n_events, (uint32_t)k);

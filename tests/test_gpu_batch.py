@@ -155,3 +155,25 @@ def test_batch_mixed_lanes_per_cell(mods):
     for i, (w, st) in enumerate(zip(evs, states)):
         assert_same(B.get_state(i), alone(sim, w, st, 13), w.name)
     B.close()
+
+
+def test_batch_mixed_cell_capacities(mods):
+    """Events of cell capacity <= 512 and > 512 are stepped by kernels of
+    different LDS size in one batch step (dense events in two one-wave-per-
+    cell spaces; a small-cell event with a large capacity takes the large
+    oversize scan); all equal the events run alone."""
+    batch, sim = mods
+    evs = small_events()
+    states = [W.riemann_state(w, seed=60 + i) for i, w in enumerate(evs)]
+    settings = [(0, 640), (0, 256), (16, 768), (0, 1024), (8, 128)]
+    B = batch.Batch(len(evs), use_graphs=True)
+    for i, ((lanes, cap), w, st) in enumerate(zip(settings, evs, states)):
+        B.admit(i, {**w.params(), "cell_capacity": cap}, st)
+        B.set_cell_lanes(i, lanes)
+    say(f"[batch] lanes/capacity {settings}")
+    for k in (5, 3):
+        B.step(k)
+    B.sync()
+    for i, (w, st) in enumerate(zip(evs, states)):
+        assert_same(B.get_state(i), alone(sim, w, st, 8), w.name)
+    B.close()
