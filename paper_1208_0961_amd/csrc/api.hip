@@ -38,13 +38,12 @@ struct Layout {
   size_t soa[2][7];  // x y z px py pz id, for the two buffers (C x cap slots)
   size_t count[2];   // per-cell occupancy of the two buffers
   size_t offsets, tile_sums, cell_sums;
-  size_t consts;  // device copies of the two buffer descriptors and the geometry
+  size_t consts;  // device copy of the geometry
   size_t total;
 };
 
-// The descriptors the kernels read from device memory.
+// What the kernels read from device memory instead of kernel arguments.
 struct DeviceConsts {
-  Cells buf[2];
   Geometry g;
 };
 
@@ -224,10 +223,8 @@ void drop_timing(cuba_ctx *c) {
   c->timing_cap = 0;
 }
 
-// Device copies of the current step's destination descriptor and geometry.
-StepDevice step_device(const cuba_ctx *c) {
-  return StepDevice{&c->consts->buf[c->cur ^ 1], &c->consts->g};
-}
+// Device copy of the geometry.
+StepDevice step_device(const cuba_ctx *c) { return StepDevice{&c->consts->g}; }
 
 // nsteps steps: stream + bin into the other buffer, then nsteps - 1 fused
 // steps (collide, then stream + bin into the other buffer), then the last
@@ -326,14 +323,24 @@ int cuba_init(cuba_ctx **out, const cuba_params *params, int64_t n, const double
     c->buf[b].count = (uint32_t *)(ws + L.count[b]);
     c->buf[b].cap = d.cap;
   }
+  // the kernels derive one buffer's arrays from the other's by a single
+  // byte distance: every array of buffer 1 lies that far from its twin
+  const ptrdiff_t shift = (char *)c->buf[1].st.x - (char *)c->buf[0].st.x;
+  for (int a = 0; a < 7; ++a)
+    if ((ptrdiff_t)(L.soa[1][a] - L.soa[0][a]) != shift) {
+      delete c;
+      return fail(CUBA_EINVAL, "internal: buffers not laid out alike");
+    }
+  if ((ptrdiff_t)(L.count[1] - L.count[0]) != shift) {
+    delete c;
+    return fail(CUBA_EINVAL, "internal: buffers not laid out alike");
+  }
   c->offsets = (uint32_t *)(ws + L.offsets);
   c->tile_sums = (uint32_t *)(ws + L.tile_sums);
   c->cell_sums = (double *)(ws + L.cell_sums);
   c->consts = (DeviceConsts *)(ws + L.consts);
   c->cur = 0;
   DeviceConsts hc{};
-  hc.buf[0] = c->buf[0];
-  hc.buf[1] = c->buf[1];
   hc.g = d.g;
 
   // clear status and counts, then check and bin the particles

@@ -117,17 +117,17 @@ void launch_stream_bin(const Cells &src, const Cells &dst, int64_t n_cells, uint
                        hipStream_t s);
 void launch_offsets(const Cells &cur, uint32_t *offsets, uint32_t *tile_sums,
                     int64_t n_cells, hipStream_t s);
-// Device copies of a step's destination descriptor and geometry, which the
-// wave-per-cell kernel reads from memory where it uses them.
+// Device copy of the geometry, which the wave-per-cell kernel reads from
+// memory where it uses it.
 struct StepDevice {
-  const Cells *dst;
   const Geometry *g;
 };
 
 // One collision launch (fused: then streaming + binning of the next step).
 // lanes > 0: the small-cell kernel on s and, concurrently on side (if not
 // NULL; else after it on s), the kernel for the cells it leaves alone.
-// dev: device copies of dst and g (equal to the host values).
+// dev: device copy of g (equal to the host value).  The buffers src and
+// dst must be laid out alike (every array at the same distance from its twin).
 void launch_step(const Cells &src, const Cells &dst, bool fused, int64_t n_cells,
                  uint32_t lanes, uint32_t t, const PairArgs &pa, const Geometry &g, DevStatus *status,
                  const TraceArgs *trace, hipStream_t s, const SideStream *side,

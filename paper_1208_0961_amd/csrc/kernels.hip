@@ -102,6 +102,26 @@ __device__ __forceinline__ void append(const Cells &dst, uint32_t c2, bool activ
   }
 }
 
+// The buffer laid out like c, `shift` bytes away.
+template <typename T>
+__device__ __forceinline__ T *shift_ptr(T *p, int64_t shift) {
+  return reinterpret_cast<T *>(reinterpret_cast<char *>(p) + shift);
+}
+
+__device__ __forceinline__ Cells shifted(const Cells &c, int64_t shift) {
+  Cells d;
+  d.st.x = shift_ptr(c.st.x, shift);
+  d.st.y = shift_ptr(c.st.y, shift);
+  d.st.z = shift_ptr(c.st.z, shift);
+  d.st.px = shift_ptr(c.st.px, shift);
+  d.st.py = shift_ptr(c.st.py, shift);
+  d.st.pz = shift_ptr(c.st.pz, shift);
+  d.st.id = shift_ptr(c.st.id, shift);
+  d.count = shift_ptr(c.count, shift);
+  d.cap = c.cap;
+  return d;
+}
+
 // One particle in registers.
 struct Particle {
   double x, y, z, px, py, pz;
@@ -668,7 +688,10 @@ __device__ __forceinline__ void cell_step(const Cells &src, const Cells &dst, ui
 
   if (kFused) {
     // stream and bin every particle (scattered momenta were written back
-    // in place; the barrier above makes them visible to all lanes)
+    // in place; the barrier above makes them visible to all lanes).  The
+    // geometry is copied to registers once: read through a reference it
+    // would be reloaded after every store.
+    const Geometry g_l = g;
     for (uint32_t j0 = 0; j0 < n; j0 += 64) {
       const uint32_t j = j0 + lane;
       const bool active = j < n;
@@ -683,8 +706,8 @@ __device__ __forceinline__ void cell_step(const Cells &src, const Cells &dst, ui
         py = st.py[o];
         pz = st.pz[o];
         id = st.id[o];
-        advance<true>(g, x, y, z, px, py, pz);
-        c2 = cell_id(g, x, y, z);
+        advance<true>(g_l, x, y, z, px, py, pz);
+        c2 = cell_id(g_l, x, y, z);
       }
       append(dst, c2, active, x, y, z, px, py, pz, id, status);
     }
@@ -936,18 +959,20 @@ __global__ __launch_bounds__(64) void k_step_large(Cells src, Cells dst, uint32_
                                          lds);
 }
 
-// dst and g are read from device memory where the binning uses them: as
-// kernel arguments they would be loaded at entry and held through the pair
-// loop, which spills scalar registers into vector lanes and reloads them in
-// the loop.
+// dst is src shifted by dst_shift bytes (the two buffers of a context are
+// laid out alike), and g is read from device memory where the binning uses
+// it: as kernel arguments both would be loaded at entry and held through the
+// pair loop, which spills scalar registers into vector lanes and reloads them
+// in the loop.  Derived from src, the dst pointers stay known to address
+// global memory.
 template <bool kFused, bool kTrace, uint32_t kCap>
-__global__ __launch_bounds__(64) void k_step(Cells src, const Cells *__restrict__ dstp,
-                                             uint32_t t, PairArgs pa,
-                                             const Geometry *__restrict__ gp,
+__global__ __launch_bounds__(64) void k_step(Cells src, int64_t dst_shift, uint32_t t,
+                                             PairArgs pa, const Geometry *__restrict__ gp,
                                              DevStatus *status, TraceArgs tr) {
   __shared__ CellLds<kFused, kCap> lds;
-  cell_step<kFused, kTrace, kCap>(src, *dstp, xcd_runs<8>(blockIdx.x, gridDim.x), t, pa, *gp,
-                                  status, tr, lds);
+  cell_step<kFused, kTrace, kCap>(src, shifted(src, dst_shift),
+                                  xcd_runs<8>(blockIdx.x, gridDim.x), t, pa, *gp, status, tr,
+                                  lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1288,7 +1313,8 @@ void launch_step_cap(const Cells &src, const Cells &dst, uint32_t n_cells, uint3
   const dim3 block(64);
   if (lanes == 0) {
     hipLaunchKernelGGL((k_step<kFused, kTrace, kCap>), dim3(n_cells), block, 0, s, src,
-                       dev.dst, t, pa, dev.g, status, tr);
+                       (int64_t)((const char *)dst.st.x - (const char *)src.st.x), t, pa,
+                       dev.g, status, tr);
     return;
   }
   // the small cells and, concurrently, the cells the small-cell kernel
