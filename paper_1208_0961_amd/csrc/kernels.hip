@@ -34,13 +34,49 @@ namespace {
 constexpr int kBlock = 256;
 constexpr uint32_t kCellsPerBlock = kBlock / 64;
 
+// Device views of the particle buffers with global-address-space pointers:
+// every kernel converts its Cells once at entry, so that all buffer accesses
+// compile to global (not flat) memory instructions, also where the pointers
+// are loaded from memory (the batch table) rather than passed as arguments.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+
+struct GSoA {
+  gptr<double> x, y, z, px, py, pz;
+  gptr<uint32_t> id;
+};
+
+struct GCells {
+  GSoA st;
+  gptr<uint32_t> count;
+  uint32_t cap;
+};
+
+__device__ __forceinline__ GCells to_global(const Cells &c) {
+  GCells g;
+  g.st.x = (gptr<double>)c.st.x;
+  g.st.y = (gptr<double>)c.st.y;
+  g.st.z = (gptr<double>)c.st.z;
+  g.st.px = (gptr<double>)c.st.px;
+  g.st.py = (gptr<double>)c.st.py;
+  g.st.pz = (gptr<double>)c.st.pz;
+  g.st.id = (gptr<uint32_t>)c.st.id;
+  g.count = (gptr<uint32_t>)c.count;
+  g.cap = c.cap;
+  return g;
+}
+
+__device__ __forceinline__ uint32_t atomic_add(gptr<uint32_t> p, uint32_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
 // Slot = old value of ctr[key] + rank of this lane among the active lanes
 // of its wave with the same key.  The lanes are grouped by key with ballots
 // first (ALU only); then every group leader issues its atomic in the same
 // instruction, so the wave waits for one atomic round trip, not one per key.
-__device__ __forceinline__ uint32_t aggregated_fetch_add(uint32_t *ctr, uint32_t key,
+__device__ __forceinline__ uint32_t aggregated_fetch_add(gptr<uint32_t> ctr, uint32_t key,
                                                          bool active) {
   const uint32_t lane = lane_id();
   const uint64_t below = (1ull << lane) - 1ull;
@@ -58,7 +94,7 @@ __device__ __forceinline__ uint32_t aggregated_fetch_add(uint32_t *ctr, uint32_t
     todo &= ~group;
   }
   uint32_t base = 0;
-  if (active && leader == lane) base = atomicAdd(&ctr[key], size);
+  if (active && leader == lane) base = atomic_add(ctr + key, size);
   base = __shfl(base, (int)leader);
   return base + rank;
 }
@@ -81,7 +117,7 @@ __device__ __forceinline__ uint32_t xcd_runs(uint32_t b, uint32_t nblocks) {
 
 // Appends particle (r, p, id) to cell c2 of dst; slots past the capacity
 // are dropped and flagged (reported as CUBA_ERANGE at the next sync).
-__device__ __forceinline__ void append(const Cells &dst, uint32_t c2, bool active,
+__device__ __forceinline__ void append(const GCells &dst, uint32_t c2, bool active,
                                        double x, double y, double z, double px,
                                        double py, double pz, uint32_t id,
                                        DevStatus *status) {
@@ -104,12 +140,12 @@ __device__ __forceinline__ void append(const Cells &dst, uint32_t c2, bool activ
 
 // The buffer laid out like c, `shift` bytes away.
 template <typename T>
-__device__ __forceinline__ T *shift_ptr(T *p, int64_t shift) {
-  return reinterpret_cast<T *>(reinterpret_cast<char *>(p) + shift);
+__device__ __forceinline__ gptr<T> shift_ptr(gptr<T> p, int64_t shift) {
+  return (gptr<T>)((gptr<char>)p + shift);
 }
 
-__device__ __forceinline__ Cells shifted(const Cells &c, int64_t shift) {
-  Cells d;
+__device__ __forceinline__ GCells shifted(const GCells &c, int64_t shift) {
+  GCells d;
   d.st.x = shift_ptr(c.st.x, shift);
   d.st.y = shift_ptr(c.st.y, shift);
   d.st.z = shift_ptr(c.st.z, shift);
@@ -128,11 +164,11 @@ struct Particle {
   uint32_t id;
 };
 
-__device__ __forceinline__ Particle load_particle(const SoA &st, size_t o) {
+__device__ __forceinline__ Particle load_particle(const GSoA &st, size_t o) {
   return Particle{st.x[o], st.y[o], st.z[o], st.px[o], st.py[o], st.pz[o], st.id[o]};
 }
 
-__device__ __forceinline__ void store_particle(const Cells &dst, uint32_t c2, uint32_t slot,
+__device__ __forceinline__ void store_particle(const GCells &dst, uint32_t c2, uint32_t slot,
                                                const Particle &q, DevStatus *status) {
   if (slot < dst.cap) {
     const size_t o = (size_t)c2 * dst.cap + slot;
@@ -154,7 +190,7 @@ __device__ __forceinline__ void store_particle(const Cells &dst, uint32_t c2, ui
 // to the cell's count, and all leaders' atomics are in flight together, so
 // the wave waits for one round trip for both halves.  A lane may lead one
 // group through its a particle and one through its b particle.
-__device__ __forceinline__ void append_two(const Cells &dst, uint32_t ca, bool act_a,
+__device__ __forceinline__ void append_two(const GCells &dst, uint32_t ca, bool act_a,
                                            const Particle &qa, uint32_t cb, bool act_b,
                                            const Particle &qb, DevStatus *status) {
   const uint32_t lane = lane_id();
@@ -187,15 +223,15 @@ __device__ __forceinline__ void append_two(const Cells &dst, uint32_t ca, bool a
     todo_b &= ~mb;
   }
   uint32_t base0 = 0, base1 = 0;
-  if (size_via_a != 0) base0 = atomicAdd(&dst.count[ca], size_via_a);
-  if (size_via_b != 0) base1 = atomicAdd(&dst.count[cb], size_via_b);
+  if (size_via_a != 0) base0 = atomic_add(dst.count + ca, size_via_a);
+  if (size_via_b != 0) base1 = atomic_add(dst.count + cb, size_via_b);
   const uint32_t a0 = __shfl(base0, (int)lead_a), a1 = __shfl(base1, (int)lead_a);
   const uint32_t b0 = __shfl(base0, (int)lead_b), b1 = __shfl(base1, (int)lead_b);
   if (act_a) store_particle(dst, ca, (sel_a ? a1 : a0) + rank_a, qa, status);
   if (act_b) store_particle(dst, cb, (sel_b ? b1 : b0) + rank_b, qb, status);
 }
 
-__device__ __forceinline__ uint32_t occupancy(const Cells &c, uint32_t cell) {
+__device__ __forceinline__ uint32_t occupancy(const GCells &c, uint32_t cell) {
   const uint32_t n = c.count[cell];
   return n < c.cap ? n : c.cap;
 }
@@ -210,8 +246,9 @@ __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, uint32_t v,
 __global__ __launch_bounds__(kBlock) void k_init_bin(
     const double *__restrict__ x, const double *__restrict__ y,
     const double *__restrict__ z, const double *__restrict__ px,
-    const double *__restrict__ py, const double *__restrict__ pz, Cells dst,
+    const double *__restrict__ py, const double *__restrict__ pz, Cells dst_arg,
     int64_t n, Geometry g, DevStatus *status) {
+  const GCells dst = to_global(dst_arg);
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool active = i < n;
   double a = 0, b = 0, c = 0, qa = 0, qb = 0, qc = 0;
@@ -236,8 +273,9 @@ __global__ __launch_bounds__(kBlock) void k_init_bin(
 
 // Cells holding more than 8, 16, 32, 64 particles (ballot counts, one
 // atomic per wave and threshold).
-__global__ __launch_bounds__(kBlock) void k_occupancy_over(Cells cur, uint32_t n_cells,
+__global__ __launch_bounds__(kBlock) void k_occupancy_over(Cells cur_arg, uint32_t n_cells,
                                                            uint32_t *over) {
+  const GCells cur = to_global(cur_arg);
   const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
   const uint32_t n = c < n_cells ? occupancy(cur, c) : 0u;
   const uint32_t lane = lane_id();
@@ -253,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_occupancy_over(Cells cur, uint32_t n
 // Clears the source counts, so the source buffer can receive the next
 // binning.
 template <uint32_t G>
-__device__ __forceinline__ void cells_stream_bin(const Cells &src, const Cells &dst,
+__device__ __forceinline__ void cells_stream_bin(const GCells &src, const GCells &dst,
                                                  uint32_t c0, uint32_t c_end,
                                                  const Geometry &g, DevStatus *status,
                                                  uint32_t *trace_cell) {
@@ -310,10 +348,12 @@ __device__ __forceinline__ void cells_stream_bin(const Cells &src, const Cells &
 
 // Four waves per block; each wave takes 64 / G consecutive source cells.
 template <uint32_t G>
-__global__ __launch_bounds__(kBlock) void k_stream_bin(Cells src, Cells dst,
+__global__ __launch_bounds__(kBlock) void k_stream_bin(Cells src_arg, Cells dst_arg,
                                                        uint32_t n_cells, Geometry g,
                                                        DevStatus *status,
                                                        uint32_t *trace_cell) {
+  const GCells src = to_global(src_arg);
+  const GCells dst = to_global(dst_arg);
   constexpr uint32_t kPer = 64 / G;
   const uint32_t c0 =
       (xcd_runs<2>(blockIdx.x, gridDim.x) * kCellsPerBlock + threadIdx.x / 64) * kPer;
@@ -324,10 +364,11 @@ __global__ __launch_bounds__(kBlock) void k_stream_bin(Cells src, Cells dst,
 
 // Exclusive scan of the counts into compact offsets (trace only; the counts
 // are left intact).  Tile-local pass, then carries from earlier tiles.
-__global__ __launch_bounds__(kBlock) void k_scan_tiles(const Cells cur,
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(Cells cur_arg,
                                                        uint32_t *offsets,
                                                        uint32_t *tile_sums,
                                                        int64_t n_cells) {
+  const GCells cur = to_global(cur_arg);
   __shared__ uint32_t s_wave[kBlock / 64];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 8;
   const uint32_t lane = lane_id(), wave = threadIdx.x / 64;
@@ -396,7 +437,7 @@ struct CellView {
 // canonical indices lane + 64 j.
 template <bool kTrace>
 __device__ __forceinline__ void resolve_filtered(
-    uint32_t nf, const CellView &cv, const PairArgs &pa, const SoA &st,
+    uint32_t nf, const CellView &cv, const PairArgs &pa, const GSoA &st,
     const uint16_t *s_perm, uint32_t *s_filt, uint32_t *s_claim,
     uint32_t &nclaim, uint32_t &claimed_bits, uint32_t &n_acc,
     const TraceArgs &tr, DevStatus *status) {
@@ -476,7 +517,7 @@ struct CellLds {
 // stream and bin the cell's particles into dst for step t+1 and clear src's
 // count.  Starts with a barrier, so a wave may call it for several cells.
 template <bool kFused, bool kTrace, uint32_t kCap>
-__device__ __forceinline__ void cell_step(const Cells &src, const Cells &dst, uint32_t c,
+__device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, uint32_t c,
                                           uint32_t t, const PairArgs &pa,
                                           const Geometry &g, DevStatus *status,
                                           const TraceArgs &tr, CellLds<kFused, kCap> &lds) {
@@ -496,7 +537,7 @@ __device__ __forceinline__ void cell_step(const Cells &src, const Cells &dst, ui
   cv.base = (size_t)cv.c * src.cap;
   cv.n = occupancy(src, cv.c);
   const uint32_t n = cv.n;
-  const SoA &st = src.st;
+  const GSoA &st = src.st;
 
   uint32_t nclaim = 0;
   if (n >= 2) {
@@ -746,7 +787,7 @@ using ClaimMask = typename std::conditional<(G == 64), uint64_t, uint32_t>::type
 // more than G particles are left alone; the result has bit grp G set for
 // each such cell c0 + grp.
 template <bool kFused, bool kTrace, uint32_t G>
-__device__ __forceinline__ uint64_t small_cells_step(const Cells &src, const Cells &dst,
+__device__ __forceinline__ uint64_t small_cells_step(const GCells &src, const GCells &dst,
                                                      uint32_t c0, uint32_t c_end,
                                                      uint32_t t, const PairArgs &pa,
                                                      const Geometry &g, DevStatus *status,
@@ -918,7 +959,7 @@ __device__ __forceinline__ uint64_t small_cells_step(const Cells &src, const Cel
 // registers of its own path (the small-cell kernel runs at twice the
 // occupancy of the wave-per-cell code).
 template <bool kFused, bool kTrace, uint32_t kCap>
-__device__ __forceinline__ void large_cells_step(const Cells &src, const Cells &dst,
+__device__ __forceinline__ void large_cells_step(const GCells &src, const GCells &dst,
                                                  uint32_t c0, uint32_t c_end, uint32_t lanes,
                                                  uint32_t t, const PairArgs &pa,
                                                  const Geometry &g, DevStatus *status,
@@ -935,9 +976,11 @@ __device__ __forceinline__ void large_cells_step(const Cells &src, const Cells &
 }
 
 template <bool kFused, bool kTrace, uint32_t G>
-__global__ __launch_bounds__(64) void k_step_small(Cells src, Cells dst, uint32_t n_cells,
+__global__ __launch_bounds__(64) void k_step_small(Cells src_arg, Cells dst_arg, uint32_t n_cells,
                                                    uint32_t t, PairArgs pa, Geometry g,
                                                    DevStatus *status, TraceArgs tr) {
+  const GCells src = to_global(src_arg);
+  const GCells dst = to_global(dst_arg);
   __shared__ SmallLds lds;
   constexpr uint32_t kPer = 64 / G;
   const uint32_t c0 = xcd_runs<8>(blockIdx.x, gridDim.x) * kPer;
@@ -948,10 +991,12 @@ __global__ __launch_bounds__(64) void k_step_small(Cells src, Cells dst, uint32_
 // One wave per 64 consecutive cells: the cells holding more than `lanes`
 // particles.
 template <bool kFused, bool kTrace, uint32_t kCap>
-__global__ __launch_bounds__(64) void k_step_large(Cells src, Cells dst, uint32_t n_cells,
+__global__ __launch_bounds__(64) void k_step_large(Cells src_arg, Cells dst_arg, uint32_t n_cells,
                                                    uint32_t lanes, uint32_t t, PairArgs pa,
                                                    Geometry g, DevStatus *status,
                                                    TraceArgs tr) {
+  const GCells src = to_global(src_arg);
+  const GCells dst = to_global(dst_arg);
   __shared__ CellLds<kFused, kCap> lds;
   const uint32_t c0 = blockIdx.x * 64u;
   const uint32_t c_end = c0 + 64u < n_cells ? c0 + 64u : n_cells;
@@ -966,9 +1011,10 @@ __global__ __launch_bounds__(64) void k_step_large(Cells src, Cells dst, uint32_
 // in the loop.  Derived from src, the dst pointers stay known to address
 // global memory.
 template <bool kFused, bool kTrace, uint32_t kCap>
-__global__ __launch_bounds__(64) void k_step(Cells src, int64_t dst_shift, uint32_t t,
+__global__ __launch_bounds__(64) void k_step(Cells src_arg, int64_t dst_shift, uint32_t t,
                                              PairArgs pa, const Geometry *__restrict__ gp,
                                              DevStatus *status, TraceArgs tr) {
+  const GCells src = to_global(src_arg);
   __shared__ CellLds<kFused, kCap> lds;
   cell_step<kFused, kTrace, kCap>(src, shifted(src, dst_shift),
                                   xcd_runs<8>(blockIdx.x, gridDim.x), t, pa, *gp, status, tr,
@@ -1016,7 +1062,7 @@ __device__ __forceinline__ uint32_t find_event(const uint32_t *__restrict__ begi
 // kernels store to global memory, so fields read through the table would
 // be reloaded after every store).
 struct EventView {
-  Cells src, dst;
+  GCells src, dst;
   Geometry g;
   PairArgs pa;
   DevStatus *status;
@@ -1026,11 +1072,11 @@ struct EventView {
 __device__ __forceinline__ EventView event_view(const BatchEvent *__restrict__ E, uint32_t j) {
   EventView v;
   if ((E->cur ^ (j & 1u)) == 0u) {
-    v.src = E->buf[0];
-    v.dst = E->buf[1];
+    v.src = to_global(E->buf[0]);
+    v.dst = to_global(E->buf[1]);
   } else {
-    v.src = E->buf[1];
-    v.dst = E->buf[0];
+    v.src = to_global(E->buf[1]);
+    v.dst = to_global(E->buf[0]);
   }
   v.g = E->g;
   v.pa = E->pa;
@@ -1048,13 +1094,13 @@ __global__ __launch_bounds__(kBlock) void k_batch_bin(const BatchEvent *__restri
   for (uint32_t item = blockIdx.x * kCellsPerBlock + w; item < n_items;
        item += gridDim.x * kCellsPerBlock) {
     const BatchEvent *__restrict__ E = ev + find_event(item_begin, n_events, item);
-    Cells src, dst;
+    GCells src, dst;
     if (E->cur == 0u) {
-      src = E->buf[0];
-      dst = E->buf[1];
+      src = to_global(E->buf[0]);
+      dst = to_global(E->buf[1]);
     } else {
-      src = E->buf[1];
-      dst = E->buf[0];
+      src = to_global(E->buf[1]);
+      dst = to_global(E->buf[0]);
     }
     const Geometry g = E->g;
     DevStatus *const status = E->status;
@@ -1131,13 +1177,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
   __shared__ CellLds<kFused, kCap> lds;
   const uint32_t unit = xcd_runs<8>(blockIdx.x, gridDim.x);
   const BatchEvent *__restrict__ E = ev + find_event(cell_begin, n_events, unit);
-  // dst and g by reference into the table, read where the binning uses
-  // them (see k_step)
+  // dst is src shifted by the distance between the event's two buffers
+  // (laid out alike), g is read by reference from the table where the
+  // binning uses it (see k_step)
   const uint32_t s = (E->cur ^ (j & 1u)) & 1u;
-  const Cells src = E->buf[s];
+  const GCells src = to_global(E->buf[s]);
+  const int64_t shift = (const char *)E->buf[s ^ 1u].st.x - (const char *)E->buf[s].st.x;
   const PairArgs pa = E->pa;
-  cell_step<kFused, false, kCap>(src, E->buf[s ^ 1u], unit - E->cell_begin, E->t + j - 1u, pa,
-                                 E->g, E->status, TraceArgs{}, lds);
+  cell_step<kFused, false, kCap>(src, shifted(src, shift), unit - E->cell_begin, E->t + j - 1u,
+                                 pa, E->g, E->status, TraceArgs{}, lds);
 }
 
 // End of a run of k steps: every event moved k buffers and k step indices.
@@ -1154,8 +1202,9 @@ __global__ void k_batch_advance(BatchEvent *ev, uint32_t n_events, uint32_t k) {
 // sums over the slab's cells in cell order.  Slab ix is the contiguous cell
 // range [ix ny nz, (ix+1) ny nz).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_observe_cells(Cells cur, uint32_t n_cells,
+__global__ __launch_bounds__(kBlock) void k_observe_cells(Cells cur_arg, uint32_t n_cells,
                                                           double *cell_sums) {
+  const GCells cur = to_global(cur_arg);
   const uint32_t lane = lane_id();
   const uint32_t c = blockIdx.x * kCellsPerBlock + threadIdx.x / 64;
   if (c >= n_cells) return;
@@ -1213,10 +1262,11 @@ __global__ __launch_bounds__(kBlock) void k_observe_slabs(const double *cell_sum
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_gather_by_id(Cells cur, uint32_t n_cells,
+__global__ __launch_bounds__(kBlock) void k_gather_by_id(Cells cur_arg, uint32_t n_cells,
                                                          double *x, double *y, double *z,
                                                          double *px, double *py,
                                                          double *pz) {
+  const GCells cur = to_global(cur_arg);
   const uint32_t lane = lane_id();
   const uint32_t c = blockIdx.x * kCellsPerBlock + threadIdx.x / 64;
   if (c >= n_cells) return;
