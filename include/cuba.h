@@ -250,6 +250,11 @@ cuba_ctx *cuba_batch_slot(cuba_batch *b, int32_t slot);
  * a cell per wave, or 64 / lanes cells per wave with lanes per cell > 0. */
 int cuba_batch_set_cells_per_item(cuba_batch *b, int32_t slot, int32_t cells);
 
+/* The profiles of a slot's event (as cuba_observe on cuba_batch_slot(b, slot),
+ * enqueued on the batch stream after the steps issued so far).  T00, T0x:
+ * device f64[nx] each.  Errors: CUBA_EINVAL for an empty slot or NULL. */
+int cuba_batch_observe(cuba_batch *b, int32_t slot, double *T00, double *T0x);
+
 /* Lanes per cell of a slot's event (as cuba_set_cell_lanes; the default is
  * cuba_init's choice); set by the autotuner. */
 int cuba_batch_set_cell_lanes(cuba_batch *b, int32_t slot, int32_t lanes);

@@ -542,6 +542,52 @@ int orc_run(const orc_params *p, int64_t n, double *x, double *y, double *z,
 /* Observables: the energy-density profile of Fig. 2 (lab-frame T^00) and  */
 /* the momentum-density profile T^0x, per slab of cells along x.           */
 /* ---------------------------------------------------------------------- */
+/* Slab moments: sums over the particles of each x-slab, then divided by
+ * the slab's physical volume (r_test dx Ly Lz), as the profiles of Sec. 5. */
+void orc_observe_moments(const orc_params *p, int64_t n, const double *x,
+                         const double *px, const double *py, const double *pz,
+                         double *T00, double *T0x, double *Txx, double *nd) {
+  double dx[3];
+  orc_constants(p, dx, NULL, NULL);
+  int32_t nx = p->cells[0];
+  for (int32_t i = 0; i < nx; ++i) T00[i] = T0x[i] = Txx[i] = nd[i] = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t ix = axis_cell(x[i], dx[0], nx);
+    double e = energy(px[i], py[i], pz[i]);
+    T00[ix] += e;
+    T0x[ix] += px[i];
+    Txx[ix] += (px[i] * px[i]) / e;
+    nd[ix] += 1.0;
+  }
+  double vol = ((p->r_test * dx[0]) * p->box[1]) * p->box[2];
+  for (int32_t i = 0; i < nx; ++i) {
+    T00[i] = T00[i] / vol;
+    T0x[i] = T0x[i] / vol;
+    Txx[i] = Txx[i] / vol;
+    nd[i] = nd[i] / vol;
+  }
+}
+
+/* The timelike eigenvector of T^mu_nu restricted to t and x: with the
+ * metric (+,-), T^mu_nu u^nu = e u^mu has the eigenvalues
+ * ((T00 - Txx) +- sqrt((T00 + Txx)^2 - 4 T0x^2)) / 2; the larger one is the
+ * rest-frame energy density, and the x-row gives T0x - Txx v = e v. */
+void orc_landau(int32_t nx, const double *T00, const double *T0x, const double *Txx,
+                double *e, double *v) {
+  for (int32_t i = 0; i < nx; ++i) {
+    /* (T00 + Txx)^2 - 4 T0x^2 as a product of two factors (no squares of
+     * large numbers); rounding can make it slightly negative at v -> 1 */
+    double a = T00[i] + Txx[i];
+    double b = 2.0 * fabs(T0x[i]);
+    double disc = (a - b) * (a + b);
+    if (disc < 0.0) disc = 0.0;
+    double ei = ((T00[i] - Txx[i]) + sqrt(disc)) / 2.0;
+    double den = ei + Txx[i];
+    e[i] = ei;
+    v[i] = den > 0.0 ? T0x[i] / den : 0.0;
+  }
+}
+
 void orc_observe(const orc_params *p, int64_t n, const double *x,
                  const double *px, const double *py, const double *pz,
                  double *T00, double *T0x) {

@@ -94,6 +94,25 @@ void orc_observe(const orc_params *p, int64_t n, const double *x,
                  const double *px, const double *py, const double *pz,
                  double *T00, double *T0x);
 
+/* Moments of the distribution over the nx slabs along x (the observables of
+ * the sigma scan, Sec. 5 / Fig. 3: the approach to ideal hydrodynamics):
+ * T00, T0x as orc_observe, T^xx[ix] = sum p_x^2 / E / (r_test dx Ly Lz)
+ * [GeV/fm^3] and the density n[ix] = count / (r_test dx Ly Lz) [fm^-3] of
+ * physical particles. */
+void orc_observe_moments(const orc_params *p, int64_t n, const double *x,
+                         const double *px, const double *py, const double *pz,
+                         double *T00, double *T0x, double *Txx, double *nd);
+
+/* Rest frame of each slab (the Landau frame of the t-x block of T^{mu nu},
+ * a reading: transverse flow is absent in the tube): the energy density e
+ * and velocity v with T^{mu nu} u_nu = e u^mu, u = gamma (1, v):
+ *   e = ((T00 - Txx) + sqrt((T00 + Txx - 2|T0x|)(T00 + Txx + 2|T0x|))) / 2,
+ *   v = T0x / (e + Txx).
+ * For an ideal fluid (T00 = (e+p) g^2 - p, T0x = (e+p) g^2 v,
+ * Txx = (e+p) g^2 v^2 + p) this returns its e and v. */
+void orc_landau(int32_t nx, const double *T00, const double *T0x, const double *Txx,
+                double *e, double *v);
+
 /* The collision of one cell with caller-supplied uniforms (for brute-force
  * tests of the claim rule).  The cell's members, in canonical order, are
  * given by their momenta (updated in place).  u_acc[k] is the acceptance

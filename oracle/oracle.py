@@ -89,6 +89,11 @@ def lib():
         L.orc_observe.argtypes = ([ctypes.POINTER(Params), ctypes.c_int64]
                                   + [dp] * 4 + [dp, dp])
         L.orc_observe.restype = None
+        L.orc_observe_moments.argtypes = ([ctypes.POINTER(Params), ctypes.c_int64]
+                                          + [dp] * 4 + [dp] * 4)
+        L.orc_observe_moments.restype = None
+        L.orc_landau.argtypes = [ctypes.c_int32] + [dp] * 5
+        L.orc_landau.restype = None
         L.orc_collide_cell_with_uniforms.argtypes = [
             ctypes.c_int32, dp, dp, dp, ctypes.c_double, dp, dp, i32p, i32p]
         L.orc_collide_cell_with_uniforms.restype = ctypes.c_int
@@ -216,6 +221,24 @@ def observe(p: Params, st: State):
     lib().orc_observe(ctypes.byref(p), st.n, _dp(st[0]), _dp(st[3]), _dp(st[4]),
                       _dp(st[5]), _dp(T00), _dp(T0x))
     return T00, T0x
+
+
+def observe_moments(p: Params, st: State):
+    """Per-slab T00, T0x, Txx [GeV/fm^3] and density n [fm^-3]."""
+    nx = int(p.cells[0])
+    out = [np.zeros(nx) for _ in range(4)]
+    lib().orc_observe_moments(ctypes.byref(p), st.n, _dp(st[0]), _dp(st[3]), _dp(st[4]),
+                              _dp(st[5]), *[_dp(a) for a in out])
+    return tuple(out)
+
+
+def landau(T00, T0x, Txx):
+    """Rest-frame energy density and velocity of each slab."""
+    T00, T0x, Txx = (np.ascontiguousarray(a, dtype=np.float64) for a in (T00, T0x, Txx))
+    e = np.zeros(len(T00))
+    v = np.zeros(len(T00))
+    lib().orc_landau(len(T00), _dp(T00), _dp(T0x), _dp(Txx), _dp(e), _dp(v))
+    return e, v
 
 
 def collide_cell_with_uniforms(p_cell, kfac, u_acc, u_kin):

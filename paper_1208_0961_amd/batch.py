@@ -103,7 +103,7 @@ class Batch:
     # -- outputs --------------------------------------------------------------
     def observe_async(self, slot: int):
         s = self.slots[slot]
-        C.cuba_observe(self.ctx(slot), s["T00"].data_ptr(), s["T0x"].data_ptr())
+        C.cuba_batch_observe(self.b, slot, s["T00"].data_ptr(), s["T0x"].data_ptr())
         return s["T00"], s["T0x"]
 
     def observe(self, slot: int):

@@ -785,6 +785,12 @@ int cuba_batch_set_cells_per_item(cuba_batch *b, int32_t slot, int32_t cells) {
   return CUBA_OK;
 }
 
+int cuba_batch_observe(cuba_batch *b, int32_t slot, double *T00, double *T0x) {
+  if (!b || slot < 0 || slot >= b->max_slots || !b->slot_ctx[slot])
+    return fail(CUBA_EINVAL, "slot is not occupied");
+  return cuba_observe(b->slot_ctx[slot], T00, T0x);
+}
+
 int cuba_batch_set_cell_lanes(cuba_batch *b, int32_t slot, int32_t lanes) {
   if (!b || slot < 0 || slot >= b->max_slots || !b->slot_ctx[slot])
     return fail(CUBA_EINVAL, "slot is not occupied");

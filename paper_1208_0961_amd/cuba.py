@@ -97,6 +97,8 @@ def _load() -> ctypes.CDLL:
     L.cuba_batch_slot.restype = vp
     L.cuba_batch_set_cells_per_item.argtypes = [vp, i32, i32]
     L.cuba_batch_set_cells_per_item.restype = ctypes.c_int
+    L.cuba_batch_observe.argtypes = [vp, i32, vp, vp]
+    L.cuba_batch_observe.restype = ctypes.c_int
     L.cuba_batch_set_cell_lanes.argtypes = [vp, i32, i32]
     L.cuba_batch_set_cell_lanes.restype = ctypes.c_int
     L.cuba_batch_set_launch.argtypes = [vp, i32, i32]
@@ -265,6 +267,10 @@ def cuba_batch_slot(b: int, slot: int):
 def cuba_batch_set_cells_per_item(b: int, slot: int, cells: int) -> None:
     _check(_lib.cuba_batch_set_cells_per_item(b, int(slot), int(cells)),
            "cuba_batch_set_cells_per_item")
+
+
+def cuba_batch_observe(b: int, slot: int, T00: int, T0x: int) -> None:
+    _check(_lib.cuba_batch_observe(b, int(slot), T00, T0x), "cuba_batch_observe")
 
 
 def cuba_batch_set_cell_lanes(b: int, slot: int, lanes: int) -> None:

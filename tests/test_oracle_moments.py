@@ -1,0 +1,110 @@
+"""Pins of the oracle's slab moments (T00, T0x, Txx, density) and of its
+rest-frame (Landau) transform, against closed forms and invariants:
+
+* an ideal fluid's stress tensor, built from (e, v) with the forward
+  relations T00 = (e+p) g^2 - p, T0x = (e+p) g^2 v, Txx = (e+p) g^2 v^2 + p,
+  p = e/3, is mapped back to the same (e, v);
+* a beam of massless particles all moving along +x (T00 = T0x = Txx) has
+  no rest frame: e = 0, v = 1;
+* per slab, T0x^2 <= T00 Txx (Cauchy-Schwarz over the slab's particles,
+  since px^2 / E = (px/sqrt(E))^2 and E = (sqrt(E))^2);
+* particles with p parallel to x have px^2 / E = E, so Txx = T00;
+* the density times the slab volume counts the slab's particles;
+* an isotropic thermal (Boltzmann, massless) gas has Txx = T00 / 3 and
+  T00 = 3 n T, its rest frame is the lab, and e equals T00.
+"""
+import numpy as np
+
+from paper_1208_0961_amd import workload as W
+
+
+def _params(orc, box=(10.0, 1.0, 1.0), cells=(20, 1, 1), r_test=10.0):
+    return orc.make_params(box, cells, 0.4, r_test, 0.02, 1)
+
+
+def test_landau_recovers_ideal_fluid_rest_frame(orc):
+    rng = np.random.default_rng(3)
+    e = rng.uniform(0.1, 30.0, 400)
+    v = rng.uniform(-0.95, 0.95, 400)
+    p = e / 3.0
+    g2 = 1.0 / (1.0 - v * v)
+    T00 = (e + p) * g2 - p
+    T0x = (e + p) * g2 * v
+    Txx = (e + p) * g2 * v * v + p
+    eL, vL = orc.landau(T00, T0x, Txx)
+    assert np.allclose(eL, e, rtol=1e-12, atol=0)
+    assert np.allclose(vL, v, rtol=1e-11, atol=1e-14)
+    # at rest: e = T00, v = 0
+    eL, vL = orc.landau(e, np.zeros_like(e), e / 3.0)
+    assert np.allclose(eL, e, rtol=1e-15) and np.all(vL == 0.0)
+
+
+def test_landau_of_a_null_beam(orc):
+    T = np.array([1.0, 2.5, 7.0])
+    eL, vL = orc.landau(T, T, T)
+    assert np.all(eL == 0.0) and np.all(vL == 1.0)
+    eL, vL = orc.landau(T, -T, T)
+    assert np.all(eL == 0.0) and np.all(vL == -1.0)
+
+
+def test_moments_invariants_random_state(orc):
+    rng = np.random.default_rng(11)
+    n = 20000
+    x = rng.uniform(0, 10, n)
+    y = rng.uniform(0, 1, n)
+    z = rng.uniform(0, 1, n)
+    pp = rng.normal(size=(n, 3)) * rng.uniform(0.05, 2.0, (n, 1))
+    pp[:, 0] += rng.uniform(-0.5, 0.5, n)        # some net flow per particle
+    p = _params(orc)
+    st = orc.State(x, y, z, pp[:, 0].copy(), pp[:, 1].copy(), pp[:, 2].copy())
+    T00, T0x, Txx, nd = orc.observe_moments(p, st)
+    assert np.all(T0x ** 2 <= T00 * Txx * (1 + 1e-12))
+    assert np.all(Txx > 0) and np.all(Txx <= T00 * (1 + 1e-15))
+    # T00 and T0x agree with orc_observe (same sums, same order)
+    o00, o0x = orc.observe(p, st)
+    assert np.array_equal(o00, T00) and np.array_equal(o0x, T0x)
+    vol = 10.0 * 0.5 * 1.0 * 1.0
+    counts = np.bincount(np.minimum((x / 0.5).astype(int), 19), minlength=20)
+    assert np.array_equal(np.rint(nd * vol).astype(int), counts)
+    assert abs((nd * vol).sum() - n) < 1e-9
+
+
+def test_moments_of_particles_along_x(orc):
+    rng = np.random.default_rng(5)
+    n = 5000
+    x = rng.uniform(0, 10, n)
+    px = rng.uniform(0.1, 3.0, n) * rng.choice([-1.0, 1.0], n)
+    zeros = np.zeros(n)
+    p = _params(orc)
+    st = orc.State(x, rng.uniform(0, 1, n), rng.uniform(0, 1, n), px, zeros.copy(),
+                   zeros.copy())
+    T00, T0x, Txx, nd = orc.observe_moments(p, st)
+    assert np.allclose(Txx, T00, rtol=1e-14)
+    # all moving the same way: a null beam, v = +-1
+    st1 = orc.State(x, rng.uniform(0, 1, n), rng.uniform(0, 1, n), np.abs(px),
+                    zeros.copy(), zeros.copy())
+    T00, T0x, Txx, nd = orc.observe_moments(p, st1)
+    eL, vL = orc.landau(T00, T0x, Txx)
+    assert np.allclose(T0x, T00, rtol=1e-14)
+    # near v = 1 the rest frame is ill-conditioned: an O(eps) error in the
+    # sums moves e and v by O(sqrt(eps))
+    assert np.all(np.abs(eL) <= 1e-6 * T00) and np.allclose(vL, 1.0, atol=1e-6)
+
+
+def test_thermal_gas_moments(orc):
+    T = 0.4
+    n = 400000
+    box = (10.0, 1.0, 1.0)
+    st = orc.State(*W.thermal_box(box, n, T, seed=21))
+    p = _params(orc, box, (10, 1, 1), r_test=1.0)
+    T00, T0x, Txx, nd = orc.observe_moments(p, st)
+    # Gamma(3, T) energies: <E> = 3T, <px^2/E> = <E>/3 for isotropic
+    # directions; 40 000 particles per slab (~0.8 % noise on Txx / T00),
+    # 400 000 in the box
+    assert abs(Txx.sum() / T00.sum() - 1.0 / 3.0) < 0.01 / 3.0
+    assert np.allclose(Txx / T00, 1.0 / 3.0, rtol=0.04)
+    assert abs(T00.sum() / (3.0 * nd.sum() * T) - 1.0) < 0.005
+    assert np.allclose(T00 / (3.0 * nd * T), 1.0, rtol=0.02)
+    eL, vL = orc.landau(T00, T0x, Txx)
+    assert np.allclose(eL / T00, 1.0, atol=1e-3)
+    assert np.all(np.abs(vL) < 0.01)
