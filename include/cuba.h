@@ -125,6 +125,20 @@ int cuba_step(cuba_ctx *ctx, int32_t nsteps);
  * doubles.  Sums run in the (unspecified) storage order. */
 int cuba_observe(cuba_ctx *ctx, double *T00, double *T0x);
 
+/* Moments of the current state over the nx slabs along x, for the approach
+ * to ideal hydrodynamics as sigma grows (Sec. 5, Fig. 3).  out: device array
+ * of 6 nx doubles, rows in this order:
+ *   T00, T0x  as cuba_observe;
+ *   Txx = sum p_x^2 / E / (r_test dx Ly Lz)              [GeV/fm^3];
+ *   n   = count / (r_test dx Ly Lz)                      [fm^-3];
+ *   e, v: the slab's rest frame, T^mu_nu u^nu = e u^mu with u = gamma (1, v)
+ *         on the t-x block (transverse flow neglected):
+ *         a = T00 + Txx, b = 2|T0x|, d = max((a - b)(a + b), 0),
+ *         e = ((T00 - Txx) + sqrt(d)) / 2, v = T0x / (e + Txx) (0 if e + Txx
+ *         is 0), evaluated in this order.
+ * Errors: CUBA_EINVAL for NULL. */
+int cuba_observe_moments(cuba_ctx *ctx, double *out);
+
 /* Copies the current state into device arrays of n doubles in id order. */
 int cuba_get_state(cuba_ctx *ctx, double *x, double *y, double *z,
                    double *px, double *py, double *pz);
@@ -254,6 +268,10 @@ int cuba_batch_set_cells_per_item(cuba_batch *b, int32_t slot, int32_t cells);
  * enqueued on the batch stream after the steps issued so far).  T00, T0x:
  * device f64[nx] each.  Errors: CUBA_EINVAL for an empty slot or NULL. */
 int cuba_batch_observe(cuba_batch *b, int32_t slot, double *T00, double *T0x);
+
+/* The moments of a slot's event (as cuba_observe_moments), on the batch
+ * stream.  out: device f64[6 nx]. */
+int cuba_batch_observe_moments(cuba_batch *b, int32_t slot, double *out);
 
 /* Lanes per cell of a slot's event (as cuba_set_cell_lanes; the default is
  * cuba_init's choice); set by the autotuner. */

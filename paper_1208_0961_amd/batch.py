@@ -111,6 +111,15 @@ class Batch:
         self.sync()
         return T00.cpu().numpy().copy(), T0x.cpu().numpy().copy()
 
+    def observe_moments_async(self, slot: int) -> torch.Tensor:
+        """Launches the moments of a slot's event; returns the device tensor
+        [6, nx] (rows T00, T0x, Txx, n, e, v)."""
+        nx = int(self.slots[slot]["params"]["cells"][0])
+        with torch.cuda.stream(self.stream):
+            out = torch.empty((6, nx), dtype=torch.float64, device=self.device)
+        C.cuba_batch_observe_moments(self.b, slot, out.data_ptr())
+        return out
+
     def get_state(self, slot: int):
         n = self.slots[slot]["n"]
         with torch.cuda.stream(self.stream):

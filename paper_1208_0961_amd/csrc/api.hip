@@ -66,7 +66,7 @@ Layout make_layout(int64_t n_cells, uint32_t cap) {
   }
   L.offsets = take((cc + 1) * sizeof(uint32_t));
   L.tile_sums = take(tiles * sizeof(uint32_t));
-  L.cell_sums = take(cc * 2 * sizeof(double));
+  L.cell_sums = take(cc * kCellSums * sizeof(double));
   L.consts = take(sizeof(DeviceConsts));
   L.total = off;
   return L;
@@ -424,8 +424,19 @@ int cuba_trace_step(cuba_ctx *c, const cuba_trace *t) {
 
 int cuba_observe(cuba_ctx *c, double *T00, double *T0x) {
   if (!c || !T00 || !T0x) return fail(CUBA_EINVAL, "NULL argument");
+  const SlabOut out{T00, T0x, nullptr, nullptr, nullptr, nullptr};
   stage(c, kStageObserve, [&] {
-    launch_observe(c->buf[c->cur], c->d.g, c->d.vol, c->cell_sums, T00, T0x, c->stream);
+    launch_observe(c->buf[c->cur], c->d.g, c->d.vol, c->cell_sums, out, c->stream);
+  });
+  return check_launch("observe launch");
+}
+
+int cuba_observe_moments(cuba_ctx *c, double *out) {
+  if (!c || !out) return fail(CUBA_EINVAL, "NULL argument");
+  const int64_t nx = c->d.g.n[0];
+  const SlabOut o{out, out + nx, out + 2 * nx, out + 3 * nx, out + 4 * nx, out + 5 * nx};
+  stage(c, kStageObserve, [&] {
+    launch_observe(c->buf[c->cur], c->d.g, c->d.vol, c->cell_sums, o, c->stream);
   });
   return check_launch("observe launch");
 }
@@ -789,6 +800,12 @@ int cuba_batch_observe(cuba_batch *b, int32_t slot, double *T00, double *T0x) {
   if (!b || slot < 0 || slot >= b->max_slots || !b->slot_ctx[slot])
     return fail(CUBA_EINVAL, "slot is not occupied");
   return cuba_observe(b->slot_ctx[slot], T00, T0x);
+}
+
+int cuba_batch_observe_moments(cuba_batch *b, int32_t slot, double *out) {
+  if (!b || slot < 0 || slot >= b->max_slots || !b->slot_ctx[slot])
+    return fail(CUBA_EINVAL, "slot is not occupied");
+  return cuba_observe_moments(b->slot_ctx[slot], out);
 }
 
 int cuba_batch_set_cell_lanes(cuba_batch *b, int32_t slot, int32_t lanes) {

@@ -135,8 +135,15 @@ void launch_step(const Cells &src, const Cells &dst, bool fused, int64_t n_cells
 // Counts the cells of cur holding more than 8, 16, 32 and 64 particles into
 // status->over (which must be zero).
 void launch_occupancy_over(const Cells &cur, int64_t n_cells, DevStatus *status, hipStream_t s);
+// Per-slab outputs of an observation (each may be NULL): T00, T0x, Txx
+// [GeV/fm^3], density n [fm^-3], rest-frame e [GeV/fm^3] and v.
+struct SlabOut {
+  double *T00, *T0x, *Txx, *n, *e, *v;
+};
+constexpr uint32_t kCellSums = 4;  // per cell: sum E, sum p_x, sum p_x^2 / E, count
+// cell_sums: scratch of kCellSums doubles per cell.
 void launch_observe(const Cells &cur, const Geometry &g, double vol, double *cell_sums,
-                    double *T00, double *T0x, hipStream_t s);
+                    const SlabOut &out, hipStream_t s);
 // A run of k >= 1 steps of every event in the device table ev (n_events
 // live events): stream + bin, k - 1 fused steps, the last collisions, then
 // the table advance.  The work spaces: items of cells_per_item cells for the

@@ -1210,55 +1210,82 @@ __global__ __launch_bounds__(kBlock) void k_observe_cells(Cells cur_arg, uint32_
   if (c >= n_cells) return;
   const uint32_t n = occupancy(cur, c);
   const size_t base = (size_t)c * cur.cap;
-  double se = 0.0, sp = 0.0;
+  double se = 0.0, sp = 0.0, sxx = 0.0;
   for (uint32_t j = lane; j < n; j += 64) {
     const double px = cur.st.px[base + j], py = cur.st.py[base + j],
                  pz = cur.st.pz[base + j];
-    se += norm3(px, py, pz);
+    const double e = norm3(px, py, pz);
+    se += e;
     sp += px;
+    sxx += (px * px) / e;
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     se += __shfl_down(se, o);
     sp += __shfl_down(sp, o);
+    sxx += __shfl_down(sxx, o);
   }
   if (lane == 0) {
-    cell_sums[2 * (size_t)c + 0] = se;
-    cell_sums[2 * (size_t)c + 1] = sp;
+    double *const out = cell_sums + kCellSums * (size_t)c;
+    out[0] = se;
+    out[1] = sp;
+    out[2] = sxx;
+    out[3] = (double)n;
   }
 }
 
+// The rest frame (Landau frame of the t-x block of T^{mu nu}) of a slab:
+// T^mu_nu u^nu = e u^mu, u = gamma (1, v), in the order the determinism
+// contract fixes (a product of two factors under the square root).
+__device__ __forceinline__ void rest_frame(double t00, double t0x, double txx, double &e,
+                                           double &v) {
+  const double a = t00 + txx;
+  const double b = 2.0 * __builtin_fabs(t0x);
+  double disc = (a - b) * (a + b);
+  if (disc < 0.0) disc = 0.0;
+  e = ((t00 - txx) + __builtin_sqrt(disc)) / 2.0;
+  const double den = e + txx;
+  v = den > 0.0 ? t0x / den : 0.0;
+}
+
+// Slab sums over the slab's cells in cell order, then the moments.
 __global__ __launch_bounds__(kBlock) void k_observe_slabs(const double *cell_sums,
                                                           uint32_t cells_per_slab,
-                                                          double vol, double *T00,
-                                                          double *T0x) {
-  __shared__ double s_e[kBlock / 64], s_p[kBlock / 64];
+                                                          double vol, SlabOut out) {
+  __shared__ double s_sum[kCellSums][kBlock / 64];
   const uint32_t ix = blockIdx.x;
   const size_t c0 = (size_t)ix * cells_per_slab;
-  double se = 0.0, sp = 0.0;
-  for (uint32_t j = threadIdx.x; j < cells_per_slab; j += kBlock) {
-    se += cell_sums[2 * (c0 + j) + 0];
-    sp += cell_sums[2 * (c0 + j) + 1];
-  }
+  double acc[kCellSums] = {0.0, 0.0, 0.0, 0.0};
+  for (uint32_t j = threadIdx.x; j < cells_per_slab; j += kBlock)
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    se += __shfl_down(se, o);
-    sp += __shfl_down(sp, o);
-  }
+    for (uint32_t k = 0; k < kCellSums; ++k) acc[k] += cell_sums[kCellSums * (c0 + j) + k];
+#pragma unroll
+  for (uint32_t k = 0; k < kCellSums; ++k)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc[k] += __shfl_down(acc[k], o);
   const uint32_t lane = lane_id(), wave = threadIdx.x / 64;
-  if (lane == 0) {
-    s_e[wave] = se;
-    s_p[wave] = sp;
-  }
+  if (lane == 0)
+#pragma unroll
+    for (uint32_t k = 0; k < kCellSums; ++k) s_sum[k][wave] = acc[k];
   __syncthreads();
   if (threadIdx.x == 0) {
-    double te = 0.0, tp = 0.0;
-    for (int w = 0; w < kBlock / 64; ++w) {
-      te += s_e[w];
-      tp += s_p[w];
+    double tot[kCellSums];
+#pragma unroll
+    for (uint32_t k = 0; k < kCellSums; ++k) {
+      tot[k] = 0.0;
+      for (int w = 0; w < kBlock / 64; ++w) tot[k] += s_sum[k][w];
     }
-    T00[ix] = te / vol;
-    T0x[ix] = tp / vol;
+    const double t00 = tot[0] / vol, t0x = tot[1] / vol, txx = tot[2] / vol;
+    if (out.T00) out.T00[ix] = t00;
+    if (out.T0x) out.T0x[ix] = t0x;
+    if (out.Txx) out.Txx[ix] = txx;
+    if (out.n) out.n[ix] = tot[3] / vol;
+    if (out.e || out.v) {
+      double e, v;
+      rest_frame(t00, t0x, txx, e, v);
+      if (out.e) out.e[ix] = e;
+      if (out.v) out.v[ix] = v;
+    }
   }
 }
 
@@ -1433,13 +1460,12 @@ void launch_occupancy_over(const Cells &cur, int64_t n_cells, DevStatus *status,
 }
 
 void launch_observe(const Cells &cur, const Geometry &g, double vol, double *cell_sums,
-                    double *T00, double *T0x, hipStream_t s) {
+                    const SlabOut &out, hipStream_t s) {
   const int64_t n_cells = (int64_t)g.n[0] * g.n[1] * g.n[2];
   hipLaunchKernelGGL(k_observe_cells, dim3(cell_blocks(n_cells)), dim3(kBlock), 0, s, cur,
                      (uint32_t)n_cells, cell_sums);
   hipLaunchKernelGGL(k_observe_slabs, dim3((unsigned)g.n[0]), dim3(kBlock), 0, s,
-                     (const double *)cell_sums, (uint32_t)(g.n[1] * g.n[2]), vol, T00,
-                     T0x);
+                     (const double *)cell_sums, (uint32_t)(g.n[1] * g.n[2]), vol, out);
 }
 
 void launch_batch_run(BatchEvent *ev, const BatchSpaces &sp, uint32_t n_events, int32_t k,

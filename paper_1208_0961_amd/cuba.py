@@ -97,6 +97,10 @@ def _load() -> ctypes.CDLL:
     L.cuba_batch_slot.restype = vp
     L.cuba_batch_set_cells_per_item.argtypes = [vp, i32, i32]
     L.cuba_batch_set_cells_per_item.restype = ctypes.c_int
+    L.cuba_observe_moments.argtypes = [vp, vp]
+    L.cuba_observe_moments.restype = ctypes.c_int
+    L.cuba_batch_observe_moments.argtypes = [vp, i32, vp]
+    L.cuba_batch_observe_moments.restype = ctypes.c_int
     L.cuba_batch_observe.argtypes = [vp, i32, vp, vp]
     L.cuba_batch_observe.restype = ctypes.c_int
     L.cuba_batch_set_cell_lanes.argtypes = [vp, i32, i32]
@@ -267,6 +271,17 @@ def cuba_batch_slot(b: int, slot: int):
 def cuba_batch_set_cells_per_item(b: int, slot: int, cells: int) -> None:
     _check(_lib.cuba_batch_set_cells_per_item(b, int(slot), int(cells)),
            "cuba_batch_set_cells_per_item")
+
+
+MOMENTS = ("T00", "T0x", "Txx", "n", "e", "v")
+
+
+def cuba_observe_moments(ctx: int, out: int) -> None:
+    _check(_lib.cuba_observe_moments(ctx, out), "cuba_observe_moments")
+
+
+def cuba_batch_observe_moments(b: int, slot: int, out: int) -> None:
+    _check(_lib.cuba_batch_observe_moments(b, int(slot), out), "cuba_batch_observe_moments")
 
 
 def cuba_batch_observe(b: int, slot: int, T00: int, T0x: int) -> None:

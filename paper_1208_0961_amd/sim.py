@@ -106,6 +106,16 @@ class Sim:
         self.sync()
         return T00.cpu().numpy().copy(), T0x.cpu().numpy().copy()
 
+    def observe_moments(self):
+        """Per-slab T00, T0x, Txx, n, e, v (see cuba_observe_moments), as a
+        dict of numpy arrays."""
+        with torch.cuda.stream(self.stream):
+            out = torch.empty(6 * self.nx, dtype=torch.float64, device=self.device)
+        C.cuba_observe_moments(self.ctx, out.data_ptr())
+        self.sync()
+        a = out.cpu().numpy().reshape(6, self.nx)
+        return {k: a[i].copy() for i, k in enumerate(C.MOMENTS)}
+
     def get_state(self):
         with torch.cuda.stream(self.stream):
             out = [torch.empty(self.n, dtype=torch.float64, device=self.device)

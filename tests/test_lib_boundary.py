@@ -56,8 +56,9 @@ def test_workspace_bytes_and_parameter_checks(C):
     n = 1020851
     ws = C.cuba_workspace_bytes(p, n)
     # two buffers of cells x capacity slots of 52 B plus per-cell arrays
+    # (two counts, trace offsets and 4 observe sums: 44 B) and small pieces
     slots = 10000 * 256
-    assert 104 * slots <= ws <= 104 * slots + 32 * 10000 + 64 * 1024
+    assert 104 * slots + 44 * 10000 <= ws <= 104 * slots + 48 * 10000 + 64 * 1024
     p2 = C.make_params((10, 2, 2), (100, 10, 10), 0.4, 2500, 0.02, 1, cell_capacity=512)
     assert C.cuba_workspace_bytes(p2, n) > ws
     p0 = C.make_params((10, 2, 2), (100, 10, 10), 0.4, 2500, 0.02, 1)   # default 512

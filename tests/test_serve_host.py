@@ -38,7 +38,7 @@ def test_footprint_matches_workspace_formula(serve):
     cap = W.capacity_for(r.work)
     slots = r.work.n_cells * cap
     fp = serve.footprint(r)
-    assert 104 * slots <= fp <= 104 * slots + 40 * r.work.n_cells + 64 * 1024
+    assert 104 * slots <= fp <= 104 * slots + 48 * r.work.n_cells + 64 * 1024
 
 
 def test_percentiles(serve):
