@@ -48,7 +48,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="tube3d",
-                    choices=["tube1d", "tube3d", "full", "batch", "serve", "sigma-scan"])
+                    choices=["tube1d", "tube3d", "full", "paper32", "batch", "serve",
+                             "sigma-scan"])
     ap.add_argument("--events", type=int, default=256,
                     help="batch: number of ensemble events")
     ap.add_argument("--requests", type=int, default=2000,
@@ -370,7 +371,8 @@ def main():
 
     cpu = None
     cpu_steps = a.cpu_steps if a.cpu_steps is not None else {"tube1d": 100, "tube3d": 24,
-                                                              "full": 2}[a.workload]
+                                                              "full": 2,
+                                                              "paper32": 2}[a.workload]
     if cpu_steps > 0:
         threads = a.cpu_threads or max(1, min(16, os.cpu_count() or 1))
         print(f"# cpu baseline: {cpu_steps} oracle steps, {threads} threads",
@@ -389,7 +391,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic: seeded thermal Riemann gas (T 0.40 / 0.32 GeV), no dataset",
+        "data": f"synthetic: seeded thermal Riemann gas (T {w.T_left:.2f} / "
+                f"{w.T_right:.2f} GeV), no dataset",
         "config": {"workload": w.name, "n_particles": w.n, "cells": list(w.cells),
                    "box_fm": list(w.box), "r_test": w.r_test, "sigma_fm2": w.sigma,
                    "dt_fm": w.dt, "observe_every": w.observe_every,

@@ -75,8 +75,17 @@ TUBE_3D = Workload("riemann-tube-10x2x2-c100x10x10-rt2500", (10.0, 2.0, 2.0),
                    (100, 10, 10), 2500.0, 0.4, 0.02, 0.40, 0.32)
 TUBE_FULL = Workload("riemann-tube-10x8x8-c100x40x40-rt2500", (10.0, 8.0, 8.0),
                      (100, 40, 40), 2500.0, 0.4, 0.02, 0.40, 0.32)
-WORKLOADS = {w.name: w for w in (TUBE_1D, TUBE_3D, TUBE_FULL)}
-ALIASES = {"tube1d": TUBE_1D, "tube3d": TUBE_3D, "full": TUBE_FULL}
+# The paper's own Riemann set-up (Sec. 5, Fig. 2): a 32^3 fm^3 box split at
+# x = 16 fm, T = 0.4 / 0.2 GeV, sigma = 10 GeV^-2 = 0.3894 fm^2, dt = 0.1
+# fm/c.  The paper states no test-particle ratio or cell size: r_test = 100
+# and 0.25 fm cells (dt below every cell edge, ~21 / ~2.6 test particles
+# per cell on the two sides).  50 steps reach t = 5 fm/c.
+SIGMA_PAPER = 10.0 * HBARC ** 2       # 10 GeV^-2 in fm^2
+PAPER_32 = Workload("riemann-box-32x32x32-c128x128x128-rt100", (32.0, 32.0, 32.0),
+                    (128, 128, 128), 100.0, SIGMA_PAPER, 0.1, 0.40, 0.20, steps=50,
+                    observe_every=10)
+WORKLOADS = {w.name: w for w in (TUBE_1D, TUBE_3D, TUBE_FULL, PAPER_32)}
+ALIASES = {"tube1d": TUBE_1D, "tube3d": TUBE_3D, "full": TUBE_FULL, "paper32": PAPER_32}
 
 
 def sample_gas(rng, n, T, lo, hi):

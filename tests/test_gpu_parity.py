@@ -369,3 +369,23 @@ def test_multistep_profiles_match_oracle_ensemble(orc, lib):
     assert np.all(np.isfinite(allz))
     assert np.mean(np.abs(allz) > 3) <= 0.01
     assert stats.chi2.sf((scores[200] ** 2).sum(), len(scores[200])) > 1e-3
+
+
+def test_paper_parameter_set_reduced(orc, lib):
+    """The paper's own set-up (32^3 fm^3, T 0.4 / 0.2 GeV, sigma 10 GeV^-2,
+    dt 0.1 fm/c) at 64^3 cells and r_test = 8 (2.0 M particles): one traced
+    step matches the oracle, and ten steps conserve energy and particle
+    number (Sec. 5)."""
+    w0 = W.PAPER_32
+    w = W.Workload("paper-box-reduced", w0.box, (64, 64, 64), 8.0, w0.sigma, w0.dt,
+                   w0.T_left, w0.T_right, seed=3)
+    state = W.riemann_state(w, seed=41)
+    _, tr = compare_step(orc, lib, w.params(), state, 0, "paper32-reduced")
+    assert len(tr["claim"]) > 10000
+    sim = lib.Sim(w.params(), state)
+    m0 = sim.observe_moments()
+    sim.step(10)
+    m1 = sim.observe_moments()
+    sim.close()
+    assert np.array_equal(m0["n"].sum() * 1.0, m1["n"].sum() * 1.0)
+    assert abs(m1["T00"].sum() / m0["T00"].sum() - 1.0) < 1e-12
