@@ -178,11 +178,13 @@ int cuba_sync(cuba_ctx *ctx);
  * whatever its occupancy.  8, 16, 32 or 64: each wave takes 64 / lanes
  * consecutive cells with one particle per lane, which serves sparse cells
  * without a mostly idle wave each; cells holding more particles than lanes
- * are stepped by the whole wave in a second kernel.  cuba_init chooses
- * from the initial occupancy: 0 below 16384 cells (launch-bound steps),
- * else the smallest of 8, 16, 32, 64 that all but 0.2 % of the cells fit,
- * else 0.  Errors: CUBA_EINVAL for NULL or any other value.  For an event in
- * a batch use cuba_batch_set_cell_lanes. */
+ * are stepped by the whole wave in a second kernel (a wave per 64 cells, or
+ * a wave per cell once the initial state has more than one such cell in 64).
+ * cuba_init chooses from the initial occupancy: 0 below 16384 cells
+ * (launch-bound steps), else the smallest of 8, 16, 32 that all but 0.2 %
+ * of the cells fit, else 8 if at least a quarter of the cells hold at most
+ * 8 particles, else 0.  Errors: CUBA_EINVAL for NULL or any other value.
+ * For an event in a batch use cuba_batch_set_cell_lanes. */
 int cuba_set_cell_lanes(cuba_ctx *ctx, int32_t lanes);
 int cuba_get_cell_lanes(const cuba_ctx *ctx, int32_t *lanes);
 
@@ -273,8 +275,10 @@ int cuba_batch_observe(cuba_batch *b, int32_t slot, double *T00, double *T0x);
  * stream.  out: device f64[6 nx]. */
 int cuba_batch_observe_moments(cuba_batch *b, int32_t slot, double *out);
 
-/* Lanes per cell of a slot's event (as cuba_set_cell_lanes; the default is
- * cuba_init's choice); set by the autotuner. */
+/* Lanes per cell of a slot's event (as cuba_set_cell_lanes).  The default
+ * is cuba_init's choice without its 8-lane fallback for boxes of dense and
+ * sparse regions (a batch steps oversize cells a wave per 64 cells); set by
+ * the autotuner. */
 int cuba_batch_set_cell_lanes(cuba_batch *b, int32_t slot, int32_t lanes);
 
 /* Launch shape: persistent_waves > 0 runs the binning kernel on that many

@@ -120,19 +120,27 @@ int derive(const cuba_params *p, Derived &d) {
   return CUBA_OK;
 }
 
-// Lanes per cell from the occupancy at init: the smallest group that all
-// but a small fraction of the cells fit (oversize cells cost a second
-// kernel), else one wave per cell; one wave per cell also for boxes of
-// fewer cells than a few waves per SIMD, whose steps are bound by launch
-// latency, which the second kernel adds to.  over[k] = cells holding more
-// than 8 << k particles.
+// Lanes per cell from the occupancy at init (over[k] = cells holding more
+// than 8 << k particles):
+//  * one wave per cell for boxes of fewer cells than a few waves per SIMD,
+//    whose steps are bound by launch latency, which the second kernel adds to;
+//  * else the smallest group of 8, 16 or 32 lanes that all but a small
+//    fraction of the cells fit (64-lane groups lost to one wave per cell
+//    in every measured occupancy mix);
+//  * else, where the oversize cells can take a wave each (the plain path),
+//    8 lanes if at least a quarter of the cells fit them: a box of dense
+//    and sparse regions steps each region with its own kernel;
+//  * else one wave per cell.
 constexpr double kOversizeFraction = 2e-3;
+constexpr double kSparseFraction = 0.25;
 constexpr int64_t kSmallCellsMinCells = 16384;
-uint32_t default_lanes(const uint32_t over[4], int64_t n_cells) {
+uint32_t default_lanes(const uint32_t over[4], int64_t n_cells, bool wave_per_oversize) {
   if (n_cells < kSmallCellsMinCells) return 0;
   const double limit = kOversizeFraction * (double)n_cells;
-  for (uint32_t k = 0; k < 4; ++k)
+  for (uint32_t k = 0; k < 3; ++k)
     if ((double)over[k] <= limit) return 8u << k;
+  if (wave_per_oversize && (double)(n_cells - over[0]) >= kSparseFraction * (double)n_cells)
+    return 8;
   return 0;
 }
 
@@ -176,6 +184,7 @@ struct cuba_ctx {
   int64_t n;
   uint32_t next_step;
   uint32_t lanes;  // lanes per cell of the cell kernels (valid_cell_lanes)
+  uint32_t over[4];  // cells of the initial state holding > 8, 16, 32, 64 particles
   hipStream_t stream;
   DevStatus *status;
   Cells buf[2];
@@ -224,7 +233,17 @@ void drop_timing(cuba_ctx *c) {
 }
 
 // Device copy of the geometry.
-StepDevice step_device(const cuba_ctx *c) { return StepDevice{&c->consts->g}; }
+// The oversize-cell launch takes a wave per cell once such cells average
+// more than one in 64 (by the initial histogram), else a wave per 64 cells.
+uint32_t over_span(const uint32_t over[4], uint32_t lanes, int64_t n_cells) {
+  if (lanes == 0) return 64;
+  const uint32_t k = lanes == 8 ? 0 : lanes == 16 ? 1 : lanes == 32 ? 2 : 3;
+  return (int64_t)over[k] * 64 > n_cells ? 1u : 64u;
+}
+
+StepDevice step_device(const cuba_ctx *c) {
+  return StepDevice{&c->consts->g, over_span(c->over, c->lanes, c->d.n_cells)};
+}
 
 // nsteps steps: stream + bin into the other buffer, then nsteps - 1 fused
 // steps (collide, then stream + bin into the other buffer), then the last
@@ -369,7 +388,8 @@ int cuba_init(cuba_ctx **out, const cuba_params *params, int64_t n, const double
     return hip_fail(e, "init check");
   }
   const uint32_t err = head[0];
-  c->lanes = default_lanes(head + 1, d.n_cells);
+  for (int k = 0; k < 4; ++k) c->over[k] = head[1 + k];
+  c->lanes = default_lanes(c->over, d.n_cells, true);
   if (err & kErrRange) {
     delete c;
     return fail(CUBA_ERANGE,
@@ -764,6 +784,8 @@ int cuba_batch_admit(cuba_batch *b, int32_t slot, const cuba_params *params, int
   const int rc = cuba_init(&c, params, n, x, y, z, px, py, pz, workspace, ws_bytes,
                            (void *)b->stream);
   if (rc != CUBA_OK) return rc;
+  // a batch steps the oversize cells of an event 64 to a wave
+  c->lanes = default_lanes(c->over, c->d.n_cells, false);
   b->slot_ctx[slot] = c;
   b->slot_cpi[slot] = default_cpi(c);
   b->dirty = true;

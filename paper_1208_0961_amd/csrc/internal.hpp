@@ -121,6 +121,10 @@ void launch_offsets(const Cells &cur, uint32_t *offsets, uint32_t *tile_sums,
 // memory where it uses it.
 struct StepDevice {
   const Geometry *g;
+  // cells per wave of the oversize-cell kernel: 64 (a wave scans 64 cells
+  // and steps the oversize ones one after another; few oversize cells) or 1
+  // (a wave per cell; many)
+  uint32_t over_span;
 };
 
 // One collision launch (fused: then streaming + binning of the next step).

@@ -1004,6 +1004,22 @@ __global__ __launch_bounds__(64) void k_step_large(Cells src_arg, Cells dst_arg,
                                          lds);
 }
 
+// One wave per cell, for the cells holding more than `lanes` particles: the
+// oversize-cell launch when such cells are common (a wave that scans 64 of
+// them would step them one after another).
+template <bool kFused, bool kTrace, uint32_t kCap>
+__global__ __launch_bounds__(64) void k_step_over(Cells src_arg, int64_t dst_shift,
+                                                  uint32_t lanes, uint32_t t, PairArgs pa,
+                                                  const Geometry *__restrict__ gp,
+                                                  DevStatus *status, TraceArgs tr) {
+  const GCells src = to_global(src_arg);
+  __shared__ CellLds<kFused, kCap> lds;
+  const uint32_t c = xcd_runs<8>(blockIdx.x, gridDim.x);
+  if (occupancy(src, c) <= lanes) return;
+  cell_step<kFused, kTrace, kCap>(src, shifted(src, dst_shift), c, t, pa, *gp, status, tr,
+                                  lds);
+}
+
 // dst is src shifted by dst_shift bytes (the two buffers of a context are
 // laid out alike), and g is read from device memory where the binning uses
 // it: as kernel arguments both would be loaded at entry and held through the
@@ -1415,8 +1431,14 @@ void launch_step_cap(const Cells &src, const Cells &dst, uint32_t n_cells, uint3
       hipLaunchKernelGGL((k_step_small<kFused, kTrace, 64>), grid, block, 0, s, src, dst,
                          n_cells, t, pa, g, status, tr);
   }
-  hipLaunchKernelGGL((k_step_large<kFused, kTrace, kCap>), dim3((n_cells + 63) / 64), block,
-                     0, side ? side->stream : s, src, dst, n_cells, lanes, t, pa, g, status, tr);
+  hipStream_t so = side ? side->stream : s;
+  if (dev.over_span == 1)
+    hipLaunchKernelGGL((k_step_over<kFused, kTrace, kCap>), dim3(n_cells), block, 0, so, src,
+                       (int64_t)((const char *)dst.st.x - (const char *)src.st.x), lanes, t,
+                       pa, dev.g, status, tr);
+  else
+    hipLaunchKernelGGL((k_step_large<kFused, kTrace, kCap>), dim3((n_cells + 63) / 64), block,
+                       0, so, src, dst, n_cells, lanes, t, pa, g, status, tr);
   join(s, side);
 }
 

@@ -145,3 +145,41 @@ def test_lanes_setting_is_validated(lib):  # noqa: F811
             s.cell_lanes = bad
         assert e.value.code == C.CUBA_EINVAL
     s.close()
+
+
+def _grid_state(occ, m=32, T=0.4, seed=9):
+    """Cell j of an m^3 grid of unit edge holds occ[j] particles, uniform in
+    the cell."""
+    rng = np.random.default_rng(seed)
+    occ = np.asarray(occ, dtype=np.int64)
+    cell = np.repeat(np.arange(m ** 3), occ)
+    ijk = np.stack([cell // (m * m), (cell // m) % m, cell % m], 1)
+    r = (ijk + 0.05 + 0.9 * rng.random((len(cell), 3))) / m
+    _, _, _, px, py, pz = W.sample_gas(rng, len(cell), T, (0, 0, 0), (1, 1, 1))
+    return [np.ascontiguousarray(a) for a in (r[:, 0], r[:, 1], r[:, 2], px, py, pz)]
+
+
+def test_default_lanes_rule(lib):  # noqa: F811
+    """cuba_init's choice from the initial occupancy (32^3 cells), and the
+    batch's, which never leaves a large share of the cells oversize."""
+    import torch
+    from paper_1208_0961_amd import batch
+    m = 32
+    C = m ** 3
+    half = np.where(np.arange(C) < C // 2, 40, 3)
+    cases = [("all 3", np.full(C, 3), 8, 8), ("all 12", np.full(C, 12), 16, 16),
+             ("all 25", np.full(C, 25), 32, 32), ("all 40", np.full(C, 40), 0, 0),
+             ("dense and sparse halves", half, 8, 0)]
+    params = dict(box=(1.0, 1.0, 1.0), cells=(m, m, m), sigma=0.1, r_test=100.0,
+                  dt=0.001, seed=5, cell_capacity=64)
+    for label, occ, want_plain, want_batch in cases:
+        state = _grid_state(occ)
+        s = lib.Sim(params, state)
+        got = s.cell_lanes
+        s.close()
+        B = batch.Batch(1)
+        B.admit(0, params, [torch.from_numpy(a).cuda() for a in state])
+        got_b = B.cell_lanes(0)
+        B.close()
+        say(f"[lanes] {label}: plain {got}, batch {got_b}")
+        assert (got, got_b) == (want_plain, want_batch), label
