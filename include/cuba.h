@@ -188,6 +188,16 @@ int cuba_sync(cuba_ctx *ctx);
 int cuba_set_cell_lanes(cuba_ctx *ctx, int32_t lanes);
 int cuba_get_cell_lanes(const cuba_ctx *ctx, int32_t *lanes);
 
+/* Variable time step (Sec. 6 names a variable dt as the method's next
+ * step).  dt [fm/c] replaces cuba_params.dt for every step issued after
+ * the call, in streaming (Eq. (2)) and in K = sigma / r_test * dt / V_cell
+ * of Eq. (3); the step index keeps counting, so the random numbers of step
+ * t are those of a run with a fixed dt.  Validated as at init: finite,
+ * 0 < dt < every cell edge (Sec. 5) and 2K <= 1.  Errors: CUBA_EINVAL (the
+ * old dt stays), CUBA_EDEVICE.  Asynchronous on the context's stream. */
+int cuba_set_dt(cuba_ctx *ctx, double dt);
+int cuba_get_dt(const cuba_ctx *ctx, double *dt);
+
 /* Index of the next step, number of particles, number of cells. */
 int cuba_info(const cuba_ctx *ctx, uint32_t *next_step, int64_t *n,
               int64_t *n_cells);
@@ -280,6 +290,10 @@ int cuba_batch_observe_moments(cuba_batch *b, int32_t slot, double *out);
  * sparse regions (a batch steps oversize cells a wave per 64 cells); set by
  * the autotuner. */
 int cuba_batch_set_cell_lanes(cuba_batch *b, int32_t slot, int32_t lanes);
+
+/* A slot's time step (as cuba_set_dt) from its next cuba_batch_step on.
+ * Errors: CUBA_EINVAL for an empty slot or a dt cuba_set_dt rejects. */
+int cuba_batch_set_dt(cuba_batch *b, int32_t slot, double dt);
 
 /* Launch shape: persistent_waves > 0 runs the binning kernel on that many
  * persistent waves taking work items with a grid stride (0: one wave per

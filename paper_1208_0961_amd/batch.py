@@ -91,6 +91,13 @@ class Batch:
     def cell_lanes(self, slot: int) -> int:
         return C.cuba_get_cell_lanes(self.ctx(slot))
 
+    def set_dt(self, slot: int, dt: float) -> None:
+        """The slot's time step from its next step on (cuba_batch_set_dt)."""
+        C.cuba_batch_set_dt(self.b, slot, dt)
+
+    def dt(self, slot: int) -> float:
+        return C.cuba_get_dt(self.ctx(slot))
+
     def set_launch(self, persistent_waves: int = 0, use_graphs: bool = False) -> None:
         C.cuba_batch_set_launch(self.b, persistent_waves, use_graphs)
 

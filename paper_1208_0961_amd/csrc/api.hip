@@ -76,6 +76,7 @@ Layout make_layout(int64_t n_cells, uint32_t cap) {
 struct Derived {
   Geometry g;
   double vcell, kfac, vol;
+  double sr;  // sigma / r_test
   int64_t n_cells;
   uint32_t cap;
 };
@@ -107,7 +108,8 @@ int derive(const cuba_params *p, Derived &d) {
   }
   d.g.dt = p->dt;
   d.vcell = (d.g.dx[0] * d.g.dx[1]) * d.g.dx[2];
-  d.kfac = ((p->sigma / p->r_test) * p->dt) / d.vcell;
+  d.sr = p->sigma / p->r_test;
+  d.kfac = (d.sr * p->dt) / d.vcell;
   if (!(2.0 * d.kfac <= 1.0))
     return fail(CUBA_EINVAL, "sigma / r_test * dt / V_cell > 1/2: P22 could exceed 1");
   d.vol = ((p->r_test * d.g.dx[0]) * p->box[1]) * p->box[2];
@@ -239,6 +241,29 @@ uint32_t over_span(const uint32_t over[4], uint32_t lanes, int64_t n_cells) {
   if (lanes == 0) return 64;
   const uint32_t k = lanes == 8 ? 0 : lanes == 16 ? 1 : lanes == 32 ? 2 : 3;
   return (int64_t)over[k] * 64 > n_cells ? 1u : 64u;
+}
+
+// A new time step for the steps issued after this call (Sec. 6 names a
+// variable dt as the next step of the method): validated as at init, then
+// K, the w1 filter bound and the device copy of the geometry follow it.
+// Nothing changes on an error.
+int apply_dt(cuba_ctx *c, double dt) {
+  if (!(std::isfinite(dt) && dt > 0.0)) return fail(CUBA_EINVAL, "dt must be finite and > 0");
+  for (int k = 0; k < 3; ++k)
+    if (!(dt < c->d.g.dx[k])) return fail(CUBA_EINVAL, "dt must be below every cell edge");
+  const double kfac = (c->d.sr * dt) / c->d.vcell;
+  if (!(2.0 * kfac <= 1.0))
+    return fail(CUBA_EINVAL, "sigma / r_test * dt / V_cell > 1/2: P22 could exceed 1");
+  launch_store_f64(&c->consts->g.dt, dt, c->stream);
+  const int rc = check_launch("dt update");
+  if (rc != CUBA_OK) return rc;
+  c->d.g.dt = dt;
+  c->d.kfac = kfac;
+  c->pa.kfac = kfac;
+  const uint64_t lim = w1_limit(kfac);
+  c->pa.any = lim > 0 ? 1u : 0u;
+  c->pa.w1_max = lim > 0 ? (uint32_t)(lim - 1) : 0u;
+  return CUBA_OK;
 }
 
 StepDevice step_device(const cuba_ctx *c) {
@@ -414,6 +439,17 @@ int cuba_set_cell_lanes(cuba_ctx *c, int32_t lanes) {
 int cuba_get_cell_lanes(const cuba_ctx *c, int32_t *lanes) {
   if (!c || !lanes) return fail(CUBA_EINVAL, "NULL argument");
   *lanes = (int32_t)c->lanes;
+  return CUBA_OK;
+}
+
+int cuba_set_dt(cuba_ctx *c, double dt) {
+  if (!c) return fail(CUBA_EINVAL, "ctx is NULL");
+  return apply_dt(c, dt);
+}
+
+int cuba_get_dt(const cuba_ctx *c, double *dt) {
+  if (!c || !dt) return fail(CUBA_EINVAL, "NULL argument");
+  *dt = c->d.g.dt;
   return CUBA_OK;
 }
 
@@ -835,6 +871,15 @@ int cuba_batch_set_cell_lanes(cuba_batch *b, int32_t slot, int32_t lanes) {
     return fail(CUBA_EINVAL, "slot is not occupied");
   if (!valid_cell_lanes(lanes)) return fail(CUBA_EINVAL, "lanes must be 0, 8, 16, 32 or 64");
   b->slot_ctx[slot]->lanes = (uint32_t)lanes;
+  b->dirty = true;
+  return CUBA_OK;
+}
+
+int cuba_batch_set_dt(cuba_batch *b, int32_t slot, double dt) {
+  if (!b || slot < 0 || slot >= b->max_slots || !b->slot_ctx[slot])
+    return fail(CUBA_EINVAL, "slot is not occupied");
+  const int rc = apply_dt(b->slot_ctx[slot], dt);
+  if (rc != CUBA_OK) return rc;
   b->dirty = true;
   return CUBA_OK;
 }

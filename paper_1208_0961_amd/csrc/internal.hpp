@@ -108,6 +108,8 @@ struct SideStream {
 
 // Launchers (kernels.hip).  All asynchronous on stream s.
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s);
+// *p = v on the device, in stream order.
+void launch_store_f64(double *p, double v, hipStream_t s);
 void launch_init_bin(const double *x, const double *y, const double *z,
                      const double *px, const double *py, const double *pz,
                      const Cells &dst, int64_t n, const Geometry &g, DevStatus *st,

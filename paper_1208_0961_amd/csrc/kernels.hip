@@ -242,6 +242,10 @@ __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, uint32_t v,
   if (i < count) p[i] = v;
 }
 
+__global__ __launch_bounds__(64) void k_store_f64(double *p, double v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
 // Initial state (id order) -> validated and binned without streaming.
 __global__ __launch_bounds__(kBlock) void k_init_bin(
     const double *__restrict__ x, const double *__restrict__ y,
@@ -1339,6 +1343,10 @@ inline unsigned cell_blocks(int64_t n_cells) {
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s) {
   if (count <= 0) return;
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(count)), dim3(kBlock), 0, s, p, v, count);
+}
+
+void launch_store_f64(double *p, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_store_f64, dim3(1), dim3(64), 0, s, p, v);
 }
 
 void launch_init_bin(const double *x, const double *y, const double *z,

@@ -75,6 +75,10 @@ def _load() -> ctypes.CDLL:
     L.cuba_set_cell_lanes.restype = ctypes.c_int
     L.cuba_get_cell_lanes.argtypes = [vp, ctypes.POINTER(i32)]
     L.cuba_get_cell_lanes.restype = ctypes.c_int
+    L.cuba_set_dt.argtypes = [vp, ctypes.c_double]
+    L.cuba_set_dt.restype = ctypes.c_int
+    L.cuba_get_dt.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.cuba_get_dt.restype = ctypes.c_int
     L.cuba_info.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(i64),
                             ctypes.POINTER(i64)]
     L.cuba_info.restype = ctypes.c_int
@@ -105,6 +109,8 @@ def _load() -> ctypes.CDLL:
     L.cuba_batch_observe.restype = ctypes.c_int
     L.cuba_batch_set_cell_lanes.argtypes = [vp, i32, i32]
     L.cuba_batch_set_cell_lanes.restype = ctypes.c_int
+    L.cuba_batch_set_dt.argtypes = [vp, i32, ctypes.c_double]
+    L.cuba_batch_set_dt.restype = ctypes.c_int
     L.cuba_batch_set_launch.argtypes = [vp, i32, i32]
     L.cuba_batch_set_launch.restype = ctypes.c_int
     L.cuba_batch_step.argtypes = [vp, i32]
@@ -206,6 +212,16 @@ def cuba_get_cell_lanes(ctx: int) -> int:
     return int(v.value)
 
 
+def cuba_set_dt(ctx: int, dt: float) -> None:
+    _check(_lib.cuba_set_dt(ctx, float(dt)), "cuba_set_dt")
+
+
+def cuba_get_dt(ctx: int) -> float:
+    v = ctypes.c_double()
+    _check(_lib.cuba_get_dt(ctx, ctypes.byref(v)), "cuba_get_dt")
+    return float(v.value)
+
+
 def cuba_info(ctx: int):
     t = ctypes.c_uint32()
     n = ctypes.c_int64()
@@ -291,6 +307,10 @@ def cuba_batch_observe(b: int, slot: int, T00: int, T0x: int) -> None:
 def cuba_batch_set_cell_lanes(b: int, slot: int, lanes: int) -> None:
     _check(_lib.cuba_batch_set_cell_lanes(b, int(slot), int(lanes)),
            "cuba_batch_set_cell_lanes")
+
+
+def cuba_batch_set_dt(b: int, slot: int, dt: float) -> None:
+    _check(_lib.cuba_batch_set_dt(b, int(slot), float(dt)), "cuba_batch_set_dt")
 
 
 def cuba_batch_set_launch(b: int, persistent_waves: int, use_graphs: bool) -> None:

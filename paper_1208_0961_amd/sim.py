@@ -44,7 +44,9 @@ class Sim:
     step0 and cell_capacity (default: suggest_cell_capacity of the initial
     state).  state: six arrays (x, y, z, px, py, pz) indexed by particle id.
     cell_lanes: lanes per cell of the cell kernels (None: the library's
-    choice from the mean occupancy; see cuba_set_cell_lanes).
+    choice from the initial occupancy; see cuba_set_cell_lanes).
+    `dt` may be changed between steps (cuba_set_dt); `time` is the time
+    advanced since construction, sum of dt over the steps taken.
     """
 
     def __init__(self, params: dict, state, device: str | torch.device = "cuda",
@@ -74,10 +76,21 @@ class Sim:
             self._inputs = arrs
         if cell_lanes is not None:
             C.cuba_set_cell_lanes(self.ctx, cell_lanes)
+        self._dt = C.cuba_get_dt(self.ctx)
+        self.time = 0.0
 
     @property
     def cell_lanes(self) -> int:
         return C.cuba_get_cell_lanes(self.ctx)
+
+    @property
+    def dt(self) -> float:
+        return self._dt
+
+    @dt.setter
+    def dt(self, dt: float) -> None:
+        C.cuba_set_dt(self.ctx, dt)
+        self._dt = C.cuba_get_dt(self.ctx)
 
     @cell_lanes.setter
     def cell_lanes(self, lanes: int) -> None:
@@ -86,6 +99,7 @@ class Sim:
     # -- stepping -------------------------------------------------------------
     def step(self, nsteps: int = 1) -> None:
         C.cuba_step(self.ctx, nsteps)
+        self.time += nsteps * self._dt
 
     def sync(self) -> None:
         C.cuba_sync(self.ctx)
