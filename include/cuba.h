@@ -270,6 +270,15 @@ int cuba_batch_retire(cuba_batch *b, int32_t slot);
 /* The context of an occupied slot, or NULL.  Owned by the batch. */
 cuba_ctx *cuba_batch_slot(cuba_batch *b, int32_t slot);
 
+/* Holds an admitted event out of the batch's steps (active = 0) or lets it
+ * take part again (active != 0; every event is admitted active).  A held event
+ * keeps its state and step index and may be observed; a scheduler uses
+ * this to run the events with the least remaining work first.  A change
+ * takes effect at the next cuba_batch_step, which then rebuilds the event
+ * table (and recaptures its graphs).  Errors: CUBA_EINVAL for an empty
+ * slot. */
+int cuba_batch_set_active(cuba_batch *b, int32_t slot, int32_t active);
+
 /* Cells per binning work item of a slot's event (default: about 64
  * particles per item, at most 64 cells; 64 cells for events with lanes per
  * cell > 0); set by the autotuner.  The collision kernels take fixed units:

@@ -91,6 +91,11 @@ class Batch:
     def cell_lanes(self, slot: int) -> int:
         return C.cuba_get_cell_lanes(self.ctx(slot))
 
+    def set_active(self, slot: int, active: bool) -> None:
+        """Holds the slot's event out of the steps (False) or lets it take
+        part again (cuba_batch_set_active)."""
+        C.cuba_batch_set_active(self.b, slot, active)
+
     def set_dt(self, slot: int, dt: float) -> None:
         """The slot's time step from its next step on (cuba_batch_set_dt)."""
         C.cuba_batch_set_dt(self.b, slot, dt)

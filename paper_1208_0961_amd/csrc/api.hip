@@ -626,6 +626,7 @@ struct cuba_batch {
   uint32_t *dev_begin = nullptr;  // kSpaces x max_slots: first unit per event of each work space
   std::vector<cuba_ctx *> slot_ctx;
   std::vector<int32_t> slot_cpi;
+  std::vector<uint8_t> slot_active;  // 0: admitted but held out of the steps
   std::vector<int32_t> table_slots;  // slots in table order
   BatchSpaces spaces{};  // unit counts of the work spaces (device begins in dev_begin)
   SideStream side{};     // library-owned stream for concurrent kernels of a step
@@ -682,7 +683,7 @@ int upload_table(cuba_batch *b) {
   std::vector<int> cell_space;
   for (int32_t s = 0; s < b->max_slots; ++s) {
     cuba_ctx *c = b->slot_ctx[s];
-    if (!c || c->d.n_cells == 0) continue;
+    if (!c || c->d.n_cells == 0 || !b->slot_active[s]) continue;
     BatchEvent e{};
     e.buf[0] = c->buf[0];
     e.buf[1] = c->buf[1];
@@ -800,6 +801,7 @@ int cuba_batch_create(cuba_batch **out, int32_t max_slots, void *workspace,
       (uint32_t *)((char *)workspace + align256((size_t)max_slots * sizeof(BatchEvent)));
   b->slot_ctx.assign(max_slots, nullptr);
   b->slot_cpi.assign(max_slots, 1);
+  b->slot_active.assign(max_slots, 1);
   const hipError_t e = create_side(b->side);
   if (e != hipSuccess) {
     delete b;
@@ -824,7 +826,19 @@ int cuba_batch_admit(cuba_batch *b, int32_t slot, const cuba_params *params, int
   c->lanes = default_lanes(c->over, c->d.n_cells, false);
   b->slot_ctx[slot] = c;
   b->slot_cpi[slot] = default_cpi(c);
+  b->slot_active[slot] = 1;
   b->dirty = true;
+  return CUBA_OK;
+}
+
+int cuba_batch_set_active(cuba_batch *b, int32_t slot, int32_t active) {
+  if (!b || slot < 0 || slot >= b->max_slots || !b->slot_ctx[slot])
+    return fail(CUBA_EINVAL, "slot is not occupied");
+  const uint8_t a = active != 0 ? 1 : 0;
+  if (b->slot_active[slot] != a) {
+    b->slot_active[slot] = a;
+    b->dirty = true;
+  }
   return CUBA_OK;
 }
 

@@ -109,6 +109,8 @@ def _load() -> ctypes.CDLL:
     L.cuba_batch_observe.restype = ctypes.c_int
     L.cuba_batch_set_cell_lanes.argtypes = [vp, i32, i32]
     L.cuba_batch_set_cell_lanes.restype = ctypes.c_int
+    L.cuba_batch_set_active.argtypes = [vp, i32, i32]
+    L.cuba_batch_set_active.restype = ctypes.c_int
     L.cuba_batch_set_dt.argtypes = [vp, i32, ctypes.c_double]
     L.cuba_batch_set_dt.restype = ctypes.c_int
     L.cuba_batch_set_launch.argtypes = [vp, i32, i32]
@@ -307,6 +309,11 @@ def cuba_batch_observe(b: int, slot: int, T00: int, T0x: int) -> None:
 def cuba_batch_set_cell_lanes(b: int, slot: int, lanes: int) -> None:
     _check(_lib.cuba_batch_set_cell_lanes(b, int(slot), int(lanes)),
            "cuba_batch_set_cell_lanes")
+
+
+def cuba_batch_set_active(b: int, slot: int, active: bool) -> None:
+    _check(_lib.cuba_batch_set_active(b, int(slot), 1 if active else 0),
+           "cuba_batch_set_active")
 
 
 def cuba_batch_set_dt(b: int, slot: int, dt: float) -> None:

@@ -78,10 +78,22 @@ def footprint(req: Request) -> int:
 
 
 class Server:
+    """policy "all": every live event takes part in every run (processor
+    sharing).  policy "srpt": each run takes the oldest live event, then
+    the others in order of least remaining work (particles x steps left)
+    while they fit `run_particles`; the rest are held (cuba_batch_set_active)
+    until chosen.  Short requests then finish in runs that large ones do not
+    slow down, and the oldest one always advances, so none starves."""
+
     def __init__(self, max_slots: int = 256, hbm_budget: int | None = None,
                  run_steps: int = 25, device: str = "cuda", use_graphs: bool = False,
-                 tuning: dict | None = None, keep_states: bool = False):
+                 tuning: dict | None = None, keep_states: bool = False,
+                 policy: str = "all", run_particles: int = 2_000_000):
+        if policy not in ("all", "srpt"):
+            raise ValueError("policy must be 'all' or 'srpt'")
         self.device = device
+        self.policy = policy
+        self.run_particles = int(run_particles)
         self.run_steps = run_steps
         self.keep_states = keep_states
         if hbm_budget is None:
@@ -93,6 +105,7 @@ class Server:
         self.use_graphs = use_graphs
         self.peak_live = 0
         self.peak_bytes = 0
+        self.peak_held = 0
 
     def _admit(self, slot: int, req: Request):
         from . import autotune as AT
@@ -125,7 +138,8 @@ class Server:
                 queue.popleft()
                 self._admit(slot, req)
                 used += need
-                live[slot] = {"req": req, "need": need, "done": 0, "admitted": now()}
+                live[slot] = {"req": req, "need": need, "done": 0, "admitted": now(),
+                              "active": True}
                 self.peak_live = max(self.peak_live, len(live))
                 self.peak_bytes = max(self.peak_bytes, used)
             if not live:
@@ -133,9 +147,12 @@ class Server:
                     time.sleep(max(0.0, min(queue[0].arrival - now(), 0.01)))
                 continue
             k = self.run_steps
+            active = self._choose(live)
             self.B.step(k)
             finished = []
             for slot, ev in live.items():
+                if slot not in active:
+                    continue
                 ev["done"] += k
                 w = ev["req"].work
                 if ev["done"] % w.observe_every == 0 or ev["done"] >= w.steps:
@@ -156,6 +173,27 @@ class Server:
                 used -= ev["need"]
                 results.append(res)
         return results
+
+    def _choose(self, live: dict) -> set:
+        """The slots that take part in the next run (holding the others)."""
+        if self.policy == "all":
+            return set(live)
+        left = lambda s: live[s]["req"].work.n * (live[s]["req"].work.steps - live[s]["done"])
+        oldest = min(live, key=lambda s: (live[s]["req"].arrival, live[s]["req"].rid))
+        active, total = {oldest}, live[oldest]["req"].work.n
+        for slot in sorted(live, key=left):
+            n = live[slot]["req"].work.n
+            if slot == oldest or total + n > self.run_particles:
+                continue
+            active.add(slot)
+            total += n
+        for slot, ev in live.items():
+            want = slot in active
+            if ev["active"] != want:
+                self.B.set_active(slot, want)
+                ev["active"] = want
+        self.peak_held = max(self.peak_held, len(live) - len(active))
+        return active
 
     def close(self):
         self.B.close()
@@ -209,16 +247,17 @@ def bench(a):
     from . import autotune as AT
     n_req = int(a.requests)
     tuning = AT.load()
+    run_steps = int(getattr(a, "serve_run_steps", 50))
     # untimed warm-up of both paths (first launches load code objects and
     # grow the allocator's pools)
     warm = request_stream(16, 0.0, seed=56)
-    srv = Server(tuning=tuning, use_graphs=False)
+    srv = Server(tuning=tuning, use_graphs=False, run_steps=run_steps)
     srv.run(warm, realtime=False)
     srv.close()
     run_alone(warm[0])
     # capacity: a closed batch of 64 requests all present at t = 0
     probe = request_stream(64, 0.0, seed=55)
-    srv = Server(tuning=tuning, use_graphs=False)
+    srv = Server(tuning=tuning, use_graphs=False, run_steps=run_steps)
     t0 = time.perf_counter()
     srv.run(probe, realtime=False)
     cap_dt = time.perf_counter() - t0
@@ -231,17 +270,30 @@ def bench(a):
     reqs = request_stream(n_req, rate, seed=5)
     print(f"# serve: {n_req} requests at {rate:.1f}/s (capacity {throughput:.3e} "
           f"particle-steps/s)", file=sys.stderr, flush=True)
-    srv = Server(tuning=tuning, use_graphs=False)
-    t0 = time.perf_counter()
-    res = srv.run(reqs, realtime=True)
-    makespan = time.perf_counter() - t0
-    srv.close()
-    p50, p99 = percentiles([r.latency for r in res])
     total_ps = sum(r.work.n * r.work.steps for r in reqs)
+    policy = getattr(a, "serve_policy", "all")
     out = {"metric": "served request stream: p50/p99 time-to-result and particle-steps/s",
-           "value": total_ps / makespan, "unit": "particle-steps/s",
-           "p50_s": p50, "p99_s": p99, "requests": len(res), "arrival_rate_per_s": rate,
-           "capacity_particle_steps_per_s": throughput, "makespan_s": makespan}
+           "unit": "particle-steps/s", "policy": policy, "run_steps": run_steps,
+           "run_particles": int(getattr(a, "serve_run_particles", 2_000_000)),
+           "requests": n_req,
+           "arrival_rate_per_s": rate, "capacity_particle_steps_per_s": throughput}
+    # the chosen policy, then the other one on the same trace for comparison
+    for pol in (policy, "all" if policy == "srpt" else "srpt"):
+        print(f"# serve policy {pol}", file=sys.stderr, flush=True)
+        srv = Server(tuning=tuning, use_graphs=False, policy=pol, run_steps=run_steps,
+                     run_particles=int(getattr(a, "serve_run_particles", 2_000_000)))
+        t0 = time.perf_counter()
+        res = srv.run(reqs, realtime=True)
+        makespan = time.perf_counter() - t0
+        srv.close()
+        assert len(res) == n_req
+        p50, p99 = percentiles([r.latency for r in res])
+        if pol == policy:
+            out.update({"value": total_ps / makespan, "p50_s": p50, "p99_s": p99,
+                        "makespan_s": makespan})
+        else:
+            out[pol] = {"value": total_ps / makespan, "p50_s": p50, "p99_s": p99,
+                        "makespan_s": makespan}
     if not getattr(a, "no_sequential", False):
         print("# sequential FIFO replay", file=sys.stderr, flush=True)
         service = {}

@@ -46,7 +46,8 @@ class Sim:
     cell_lanes: lanes per cell of the cell kernels (None: the library's
     choice from the initial occupancy; see cuba_set_cell_lanes).
     `dt` may be changed between steps (cuba_set_dt); `time` is the time
-    advanced since construction, sum of dt over the steps taken.
+    advanced since construction, sum of dt over the steps taken, and
+    `dt_log` lists (step index, dt) for the initial dt and every change.
     """
 
     def __init__(self, params: dict, state, device: str | torch.device = "cuda",
@@ -78,6 +79,7 @@ class Sim:
             C.cuba_set_cell_lanes(self.ctx, cell_lanes)
         self._dt = C.cuba_get_dt(self.ctx)
         self.time = 0.0
+        self.dt_log = [(C.cuba_info(self.ctx)[0], self._dt)]
 
     @property
     def cell_lanes(self) -> int:
@@ -91,6 +93,11 @@ class Sim:
     def dt(self, dt: float) -> None:
         C.cuba_set_dt(self.ctx, dt)
         self._dt = C.cuba_get_dt(self.ctx)
+        t = C.cuba_info(self.ctx)[0]
+        if self.dt_log[-1][0] == t:
+            self.dt_log[-1] = (t, self._dt)
+        else:
+            self.dt_log.append((t, self._dt))
 
     @cell_lanes.setter
     def cell_lanes(self, lanes: int) -> None:

@@ -34,32 +34,35 @@ def dt_limits(params: dict) -> tuple[float, float]:
 
 
 def collision_dt(n_max: float, params: dict, p_max: float = 0.05,
-                 cfl: float = 0.5) -> float:
+                 cfl: float = 0.5, p22_max: float = 1.0) -> float:
     """The largest dt with n_max sigma dt <= p_max, at most cfl times the
-    smallest cell edge and below the 2K <= 1 bound (by a margin of 1e-9
-    relative, for the rounding of K)."""
-    if not (0.0 < p_max and 0.0 < cfl < 1.0):
-        raise ValueError("p_max must be > 0 and 0 < cfl < 1")
+    smallest cell edge, and with the largest pair probability 2K at most
+    p22_max (1: the bound P22 <= 1; less by a margin of 1e-9 relative, for
+    the rounding of K)."""
+    if not (0.0 < p_max and 0.0 < cfl < 1.0 and 0.0 < p22_max <= 1.0):
+        raise ValueError("p_max must be > 0, 0 < cfl < 1 and 0 < p22_max <= 1")
     edge, k_max = dt_limits(params)
     dt = cfl * edge
     sigma = float(params["sigma"])
     if n_max > 0.0 and sigma > 0.0:
         dt = min(dt, p_max / (n_max * sigma))
-    return min(dt, k_max * (1.0 - 1e-9))
+    return min(dt, p22_max * k_max * (1.0 - 1e-9))
 
 
-def run_to(sim, t_end: float, p_max: float = 0.05, every: int = 10, cfl: float = 0.5):
+def run_to(sim, t_end: float, p_max: float = 0.05, every: int = 10, cfl: float = 0.5,
+           p22_max: float = 1.0):
     """Advances `sim` (a Sim) from sim.time to t_end, choosing dt every
     `every` steps from the observed densest slab; the last run shortens dt
     so that the run ends at t_end.  Returns the schedule as a list of
-    (steps, dt)."""
+    (steps, dt); sim.dt_log records the step index at which each dt took
+    effect."""
     schedule = []
     while True:
         left = t_end - sim.time
         if left <= 1e-12 * max(1.0, abs(t_end)):
             return schedule
         n_max = float(np.max(sim.observe_moments()["n"]))
-        dt = collision_dt(n_max, sim.params, p_max, cfl)
+        dt = collision_dt(n_max, sim.params, p_max, cfl, p22_max)
         k = min(every, int(math.ceil(left / dt)))
         if k * dt > left:
             dt = left / k

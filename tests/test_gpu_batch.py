@@ -177,3 +177,31 @@ def test_batch_mixed_cell_capacities(mods):
     for i, (w, st) in enumerate(zip(evs, states)):
         assert_same(B.get_state(i), alone(sim, w, st, 8), w.name)
     B.close()
+
+
+def test_held_events_keep_their_state(mods):
+    """cuba_batch_set_active: an event held out of some runs keeps its state
+    and step index, and once resumed ends as its lone run of the steps it
+    took part in; held with graphs on, so the table and graphs are rebuilt."""
+    batch, sim = mods
+    evs = small_events()[1:4]
+    states = [W.riemann_state(w, seed=21 + i) for i, w in enumerate(evs)]
+    B = batch.Batch(3, use_graphs=True)
+    for i, (w, st) in enumerate(zip(evs, states)):
+        B.admit(i, w.params(), st)
+    B.step(4)                     # all: 4
+    B.set_active(1, False)
+    B.step(4)                     # 0 and 2: 8
+    held = B.get_state(1)
+    B.set_active(0, False)
+    B.set_active(2, False)
+    B.set_active(1, True)
+    B.step(4)                     # 1: 8
+    B.set_active(0, True)
+    B.step(3)                     # 0: 11, 1: 11
+    B.sync()
+    assert [B.next_step(i) for i in range(3)] == [11, 11, 8]
+    assert_same(held, alone(sim, evs[1], states[1], 4), "held")
+    for i, n in enumerate((11, 11, 8)):
+        assert_same(B.get_state(i), alone(sim, evs[i], states[i], n), evs[i].name)
+    B.close()

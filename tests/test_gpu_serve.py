@@ -20,13 +20,20 @@ def serve():
     return serve
 
 
-def test_results_same_alone_and_in_the_mix(serve):
+@pytest.mark.parametrize("policy", ("all", "srpt"))
+def test_results_same_alone_and_in_the_mix(serve, policy):
     reqs = serve.request_stream(10, 0.0, seed=8, nmin=1e4, nmax=8e4, steps=100)
     budget = 3 * max(serve.footprint(r) for r in reqs)
-    srv = serve.Server(max_slots=4, hbm_budget=budget, run_steps=25, keep_states=True)
+    # srpt: a run holds about two of the requests, so events wait, are held
+    # and resume between runs
+    run_particles = 2 * max(r.work.n for r in reqs)
+    srv = serve.Server(max_slots=4, hbm_budget=budget, run_steps=25, keep_states=True,
+                       policy=policy, run_particles=run_particles)
     res = srv.run(reqs, realtime=False)
     assert srv.peak_live <= 4 and srv.peak_bytes <= budget
     assert srv.peak_live >= 2          # the requests overlapped on the device
+    if policy == "srpt":
+        assert srv.peak_held >= 1
     srv.close()
     assert sorted(r.rid for r in res) == list(range(len(reqs)))
     by_id = {r.rid: r for r in reqs}

@@ -152,6 +152,10 @@ def test_collision_limited_schedule(lib):  # noqa: F811
     # hot side's mean (~230 particles per slab)
     n_hot = W.gluon_density(0.45)
     assert 0.2 / (1.4 * n_hot * 1.8) < sched[0][1] < 0.2 / (n_hot * 1.8)
+    # the log holds the step index at which each dt took effect (the
+    # policy's first dt replaces the initial one at step 0)
+    starts = np.cumsum([0] + [k for k, _ in sched[:-1]])
+    assert sim.dt_log == [(int(t), dt) for t, (_, dt) in zip(starts, sched)]
     m = sim.observe_moments()
     assert float(m["T00"].sum()) == pytest.approx(e0, rel=1e-12)
     dx = 10.0 / 100

@@ -48,10 +48,14 @@ def test_collision_dt_closed_forms():
     q = dict(p, sigma=4000.0)
     assert TS.collision_dt(1e-9, q, 1e9) == pytest.approx(2500 * 0.004 / 8000, rel=1e-8)
     assert TS.collision_dt(1e-9, q, 1e9) * 4000.0 / 2500.0 / 0.004 * 2 <= 1.0
+    # a bound on the largest pair probability 2K
+    assert TS.collision_dt(n, p, 10.0, cfl=0.9, p22_max=0.001) == pytest.approx(
+        0.001 * 2500 * 0.004 / 0.8, rel=1e-8)
     # no cross section: only the cell edge limits dt
     assert TS.collision_dt(n, dict(p, sigma=0.0), 0.05) == pytest.approx(0.05, rel=1e-15)
-    with pytest.raises(ValueError):
-        TS.collision_dt(n, p, 0.0)
+    for bad in (dict(p_max=0.0), dict(cfl=1.0), dict(p22_max=1.5)):
+        with pytest.raises(ValueError):
+            TS.collision_dt(n, p, **bad)
 
 
 def test_policy_dt_gives_the_kinetic_scattering_fraction(orc):
