@@ -221,9 +221,11 @@ __device__ __forceinline__ void scatter_pair(double &ax, double &ay, double &az,
 
   const double cth = 2.0 * uc - 1.0;
   const double sth = __builtin_sqrt((1.0 - cth) * (1.0 + cth));
-  const double phi = 6.283185307179586 * uphi;
+  // phi = 2 pi uphi: sin and cos of pi * (2 uphi), whose argument needs no
+  // range reduction (the oracle rounds 2 pi uphi first and calls sin, cos;
+  // the two differ by ulps)
   double sphi, cphi;
-  sincos(phi, &sphi, &cphi);
+  sincospi(2.0 * uphi, &sphi, &cphi);
   const double qx = estar * (sth * cphi);
   const double qy = estar * (sth * sphi);
   const double qz = estar * cth;
