@@ -87,6 +87,26 @@ KERNEL_SOURCES = ("paper_1208_0961_amd/csrc/kernels.hip", "paper_1208_0961_amd/c
 DOMINANT_KERNEL = "k_step<true, false,"   # the fused step, any cell capacity
 
 
+def device_copy_gbs(stream, nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Read + write GB/s of torch's device-to-device copy of nbytes."""
+    import torch
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    with torch.cuda.stream(stream):
+        src.fill_(1.0)
+        for _ in range(2):
+            dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -377,6 +397,12 @@ def main():
     stage_out["step"]["hbm_gbs_algorithmic"] = gbs(BYTES_BIN * w.n, step_ms)
     stage_out["step"]["fp64_tflops_algorithmic"] = (
         FP64_FLOPS_PER_PAIR * pairs_per_step / (step_ms * 1e-3) / 1e12)
+
+    # a plain device copy of 1 GiB, timed after the run, as the practical
+    # HBM ceiling beside the 8 TB/s peak (read + write bytes per second)
+    copy_gbs = device_copy_gbs(sim.stream)
+    stage_out["bin"]["copy_gbs"] = copy_gbs
+    stage_out["bin"]["frac_copy"] = stage_out["bin"]["gbs"] / copy_gbs
 
     cpu = None
     cpu_steps = a.cpu_steps if a.cpu_steps is not None else {"tube1d": 100, "tube3d": 24,
