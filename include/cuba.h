@@ -311,7 +311,8 @@ int cuba_batch_set_dt(cuba_batch *b, int32_t slot, double dt);
 int cuba_batch_set_launch(cuba_batch *b, int32_t persistent_waves,
                           int32_t use_graphs);
 
-/* Advances every live event by nsteps steps (asynchronous). */
+/* Advances every admitted event that is not held (cuba_batch_set_active)
+ * by nsteps steps (asynchronous). */
 int cuba_batch_step(cuba_batch *b, int32_t nsteps);
 
 /* Waits for the stream and reports the first event's device error (its
