@@ -44,3 +44,63 @@ def test_footprint_matches_workspace_formula(serve):
 def test_percentiles(serve):
     p50, p99 = serve.percentiles(np.arange(1, 101, dtype=float))
     assert p50 == pytest.approx(50.5) and p99 == pytest.approx(99.01)
+
+
+class _FakeBatch:
+    """Records set_active calls; stands in for the device batch."""
+
+    def __init__(self):
+        self.calls = []
+
+    def set_active(self, slot, active):
+        self.calls.append((slot, bool(active)))
+
+
+def _live(serve, specs):
+    """live dict as Server.run keeps it: slot -> request of equal size with
+    (steps done, arrival), active flag."""
+    from paper_1208_0961_amd import workload as W
+    live = {}
+    for slot, (done, arrival) in enumerate(specs):
+        w = W.Workload(f"r{slot}", (10.0, 1.0, 1.0), (100, 5, 5), 100.0, 0.5, 0.02, 0.4, 0.32,
+                       steps=200)
+        req = serve.Request(slot, w, arrival, 0)
+        live[slot] = {"req": req, "need": 0, "done": done, "admitted": 0.0, "active": True}
+    return live
+
+
+def test_srpt_policy_choice(serve):
+    """The oldest event always runs; the others join by least remaining work
+    (particles x steps left) while they fit the particle budget; set_active
+    is called only for events whose state changes."""
+    live = _live(serve, [(0, 0.5), (150, 0.1), (0, 0.2), (100, 0.3)])
+    n = {s: ev["req"].work.n for s, ev in live.items()}
+    srv = serve.Server.__new__(serve.Server)
+    srv.policy, srv.peak_held = "srpt", 0
+    srv.B = _FakeBatch()
+    # room for the oldest (slot 1) and one more
+    srv.run_particles = n[1] + n[3]
+    act = srv._choose(live)
+    left = {s: n[s] * (200 - live[s]["done"]) for s in live}
+    assert 1 in act                           # oldest arrival
+    # the event with the least remaining work besides the oldest is slot 3
+    assert min((s for s in live if s != 1), key=left.get) == 3
+    assert act == {1, 3}
+    assert sorted(srv.B.calls) == [(0, False), (2, False)]
+    assert srv.peak_held == 2
+    # nothing changes: no calls
+    srv.B.calls.clear()
+    assert srv._choose(live) == {1, 3} and srv.B.calls == []
+    # a budget below the oldest's size still runs the oldest alone
+    srv.run_particles = 1
+    assert srv._choose(live) == {1}
+    assert srv.B.calls == [(3, False)]
+    # policy all: every live event, no calls
+    srv2 = serve.Server.__new__(serve.Server)
+    srv2.policy, srv2.peak_held, srv2.B = "all", 0, _FakeBatch()
+    assert srv2._choose(live) == set(live) and srv2.B.calls == []
+
+
+def test_server_rejects_unknown_policy(serve):
+    with pytest.raises(ValueError):
+        serve.Server(policy="lifo", hbm_budget=1 << 20)
