@@ -275,18 +275,29 @@ __global__ __launch_bounds__(kBlock) void k_init_bin(
   append(dst, cell, active, a, b, c, qa, qb, qc, (uint32_t)i, status);
 }
 
-// Cells holding more than 8, 16, 32, 64 particles (ballot counts, one
-// atomic per wave and threshold).
+// Cells holding more than 8, 16, 32 and 64 particles, added into over[4]:
+// a grid stride over the cells, counts kept per wave, summed per block in
+// LDS, then four atomics per block (one atomic per wave and counter
+// serialised on the four addresses at 2 M cells).
 __global__ __launch_bounds__(kBlock) void k_occupancy_over(Cells cur_arg, uint32_t n_cells,
                                                            uint32_t *over) {
   const GCells cur = to_global(cur_arg);
-  const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
-  const uint32_t n = c < n_cells ? occupancy(cur, c) : 0u;
-  const uint32_t lane = lane_id();
+  __shared__ uint32_t part[kBlock / 64][4];
+  uint32_t acc[4] = {0u, 0u, 0u, 0u};
+  for (uint32_t c0 = blockIdx.x * kBlock; c0 < n_cells; c0 += gridDim.x * kBlock) {
+    const uint32_t c = c0 + threadIdx.x;
+    const uint32_t n = c < n_cells ? occupancy(cur, c) : 0u;
 #pragma unroll
-  for (uint32_t k = 0; k < 4; ++k) {
-    const uint32_t cnt = (uint32_t)__popcll(__ballot(n > (8u << k)));
-    if (lane == 0 && cnt != 0) atomicAdd(&over[k], cnt);
+    for (uint32_t k = 0; k < 4; ++k) acc[k] += (uint32_t)__popcll(__ballot(n > (8u << k)));
+  }
+  const uint32_t w = threadIdx.x / 64;
+  if (lane_id() == 0)
+    for (uint32_t k = 0; k < 4; ++k) part[w][k] = acc[k];
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    uint32_t sum = 0;
+    for (uint32_t i = 0; i < kBlock / 64; ++i) sum += part[i][threadIdx.x];
+    if (sum != 0) atomicAdd(&over[threadIdx.x], sum);
   }
 }
 
@@ -1485,7 +1496,8 @@ void launch_step(const Cells &src, const Cells &dst, bool fused, int64_t n_cells
 void launch_occupancy_over(const Cells &cur, int64_t n_cells, DevStatus *status,
                            hipStream_t s) {
   if (n_cells <= 0) return;
-  hipLaunchKernelGGL(k_occupancy_over, dim3(grid_for(n_cells)), dim3(kBlock), 0, s, cur,
+  const unsigned grid = grid_for(n_cells) < 1024u ? grid_for(n_cells) : 1024u;
+  hipLaunchKernelGGL(k_occupancy_over, dim3(grid), dim3(kBlock), 0, s, cur,
                      (uint32_t)n_cells, status->over);
 }
 
