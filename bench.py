@@ -164,17 +164,29 @@ def measured_traffic(workload: str):
 
 
 def cpu_baseline(w, state, steps, threads):
+    """The oracle on `steps` steps with `threads` threads over cells, then,
+    for boxes of at most 4 M particles, one or two steps on a single
+    thread."""
     from oracle import oracle as O
     st = O.State(*state)
     p = O.make_params(**w.params())
     t0 = time.perf_counter()
     O.run(p, st, 0, steps, threads)
     dt = time.perf_counter() - t0
-    return {"value": w.n * steps / dt, "unit": "particle-steps/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{w.name}: {steps} steps of all {w.n} particles from the "
-                      f"benchmark's initial state, {threads} threads over cells, "
-                      f"{dt:.1f} s wall"}
+    out = {"value": w.n * steps / dt, "unit": "particle-steps/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"{w.name}: {steps} steps of all {w.n} particles from the "
+                     f"benchmark's initial state, {threads} threads over cells, "
+                     f"{dt:.1f} s wall"}
+    if w.n <= 4_000_000:
+        steps1 = 2 if w.n < 2_000_000 else 1
+        st1 = O.State(*state)
+        t0 = time.perf_counter()
+        O.run(p, st1, 0, steps1, 1)
+        dt1 = time.perf_counter() - t0
+        out["single_thread_value"] = w.n * steps1 / dt1
+        out["sample"] += f"; single thread: {steps1} step(s), {dt1:.1f} s"
+    return out
 
 
 def bench_sigma_scan(a):
