@@ -67,9 +67,10 @@ def parse():
                     help="serve, srpt: particles per run beside the oldest request")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batch: skip the one-at-a-time comparison")
-    ap.add_argument("--lanes", type=int, default=None, choices=[0, 8, 16, 32, 64],
-                    help="plain workloads: lanes per cell of the cell kernels "
-                         "(default: the library's choice from the mean occupancy)")
+    ap.add_argument("--lanes", type=int, default=None, choices=[0, 8, 16, 32, 64, 128],
+                    help="plain workloads: lanes per cell of the cell kernels, 128 for "
+                         "two waves per cell (default: the library's choice from the "
+                         "initial occupancy)")
     ap.add_argument("--cpu-steps", type=int, default=None,
                     help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--cpu-threads", type=int, default=None)

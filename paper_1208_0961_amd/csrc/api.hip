@@ -129,19 +129,27 @@ int derive(const cuba_params *p, Derived &d) {
 //  * else the smallest group of 8, 16 or 32 lanes that all but a small
 //    fraction of the cells fit (64-lane groups lost to one wave per cell
 //    in every measured occupancy mix);
-//  * else, where the oversize cells can take a wave each (the plain path),
-//    8 lanes if at least a quarter of the cells fit them: a box of dense
-//    and sparse regions steps each region with its own kernel;
+//  * else, on the plain path (plain: not in a batch), where the oversize
+//    cells take a wave each, 8 lanes if at least a quarter of the cells fit
+//    them: a box of dense and sparse regions steps each region with its
+//    own kernel;
 //  * else one wave per cell.
+// Except: on the plain path, a box of fewer cells than the chip has SIMDs,
+// most of them holding more than 32 particles, takes two waves per cell (the
+// 1-D tube's 100 cells step in 24 instead of 33 us; at 10 000 cells and
+// more the second wave's extra work outweighs its parallelism).
 constexpr double kOversizeFraction = 2e-3;
 constexpr double kSparseFraction = 0.25;
 constexpr int64_t kSmallCellsMinCells = 16384;
-uint32_t default_lanes(const uint32_t over[4], int64_t n_cells, bool wave_per_oversize) {
+constexpr int64_t kTwoWaveMaxCells = 1024;
+uint32_t default_lanes(const uint32_t over[4], int64_t n_cells, bool plain) {
+  if (plain && n_cells < kTwoWaveMaxCells && 2 * (int64_t)over[2] >= n_cells)
+    return kTwoWavesPerCell;
   if (n_cells < kSmallCellsMinCells) return 0;
   const double limit = kOversizeFraction * (double)n_cells;
   for (uint32_t k = 0; k < 3; ++k)
     if ((double)over[k] <= limit) return 8u << k;
-  if (wave_per_oversize && (double)(n_cells - over[0]) >= kSparseFraction * (double)n_cells)
+  if (plain && (double)(n_cells - over[0]) >= kSparseFraction * (double)n_cells)
     return 8;
   return 0;
 }
@@ -238,7 +246,7 @@ void drop_timing(cuba_ctx *c) {
 // The oversize-cell launch takes a wave per cell once such cells average
 // more than one in 64 (by the initial histogram), else a wave per 64 cells.
 uint32_t over_span(const uint32_t over[4], uint32_t lanes, int64_t n_cells) {
-  if (lanes == 0) return 64;
+  if (lanes == 0 || lanes == kTwoWavesPerCell) return 64;
   const uint32_t k = lanes == 8 ? 0 : lanes == 16 ? 1 : lanes == 32 ? 2 : 3;
   return (int64_t)over[k] * 64 > n_cells ? 1u : 64u;
 }
@@ -431,7 +439,8 @@ int cuba_init(cuba_ctx **out, const cuba_params *params, int64_t n, const double
 
 int cuba_set_cell_lanes(cuba_ctx *c, int32_t lanes) {
   if (!c) return fail(CUBA_EINVAL, "ctx is NULL");
-  if (!valid_cell_lanes(lanes)) return fail(CUBA_EINVAL, "lanes must be 0, 8, 16, 32 or 64");
+  if (!valid_plain_cell_lanes(lanes))
+    return fail(CUBA_EINVAL, "lanes must be 0, 8, 16, 32, 64 or 128");
   c->lanes = (uint32_t)lanes;
   return CUBA_OK;
 }

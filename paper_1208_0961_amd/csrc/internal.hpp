@@ -95,8 +95,15 @@ struct BatchSpaces {
 // Lanes-per-cell settings of the cell kernels: 0 runs one wave per cell;
 // 8, 16, 32 and 64 run 64 / lanes small cells per wave, one particle per
 // lane, and step larger cells with the whole wave.
+// Lanes per cell: 0 (one wave per cell), 8, 16, 32, 64 (64 / lanes cells
+// per wave, one particle per lane) or kTwoWavesPerCell (a workgroup of two
+// waves per cell; plain path only).
+constexpr uint32_t kTwoWavesPerCell = 128;
 inline bool valid_cell_lanes(int32_t v) {
   return v == 0 || v == 8 || v == 16 || v == 32 || v == 64;
+}
+inline bool valid_plain_cell_lanes(int32_t v) {
+  return valid_cell_lanes(v) || v == (int32_t)kTwoWavesPerCell;
 }
 
 // A second stream on which a step runs work that is independent of the

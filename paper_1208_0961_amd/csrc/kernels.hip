@@ -446,18 +446,37 @@ struct CellView {
   size_t base;
 };
 
+// Orders the calling wave's LDS accesses before and after this point for
+// its own lanes (LDS executes one wave's operations in order; the fence
+// keeps the compiler from moving accesses across and waits for them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// kBlockSync: the workgroup is this one wave, and its barriers order the
+// LDS accesses; otherwise a wave that shares its workgroup with others
+// synchronises with itself only.
+template <bool kBlockSync>
+__device__ __forceinline__ void cell_sync() {
+  if (kBlockSync)
+    __syncthreads();
+  else
+    wave_lds_sync();
+}
+
 // Exact Eq. (3) test of the nf filtered pairs in s_filt (increasing pair
 // index), then greedy claim in that order.  Entries are rewritten as
 // flag | a << 10 | b.  claimed_bits holds, per lane, the claimed flags of
-// canonical indices lane + 64 j.
-template <bool kTrace>
+// canonical indices lane + 64 j.  One wave; see cell_sync for kBlockSync.
+template <bool kTrace, bool kBlockSync = true>
 __device__ __forceinline__ void resolve_filtered(
     uint32_t nf, const CellView &cv, const PairArgs &pa, const GSoA &st,
     const uint16_t *s_perm, uint32_t *s_filt, uint32_t *s_claim,
     uint32_t &nclaim, uint32_t &claimed_bits, uint32_t &n_acc,
     const TraceArgs &tr, DevStatus *status) {
   const uint32_t lane = lane_id();
-  __syncthreads();
+  cell_sync<kBlockSync>();
   for (uint32_t i = lane; i < nf; i += 64) {
     const uint32_t k = s_filt[i];
     const Words4 w = philox10(k, cv.c, cv.t, 0u, pa.key0, pa.key1);
@@ -481,7 +500,7 @@ __device__ __forceinline__ void resolve_filtered(
       }
     }
   }
-  __syncthreads();
+  cell_sync<kBlockSync>();
   for (uint32_t i = 0; i < nf; ++i) {
     const uint32_t v = s_filt[i];
     if (v & 0x80000000u) {
@@ -497,7 +516,63 @@ __device__ __forceinline__ void resolve_filtered(
       }
     }
   }
-  __syncthreads();
+  cell_sync<kBlockSync>();
+}
+
+// Pair tests k = k_begin .. k_end - 1 of a cell by one wave, lane-strided,
+// two rows of 64 pairs per iteration while two rows remain.  A pair whose
+// Philox word w1 rules out acceptance (u >= w1 2^-32 > P22) is dropped at
+// once; the others are appended to filt (nf entries, increasing k; at most
+// kFiltCap).  kResolve: when filt nears full its entries are resolved
+// (exact test and claims) and the tests go on; otherwise the tests stop
+// there.  Returns the first pair not tested (k_end when all were).
+template <bool kResolve, bool kTrace, bool kBlockSync, uint32_t kFiltCap>
+__device__ __forceinline__ uint32_t test_pairs(
+    uint32_t k_begin, uint32_t k_end, const CellView &cv, const PairArgs &pa,
+    const GSoA &st, const uint16_t *s_perm, uint32_t *filt, uint32_t &nf,
+    uint32_t *s_claim, uint32_t &nclaim, uint32_t &claimed_bits, uint32_t &n_acc,
+    const TraceArgs &tr, DevStatus *status) {
+  static_assert(kFiltCap >= 256, "filter buffer");
+  const uint32_t lane = lane_id();
+  const uint64_t below = (1ull << lane) - 1ull;
+  const uint32_t lim = pa.w1_max;
+  uint32_t k0 = k_begin;
+  for (; k0 + 128u <= k_end; k0 += 128u) {
+    const uint32_t ka = k0 + lane, kb = k0 + 64u + lane;
+    const uint32_t wa = philox10_w1(ka, cv.c, cv.t, 0u, pa.key0, pa.key1);
+    const uint32_t wb = philox10_w1(kb, cv.c, cv.t, 0u, pa.key0, pa.key1);
+    const bool pass_a = wa <= lim, pass_b = wb <= lim;
+    const uint64_t ma = __ballot(pass_a), mb = __ballot(pass_b);
+    if ((ma | mb) != 0) {
+      if (pass_a) filt[nf + (uint32_t)__popcll(ma & below)] = ka;
+      nf += (uint32_t)__popcll(ma);
+      if (pass_b) filt[nf + (uint32_t)__popcll(mb & below)] = kb;
+      nf += (uint32_t)__popcll(mb);
+      if (nf > kFiltCap - 128u) {
+        if (!kResolve) return k0 + 128u;
+        resolve_filtered<kTrace, kBlockSync>(nf, cv, pa, st, s_perm, filt, s_claim, nclaim,
+                                             claimed_bits, n_acc, tr, status);
+        nf = 0;
+      }
+    }
+  }
+  for (; k0 < k_end; k0 += 64u) {
+    const uint32_t k = k0 + lane;
+    bool pass = false;
+    if (k < k_end) pass = philox10_w1(k, cv.c, cv.t, 0u, pa.key0, pa.key1) <= lim;
+    const uint64_t m = __ballot(pass);
+    if (m != 0) {
+      if (pass) filt[nf + (uint32_t)__popcll(m & below)] = k;
+      nf += (uint32_t)__popcll(m);
+      if (nf > kFiltCap - 64u) {
+        if (!kResolve) return k0 + 64u < k_end ? k0 + 64u : k_end;
+        resolve_filtered<kTrace, kBlockSync>(nf, cv, pa, st, s_perm, filt, s_claim, nclaim,
+                                             claimed_bits, n_acc, tr, status);
+        nf = 0;
+      }
+    }
+  }
+  return k_end;
 }
 
 // Cells of more than kBucketRankMin particles rank their ids through
@@ -528,14 +603,35 @@ struct CellLds {
   uint32_t sorted[kCap];                         // ids in bucket order
 };
 
-// Collisions of cell c of src at step t (one wave).  kFused: afterwards
-// stream and bin the cell's particles into dst for step t+1 and clear src's
-// count.  Starts with a barrier, so a wave may call it for several cells.
-template <bool kFused, bool kTrace, uint32_t kCap>
+// LDS of the second wave of a cell stepped by two: its filtered pairs, and
+// what it hands to the first wave (count, first pair it did not test), and
+// the first wave's claim count for the kinematics.
+template <uint32_t kCap>
+struct SecondWaveLds {
+  uint32_t filt[kCap / 2];
+  uint32_t n_filt, k_resume, nclaim, pad;
+};
+
+// Collisions of cell c of src at step t by a workgroup of kW waves (1 or
+// 2).  kFused: afterwards stream and bin the cell's particles into dst for
+// step t+1 and clear src's count.  Starts with a barrier, so a wave may call
+// it for several cells.  With two waves (x2: the second wave's LDS) the
+// pair range is split: the first wave tests the pairs below kh, resolving
+// and claiming as it goes, while the second filters the pairs from kh on
+// into its own buffer; the first wave then resolves those in order (they
+// all follow its own) and tests any pairs the second left once its buffer
+// filled.  Claims are thus made in increasing pair order as with one wave,
+// and every other phase is split over the workgroup's lanes.  Both waves
+// pass the same barriers; code that one wave runs alone synchronises with
+// itself only.
+template <bool kFused, bool kTrace, uint32_t kCap, uint32_t kW = 1>
 __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, uint32_t c,
                                           uint32_t t, const PairArgs &pa,
                                           const Geometry &g, DevStatus *status,
-                                          const TraceArgs &tr, CellLds<kFused, kCap> &lds) {
+                                          const TraceArgs &tr, CellLds<kFused, kCap> &lds,
+                                          SecondWaveLds<kCap> *x2 = nullptr) {
+  static_assert(kW == 1 || (kW == 2 && !kTrace), "one or two waves, traces with one");
+  constexpr uint32_t kT = 64 * kW;
   // filtered pairs and claimed pairs share the id buffer, kCap / 2 each
   constexpr uint32_t kFilt = kCap / 2;
   static_assert(kCap <= kCellCap && kFilt >= 256, "cell capacity");
@@ -546,6 +642,8 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
   __syncthreads();
 
   const uint32_t lane = lane_id();
+  const uint32_t tid = kW == 1 ? lane : (uint32_t)threadIdx.x;
+  const uint32_t wv = tid / 64;  // this wave within the cell's workgroup
   CellView cv;
   cv.c = c;
   cv.t = t;
@@ -558,7 +656,7 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
   if (n >= 2) {
     // ids to LDS, padded to a multiple of 4 with an id no particle has
     const uint32_t n4 = (n + 3u) & ~3u;
-    for (uint32_t j = lane; j < n4; j += 64)
+    for (uint32_t j = tid; j < n4; j += kT)
       s_id[j] = j < n ? st.id[cv.base + j] : 0xFFFFFFFFu;
     __syncthreads();
 
@@ -580,12 +678,12 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
       const uint32_t shift = bits > 8u ? bits - 8u : 0u;
       uint32_t *const s_bkt = lds.bkt;
       uint32_t *const s_sorted = lds.sorted;
-      for (uint32_t b = lane; b < kRankBuckets; b += 64) s_bkt[b] = 0u;
-      if (lane == 0) s_bkt[kRankBuckets] = n;
+      for (uint32_t b = tid; b < kRankBuckets; b += kT) s_bkt[b] = 0u;
+      if (tid == 0) s_bkt[kRankBuckets] = n;
       __syncthreads();
-      for (uint32_t j = lane; j < n; j += 64) atomicAdd(&s_bkt[(s_id[j] - lo) >> shift], 1u);
+      for (uint32_t j = tid; j < n; j += kT) atomicAdd(&s_bkt[(s_id[j] - lo) >> shift], 1u);
       __syncthreads();
-      {  // inclusive scan of the counts: s_bkt[b] = end of bucket b
+      if (wv == 0) {  // inclusive scan of the counts: s_bkt[b] = end of bucket b
         uint4 q = reinterpret_cast<uint4 *>(s_bkt)[lane];
         q.y += q.x;
         q.z += q.y;
@@ -605,13 +703,13 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
       }
       __syncthreads();
       // each bucket filled from its end: afterwards s_bkt[b] is its start
-      for (uint32_t j = lane; j < n; j += 64) {
+      for (uint32_t j = tid; j < n; j += kT) {
         const uint32_t v = s_id[j];
         const uint32_t pos = atomicSub(&s_bkt[(v - lo) >> shift], 1u) - 1u;
         s_sorted[pos] = v;
       }
       __syncthreads();
-      for (uint32_t j = lane; j < n; j += 64) {
+      for (uint32_t j = tid; j < n; j += kT) {
         const uint32_t me = s_id[j], b = (me - lo) >> shift;
         const uint32_t p1 = s_bkt[b + 1];
         uint32_t r = s_bkt[b];
@@ -623,7 +721,7 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
       // at most kBucketRankMin < 64 particles: one per lane, counting all ids
       const uint4 *s_id4 = reinterpret_cast<const uint4 *>(s_id);
       static_assert(kBucketRankMin < 64, "one particle per lane");
-      if (lane < n) {
+      if (tid < n) {
         const uint32_t me = s_id[lane];
         uint32_t r = 0;
         for (uint32_t m = 0; m < n4 / 4; ++m) {
@@ -636,59 +734,65 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
     }
     __syncthreads();
 
-    // every pair k = 0 .. n(n-1)/2 - 1, lane-strided; pairs whose Philox
-    // word w1 rules out acceptance (u >= w1 2^-32 > P22) are dropped at
-    // once, the rest are compacted (in increasing k) for the exact test.
-    // The main loop takes two full rows of 64 pairs per iteration.
+    // every pair k = 0 .. n(n-1)/2 - 1 (test_pairs), then the exact test
+    // and the claims of the filtered ones in increasing k
     const uint32_t npairs = n * (n - 1u) / 2u;
-    const uint64_t below = (1ull << lane) - 1ull;
-    const uint32_t lim = pa.w1_max;
     uint32_t nf = 0, claimed_bits = 0, n_acc = 0;
-    uint32_t k0 = 0;
-    if (pa.any) {
-      for (; k0 + 128u <= npairs; k0 += 128u) {
-        const uint32_t ka = k0 + lane, kb = k0 + 64u + lane;
-        const uint32_t wa = philox10_w1(ka, cv.c, t, 0u, pa.key0, pa.key1);
-        const uint32_t wb = philox10_w1(kb, cv.c, t, 0u, pa.key0, pa.key1);
-        const bool pass_a = wa <= lim, pass_b = wb <= lim;
-        const uint64_t ma = __ballot(pass_a), mb = __ballot(pass_b);
-        if ((ma | mb) != 0) {
-          if (pass_a) s_filt[nf + (uint32_t)__popcll(ma & below)] = ka;
-          nf += (uint32_t)__popcll(ma);
-          if (pass_b) s_filt[nf + (uint32_t)__popcll(mb & below)] = kb;
-          nf += (uint32_t)__popcll(mb);
-          if (nf > kFilt - 128u) {
-            resolve_filtered<kTrace>(nf, cv, pa, st, s_perm, s_filt, s_claim, nclaim,
-                                     claimed_bits, n_acc, tr, status);
-            nf = 0;
-          }
+    if (kW == 1) {
+      if (pa.any)
+        test_pairs<true, kTrace, true, kFilt>(0u, npairs, cv, pa, st, s_perm, s_filt, nf,
+                                              s_claim, nclaim, claimed_bits, n_acc, tr,
+                                              status);
+      if (nf != 0)
+        resolve_filtered<kTrace>(nf, cv, pa, st, s_perm, s_filt, s_claim, nclaim,
+                                 claimed_bits, n_acc, tr, status);
+      __syncthreads();
+    } else {
+      const uint32_t kh = npairs / 2u / 128u * 128u;
+      if (wv == 0) {
+        if (pa.any)
+          test_pairs<true, false, false, kFilt>(0u, kh, cv, pa, st, s_perm, s_filt, nf,
+                                                s_claim, nclaim, claimed_bits, n_acc, tr,
+                                                status);
+        if (nf != 0)
+          resolve_filtered<false, false>(nf, cv, pa, st, s_perm, s_filt, s_claim, nclaim,
+                                         claimed_bits, n_acc, tr, status);
+        nf = 0;
+      } else {
+        uint32_t n1 = 0, k_resume = npairs;
+        if (pa.any)
+          k_resume = test_pairs<false, false, false, kCap / 2>(
+              kh, npairs, cv, pa, st, s_perm, x2->filt, n1, s_claim, nclaim, claimed_bits,
+              n_acc, tr, status);
+        if (lane == 0) {
+          x2->n_filt = n1;
+          x2->k_resume = k_resume;
         }
       }
-      for (; k0 < npairs; k0 += 64u) {
-        const uint32_t k = k0 + lane;
-        bool pass = false;
-        if (k < npairs) pass = philox10_w1(k, cv.c, t, 0u, pa.key0, pa.key1) <= lim;
-        const uint64_t m = __ballot(pass);
-        if (m != 0) {
-          if (pass) s_filt[nf + (uint32_t)__popcll(m & below)] = k;
-          nf += (uint32_t)__popcll(m);
-          if (nf > kFilt - 64u) {
-            resolve_filtered<kTrace>(nf, cv, pa, st, s_perm, s_filt, s_claim, nclaim,
-                                     claimed_bits, n_acc, tr, status);
-            nf = 0;
-          }
+      __syncthreads();
+      if (wv == 0) {
+        const uint32_t n1 = x2->n_filt, k_resume = x2->k_resume;
+        if (n1 != 0)
+          resolve_filtered<false, false>(n1, cv, pa, st, s_perm, x2->filt, s_claim, nclaim,
+                                         claimed_bits, n_acc, tr, status);
+        if (k_resume < npairs) {
+          test_pairs<true, false, false, kFilt>(k_resume, npairs, cv, pa, st, s_perm, s_filt,
+                                                nf, s_claim, nclaim, claimed_bits, n_acc, tr,
+                                                status);
+          if (nf != 0)
+            resolve_filtered<false, false>(nf, cv, pa, st, s_perm, s_filt, s_claim, nclaim,
+                                           claimed_bits, n_acc, tr, status);
         }
+        if (lane == 0) x2->nclaim = nclaim;
       }
+      __syncthreads();
+      nclaim = x2->nclaim;
     }
-    if (nf != 0)
-      resolve_filtered<kTrace>(nf, cv, pa, st, s_perm, s_filt, s_claim, nclaim,
-                               claimed_bits, n_acc, tr, status);
-    __syncthreads();
 
     // work counters (spread over slots by cell against contention)
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) n_acc += __shfl_down(n_acc, o);
-    if (lane == 0) {
+    if (tid == 0) {
       const uint32_t slot = cv.c % kCounterSlots;
       atomicAdd(&status->pairs[slot], (unsigned long long)npairs);
       atomicAdd(&status->cand[slot], (unsigned long long)n_acc);
@@ -697,7 +801,7 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
 
     // kinematics of the claimed pairs (disjoint: one writer per particle),
     // written back in place; a fused step then bins every particle
-    for (uint32_t i0 = 0; i0 < nclaim; i0 += 64) {
+    for (uint32_t i0 = wv * 64u; i0 < nclaim; i0 += kT) {
       const uint32_t i = i0 + lane;
       const bool active = i < nclaim;
       double ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0;
@@ -738,7 +842,7 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
       }
     }
     if (kFused) __syncthreads();
-  } else if (kTrace && n == 1 && lane == 0 && tr.perm) {
+  } else if (kTrace && n == 1 && tid == 0 && tr.perm) {
     tr.perm[tr.offsets[cv.c]] = st.id[cv.base];
   }
 
@@ -748,7 +852,7 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
     // geometry is copied to registers once: read through a reference it
     // would be reloaded after every store.
     const Geometry g_l = g;
-    for (uint32_t j0 = 0; j0 < n; j0 += 64) {
+    for (uint32_t j0 = wv * 64u; j0 < n; j0 += kT) {
       const uint32_t j = j0 + lane;
       const bool active = j < n;
       double x = 0, y = 0, z = 0, px = 0, py = 0, pz = 0;
@@ -767,7 +871,7 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
       }
       append(dst, c2, active, x, y, z, px, py, pz, id, status);
     }
-    if (lane == 0) src.count[cv.c] = 0u;
+    if (tid == 0) src.count[cv.c] = 0u;
   }
 }
 
@@ -1050,6 +1154,21 @@ __global__ __launch_bounds__(64) void k_step(Cells src_arg, int64_t dst_shift, u
   cell_step<kFused, kTrace, kCap>(src, shifted(src, dst_shift),
                                   xcd_runs<8>(blockIdx.x, gridDim.x), t, pa, *gp, status, tr,
                                   lds);
+}
+
+// Two waves per cell (a workgroup of 128): half the pair tests each, so a
+// box of few cells has twice as many, shorter waves to spread over the
+// SIMDs (the tail of a launch whose waves are long and few is idle time).
+template <bool kFused, uint32_t kCap>
+__global__ __launch_bounds__(128) void k_step2(Cells src_arg, int64_t dst_shift, uint32_t t,
+                                               PairArgs pa, const Geometry *__restrict__ gp,
+                                               DevStatus *status) {
+  const GCells src = to_global(src_arg);
+  __shared__ CellLds<kFused, kCap> lds;
+  __shared__ SecondWaveLds<kCap> x2;
+  cell_step<kFused, false, kCap, 2>(src, shifted(src, dst_shift),
+                                    xcd_runs<8>(blockIdx.x, gridDim.x), t, pa, *gp, status,
+                                    TraceArgs{}, lds, &x2);
 }
 
 // ---------------------------------------------------------------------------
@@ -1373,7 +1492,7 @@ void launch_stream_bin(const Cells &src, const Cells &dst, int64_t n_cells, uint
                        const Geometry &g, DevStatus *status, uint32_t *trace_cell,
                        hipStream_t s) {
   if (n_cells <= 0) return;
-  const uint32_t G = lanes == 0 ? 64u : lanes;
+  const uint32_t G = lanes == 0 || lanes == kTwoWavesPerCell ? 64u : lanes;
   const int64_t waves = (n_cells + 64 / G - 1) / (64 / G);
   const dim3 grid(cell_blocks(waves)), block(kBlock);
   const uint32_t nc = (uint32_t)n_cells;
@@ -1423,7 +1542,13 @@ void launch_step_cap(const Cells &src, const Cells &dst, uint32_t n_cells, uint3
                      const TraceArgs &tr, hipStream_t s, const SideStream *side,
                      const StepDevice &dev) {
   const dim3 block(64);
-  if (lanes == 0) {
+  if (lanes == kTwoWavesPerCell && !kTrace) {
+    hipLaunchKernelGGL((k_step2<kFused, kCap>), dim3(n_cells), dim3(128), 0, s, src,
+                       (int64_t)((const char *)dst.st.x - (const char *)src.st.x), t, pa,
+                       dev.g, status);
+    return;
+  }
+  if (lanes == 0 || lanes == kTwoWavesPerCell) {
     hipLaunchKernelGGL((k_step<kFused, kTrace, kCap>), dim3(n_cells), block, 0, s, src,
                        (int64_t)((const char *)dst.st.x - (const char *)src.st.x), t, pa,
                        dev.g, status, tr);

@@ -201,7 +201,8 @@ def cuba_sync(ctx: int) -> None:
     _check(_lib.cuba_sync(ctx), "cuba_sync")
 
 
-CELL_LANES = (0, 8, 16, 32, 64)
+CELL_LANES = (0, 8, 16, 32, 64)      # every context, batched or not
+TWO_WAVES_PER_CELL = 128             # plain contexts only
 
 
 def cuba_set_cell_lanes(ctx: int, lanes: int) -> None:

@@ -140,7 +140,7 @@ def test_lanes_setting_is_validated(lib):  # noqa: F811
     w = sparse_workload()
     s = lib.Sim(w.params(), W.riemann_state(w))
     assert s.cell_lanes in (0,) + LANES
-    for bad in (-1, 1, 4, 12, 128):
+    for bad in (-1, 1, 4, 12, 256):
         with pytest.raises(C.CubaError) as e:
             s.cell_lanes = bad
         assert e.value.code == C.CUBA_EINVAL
@@ -183,3 +183,17 @@ def test_default_lanes_rule(lib):  # noqa: F811
         B.close()
         say(f"[lanes] {label}: plain {got}, batch {got_b}")
         assert (got, got_b) == (want_plain, want_batch), label
+    # fewer cells than SIMDs, dense: two waves per cell on the plain path
+    m = 8
+    params_small = dict(params, cells=(m, m, m))
+    for occ, want in ((40, 128), (20, 0)):
+        state = _grid_state(np.full(m ** 3, occ), m=m)
+        s = lib.Sim(params_small, state)
+        got = s.cell_lanes
+        s.close()
+        B = batch.Batch(1)
+        B.admit(0, params_small, [torch.from_numpy(a).cuda() for a in state])
+        got_b = B.cell_lanes(0)
+        B.close()
+        say(f"[lanes] 512 cells of {occ}: plain {got}, batch {got_b}")
+        assert (got, got_b) == (want, 0)
