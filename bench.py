@@ -108,12 +108,21 @@ def device_copy_gbs(stream, nbytes: int = 1 << 30, reps: int = 5) -> float:
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
+def code_text(text: str) -> str:
+    """Source text without comments and blank lines: what the compiler
+    sees, so that an edit of a comment keeps the measured traffic valid."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines()]
+    return "\n".join(ln for ln in lines if ln.strip())
+
+
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            h.update(code_text(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -17,7 +17,13 @@
 //                  F (fused) the same wave then streams and bins its
 //                  particles for step t+1, so the binning traffic overlaps
 //                  the ALU-bound pair tests.
-//   observe        per-cell sums of E and p_x, then fixed-order slab sums.
+//   k_step_small   64 / G cells per wave, one particle per lane (sparse
+//                  cells); k_step_large / k_step_over step the cells that
+//                  do not fit G lanes.
+//   k_step2        a workgroup of two waves per cell, splitting its pair
+//                  tests (boxes of fewer cells than SIMDs).
+//   observe        per-cell sums of E, p_x, p_x^2/E and counts, then
+//                  fixed-order slab sums.
 //   gather         state export by id.
 // A run of n steps is one stream_bin, n-1 fused steps and one collide-only
 // step, which leaves the state binned and collided (positions of step t+n-1).
@@ -439,7 +445,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_carry(uint32_t *offsets,
 }
 
 // ---------------------------------------------------------------------------
-// Collisions: one wave64 (one workgroup) per cell.
+// Collisions: one wave64 (one workgroup) per cell, or two (k_step2).
 // ---------------------------------------------------------------------------
 struct CellView {
   uint32_t c, n, t;
@@ -592,7 +598,7 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
   return v;
 }
 
-// LDS of one wave's cell: buf holds the cell's ids while the canonical
+// LDS of a cell: buf holds the cell's ids while the canonical
 // order is built; after that its first half holds the filtered pairs and its
 // second half the claimed pairs.
 template <bool kFused, uint32_t kCap>
