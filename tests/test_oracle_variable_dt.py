@@ -78,3 +78,49 @@ def test_policy_dt_gives_the_kinetic_scattering_fraction(orc):
     # most once per step (a ~p_max / 2 relative loss)
     sd = math.sqrt(claims) / claims
     assert abs(frac / want - 1.0) < 4 * sd + p_max / 2, (frac, want)
+
+
+class _FakeSim:
+    """The parts of Sim that timestep.run_to uses, with a density that
+    halves every 0.1 fm/c (an expanding gas)."""
+
+    def __init__(self, params, n0):
+        self.params, self.n0 = params, n0
+        self.time, self._dt, self.calls = 0.0, params["dt"], []
+
+    def observe_moments(self):
+        return {"n": np.array([self.n0 * 0.5 ** (self.time / 0.1), 1.0])}
+
+    @property
+    def dt(self):
+        return self._dt
+
+    @dt.setter
+    def dt(self, dt):
+        self._dt = dt
+
+    def step(self, k):
+        self.calls.append((k, self._dt))
+        self.time += k * self._dt
+
+
+def test_run_to_schedule_follows_the_density():
+    params = dict(box=(10.0, 1.0, 1.0), cells=(100, 5, 5), sigma=0.4, r_test=100.0, dt=0.02)
+    sim = _FakeSim(params, n0=50.0)
+    sched = TS.run_to(sim, 0.5, p_max=0.05, every=4)
+    assert sched == sim.calls
+    assert abs(sim.time - 0.5) < 1e-12
+    edge, k_max = TS.dt_limits(params)
+    assert all(0 < dt <= 0.5 * edge for _, dt in sched)
+    # dt grows as the gas thins (until the cell-edge limit) and each dt is
+    # the policy's value at the start of its run, except the shortened last
+    t = 0.0
+    for i, (k, dt) in enumerate(sched):
+        n = 50.0 * 0.5 ** (t / 0.1)
+        want = TS.collision_dt(n, params, 0.05)
+        if i < len(sched) - 1:
+            assert dt == pytest.approx(want, rel=1e-12)
+        else:
+            assert dt <= want * (1 + 1e-12)
+        t += k * dt
+    assert sched[-2][1] > sched[0][1]
