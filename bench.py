@@ -60,11 +60,15 @@ def parse():
                     help="serve: least remaining work first within a particle budget per "
                          "run (srpt) or every live event in every run (all); the other "
                          "policy runs on the same trace for comparison")
-    ap.add_argument("--serve-run-steps", type=int, default=50,
-                    help="serve: steps per run (a divisor of the 50-step observation "
-                         "interval keeps every observation)")
+    ap.add_argument("--serve-run-steps", type=int, default=200,
+                    help="serve: steps per run (with --serve-observe 50, a divisor of 50 "
+                         "keeps every observation)")
     ap.add_argument("--serve-run-particles", type=int, default=2_000_000,
                     help="serve, srpt: particles per run beside the oldest request")
+    ap.add_argument("--serve-observe", choices=["final", "50"], default="final",
+                    help="serve: observe each request's profile at its end only (its "
+                         "result) or also every 50 steps, in the server and in the "
+                         "one-at-a-time replay")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batch: skip the one-at-a-time comparison")
     ap.add_argument("--lanes", type=int, default=None, choices=[0, 8, 16, 32, 64, 128],

@@ -2,8 +2,8 @@
 
 Each request is one Riemann event (parameters from the ensemble
 distribution, an initial state drawn from its seed) to be advanced a fixed
-number of steps, with T00/T0x observed every 50 steps; the result is the
-final profile.  The server admits arrived requests in FIFO order as a batch
+number of steps, with T00/T0x observed every 50 steps (or, with final_only,
+at the end only); the result is the final profile.  The server admits arrived requests in FIFO order as a batch
 slot and enough HBM (the event's workspace footprint) free up, advances all
 live events together in runs of `run_steps` steps (one launch per step for
 all of them), and retires events that are done.  Requests that arrive while
@@ -88,12 +88,14 @@ class Server:
     def __init__(self, max_slots: int = 256, hbm_budget: int | None = None,
                  run_steps: int = 25, device: str = "cuda", use_graphs: bool = False,
                  tuning: dict | None = None, keep_states: bool = False,
-                 policy: str = "all", run_particles: int = 2_000_000):
+                 policy: str = "all", run_particles: int = 2_000_000,
+                 final_only: bool = False):
         if policy not in ("all", "srpt"):
             raise ValueError("policy must be 'all' or 'srpt'")
         self.device = device
         self.policy = policy
         self.run_particles = int(run_particles)
+        self.final_only = final_only
         self.run_steps = run_steps
         self.keep_states = keep_states
         if hbm_budget is None:
@@ -155,7 +157,8 @@ class Server:
                     continue
                 ev["done"] += k
                 w = ev["req"].work
-                if ev["done"] % w.observe_every == 0 or ev["done"] >= w.steps:
+                if ((not self.final_only and ev["done"] % w.observe_every == 0)
+                        or ev["done"] >= w.steps):
                     self.B.observe_async(slot)
                 if ev["done"] >= w.steps:
                     finished.append(slot)
@@ -199,7 +202,8 @@ class Server:
         self.B.close()
 
 
-def run_alone(req: Request, device: str = "cuda", keep_state: bool = False):
+def run_alone(req: Request, device: str = "cuda", keep_state: bool = False,
+              final_only: bool = False):
     """The same request through the plain path: (service seconds, T00, T0x, state)."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -209,8 +213,9 @@ def run_alone(req: Request, device: str = "cuda", keep_state: bool = False):
     del state
     w = req.work
     done = 0
+    every = w.steps if final_only else w.observe_every
     while done < w.steps:
-        k = min(w.observe_every, w.steps - done)
+        k = min(every, w.steps - done)
         sim.step(k)
         done += k
         sim.observe_async()
@@ -247,17 +252,18 @@ def bench(a):
     from . import autotune as AT
     n_req = int(a.requests)
     tuning = AT.load()
-    run_steps = int(getattr(a, "serve_run_steps", 50))
+    run_steps = int(getattr(a, "serve_run_steps", 200))
     # untimed warm-up of both paths (first launches load code objects and
     # grow the allocator's pools)
     warm = request_stream(16, 0.0, seed=56)
-    srv = Server(tuning=tuning, use_graphs=False, run_steps=run_steps)
+    final_only = getattr(a, "serve_observe", "final") == "final"
+    srv = Server(tuning=tuning, use_graphs=False, run_steps=run_steps, final_only=final_only)
     srv.run(warm, realtime=False)
     srv.close()
-    run_alone(warm[0])
+    run_alone(warm[0], final_only=final_only)
     # capacity: a closed batch of 64 requests all present at t = 0
     probe = request_stream(64, 0.0, seed=55)
-    srv = Server(tuning=tuning, use_graphs=False, run_steps=run_steps)
+    srv = Server(tuning=tuning, use_graphs=False, run_steps=run_steps, final_only=final_only)
     t0 = time.perf_counter()
     srv.run(probe, realtime=False)
     cap_dt = time.perf_counter() - t0
@@ -274,6 +280,7 @@ def bench(a):
     policy = getattr(a, "serve_policy", "all")
     out = {"metric": "served request stream: p50/p99 time-to-result and particle-steps/s",
            "unit": "particle-steps/s", "policy": policy, "run_steps": run_steps,
+           "observed": "final profile" if final_only else "every 50 steps",
            "run_particles": int(getattr(a, "serve_run_particles", 2_000_000)),
            "requests": n_req,
            "arrival_rate_per_s": rate, "capacity_particle_steps_per_s": throughput}
@@ -281,7 +288,8 @@ def bench(a):
     for pol in (policy, "all" if policy == "srpt" else "srpt"):
         print(f"# serve policy {pol}", file=sys.stderr, flush=True)
         srv = Server(tuning=tuning, use_graphs=False, policy=pol, run_steps=run_steps,
-                     run_particles=int(getattr(a, "serve_run_particles", 2_000_000)))
+                     run_particles=int(getattr(a, "serve_run_particles", 2_000_000)),
+                     final_only=final_only)
         t0 = time.perf_counter()
         res = srv.run(reqs, realtime=True)
         makespan = time.perf_counter() - t0
@@ -298,7 +306,7 @@ def bench(a):
         print("# sequential FIFO replay", file=sys.stderr, flush=True)
         service = {}
         for r in reqs:
-            service[r.rid] = run_alone(r)[0]
+            service[r.rid] = run_alone(r, final_only=final_only)[0]
         fin = fifo_replay(reqs, service)
         lat = [fin[r.rid] - r.arrival for r in reqs]
         sp50, sp99 = percentiles(lat)

@@ -20,15 +20,17 @@ def serve():
     return serve
 
 
-@pytest.mark.parametrize("policy", ("all", "srpt"))
-def test_results_same_alone_and_in_the_mix(serve, policy):
+@pytest.mark.parametrize("policy,final_only", (("all", False), ("srpt", False),
+                                               ("srpt", True)))
+def test_results_same_alone_and_in_the_mix(serve, policy, final_only):
     reqs = serve.request_stream(10, 0.0, seed=8, nmin=1e4, nmax=8e4, steps=100)
     budget = 3 * max(serve.footprint(r) for r in reqs)
     # srpt: a run holds about two of the requests, so events wait, are held
     # and resume between runs
     run_particles = 2 * max(r.work.n for r in reqs)
-    srv = serve.Server(max_slots=4, hbm_budget=budget, run_steps=25, keep_states=True,
-                       policy=policy, run_particles=run_particles)
+    srv = serve.Server(max_slots=4, hbm_budget=budget, run_steps=50 if final_only else 25,
+                       keep_states=True, policy=policy, run_particles=run_particles,
+                       final_only=final_only)
     res = srv.run(reqs, realtime=False)
     assert srv.peak_live <= 4 and srv.peak_bytes <= budget
     assert srv.peak_live >= 2          # the requests overlapped on the device
@@ -39,7 +41,8 @@ def test_results_same_alone_and_in_the_mix(serve, policy):
     by_id = {r.rid: r for r in reqs}
     for r in res:
         print(f"[serve] request {r.rid} n={r.n}", flush=True)
-        _, T00, T0x, state = serve.run_alone(by_id[r.rid], keep_state=True)
+        _, T00, T0x, state = serve.run_alone(by_id[r.rid], keep_state=True,
+                                             final_only=final_only)
         for d in range(6):
             assert np.array_equal(r.state[d], state[d]), (r.rid, d)
         # profile sums run in storage order: equal to rounding
