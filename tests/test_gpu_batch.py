@@ -205,3 +205,59 @@ def test_held_events_keep_their_state(mods):
     for i, n in enumerate((11, 11, 8)):
         assert_same(B.get_state(i), alone(sim, evs[i], states[i], n), evs[i].name)
     B.close()
+
+
+def test_full_ensemble_sampled_parity(mods, orc):
+    """The 256-event ensemble of the batched benchmark, admitted and tuned as
+    it is there (graph-captured runs): after 4 steps, one more batched step
+    of each sampled event (the smallest, the median, the largest below 2 M
+    particles, and one stepped with several cells per wave if the tuning
+    gives one) equals one oracle step from its state: positions and
+    unscattered momenta bit-exact, scattered momenta within 1e-12 of the
+    pair energy."""
+    import torch
+    from paper_1208_0961_amd import autotune as AT
+    from test_gpu_parity import _orc_params, _rows
+    batch, sim = mods
+    events = W.ensemble_events(256)
+    B = batch.Batch(len(events))
+    for i, w in enumerate(events):
+        st = W.riemann_state_torch(w, 100000 + i)
+        B.admit(i, {**w.params(), "cell_capacity": W.capacity_for(w)}, st)
+        del st
+    table = AT.load() or AT.tune(events)
+    AT.apply(B, table, dict(enumerate(events)), use_graphs=True)
+    order = sorted(range(len(events)), key=lambda i: events[i].n)
+    small = [i for i in order if events[i].n < 2_000_000]
+    sample = {order[0], order[len(order) // 2], small[-1]}
+    lanes = [i for i in small if B.cell_lanes(i) > 0]
+    if lanes:
+        sample.add(lanes[len(lanes) // 2])
+    B.step(4)
+    prev = {i: B.get_state(i) for i in sample}
+    B.step(1)
+    got = {i: B.get_state(i) for i in sample}
+    B.close()
+    torch.cuda.synchronize()
+    scattered_total = 0
+    for i in sorted(sample):
+        w = events[i]
+        say(f"[ensemble] event {i}: n={w.n}, lanes={lanes and i in lanes}")
+        st = orc.State(*prev[i])
+        tr = orc.step(_orc_params(orc, w.params()), st, 4, trace=True)
+        for d in range(3):
+            assert np.array_equal(got[i][d], st[d]), (i, d)
+        scattered = np.zeros(w.n, bool)
+        pair_e = np.zeros(w.n)
+        offs = tr["offsets"].astype(np.int64)
+        E = np.sqrt(st[3] ** 2 + st[4] ** 2 + st[5] ** 2)
+        for c, a, b in _rows(tr["claim"]):
+            ia, ib = tr["perm"][offs[c] + a], tr["perm"][offs[c] + b]
+            scattered[[ia, ib]] = True
+            pair_e[[ia, ib]] = E[ia] + E[ib]
+        for d in range(3, 6):
+            assert np.array_equal(got[i][d][~scattered], st[d][~scattered]), (i, d)
+            assert np.all(np.abs(got[i][d][scattered] - st[d][scattered])
+                          <= 1e-12 * pair_e[scattered]), (i, d)
+        scattered_total += int(scattered.sum())
+    assert scattered_total > 1000
