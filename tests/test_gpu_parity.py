@@ -389,3 +389,54 @@ def test_paper_parameter_set_reduced(orc, lib):
     sim.close()
     assert np.array_equal(m0["n"].sum() * 1.0, m1["n"].sum() * 1.0)
     assert abs(m1["T00"].sum() / m0["T00"].sum() - 1.0) < 1e-12
+
+
+def _full_size_step_check(orc, got_prev, got, params, t, label, threads=16):
+    """One oracle step (threads over cells) from the GPU state got_prev at
+    step index t must give the GPU state got: positions bit-exact for every
+    particle; momenta bit-exact except for particles scattered in the step
+    (at most 2 per claim), which agree within 1e-10 of their energy (a
+    wrong decision would move them by O(E))."""
+    st = orc.State(*got_prev)
+    orc.run(_orc_params(orc, params), st, t, 1, threads)
+    for d in range(3):
+        assert np.array_equal(got[d], st[d]), f"{label}: positions differ on axis {d}"
+    diff = np.zeros(len(got[0]), bool)
+    for d in range(3, 6):
+        diff |= got[d] != st[d]
+    E = np.sqrt(st[3] ** 2 + st[4] ** 2 + st[5] ** 2)
+    for d in range(3, 6):
+        assert np.all(np.abs(got[d][diff] - st[d][diff]) <= 1e-10 * E[diff]), label
+    return int(diff.sum())
+
+
+def test_paper_parameter_set_full_size(orc, lib):
+    """The paper's own set-up at full size (128^3 cells, 24.9 M particles) in
+    the benchmark's launch configuration (8 lanes per cell, oversize cells a
+    wave each): one step (stream-bin and collide-only kernels) and a second
+    step from it (fused kernel) against one threaded oracle step each, and
+    the scattered particles against twice the claims counted on the device."""
+    import torch
+    from paper_1208_0961_amd import cuba as C
+    w = W.PAPER_32
+    params = w.params()   # as the benchmark: capacity from the initial state
+    st0 = [a.cpu().numpy() for a in W.riemann_state_torch(w, seed=77, device="cuda")]
+    say(f"[paper32] {w.n} particles, 1 step")
+    a = lib.Sim(params, st0)
+    assert a.cell_lanes == 8
+    a.step(1)
+    s1 = a.get_state()
+    claims1 = C.cuba_counters(a.ctx)["claims"]
+    a.close()
+    torch.cuda.empty_cache()
+    changed1 = _full_size_step_check(orc, st0, s1, params, 0, "paper32 step 0")
+    say("[paper32] 2 steps (fused)")
+    b = lib.Sim(params, st0)
+    b.step(2)
+    s2 = b.get_state()
+    claims2 = C.cuba_counters(b.ctx)["claims"] - claims1
+    b.close()
+    torch.cuda.empty_cache()
+    changed2 = _full_size_step_check(orc, s1, s2, params, 1, "paper32 step 1")
+    assert claims1 > 1_000_000 and claims2 > 1_000_000
+    assert changed1 <= 2 * claims1 and changed2 <= 2 * claims2
