@@ -440,3 +440,24 @@ def test_paper_parameter_set_full_size(orc, lib):
     changed2 = _full_size_step_check(orc, s1, s2, params, 1, "paper32 step 1")
     assert claims1 > 1_000_000 and claims2 > 1_000_000
     assert changed1 <= 2 * claims1 and changed2 <= 2 * claims2
+
+
+def test_tube3d_benchmark_configuration(orc, lib):
+    """The default benchmark's workload and initial state (3-D tube, 1.02 M
+    particles, one wave per cell): the first step of a run (stream-bin and
+    collide-only kernels) and a fused step after it, each against one
+    threaded oracle step."""
+    w = W.TUBE_3D
+    st0 = W.riemann_state(w)
+    a = lib.Sim(w.params(), st0)
+    assert a.cell_lanes == 0
+    a.step(1)
+    s1 = a.get_state()
+    a.close()
+    changed1 = _full_size_step_check(orc, st0, s1, w.params(), 0, "tube3d step 0")
+    b = lib.Sim(w.params(), st0)
+    b.step(2)
+    s2 = b.get_state()
+    b.close()
+    changed2 = _full_size_step_check(orc, s1, s2, w.params(), 1, "tube3d step 1")
+    assert changed1 > 1000 and changed2 > 1000
