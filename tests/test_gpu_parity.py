@@ -458,6 +458,11 @@ def test_tube3d_benchmark_configuration(orc, lib):
     b = lib.Sim(w.params(), st0)
     b.step(2)
     s2 = b.get_state()
+    T00, T0x = b.observe()
     b.close()
     changed2 = _full_size_step_check(orc, s1, s2, w.params(), 1, "tube3d step 1")
     assert changed1 > 1000 and changed2 > 1000
+    # the profiles the benchmark observes, at this size
+    p = _orc_params(orc, w.params())
+    oT00, oT0x = orc.observe(p, orc.State(*s2))
+    _assert_profiles_close(p, s2, T00, T0x, oT00, oT0x)
