@@ -341,8 +341,8 @@ def main():
     if a.pmc_csv:
         return write_traffic(a)
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the method's "
-              "multi-GPU slab decomposition is not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); a multi-GPU "
+              "slab decomposition of the box is not implemented.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
