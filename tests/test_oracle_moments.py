@@ -11,7 +11,8 @@ rest-frame (Landau) transform, against closed forms and invariants:
 * particles with p parallel to x have px^2 / E = E, so Txx = T00;
 * the density times the slab volume counts the slab's particles;
 * an isotropic thermal (Boltzmann, massless) gas has Txx = T00 / 3 and
-  T00 = 3 n T, its rest frame is the lab, and e equals T00.
+  T00 = 3 n T, its rest frame is the lab, and e equals T00;
+* the same gas moving at v0 has its rest frame at v0, with e = 3 n_rest T.
 """
 import numpy as np
 
@@ -108,3 +109,31 @@ def test_thermal_gas_moments(orc):
     eL, vL = orc.landau(T00, T0x, Txx)
     assert np.allclose(eL / T00, 1.0, atol=1e-3)
     assert np.all(np.abs(vL) < 0.01)
+
+
+def test_boosted_thermal_gas_rest_frame(orc):
+    """A thermal (Boltzmann, massless) gas moving with velocity v0 along x:
+    momenta of a gas at rest boosted (E' = g (E + v0 p_x), p_x' = g (p_x +
+    v0 E)), and kept with probability E' / (g (1 + v0) E), since a sample at
+    one lab time weighs each momentum by E'/E (d^3p / E is invariant).  The
+    slab moments' rest frame recovers v0 and the rest-frame energy density
+    e = 3 n_rest T with n_rest = n_lab / g (the density current is n_rest
+    u), to the sampling noise of ~30 000 particles per slab."""
+    T, v0 = 0.35, 0.4
+    g = 1.0 / np.sqrt(1.0 - v0 * v0)
+    n = 400000
+    box = (10.0, 1.0, 1.0)
+    x, y, z, px, py, pz = W.thermal_box(box, n, T, seed=29)
+    E = np.sqrt(px * px + py * py + pz * pz)
+    keep = np.random.default_rng(31).random(n) < (1.0 + v0 * px / E) / (1.0 + v0)
+    x, y, z, px, py, pz, E = (a[keep] for a in (x, y, z, px, py, pz, E))
+    pxb = g * (px + v0 * E)
+    st = orc.State(x, y, z, pxb, py.copy(), pz.copy())
+    p = _params(orc, box, (10, 1, 1), r_test=1.0)
+    T00, T0x, Txx, nd = orc.observe_moments(p, st)
+    e, v = orc.landau(T00, T0x, Txx)
+    assert np.allclose(v, v0, atol=0.01)
+    assert abs(v.mean() - v0) < 0.003
+    e_rest = 3.0 * (nd / g) * T
+    assert np.allclose(e / e_rest, 1.0, rtol=0.03)
+    assert abs((e / e_rest).mean() - 1.0) < 0.01
