@@ -61,8 +61,8 @@ def parse():
                          "run (srpt) or every live event in every run (all); the other "
                          "policy runs on the same trace for comparison")
     ap.add_argument("--serve-run-steps", type=int, default=200,
-                    help="serve: steps per run (with --serve-observe 50, a divisor of 50 "
-                         "keeps every observation)")
+                    help="serve: at most this many steps per run; a run ends early where "
+                         "one of its requests ends or is due for an observation")
     ap.add_argument("--serve-run-particles", type=int, default=2_000_000,
                     help="serve, srpt: particles per run beside the oldest request")
     ap.add_argument("--serve-observe", choices=["final", "50"], default="final",

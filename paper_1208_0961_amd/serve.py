@@ -5,8 +5,9 @@ distribution, an initial state drawn from its seed) to be advanced a fixed
 number of steps, with T00/T0x observed every 50 steps (or, with final_only,
 at the end only); the result is the final profile.  The server admits arrived requests in FIFO order as a batch
 slot and enough HBM (the event's workspace footprint) free up, advances all
-live events together in runs of `run_steps` steps (one launch per step for
-all of them), and retires events that are done.  Requests that arrive while
+live events together in runs of at most `run_steps` steps (one launch per
+step for all of them), each ending where an event in it ends or is due for
+an observation, and retires events that are done.  Requests that arrive while
 others run join at the next run boundary, so their work overlaps on the
 device.
 """
@@ -92,6 +93,8 @@ class Server:
                  final_only: bool = False):
         if policy not in ("all", "srpt"):
             raise ValueError("policy must be 'all' or 'srpt'")
+        if run_steps < 1:
+            raise ValueError("run_steps must be at least 1")
         self.device = device
         self.policy = policy
         self.run_particles = int(run_particles)
@@ -148,8 +151,9 @@ class Server:
                 if queue and realtime:
                     time.sleep(max(0.0, min(queue[0].arrival - now(), 0.01)))
                 continue
-            k = self.run_steps
             active = self._choose(live)
+            k = min(self.steps_to_stop(live[slot]["req"].work, live[slot]["done"])
+                    for slot in active)
             self.B.step(k)
             finished = []
             for slot, ev in live.items():
@@ -176,6 +180,15 @@ class Server:
                 used -= ev["need"]
                 results.append(res)
         return results
+
+    def steps_to_stop(self, work: W.Workload, done: int) -> int:
+        """Steps an event that has done `done` of its steps may take in the
+        next run: at most run_steps, and never past its end or (unless only
+        its final profile is wanted) past its next observation."""
+        k = min(self.run_steps, work.steps - done)
+        if not self.final_only:
+            k = min(k, work.observe_every - done % work.observe_every)
+        return k
 
     def _choose(self, live: dict) -> set:
         """The slots that take part in the next run (holding the others)."""

@@ -20,15 +20,18 @@ def serve():
     return serve
 
 
-@pytest.mark.parametrize("policy,final_only", (("all", False), ("srpt", False),
-                                               ("srpt", True)))
-def test_results_same_alone_and_in_the_mix(serve, policy, final_only):
+# run lengths: 25 and 50 divide the 100 steps and the 50-step observations;
+# 40 does not, so runs stop early at every observation (40, 10, 40, 10)
+@pytest.mark.parametrize("policy,final_only,run_steps",
+                         (("all", False, 25), ("srpt", False, 25), ("srpt", True, 50),
+                          ("all", False, 40)))
+def test_results_same_alone_and_in_the_mix(serve, policy, final_only, run_steps):
     reqs = serve.request_stream(10, 0.0, seed=8, nmin=1e4, nmax=8e4, steps=100)
     budget = 3 * max(serve.footprint(r) for r in reqs)
     # srpt: a run holds about two of the requests, so events wait, are held
     # and resume between runs
     run_particles = 2 * max(r.work.n for r in reqs)
-    srv = serve.Server(max_slots=4, hbm_budget=budget, run_steps=50 if final_only else 25,
+    srv = serve.Server(max_slots=4, hbm_budget=budget, run_steps=run_steps,
                        keep_states=True, policy=policy, run_particles=run_particles,
                        final_only=final_only)
     res = srv.run(reqs, realtime=False)

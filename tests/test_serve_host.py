@@ -104,3 +104,35 @@ def test_srpt_policy_choice(serve):
 def test_server_rejects_unknown_policy(serve):
     with pytest.raises(ValueError):
         serve.Server(policy="lifo", hbm_budget=1 << 20)
+
+
+def test_runs_stop_at_ends_and_observations(serve):
+    """A run never takes an event past its last step, nor (when every
+    profile is wanted) past its next observation."""
+    from paper_1208_0961_amd import workload as W
+    w = W.Workload("r", (10.0, 1.0, 1.0), (100, 5, 5), 100.0, 0.5, 0.02, 0.4, 0.32,
+                   steps=130, observe_every=50)
+    srv = serve.Server.__new__(serve.Server)
+    srv.run_steps, srv.final_only = 40, False
+    seq, done = [], 0
+    while done < w.steps:
+        k = srv.steps_to_stop(w, done)
+        seq.append(k)
+        done += k
+    assert seq == [40, 10, 40, 10, 30] and done == 130
+    srv.final_only = True
+    seq, done = [], 0
+    while done < w.steps:
+        k = srv.steps_to_stop(w, done)
+        seq.append(k)
+        done += k
+    assert seq == [40, 40, 40, 10]
+    srv.run_steps = 200
+    assert srv.steps_to_stop(w, 0) == 130 and srv.steps_to_stop(w, 125) == 5
+    srv.final_only = False
+    assert srv.steps_to_stop(w, 0) == 50 and srv.steps_to_stop(w, 120) == 10
+
+
+def test_server_rejects_empty_runs(serve):
+    with pytest.raises(ValueError):
+        serve.Server(run_steps=0, hbm_budget=1 << 20)
