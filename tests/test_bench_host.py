@@ -1,0 +1,81 @@
+"""Host-side logic of bench.py (no device work): the one-GPU guard, the
+source hash that keys measured traffic, and the scaling of the HBM
+counters into bytes per launch."""
+import argparse
+import csv
+import importlib.util
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test",
+                                                  os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""          # no JSON line
+
+
+def test_code_text_ignores_comments_and_blank_lines(bench):
+    a = "int f(int x) {\n  return x + 1;  // one more\n}\n"
+    b = "/* header\n   comment */\nint f(int x) {\n\n  // a note\n  return x + 1;\n}\n"
+    assert bench.code_text(a) == bench.code_text(b)
+    # a change of code is seen
+    assert bench.code_text(a) != bench.code_text(a.replace("+ 1", "+ 2"))
+
+
+def _counter_csv(path, counter, rows):
+    cols = ["Dispatch_Id", "Grid_Size", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=cols)
+        w.writeheader()
+        for i, (name, grid, value) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i, "Grid_Size": grid, "Kernel_Name": name,
+                        "Counter_Name": counter, "Counter_Value": value})
+
+
+def test_traffic_scaled_by_the_copy_reading(bench, tmp_path, monkeypatch):
+    """FETCH_SIZE reading half of a 1 GiB copy's bytes doubles the kernel's
+    reading; WRITE_SIZE reading all of them keeps it; other kernels and
+    small copies are ignored; the result is keyed by the source hash."""
+    step = "void cuba::k_step<true, false, 512u>(cuba::Cells, long)"
+    other = "void cuba::k_step<false, false, 512u>(cuba::Cells, long)"
+    copy = "__amd_rocclr_copyBuffer"
+    gib_kib = float(1 << 20)
+    fetch = tmp_path / "fetch.csv"
+    write = tmp_path / "write.csv"
+    _counter_csv(fetch, "FETCH_SIZE", [(step, 10000, 1000.0), (step, 10000, 3000.0),
+                                       (other, 10000, 9e9), (copy, 65536, gib_kib / 2),
+                                       (copy, 256, 1.0)])
+    _counter_csv(write, "WRITE_SIZE", [(step, 10000, 5000.0), (copy, 65536, gib_kib)])
+    out = tmp_path / "traffic.json"
+    monkeypatch.setattr(bench, "traffic_path", lambda workload: str(out))
+    a = argparse.Namespace(pmc_csv=[str(fetch), str(write)], workload="unit")
+    bench.write_traffic(a)
+    t = json.load(open(out))
+    assert t["fetch_scale"] == pytest.approx(2.0) and t["write_scale"] == pytest.approx(1.0)
+    assert t["fetch_bytes_per_launch"] == pytest.approx(2000.0 * 1024 * 2.0)
+    assert t["write_bytes_per_launch"] == pytest.approx(5000.0 * 1024)
+    assert t["bytes_per_launch"] == pytest.approx(t["fetch_bytes_per_launch"]
+                                                  + t["write_bytes_per_launch"])
+    assert t["kernel_source_hash"] == bench.kernel_source_hash()
+    # read back only while the sources still hash to the stored key
+    assert bench.measured_traffic("unit") == pytest.approx(t["bytes_per_launch"])
+    t["kernel_source_hash"] = "0" * 16
+    json.dump(t, open(out, "w"))
+    assert bench.measured_traffic("unit") is None
