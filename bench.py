@@ -8,10 +8,15 @@ binned Riemann tube: 10 x 2 x 2 fm, 100 x 10 x 10 cells, r_test = 2500,
 1 020 851 test particles, sigma = 0.4 fm^2, dt = 0.02 fm/c, FP64.  Inputs
 are synthetic (seeded thermal gases) and resident in HBM before timing.
 
-Prints one JSON line: particle-steps/s (whole job) plus pair tests/s, the
-roofline of the dominant kernel (the pair-test kernel, bound by integer
-ALU work: Philox4x32-10), per-stage times and HBM rates, and the CPU oracle
-timed on a bounded sample of the same workload.
+Prints one JSON line: particle-steps/s (whole job) plus pair tests/s; the
+roofline of the dominant kernel (the fused pair-test kernel) as FP64 FLOP/s
+of the pair stage against the FP64 vector peak, with its integer issue rate
+(Philox4x32-10 bounds it) and VALU busy beside; the streaming/binning rate
+against the HBM peak; per-stage times; the CPU oracle timed on a bounded
+sample of the same workload on all usable host cores; and, unless
+--no-extras, the two ensemble legs of the metric: the 256-event batched
+ensemble against the same events one at a time, and a short served request
+stream against a one-at-a-time FIFO (p50/p99 time-to-result).
 """
 from __future__ import annotations
 
@@ -35,11 +40,18 @@ INT32_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # words are shared by the cell's pairs: 16 products (32x32 -> 64, hi or lo),
 # 15 three-input XORs, and the compare.
 PHILOX_OPS_PER_PAIR = 16 + 15 + 1
-FP64_FLOPS_PER_PAIR = 12            # Eq. (3): dot, E1 E2, s, s/(2 E1 E2), x K
-# Algorithmic HBM bytes per particle of the streaming + binning work (read
+# Algorithmic FP64 work of one pair test, Eq. (3): the dot product (5),
+# E1 E2, s = 2 (E1 E2 - dot) (2), s / (2 E1 E2) (2), x K, and the compare.
+FP64_FLOPS_PER_PAIR = 12
+# HBM bytes per particle that the streaming + binning kernels move (read
 # and write x y z px py pz id), done by the fused step kernel for all but
 # the first step of a run and by the stream-bin kernel for that one.
 BYTES_BIN = 52 + 52
+# Algorithmic HBM bytes per particle-step of streaming + binning as a
+# three-pass counting sort: stream + count (read r, p: 48 B; write r, cell,
+# rank: 32 B) and scatter (read cell, rank, state, id: 60 B; write state and
+# id: 52 B).
+BYTES_BIN_ALGO = 80 + 112
 
 
 def parse():
@@ -77,7 +89,16 @@ def parse():
                          "initial occupancy)")
     ap.add_argument("--cpu-steps", type=int, default=None,
                     help="oracle steps for the CPU baseline (0: skip)")
-    ap.add_argument("--cpu-threads", type=int, default=None)
+    ap.add_argument("--cpu-threads", type=int, default=None,
+                    help="oracle threads (default: every usable host core)")
+    ap.add_argument("--cpu-seconds", type=float, default=25.0,
+                    help="wall-clock budget of the CPU baseline's threaded run")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload: skip the ensemble and serving legs")
+    ap.add_argument("--extra-steps", type=int, default=50,
+                    help="ensemble leg: timed steps of the batched ensemble")
+    ap.add_argument("--extra-requests", type=int, default=200,
+                    help="serving leg: requests in the served stream")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the run, copy a 1 GiB device buffer 3 times (a plain "
                          "copy kernel of known size for scaling HBM counters)")
@@ -85,6 +106,10 @@ def parse():
                     help="rocprofv3 counter_collection.csv files of a --calibrate-copy run "
                          "(FETCH_SIZE, WRITE_SIZE): write the measured HBM traffic of "
                          "the dominant kernel to profiles/ and exit")
+    ap.add_argument("--pmc-sq", nargs=2, metavar=("SQ_CSV", "KERNEL_STATS_CSV"),
+                    help="with --pmc-csv: a counter pass with SQ_ACTIVE_INST_VALU and the "
+                         "kernel_stats.csv of a --kernel-trace --stats run of the same "
+                         "command; adds the dominant kernel's VALU busy")
     return ap.parse_args()
 
 
@@ -160,38 +185,55 @@ def write_traffic(a):
            "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
            "bytes_per_launch": fetch + write,
            "fetch_scale": fscale, "write_scale": wscale}
+    if a.pmc_sq:
+        out.update(valu_busy(*a.pmc_sq))
     with open(traffic_path(a.workload), "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out))
 
 
-def measured_traffic(workload: str):
-    """Measured bytes per launch, if taken on the current kernel source."""
+def usable_cores() -> dict:
+    """Host cores this process may run on: the CPU affinity set, capped by
+    the cgroup CPU quota where one is set (a container's share of a larger
+    host); os.cpu_count() beside it for the record."""
+    affinity = len(os.sched_getaffinity(0))
+    quota = None
     try:
-        with open(traffic_path(workload)) as f:
-            t = json.load(f)
-    except OSError:
-        return None
-    if t.get("kernel_source_hash") != kernel_source_hash():
-        return None
-    return t.get("bytes_per_launch")
+        with open("/sys/fs/cgroup/cpu.max") as f:
+            q, period = f.read().split()[:2]
+        if q != "max":
+            quota = float(q) / float(period)
+    except (OSError, ValueError):
+        pass
+    usable = affinity if quota is None else max(1, min(affinity, int(quota + 0.5)))
+    return {"usable": usable, "affinity": affinity, "cpu_quota": quota,
+            "cpu_count": os.cpu_count()}
 
 
-def cpu_baseline(w, state, steps, threads):
-    """The oracle on `steps` steps with `threads` threads over cells, then,
-    for boxes of at most 4 M particles, one or two steps on a single
-    thread."""
+def cpu_baseline(w, state, max_steps, threads, budget_s):
+    """The oracle as it stands, on the benchmark's initial state: up to
+    max_steps steps with `threads` threads over cells, stopping at the
+    first 10-step boundary past budget_s seconds; then, for boxes of at most
+    4 M particles, one or two steps on a single thread."""
     from oracle import oracle as O
     st = O.State(*state)
     p = O.make_params(**w.params())
+    done = 0
     t0 = time.perf_counter()
-    O.run(p, st, 0, steps, threads)
+    while done < max_steps:
+        k = min(10, max_steps - done)
+        O.run(p, st, done, k, threads)
+        done += k
+        if time.perf_counter() - t0 > budget_s:
+            break
     dt = time.perf_counter() - t0
-    out = {"value": w.n * steps / dt, "unit": "particle-steps/s", "cores": threads,
-           "kind": "oracle",
-           "sample": f"{w.name}: {steps} steps of all {w.n} particles from the "
-                     f"benchmark's initial state, {threads} threads over cells, "
-                     f"{dt:.1f} s wall"}
+    cores = usable_cores()
+    out = {"value": w.n * done / dt, "unit": "particle-steps/s", "cores": threads,
+           "kind": "oracle", "host": cores,
+           "sample": f"{w.name}: steps 0..{done - 1} of all {w.n} particles from the "
+                     f"benchmark's initial state, {threads} threads over cells "
+                     f"({cores['usable']} usable host cores, os.cpu_count() "
+                     f"{cores['cpu_count']}), {dt:.1f} s wall"}
     if w.n <= 4_000_000:
         steps1 = 2 if w.n < 2_000_000 else 1
         st1 = O.State(*state)
@@ -201,6 +243,121 @@ def cpu_baseline(w, state, steps, threads):
         out["single_thread_value"] = w.n * steps1 / dt1
         out["sample"] += f"; single thread: {steps1} step(s), {dt1:.1f} s"
     return out
+
+
+SIMDS = 256 * 4
+CLOCK_HZ = 2.4e9
+
+
+def valu_busy(sq_csv: str, stats_csv: str) -> dict:
+    """VALU busy of the dominant kernel: 4 SQ_ACTIVE_INST_VALU (quad-cycles,
+    summed over the chip) / (SIMDs x cycles of its average trace duration)."""
+    import csv
+    rows = [r for r in csv.DictReader(open(sq_csv))
+            if r["Counter_Name"] == "SQ_ACTIVE_INST_VALU"
+            and DOMINANT_KERNEL.replace(" ", "") in r["Kernel_Name"].replace(" ", "")]
+    stats = [r for r in csv.DictReader(open(stats_csv))
+             if DOMINANT_KERNEL.replace(" ", "") in r["Name"].replace(" ", "")]
+    if not rows or not stats:
+        raise SystemExit(f"{sq_csv} / {stats_csv}: no {DOMINANT_KERNEL} entries")
+    active = sum(float(r["Counter_Value"]) for r in rows) / len(rows)
+    ns = float(stats[0]["AverageNs"])
+    return {"valu_busy": 4.0 * active / (SIMDS * ns * 1e-9 * CLOCK_HZ),
+            "sq_active_inst_valu_per_launch": active, "trace_avg_ns": ns}
+
+
+def measured_profile(workload: str):
+    """Measured traffic and VALU busy of the dominant kernel, if taken on the
+    current kernel source (None otherwise)."""
+    try:
+        with open(traffic_path(workload)) as f:
+            t = json.load(f)
+    except OSError:
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t
+
+
+def ensemble_leg(steps: int, warmup: int = 5, n_events: int = 256) -> dict:
+    """The batched half of the metric: the 256-event ensemble through the
+    batch API (tuned, graph-captured runs of up to 50 steps, every profile
+    observed after each run) against the same events one at a time through
+    cuba_step (the same runs and observations)."""
+    import torch
+    from paper_1208_0961_amd import autotune as AT
+    from paper_1208_0961_amd import batch as BT
+    from paper_1208_0961_amd import sim as S
+    from paper_1208_0961_amd import workload as W
+    events = W.ensemble_events(n_events)
+    total_n = sum(w.n for w in events)
+    table = AT.load()
+    if table is None:
+        print("# ensemble: tuning", file=sys.stderr, flush=True)
+        table = AT.tune(events)
+    oe = events[0].observe_every
+    runs = [oe] * (steps // oe) + ([steps % oe] if steps % oe else [])
+    print(f"# ensemble: {len(events)} events, {total_n} particles, {steps} steps",
+          file=sys.stderr, flush=True)
+    B = BT.Batch(len(events))
+    for i, w in enumerate(events):
+        st = W.riemann_state_torch(w, 100000 + i)
+        B.admit(i, {**w.params(), "cell_capacity": W.capacity_for(w)}, st)
+        del st
+    AT.apply(B, table, dict(enumerate(events)), use_graphs=True)
+    footprint = sum(int(B.slots[i]["workspace"].numel()) for i in range(len(events)))
+    B.step(warmup)
+    B.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in runs:
+        B.step(k)
+        for i in range(len(events)):
+            B.observe_async(i)
+    B.sync()
+    batched_s = time.perf_counter() - t0
+    B.close()
+    del B
+    torch.cuda.empty_cache()
+    print("# ensemble: one event at a time", file=sys.stderr, flush=True)
+    busy = 0.0
+    for i, w in enumerate(events):
+        st = W.riemann_state_torch(w, 100000 + i)
+        sim = S.Sim({**w.params(), "cell_capacity": W.capacity_for(w)}, st)
+        del st
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        for k in runs:
+            sim.step(k)
+            sim.observe_async()
+        torch.cuda.synchronize()
+        busy += time.perf_counter() - s0
+        sim.close()
+    torch.cuda.empty_cache()
+    batched = total_n * steps / batched_s
+    seq = total_n * steps / busy
+    return {"workload": f"ensemble-{len(events)}-events (r_test 50..2500 log-uniform, "
+                        "sigma 0.05..1 fm^2, T_L 0.30..0.50 GeV, T_R = 0.8 T_L, "
+                        "box 10 x L x L fm, L in 1, 2, 4)",
+            "n_particles": total_n, "steps": steps, "warmup": warmup,
+            "batched_particle_steps_per_s": batched,
+            "sequential_particle_steps_per_s": seq,
+            "speedup_vs_sequential": batched / seq,
+            "batched_ms_per_step": 1e3 * batched_s / steps,
+            "workspace_bytes": footprint,
+            "compact_state_bytes": 2 * 52 * total_n,
+            "tuning": {k: table.get(k) for k in ("cell_lanes", "cells_per_item",
+                                                 "persistent_waves")}}
+
+
+def serve_leg(n_requests: int) -> dict:
+    """The served half of the metric on a short request stream (sizes 1e4 to
+    4e6 test particles, 200 steps each, Poisson arrivals at 0.8 of the
+    server's measured capacity): p50/p99 time-to-result and particle-steps/s
+    against a one-at-a-time FIFO of plain runs on the same trace."""
+    from paper_1208_0961_amd import serve
+    return serve.measure(n_requests)
 
 
 def bench_sigma_scan(a):
@@ -407,8 +564,9 @@ def main():
     # binning of step t+1)
     step_ms = avg_ms("step") if stages["step"][1] else avg_ms("collide")
     pairs_per_step = pairs / a.steps
-    achieved_tops = PHILOX_OPS_PER_PAIR * pairs_per_step / (step_ms * 1e-3) / 1e12
-    traffic = measured_traffic(a.workload)
+    fp64_tflops = FP64_FLOPS_PER_PAIR * pairs_per_step / (step_ms * 1e-3) / 1e12
+    int32_tops = PHILOX_OPS_PER_PAIR * pairs_per_step / (step_ms * 1e-3) / 1e12
+    prof = measured_profile(a.workload)
 
     def gbs(nbytes, ms):
         return nbytes / (ms * 1e-3) / 1e9
@@ -417,28 +575,31 @@ def main():
     for name in C.STAGES:
         ms, k = stages[name]
         stage_out[name] = {"ms_per_launch": ms / k if k else None, "launches": k}
-    stage_out["bin"]["gbs"] = gbs(BYTES_BIN * w.n, avg_ms("bin"))
-    stage_out["bin"]["frac_hbm"] = stage_out["bin"]["gbs"] / HBM_PEAK_GBS
+    stage_out["bin"]["gbs_moved"] = gbs(BYTES_BIN * w.n, avg_ms("bin"))
     stage_out["step"]["pair_tests_per_launch"] = pairs_per_step
-    stage_out["step"]["hbm_gbs_algorithmic"] = gbs(BYTES_BIN * w.n, step_ms)
-    stage_out["step"]["fp64_tflops_algorithmic"] = (
-        FP64_FLOPS_PER_PAIR * pairs_per_step / (step_ms * 1e-3) / 1e12)
+    stage_out["step"]["binning_gbs_moved"] = gbs(BYTES_BIN * w.n, step_ms)
 
     # a plain device copy of 1 GiB, timed after the run, as the practical
     # HBM ceiling beside the 8 TB/s peak (read + write bytes per second)
     copy_gbs = device_copy_gbs(sim.stream)
-    stage_out["bin"]["copy_gbs"] = copy_gbs
-    stage_out["bin"]["frac_copy"] = stage_out["bin"]["gbs"] / copy_gbs
+    bin_ms = avg_ms("bin")
+    hbm = {"kernel": "k_stream_bin (streaming, reflection, binning)",
+           "bytes_per_particle_step": BYTES_BIN_ALGO,
+           "achieved": gbs(BYTES_BIN_ALGO * w.n, bin_ms), "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": gbs(BYTES_BIN_ALGO * w.n, bin_ms) / HBM_PEAK_GBS,
+           "ms_per_launch": bin_ms, "moved_bytes_per_particle": BYTES_BIN,
+           "moved_gbs": gbs(BYTES_BIN * w.n, bin_ms), "copy_gbs": copy_gbs,
+           "moved_frac_of_copy": gbs(BYTES_BIN * w.n, bin_ms) / copy_gbs}
 
     cpu = None
-    cpu_steps = a.cpu_steps if a.cpu_steps is not None else {"tube1d": 100, "tube3d": 24,
+    cpu_steps = a.cpu_steps if a.cpu_steps is not None else {"tube1d": 200, "tube3d": 200,
                                                               "full": 2,
                                                               "paper32": 2}[a.workload]
     if cpu_steps > 0:
-        threads = a.cpu_threads or max(1, min(16, os.cpu_count() or 1))
-        print(f"# cpu baseline: {cpu_steps} oracle steps, {threads} threads",
+        threads = a.cpu_threads or usable_cores()["usable"]
+        print(f"# cpu baseline: up to {cpu_steps} oracle steps, {threads} threads",
               file=sys.stderr, flush=True)
-        cpu = cpu_baseline(w, state, cpu_steps, threads)
+        cpu = cpu_baseline(w, state, cpu_steps, threads, a.cpu_seconds)
 
     out = {
         "metric": "particle-steps/s + FP64 pair-tests/s; ensemble p50/p99 latency vs plain",
@@ -459,18 +620,29 @@ def main():
                    "dt_fm": w.dt, "observe_every": w.observe_every,
                    "cell_lanes": lanes},
         "pair_tests_per_s": pairs / elapsed,
+        "fp64_pair_test_flops_per_s": FP64_FLOPS_PER_PAIR * pairs / elapsed,
         "candidates_per_step": cand / a.steps,
         "scatterings_per_step": claims / a.steps,
-        "roofline": {"bound": "alu", "kernel": "k_step (fused)",
-                     "achieved": achieved_tops, "peak": INT32_PEAK_TOPS,
-                     "unit": "Tops/s", "frac": achieved_tops / INT32_PEAK_TOPS,
-                     "traffic": traffic,
-                     "ops_per_pair_test": PHILOX_OPS_PER_PAIR,
-                     "ms_per_launch": step_ms},
+        "roofline": {"bound": "alu", "kernel": "k_step (fused): pair stage, FP64 vector",
+                     "achieved": fp64_tflops, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": fp64_tflops / FP64_PEAK_TFLOPS,
+                     "traffic": prof["bytes_per_launch"] if prof else None,
+                     "flops_per_pair_test": FP64_FLOPS_PER_PAIR,
+                     "algorithmic_bytes_per_launch": BYTES_BIN * w.n,
+                     "ms_per_launch": step_ms,
+                     "int32_issue": {"achieved": int32_tops, "peak": INT32_PEAK_TOPS,
+                                     "unit": "Tops/s", "frac": int32_tops / INT32_PEAK_TOPS,
+                                     "ops_per_pair_test": PHILOX_OPS_PER_PAIR},
+                     "valu_busy": prof.get("valu_busy") if prof else None},
+        "hbm": hbm,
         "stages": stage_out,
         "cpu_baseline": cpu,
+        "library": {"build_info": C.cuba_build_info(),
+                    "matches_sources": C.build_hash() == hip_build.source_hash()},
     }
     sim.close()
+    del sim
+    torch.cuda.empty_cache()
     if a.calibrate_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -478,6 +650,14 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = 1 << 30
+    if a.workload == "tube3d" and not a.no_extras:
+        for key, leg in (("ensemble", lambda: ensemble_leg(a.extra_steps)),
+                         ("serve", lambda: serve_leg(a.extra_requests))):
+            try:
+                out[key] = leg()
+            except Exception as e:    # the headline line is printed regardless
+                out[key] = {"error": f"{type(e).__name__}: {e}"}
+            torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 

@@ -235,6 +235,12 @@ void cuba_destroy(cuba_ctx *ctx);
 const char *cuba_strerror(int code);
 const char *cuba_last_error(void);
 
+/* Identification of the loaded library: "sources <h>; <arch>", where <h>
+ * is the first 16 hex digits of a SHA-256 over the library's source files
+ * and build flags, fixed when the library was compiled ("unknown" if the
+ * build did not supply it).  A static string; never NULL. */
+const char *cuba_build_info(void);
+
 /* ------------------------------------------------------------------------
  * Batches: many independent events (each a cuba_ctx with its own
  * parameters, seed, step index and workspace) advanced together, one

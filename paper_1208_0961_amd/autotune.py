@@ -27,6 +27,9 @@ AUTO = -1
 LANES_CANDIDATES = (AUTO, 0, 8, 16, 32, 64)
 PERSISTENT_CANDIDATES = (0, 256 * 16, 256 * 32)
 DEFAULT_TABLE = os.path.join(os.path.expanduser("~"), ".cache", "cuba_mi355x", "tuning.json")
+# the table measured on an MI355X and shipped with the package: used when no
+# table of the user's own has been saved
+PACKAGED_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_mi355x.json")
 
 
 def occupancy_class(mean_occupancy: float) -> int:
@@ -134,11 +137,14 @@ def save(table: dict, path: str = DEFAULT_TABLE) -> None:
         json.dump(table, f, indent=1)
 
 
-def load(path: str = DEFAULT_TABLE) -> dict | None:
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        return json.load(f)
+def load(path: str | None = None) -> dict | None:
+    """The tuning table at path; by default the user's saved table, else the
+    packaged MI355X table, else None."""
+    for p in ([path] if path else [DEFAULT_TABLE, PACKAGED_TABLE]):
+        if os.path.exists(p):
+            with open(p) as f:
+                return json.load(f)
+    return None
 
 
 def apply(B: Batch, table: dict, events_by_slot: dict, use_graphs: bool = True) -> None:

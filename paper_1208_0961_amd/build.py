@@ -8,6 +8,7 @@ hipcc flags that define the library's arithmetic:
 """
 from __future__ import annotations
 
+import hashlib
 import os
 import shutil
 import subprocess
@@ -25,8 +26,31 @@ def hipcc() -> str:
     return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 
-def flags() -> list[str]:
-    return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
+def source_files() -> list[str]:
+    """Every file the library is compiled from, in a fixed order."""
+    files = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
+                   if f.endswith((".hip", ".hpp", ".h")))
+    return files + [os.path.join(INCLUDE, "cuba.h")]
+
+
+def source_hash() -> str:
+    """SHA-256 (first 16 hex digits) of the library's sources and build
+    flags; compiled into libcuba.so (cuba_build_info) so that a loaded
+    library can be matched to the sources it was built from."""
+    h = hashlib.sha256()
+    for path in source_files():
+        h.update(os.path.relpath(path, ROOT).encode() + b"\0")
+        with open(path, "rb") as f:
+            h.update(f.read())
+    # flags with the checkout's location removed, so that a copy of the
+    # tree elsewhere hashes alike
+    h.update(" ".join(flags(with_hash=False)).replace(ROOT, ".").encode())
+    return h.hexdigest()[:16]
+
+
+def flags(with_hash: bool = True) -> list[str]:
+    extra = ['-DCUBA_SOURCE_HASH="' + source_hash() + '"'] if with_hash else []
+    return extra + ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
             "-ffp-contract=off", "-fno-fast-math",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wall", "-I", INCLUDE, "-I", CSRC,
@@ -49,9 +73,7 @@ def sources_newer_than_lib() -> bool:
     if not os.path.exists(LIB):
         return True
     t = os.path.getmtime(LIB)
-    deps = [os.path.join(CSRC, f) for f in os.listdir(CSRC)]
-    deps.append(os.path.join(INCLUDE, "cuba.h"))
-    return any(os.path.getmtime(d) > t for d in deps)
+    return any(os.path.getmtime(d) > t for d in source_files())
 
 
 if __name__ == "__main__":

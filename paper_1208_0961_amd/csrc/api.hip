@@ -623,6 +623,11 @@ const char *cuba_strerror(int code) {
 
 const char *cuba_last_error(void) { return g_last_error.c_str(); }
 
+#ifndef CUBA_SOURCE_HASH
+#define CUBA_SOURCE_HASH "unknown"
+#endif
+const char *cuba_build_info(void) { return "sources " CUBA_SOURCE_HASH "; gfx950"; }
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------

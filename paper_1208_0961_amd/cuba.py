@@ -128,6 +128,8 @@ def _load() -> ctypes.CDLL:
     L.cuba_batch_destroy.restype = None
     L.cuba_destroy.argtypes = [vp]
     L.cuba_destroy.restype = None
+    L.cuba_build_info.argtypes = []
+    L.cuba_build_info.restype = ctypes.c_char_p
     L.cuba_strerror.argtypes = [ctypes.c_int]
     L.cuba_strerror.restype = ctypes.c_char_p
     L.cuba_last_error.argtypes = []
@@ -166,6 +168,16 @@ def cuba_strerror(code: int) -> str:
 
 def cuba_last_error() -> str:
     return _lib.cuba_last_error().decode()
+
+
+def cuba_build_info() -> str:
+    return _lib.cuba_build_info().decode()
+
+
+def build_hash() -> str:
+    """The source hash compiled into the loaded library."""
+    info = cuba_build_info()
+    return info.split()[1].rstrip(";") if info.startswith("sources ") else "unknown"
 
 
 def cuba_workspace_bytes(params: cuba_params, n: int) -> int:

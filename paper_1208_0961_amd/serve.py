@@ -44,6 +44,8 @@ class Result:
     T00: np.ndarray
     T0x: np.ndarray
     state: list | None = None
+    admitted_run: int = 0     # runs completed before admission
+    finished_run: int = 0     # runs completed at its end
 
     @property
     def latency(self) -> float:
@@ -121,9 +123,12 @@ class Server:
         if self.tuning:
             AT.settings_for(self.B, slot, req.work, self.tuning)
 
-    def run(self, requests: list[Request], realtime: bool = True) -> list[Result]:
-        """Serves the requests; with realtime, a request is only admitted once
-        its arrival time has passed on the wall clock."""
+    def run(self, requests: list[Request], realtime=True) -> list[Result]:
+        """Serves the requests.  realtime=True admits a request once its
+        arrival time has passed on the wall clock; False treats every request
+        as present at the start; "runs" reads arrival times as a count of
+        completed runs (a logical clock: admission mid-stream at a
+        reproducible point)."""
         if self.tuning:
             self.B.set_launch(int(self.tuning.get("persistent_waves", 0)), self.use_graphs)
         queue = deque(sorted(requests, key=lambda r: r.arrival))
@@ -132,9 +137,12 @@ class Server:
         results: list[Result] = []
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0
+        runs_done = [0]
+        logical = realtime == "runs"
+        clock = (lambda: runs_done[0]) if logical else now
         while queue or live:
             # admission: FIFO, by free slot and HBM footprint
-            while queue and (not realtime or queue[0].arrival <= now()):
+            while queue and (not realtime or queue[0].arrival <= clock()):
                 req = queue[0]
                 need = footprint(req)
                 slot = self.B.free_slot()
@@ -144,11 +152,13 @@ class Server:
                 self._admit(slot, req)
                 used += need
                 live[slot] = {"req": req, "need": need, "done": 0, "admitted": now(),
-                              "active": True}
+                              "admitted_run": runs_done[0], "active": True}
                 self.peak_live = max(self.peak_live, len(live))
                 self.peak_bytes = max(self.peak_bytes, used)
             if not live:
-                if queue and realtime:
+                if queue and logical:
+                    runs_done[0] = max(runs_done[0], int(math.ceil(queue[0].arrival)))
+                elif queue and realtime:
                     time.sleep(max(0.0, min(queue[0].arrival - now(), 0.01)))
                 continue
             active = self._choose(live)
@@ -168,12 +178,14 @@ class Server:
                     finished.append(slot)
             self.B.sync()
             t_done = now()
+            runs_done[0] += 1
             for slot in finished:
                 ev = live.pop(slot)
                 s = self.B.slots[slot]
                 res = Result(ev["req"].rid, ev["req"].work.n, ev["req"].arrival,
                              ev["admitted"], t_done, s["T00"].cpu().numpy().copy(),
-                             s["T0x"].cpu().numpy().copy())
+                             s["T0x"].cpu().numpy().copy(),
+                             admitted_run=ev["admitted_run"], finished_run=runs_done[0])
                 if self.keep_states:
                     res.state = self.B.get_state(slot)
                 self.B.retire(slot)
@@ -255,67 +267,69 @@ def percentiles(lat):
     return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
 
 
-def bench(a):
-    """2000 requests (sizes 1e4 .. 4e6 test particles), Poisson arrivals at 0.8
-    of the measured batched capacity; p50/p99 time-to-result and aggregate
-    particle-steps/s of the served stream against a one-at-a-time FIFO of
-    plain runs on the same trace."""
-    import json
+def measure(n_req: int, policy: str = "all", run_steps: int = 200, final_only: bool = True,
+            run_particles: int = 2_000_000, other_policy: bool = False,
+            sequential: bool = True, seed: int = 5) -> dict:
+    """n_req requests (sizes 1e4 .. 4e6 test particles), Poisson arrivals at
+    0.8 of the server's batched capacity (measured on a closed batch of 64
+    requests); p50/p99 time-to-result and aggregate particle-steps/s of the
+    served stream against a one-at-a-time FIFO of plain runs on the same
+    trace (each request's service time measured alone, the FIFO recurrence
+    giving completion times)."""
     import sys
     from . import autotune as AT
-    n_req = int(a.requests)
     tuning = AT.load()
-    run_steps = int(getattr(a, "serve_run_steps", 200))
+
+    def server(pol):
+        return Server(tuning=tuning, use_graphs=False, policy=pol, run_steps=run_steps,
+                      run_particles=run_particles, final_only=final_only)
+
     # untimed warm-up of both paths (first launches load code objects and
     # grow the allocator's pools)
     warm = request_stream(16, 0.0, seed=56)
-    final_only = getattr(a, "serve_observe", "final") == "final"
-    srv = Server(tuning=tuning, use_graphs=False, run_steps=run_steps, final_only=final_only)
+    srv = server(policy)
     srv.run(warm, realtime=False)
     srv.close()
     run_alone(warm[0], final_only=final_only)
     # capacity: a closed batch of 64 requests all present at t = 0
     probe = request_stream(64, 0.0, seed=55)
-    srv = Server(tuning=tuning, use_graphs=False, run_steps=run_steps, final_only=final_only)
+    srv = server(policy)
     t0 = time.perf_counter()
     srv.run(probe, realtime=False)
     cap_dt = time.perf_counter() - t0
     srv.close()
-    probe_ps = sum(r.work.n * r.work.steps for r in probe)
-    throughput = probe_ps / cap_dt
-    reqs0 = request_stream(n_req, 1.0, seed=5)
+    throughput = sum(r.work.n * r.work.steps for r in probe) / cap_dt
+    reqs0 = request_stream(n_req, 1.0, seed=seed)
     mean_ps = float(np.mean([r.work.n * r.work.steps for r in reqs0]))
     rate = 0.8 * throughput / mean_ps
-    reqs = request_stream(n_req, rate, seed=5)
+    reqs = request_stream(n_req, rate, seed=seed)
     print(f"# serve: {n_req} requests at {rate:.1f}/s (capacity {throughput:.3e} "
           f"particle-steps/s)", file=sys.stderr, flush=True)
     total_ps = sum(r.work.n * r.work.steps for r in reqs)
-    policy = getattr(a, "serve_policy", "all")
     out = {"metric": "served request stream: p50/p99 time-to-result and particle-steps/s",
            "unit": "particle-steps/s", "policy": policy, "run_steps": run_steps,
            "observed": "final profile" if final_only else "every 50 steps",
-           "run_particles": int(getattr(a, "serve_run_particles", 2_000_000)),
-           "requests": n_req,
+           "run_particles": run_particles, "requests": n_req,
+           "request_sizes": "1e4 .. 4e6 test particles, 200 steps",
            "arrival_rate_per_s": rate, "capacity_particle_steps_per_s": throughput}
-    # the chosen policy, then the other one on the same trace for comparison
-    for pol in (policy, "all" if policy == "srpt" else "srpt"):
+    pols = (policy, "all" if policy == "srpt" else "srpt") if other_policy else (policy,)
+    for pol in pols:
         print(f"# serve policy {pol}", file=sys.stderr, flush=True)
-        srv = Server(tuning=tuning, use_graphs=False, policy=pol, run_steps=run_steps,
-                     run_particles=int(getattr(a, "serve_run_particles", 2_000_000)),
-                     final_only=final_only)
+        srv = server(pol)
         t0 = time.perf_counter()
         res = srv.run(reqs, realtime=True)
         makespan = time.perf_counter() - t0
+        peak = {"peak_live": srv.peak_live, "peak_bytes": srv.peak_bytes}
         srv.close()
         assert len(res) == n_req
         p50, p99 = percentiles([r.latency for r in res])
+        row = {"value": total_ps / makespan, "p50_s": p50, "p99_s": p99,
+               "makespan_s": makespan, **peak}
         if pol == policy:
-            out.update({"value": total_ps / makespan, "p50_s": p50, "p99_s": p99,
-                        "makespan_s": makespan})
+            out.update(row)
         else:
-            out[pol] = {"value": total_ps / makespan, "p50_s": p50, "p99_s": p99,
-                        "makespan_s": makespan}
-    if not getattr(a, "no_sequential", False):
+            out[pol] = row
+    if sequential:
         print("# sequential FIFO replay", file=sys.stderr, flush=True)
         service = {}
         for r in reqs:
@@ -326,4 +340,20 @@ def bench(a):
         out.update({"sequential_p50_s": sp50, "sequential_p99_s": sp99,
                     "sequential_value": total_ps / max(fin.values()),
                     "sequential_busy_particle_steps_per_s": total_ps / sum(service.values())})
+        out["beats_fifo_p50"] = out["p50_s"] < sp50
+        out["beats_fifo_p99"] = out["p99_s"] < sp99
+    return out
+
+
+def bench(a):
+    """2000 requests (sizes 1e4 .. 4e6 test particles), Poisson arrivals at 0.8
+    of the measured batched capacity; p50/p99 time-to-result and aggregate
+    particle-steps/s of the served stream against a one-at-a-time FIFO of
+    plain runs on the same trace."""
+    import json
+    out = measure(int(a.requests), policy=getattr(a, "serve_policy", "all"),
+                  run_steps=int(getattr(a, "serve_run_steps", 200)),
+                  final_only=getattr(a, "serve_observe", "final") == "final",
+                  run_particles=int(getattr(a, "serve_run_particles", 2_000_000)),
+                  other_policy=True, sequential=not getattr(a, "no_sequential", False))
     print(json.dumps(out), flush=True)

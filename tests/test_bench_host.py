@@ -65,7 +65,7 @@ def test_traffic_scaled_by_the_copy_reading(bench, tmp_path, monkeypatch):
     _counter_csv(write, "WRITE_SIZE", [(step, 10000, 5000.0), (copy, 65536, gib_kib)])
     out = tmp_path / "traffic.json"
     monkeypatch.setattr(bench, "traffic_path", lambda workload: str(out))
-    a = argparse.Namespace(pmc_csv=[str(fetch), str(write)], workload="unit")
+    a = argparse.Namespace(pmc_csv=[str(fetch), str(write)], workload="unit", pmc_sq=None)
     bench.write_traffic(a)
     t = json.load(open(out))
     assert t["fetch_scale"] == pytest.approx(2.0) and t["write_scale"] == pytest.approx(1.0)
@@ -75,7 +75,32 @@ def test_traffic_scaled_by_the_copy_reading(bench, tmp_path, monkeypatch):
                                                   + t["write_bytes_per_launch"])
     assert t["kernel_source_hash"] == bench.kernel_source_hash()
     # read back only while the sources still hash to the stored key
-    assert bench.measured_traffic("unit") == pytest.approx(t["bytes_per_launch"])
+    assert bench.measured_profile("unit")["bytes_per_launch"] == pytest.approx(
+        t["bytes_per_launch"])
     t["kernel_source_hash"] = "0" * 16
     json.dump(t, open(out, "w"))
-    assert bench.measured_traffic("unit") is None
+    assert bench.measured_profile("unit") is None
+
+
+def test_valu_busy_from_sq_counter_and_trace(bench, tmp_path):
+    """4 SQ_ACTIVE_INST_VALU quad-cycles per SIMD-cycle of the kernel's
+    average trace duration: a kernel keeping all 1024 SIMDs busy for its
+    whole 100 us reads 1024 x 240000 / 4 quad-cycles, i.e. busy 1."""
+    step = "void cuba::k_step<true, false, 512u>(cuba::Cells, long)"
+    sq = tmp_path / "sq.csv"
+    full = 1024 * 240000 / 4
+    _counter_csv(sq, "SQ_ACTIVE_INST_VALU", [(step, 10000, full), (step, 10000, full / 2)])
+    stats = tmp_path / "stats.csv"
+    with open(stats, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Name", "Calls", "AverageNs"])
+        w.writeheader()
+        w.writerow({"Name": "__amd_rocclr_copyBuffer", "Calls": 3, "AverageNs": 5.0})
+        w.writerow({"Name": step, "Calls": 2, "AverageNs": 100000.0})
+    v = bench.valu_busy(str(sq), str(stats))
+    assert v["valu_busy"] == pytest.approx(0.75)
+    assert v["trace_avg_ns"] == 100000.0
+
+
+def test_usable_cores_reports_affinity_and_count(bench):
+    c = bench.usable_cores()
+    assert 1 <= c["usable"] <= c["affinity"] <= (c["cpu_count"] or c["affinity"])

@@ -51,3 +51,56 @@ def test_results_same_alone_and_in_the_mix(serve, policy, final_only, run_steps)
         # profile sums run in storage order: equal to rounding
         assert np.allclose(r.T00, T00, rtol=1e-12, atol=0)
         assert np.allclose(r.T0x, T0x, rtol=1e-12, atol=1e-12 * np.abs(T00).max())
+
+
+def _anchor_requests(serve, steps):
+    """Six requests of the served distribution (1e4 .. 4e6 test particles):
+    the smallest, the largest and four between, arriving at runs 0, 0, 1,
+    2, 3 and 4 of the server's logical clock, so that later requests are
+    admitted while earlier ones are on the device."""
+    pool = serve.request_stream(80, 0.0, seed=21, nmin=1e4, nmax=4e6, steps=steps)
+    pool = sorted(pool, key=lambda r: r.work.n)
+    picks = [pool[0], pool[-1], pool[20], pool[40], pool[60], pool[-2]]
+    out = []
+    for i, (r, run) in enumerate(zip(picks, (0, 0, 1, 2, 3, 4))):
+        out.append(serve.Request(i, r.work, float(run), r.state_seed))
+    return out
+
+
+def test_served_requests_anchor_to_the_oracle(serve, orc):
+    """Requests served with staggered admission, once with S - 1 = 7 steps
+    and once with S = 8 (runs of 3 steps): one traced oracle step from each
+    request's S - 1 result reproduces its S result at the parity contract's
+    tolerance (positions and unscattered momenta bit-exact, the scattered set
+    equal to the oracle's claims, scattered momenta within 1e-12 (Ea + Eb)).
+    The S result also equals the request run alone, bit for bit."""
+    import dataclasses
+    import parity
+    S = 8
+    results = {}
+    for steps in (S - 1, S):
+        reqs = [dataclasses.replace(r, work=dataclasses.replace(r.work, steps=steps))
+                for r in _anchor_requests(serve, S)]
+        assert max(r.work.n for r in reqs) > 3_000_000
+        srv = serve.Server(max_slots=8, run_steps=3, keep_states=True, final_only=True)
+        res = srv.run(reqs, realtime="runs")
+        srv.close()
+        assert sorted(r.rid for r in res) == list(range(len(reqs)))
+        by = {r.rid: r for r in res}
+        # a request admitted while others were still on the device
+        assert any(by[j].admitted_run > by[i].admitted_run
+                   and by[j].admitted_run < by[i].finished_run
+                   for i in by for j in by if i != j)
+        results[steps] = by
+    reqs = {r.rid: r for r in _anchor_requests(serve, S)}
+    for rid, req in reqs.items():
+        prev, got = results[S - 1][rid].state, results[S][rid].state
+        print(f"[serve-anchor] request {rid}: n={req.work.n}", flush=True)
+        n_sc = parity.full_step_check(orc, prev, got, req.work.params(), S - 1,
+                                      f"request {rid}", threads=16)
+        assert n_sc > 0
+        _, _, _, alone = serve.run_alone(dataclasses.replace(
+            req, work=dataclasses.replace(req.work, steps=S)), keep_state=True,
+            final_only=True)
+        for d in range(6):
+            assert np.array_equal(got[d], alone[d]), (rid, d)
