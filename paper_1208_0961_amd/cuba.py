@@ -51,6 +51,12 @@ class cuba_trace(ctypes.Structure):
 
 
 def _load() -> ctypes.CDLL:
+    # torch's ROCm build ships its own HIP runtime, which its libraries name
+    # "libamdhip64.so"; libcuba.so names the soname "libamdhip64.so.7".
+    # Loaded first, torch's copy satisfies both and the process holds one
+    # runtime.  Loaded the other way round, the process would hold two, and
+    # the second finds no device.
+    import torch  # noqa: F401
     if not os.path.exists(_LIB_PATH):
         raise ImportError(f"{_LIB_PATH} is not built: the HIP library is required "
                           "(build it with paper_1208_0961_amd.build.build())")
