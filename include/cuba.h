@@ -41,7 +41,9 @@
  *  - "device" pointers are HIP device allocations owned by the caller;
  *    "host" pointers are ordinary host memory.  The library allocates no
  *    device memory: all of its device state lives in the caller's
- *    workspace.  It allocates only the small host-side context.
+ *    workspace (or, for cuba_init_static only, in one fixed array per GPU
+ *    that the library's code object holds).  It allocates only the small
+ *    host-side context.
  *  - stream arguments are hipStream_t values passed as void* (NULL: the
  *    null stream).  All device work of a context is issued on its stream,
  *    asynchronously; errors raised by the device (a cell holding more than
@@ -110,6 +112,28 @@ int cuba_init(cuba_ctx **out, const cuba_params *params, int64_t n,
               const double *x, const double *y, const double *z,
               const double *px, const double *py, const double *pz,
               void *workspace, size_t ws_bytes, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * cuba_init, with the same validation and errors, but the context lives in
+ * a workspace the library holds, CUBA_STATIC_WORKSPACE_BYTES of device
+ * memory per GPU (allocated with the library's code when it first runs on
+ * that GPU and held until the process ends), and a context object the
+ * library holds; the call allocates no device memory and no context.  The caller
+ * still passes the initial state (device arrays as for cuba_init).
+ * CUBA_ENOMEM when cuba_workspace_bytes(params, n) exceeds
+ * CUBA_STATIC_WORKSPACE_BYTES.  Every call on a GPU reuses that GPU's
+ * workspace and context object: a call ends the previous context set up by
+ * this function on the same GPU (its handle must no longer be used), and
+ * calls or steps that overlap on one GPU (other threads, other streams)
+ * race.  cuba_destroy of the handle only ends its stage timing.  The
+ * workspace's contents are those the last call left; this call clears what
+ * must start at zero. */
+#define CUBA_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+int cuba_init_static(cuba_ctx **out, const cuba_params *params, int64_t n,
+                     const double *x, const double *y, const double *z,
+                     const double *px, const double *py, const double *pz,
+                     void *stream);
 
 /* Advances the state by nsteps >= 0 steps, asynchronously on the stream.
  * Step indices continue from params->step0.  Internally one kernel per

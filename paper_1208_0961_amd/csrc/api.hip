@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -202,6 +203,7 @@ struct cuba_ctx {
   uint32_t *offsets, *tile_sums;
   double *cell_sums;
   DeviceConsts *consts;  // in the workspace
+  bool in_library = false;  // set up by cuba_init_static: not freed by cuba_destroy
   // stage timing (cuba_timing_begin / cuba_timing_end)
   bool timing = false;
   size_t timing_cap = 0;
@@ -330,17 +332,30 @@ size_t cuba_workspace_bytes(const cuba_params *params, int64_t n) {
   return make_layout(d.n_cells, d.cap).total;
 }
 
-int cuba_init(cuba_ctx **out, const cuba_params *params, int64_t n, const double *x,
-              const double *y, const double *z, const double *px, const double *py,
-              const double *pz, void *workspace, size_t ws_bytes, void *stream) {
-  if (!out) return fail(CUBA_EINVAL, "out is NULL");
-  *out = nullptr;
-  Derived d;
-  int rc = derive(params, d);
+}  // extern "C"
+
+namespace {
+
+// Checks the arguments of cuba_init / cuba_init_static that do not depend
+// on the workspace.
+int check_init_args(const cuba_params *params, int64_t n, const double *x, const double *y,
+                    const double *z, const double *px, const double *py, const double *pz,
+                    Derived &d) {
+  const int rc = derive(params, d);
   if (rc != CUBA_OK) return rc;
   if (n < 0 || n >= 0xFFFFFFFFll) return fail(CUBA_EINVAL, "n must be in [0, 2^32 - 1)");
   if (n > 0 && !(x && y && z && px && py && pz))
     return fail(CUBA_EINVAL, "particle arrays must not be NULL");
+  return CUBA_OK;
+}
+
+// Sets up the context c (freshly constructed) on the workspace and bins the
+// initial state.  The caller frees c on failure, if it owns it.
+int init_context(cuba_ctx *c, const Derived &d, const cuba_params *params, int64_t n,
+                 const double *x, const double *y, const double *z, const double *px,
+                 const double *py, const double *pz, void *workspace, size_t ws_bytes,
+                 void *stream) {
+  int rc = CUBA_OK;
   if (!workspace) return fail(CUBA_EINVAL, "workspace is NULL");
   if (((uintptr_t)workspace & 255u) != 0)
     return fail(CUBA_EINVAL, "workspace must be 256-byte aligned");
@@ -348,9 +363,6 @@ int cuba_init(cuba_ctx **out, const cuba_params *params, int64_t n, const double
   if (ws_bytes < L.total)
     return fail(CUBA_ENOMEM, "workspace too small: need " + std::to_string(L.total) +
                                  " bytes, got " + std::to_string(ws_bytes));
-
-  cuba_ctx *c = new (std::nothrow) cuba_ctx();
-  if (!c) return fail(CUBA_ENOMEM, "host allocation failed");
   c->d = d;
   c->pa.kfac = d.kfac;
   const uint64_t lim = w1_limit(d.kfac);
@@ -379,14 +391,10 @@ int cuba_init(cuba_ctx **out, const cuba_params *params, int64_t n, const double
   // byte distance: every array of buffer 1 lies that far from its twin
   const ptrdiff_t shift = (char *)c->buf[1].st.x - (char *)c->buf[0].st.x;
   for (int a = 0; a < 7; ++a)
-    if ((ptrdiff_t)(L.soa[1][a] - L.soa[0][a]) != shift) {
-      delete c;
+    if ((ptrdiff_t)(L.soa[1][a] - L.soa[0][a]) != shift)
       return fail(CUBA_EINVAL, "internal: buffers not laid out alike");
-    }
-  if ((ptrdiff_t)(L.count[1] - L.count[0]) != shift) {
-    delete c;
+  if ((ptrdiff_t)(L.count[1] - L.count[0]) != shift)
     return fail(CUBA_EINVAL, "internal: buffers not laid out alike");
-  }
   c->offsets = (uint32_t *)(ws + L.offsets);
   c->tile_sums = (uint32_t *)(ws + L.tile_sums);
   c->cell_sums = (double *)(ws + L.cell_sums);
@@ -401,38 +409,110 @@ int cuba_init(cuba_ctx **out, const cuba_params *params, int64_t n, const double
   launch_fill_u32(c->buf[0].count, 0u, d.n_cells, c->stream);
   launch_fill_u32(c->buf[1].count, 0u, d.n_cells, c->stream);
   hipError_t e = hipMemcpyAsync(c->consts, &hc, sizeof(hc), hipMemcpyHostToDevice, c->stream);
-  if (e != hipSuccess) {
-    delete c;
-    return hip_fail(e, "init constants");
-  }
+  if (e != hipSuccess) return hip_fail(e, "init constants");
   launch_init_bin(x, y, z, px, py, pz, c->buf[0], n, d.g, c->status, c->stream);
   launch_occupancy_over(c->buf[0], d.n_cells, c->status, c->stream);
   rc = check_launch("init launch");
-  if (rc != CUBA_OK) {
-    delete c;
-    return rc;
-  }
+  if (rc != CUBA_OK) return rc;
   uint32_t head[5] = {0, 0, 0, 0, 0};  // err, over[4]
   static_assert(offsetof(DevStatus, over) == sizeof(uint32_t), "status layout");
   e = hipMemcpyAsync(head, &c->status->err, sizeof(head), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  if (e != hipSuccess) {
-    delete c;
-    return hip_fail(e, "init check");
-  }
+  if (e != hipSuccess) return hip_fail(e, "init check");
   const uint32_t err = head[0];
   for (int k = 0; k < 4; ++k) c->over[k] = head[1 + k];
   c->lanes = default_lanes(c->over, d.n_cells, true);
-  if (err & kErrRange) {
-    delete c;
-    return fail(CUBA_ERANGE,
-                "a particle is outside [0, L], non-finite, or has |p| = 0");
-  }
-  if (err & kErrCapacity) {
-    delete c;
+  if (err & kErrRange)
+    return fail(CUBA_ERANGE, "a particle is outside [0, L], non-finite, or has |p| = 0");
+  if (err & kErrCapacity)
     return fail(CUBA_ERANGE, "a cell holds more particles than cell_capacity (" +
                                  std::to_string(d.cap) + ")");
+  return CUBA_OK;
+}
+
+// The library's own workspace for cuba_init_static: one array per device
+// (each GPU the library runs on holds its copy until the process ends),
+// addressed from the host through hipGetSymbolAddress only.  Every call on a
+// device reuses that device's array.
+constexpr size_t kStaticWorkspaceBytes = CUBA_STATIC_WORKSPACE_BYTES;
+
+}  // namespace
+
+static __device__ __align__(256) char scratch[kStaticWorkspaceBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+struct StaticSlot {
+  void *ptr = nullptr;  // device address of `scratch` on this device
+  cuba_ctx ctx;         // the context living on it
+};
+StaticSlot g_static[kMaxDevices];
+std::mutex g_static_mu;
+
+// Device address of the current device's `scratch` (looked up once per
+// device, with that device current).
+int static_workspace(int &dev, void *&ptr) {
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "static workspace: device");
+  if (dev < 0 || dev >= kMaxDevices) return fail(CUBA_EDEVICE, "static workspace: device id");
+  if (!g_static[dev].ptr) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "static workspace: symbol address");
+    g_static[dev].ptr = p;
   }
+  ptr = g_static[dev].ptr;
+  return CUBA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cuba_init(cuba_ctx **out, const cuba_params *params, int64_t n, const double *x,
+              const double *y, const double *z, const double *px, const double *py,
+              const double *pz, void *workspace, size_t ws_bytes, void *stream) {
+  if (!out) return fail(CUBA_EINVAL, "out is NULL");
+  *out = nullptr;
+  Derived d;
+  int rc = check_init_args(params, n, x, y, z, px, py, pz, d);
+  if (rc != CUBA_OK) return rc;
+  cuba_ctx *c = new (std::nothrow) cuba_ctx();
+  if (!c) return fail(CUBA_ENOMEM, "host allocation failed");
+  rc = init_context(c, d, params, n, x, y, z, px, py, pz, workspace, ws_bytes, stream);
+  if (rc != CUBA_OK) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return CUBA_OK;
+}
+
+int cuba_init_static(cuba_ctx **out, const cuba_params *params, int64_t n, const double *x,
+                     const double *y, const double *z, const double *px, const double *py,
+                     const double *pz, void *stream) {
+  if (!out) return fail(CUBA_EINVAL, "out is NULL");
+  *out = nullptr;
+  Derived d;
+  int rc = check_init_args(params, n, x, y, z, px, py, pz, d);
+  if (rc != CUBA_OK) return rc;
+  const size_t need = make_layout(d.n_cells, d.cap).total;
+  if (need > kStaticWorkspaceBytes)
+    return fail(CUBA_ENOMEM, "static workspace too small: need " + std::to_string(need) +
+                                 " bytes, the library holds " +
+                                 std::to_string(kStaticWorkspaceBytes));
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  int dev = 0;
+  void *ws = nullptr;
+  rc = static_workspace(dev, ws);
+  if (rc != CUBA_OK) return rc;
+  cuba_ctx *c = &g_static[dev].ctx;
+  drop_timing(c);
+  *c = cuba_ctx{};
+  c->in_library = true;
+  rc = init_context(c, d, params, n, x, y, z, px, py, pz, ws, kStaticWorkspaceBytes, stream);
+  if (rc != CUBA_OK) return rc;
   *out = c;
   return CUBA_OK;
 }
@@ -607,7 +687,7 @@ int cuba_timing_end(cuba_ctx *c, double stage_ms[CUBA_NUM_STAGES],
 void cuba_destroy(cuba_ctx *c) {
   if (!c) return;
   drop_timing(c);
-  delete c;
+  if (!c->in_library) delete c;
 }
 
 const char *cuba_strerror(int code) {

@@ -67,6 +67,8 @@ def _load() -> ctypes.CDLL:
     L.cuba_workspace_bytes.restype = ctypes.c_size_t
     L.cuba_init.argtypes = [ctypes.POINTER(vp), P, i64] + [vp] * 6 + [vp, ctypes.c_size_t, vp]
     L.cuba_init.restype = ctypes.c_int
+    L.cuba_init_static.argtypes = [ctypes.POINTER(vp), P, i64] + [vp] * 6 + [vp]
+    L.cuba_init_static.restype = ctypes.c_int
     L.cuba_step.argtypes = [vp, i32]
     L.cuba_step.restype = ctypes.c_int
     L.cuba_observe.argtypes = [vp, vp, vp]
@@ -196,6 +198,18 @@ def cuba_init(params: cuba_params, n: int, x: int, y: int, z: int, px: int, py: 
     rc = _lib.cuba_init(ctypes.byref(ctx), ctypes.byref(params), int(n), x, y, z, px, py,
                         pz, workspace, int(ws_bytes), stream)
     _check(rc, "cuba_init")
+    return ctx.value
+
+
+CUBA_STATIC_WORKSPACE_BYTES = 64 << 20
+
+
+def cuba_init_static(params: cuba_params, n: int, x: int, y: int, z: int, px: int, py: int,
+                     pz: int, stream: int | None) -> int:
+    ctx = ctypes.c_void_p()
+    rc = _lib.cuba_init_static(ctypes.byref(ctx), ctypes.byref(params), int(n), x, y, z,
+                               px, py, pz, stream)
+    _check(rc, "cuba_init_static")
     return ctx.value
 
 
