@@ -47,7 +47,7 @@
  *  - stream arguments are hipStream_t values passed as void* (NULL: the
  *    null stream).  All device work of a context is issued on its stream,
  *    asynchronously; errors raised by the device (a cell holding more than
- *    CUBA_MAX_CELL_OCCUPANCY particles, a trace buffer too small) are
+ *    CUBA_MAX_CELL_PARTICLES particles, a trace buffer too small) are
  *    reported by the next cuba_sync.
  *  - A context is not thread-safe; one context per stream.
  *  - Return values: CUBA_OK (0) or a negative CUBA_E* code; cuba_strerror
@@ -67,12 +67,24 @@ extern "C" {
 #define CUBA_OK 0
 #define CUBA_EINVAL -1  /* invalid parameters or arguments                 */
 #define CUBA_ERANGE -2  /* a particle outside the box, a non-finite value,
-                           |p| = 0, or a cell over the occupancy limit      */
+                           |p| = 0, or a cell holding more particles than
+                           CUBA_MAX_CELL_PARTICLES                          */
 #define CUBA_ENOMEM -3  /* workspace (or trace buffer) too small           */
 #define CUBA_EDEVICE -4 /* HIP runtime error; see cuba_last_error()         */
 
-/* Largest per-cell capacity (particles one cell may hold in a step). */
-#define CUBA_MAX_CELL_OCCUPANCY 1024
+/* Largest cuba_params.cell_capacity (the slots of a cell's block; the
+ * collision kernels hold a block's ids in LDS).  Not a limit on how many
+ * particles a cell may hold: those past the block are kept in a spill
+ * region (sized for every particle of the context) and the cell is stepped
+ * by a kernel for such cells. */
+#define CUBA_MAX_CELL_CAPACITY 1024
+
+/* Most particles one cell may hold: the pair index k < n (n - 1) / 2 of the
+ * determinism contract is one 32-bit word of the Philox counter (it fits up
+ * to 92 682 members; the bound stays one lower).  A cell
+ * holding more has its collisions skipped (its particles still stream) and
+ * the next cuba_sync reports CUBA_ERANGE. */
+#define CUBA_MAX_CELL_PARTICLES 92681
 
 typedef struct cuba_ctx cuba_ctx;
 
@@ -85,17 +97,21 @@ typedef struct {
   double dt;        /* time step [fm/c], 0 < dt < min_d dx_d                */
   uint64_t seed;    /* Philox key: key[0] = low 32 bits, key[1] = high      */
   uint32_t step0;   /* index t of the first step (0, or t when resuming)    */
-  int32_t cell_capacity; /* slots reserved per cell in the workspace, in
-                            [1, CUBA_MAX_CELL_OCCUPANCY]; 0 selects 512.  A
-                            cell that receives more particles drops the
-                            surplus and cuba_sync reports CUBA_ERANGE.     */
+  int32_t cell_capacity; /* slots of each cell's block in the workspace, in
+                            [1, CUBA_MAX_CELL_CAPACITY]; 0 selects twice the
+                            mean occupancy n / cells + 32, rounded up to 32.
+                            A layout choice, not a limit: a cell receiving
+                            more keeps the surplus in the spill region and
+                            is stepped (slower, same result) by the kernel
+                            for such cells.                                */
 } cuba_params;
 
 /* Bytes of device workspace cuba_init needs for n particles with these
  * parameters (for admission by memory footprint): two state buffers of
- * cells x cell_capacity slots of 52 bytes plus per-cell bookkeeping.
- * Returns 0 if the parameters are invalid.  The workspace must be 256-byte
- * aligned. */
+ * cells x cell_capacity slots of 52 bytes, each with a spill region of n
+ * particles (56 bytes each), scratch of 10 bytes per particle for stepping
+ * overflowing cells, and per-cell bookkeeping.  Returns 0 if the parameters
+ * are invalid.  The workspace must be 256-byte aligned. */
 size_t cuba_workspace_bytes(const cuba_params *params, int64_t n);
 
 /* Creates a context.  x..pz are device arrays of n doubles (particle id =
@@ -349,8 +365,11 @@ int cuba_batch_set_launch(cuba_batch *b, int32_t persistent_waves,
  * by nsteps steps (asynchronous). */
 int cuba_batch_step(cuba_batch *b, int32_t nsteps);
 
-/* Waits for the stream and reports the first event's device error (its
- * slot in *bad_slot, else -1). */
+/* Waits for the stream and reports the device error of the first event
+ * (in slot order) that has one, with its slot in *bad_slot (else -1), and
+ * clears it; other events' errors stay pending and are reported by the
+ * following calls, one per call, so a caller can retire each failing event
+ * and go on with the rest. */
 int cuba_batch_sync(cuba_batch *b, int32_t *bad_slot);
 
 /* Stage timing of the following non-graph runs, as cuba_timing_begin/end

@@ -37,7 +37,12 @@ inline size_t align256(size_t v) { return (v + 255u) & ~(size_t)255u; }
 struct Layout {
   size_t status;
   size_t soa[2][7];  // x y z px py pz id, for the two buffers (C x cap slots)
-  size_t count[2];   // per-cell occupancy of the two buffers
+  size_t count[2];   // per-cell particle counts of the two buffers
+  size_t spill_desc[2];      // SpillDesc of each buffer
+  size_t spill_soa[2][7];    // spilled particles (n slots)
+  size_t spill_cell[2], spill_ocell[2], spill_hdr[2];
+  size_t pool, pool_hdr;     // overflow-kernel scratch
+  uint64_t pool_words;
   size_t offsets, tile_sums, cell_sums;
   size_t consts;  // device copy of the geometry
   size_t total;
@@ -48,7 +53,11 @@ struct DeviceConsts {
   Geometry g;
 };
 
-Layout make_layout(int64_t n_cells, uint32_t cap) {
+// The spill region of a buffer holds every particle of the context (so no
+// binning can lose one); the overflow kernel's pool holds, per overflowing
+// cell of n members, n - cap + n + n / 2 + 1 words, at most 5 n_total / 2
+// plus one word per cell in all.
+Layout make_layout(int64_t n_cells, uint32_t cap, int64_t n) {
   Layout L{};
   size_t off = 0;
   auto take = [&off](size_t bytes) {
@@ -58,13 +67,25 @@ Layout make_layout(int64_t n_cells, uint32_t cap) {
   };
   const size_t cc = (size_t)n_cells;
   const size_t slots = cc * cap;
+  const size_t sn = n > 0 ? (size_t)n : 1u;
   const size_t tiles = (cc + kScanTile - 1) / kScanTile;
   L.status = take(sizeof(DevStatus));
+  // the two buffers are laid out alike (every array of buffer 1 at one
+  // distance from its twin in buffer 0)
   for (int b = 0; b < 2; ++b) {
     for (int a = 0; a < 6; ++a) L.soa[b][a] = take(slots * sizeof(double));
     L.soa[b][6] = take(slots * sizeof(uint32_t));
     L.count[b] = take(cc * sizeof(uint32_t));
+    L.spill_desc[b] = take(sizeof(SpillDesc));
+    for (int a = 0; a < 6; ++a) L.spill_soa[b][a] = take(sn * sizeof(double));
+    L.spill_soa[b][6] = take(sn * sizeof(uint32_t));
+    L.spill_cell[b] = take(sn * sizeof(uint32_t));
+    L.spill_ocell[b] = take(cc * sizeof(uint32_t));
+    L.spill_hdr[b] = take(kSpillHdrWords * sizeof(uint32_t));
   }
+  L.pool_words = (uint64_t)sn * 5u / 2u + cc + 64u;
+  L.pool = take((size_t)L.pool_words * sizeof(uint32_t));
+  L.pool_hdr = take(2 * sizeof(unsigned long long));
   L.offsets = take((cc + 1) * sizeof(uint32_t));
   L.tile_sums = take(tiles * sizeof(uint32_t));
   L.cell_sums = take(cc * kCellSums * sizeof(double));
@@ -82,9 +103,17 @@ struct Derived {
   uint32_t cap;
 };
 
-constexpr uint32_t kDefaultCellCapacity = 512;
+// Default slots per cell: twice the mean occupancy plus 32, rounded up to
+// 32 (a Poisson cell exceeds it rarely; one that does is stepped by the
+// overflow kernel).
+uint32_t default_capacity(int64_t n, int64_t n_cells) {
+  const double mean = n_cells > 0 ? (double)n / (double)n_cells : 0.0;
+  double cap = std::ceil((2.0 * mean + 32.0) / 32.0) * 32.0;
+  if (cap > (double)kCellCap) cap = (double)kCellCap;
+  return (uint32_t)cap;
+}
 
-int derive(const cuba_params *p, Derived &d) {
+int derive(const cuba_params *p, int64_t n, Derived &d) {
   if (!p) return fail(CUBA_EINVAL, "params is NULL");
   int64_t nc = 1;
   for (int k = 0; k < 3; ++k) {
@@ -117,7 +146,7 @@ int derive(const cuba_params *p, Derived &d) {
   d.n_cells = nc;
   if (p->cell_capacity < 0 || p->cell_capacity > (int32_t)kCellCap)
     return fail(CUBA_EINVAL, "cell_capacity must be in [0, " + std::to_string(kCellCap) + "]");
-  d.cap = p->cell_capacity == 0 ? kDefaultCellCapacity : (uint32_t)p->cell_capacity;
+  d.cap = p->cell_capacity == 0 ? default_capacity(n, nc) : (uint32_t)p->cell_capacity;
   if ((size_t)nc * d.cap >= ((size_t)1 << 40))
     return fail(CUBA_EINVAL, "cells x cell_capacity too large");
   return CUBA_OK;
@@ -200,6 +229,7 @@ struct cuba_ctx {
   DevStatus *status;
   Cells buf[2];
   int cur;
+  OverflowPool pool;
   uint32_t *offsets, *tile_sums;
   double *cell_sums;
   DeviceConsts *consts;  // in the workspace
@@ -277,7 +307,7 @@ int apply_dt(cuba_ctx *c, double dt) {
 }
 
 StepDevice step_device(const cuba_ctx *c) {
-  return StepDevice{&c->consts->g, over_span(c->over, c->lanes, c->d.n_cells)};
+  return StepDevice{&c->consts->g, c->pool, over_span(c->over, c->lanes, c->d.n_cells)};
 }
 
 // nsteps steps: stream + bin into the other buffer, then nsteps - 1 fused
@@ -292,8 +322,7 @@ int run_steps(cuba_ctx *c, int32_t nsteps, const TraceArgs *trace_in) {
   const SideStream *side = nullptr;
   stage(c, kStageBin, [&] {
     launch_stream_bin(c->buf[c->cur], c->buf[c->cur ^ 1], c->d.n_cells, c->lanes, c->d.g,
-                      c->status,
-                      trace_in ? trace_in->cell : nullptr, c->stream);
+                      c->status, trace_in ? trace_in->cell : nullptr, c->pool, c->stream);
   });
   c->cur ^= 1;
   for (int32_t s = 1; s < nsteps; ++s) {
@@ -328,8 +357,8 @@ extern "C" {
 
 size_t cuba_workspace_bytes(const cuba_params *params, int64_t n) {
   Derived d;
-  if (derive(params, d) != CUBA_OK || n < 0 || n >= 0xFFFFFFFFll) return 0;
-  return make_layout(d.n_cells, d.cap).total;
+  if (n < 0 || n >= 0xFFFFFFFFll || derive(params, n, d) != CUBA_OK) return 0;
+  return make_layout(d.n_cells, d.cap, n).total;
 }
 
 }  // extern "C"
@@ -341,9 +370,9 @@ namespace {
 int check_init_args(const cuba_params *params, int64_t n, const double *x, const double *y,
                     const double *z, const double *px, const double *py, const double *pz,
                     Derived &d) {
-  const int rc = derive(params, d);
-  if (rc != CUBA_OK) return rc;
   if (n < 0 || n >= 0xFFFFFFFFll) return fail(CUBA_EINVAL, "n must be in [0, 2^32 - 1)");
+  const int rc = derive(params, n, d);
+  if (rc != CUBA_OK) return rc;
   if (n > 0 && !(x && y && z && px && py && pz))
     return fail(CUBA_EINVAL, "particle arrays must not be NULL");
   return CUBA_OK;
@@ -359,7 +388,7 @@ int init_context(cuba_ctx *c, const Derived &d, const cuba_params *params, int64
   if (!workspace) return fail(CUBA_EINVAL, "workspace is NULL");
   if (((uintptr_t)workspace & 255u) != 0)
     return fail(CUBA_EINVAL, "workspace must be 256-byte aligned");
-  const Layout L = make_layout(d.n_cells, d.cap);
+  const Layout L = make_layout(d.n_cells, d.cap, n);
   if (ws_bytes < L.total)
     return fail(CUBA_ENOMEM, "workspace too small: need " + std::to_string(L.total) +
                                  " bytes, got " + std::to_string(ws_bytes));
@@ -386,14 +415,35 @@ int init_context(cuba_ctx *c, const Derived &d, const cuba_params *params, int64
     st.id = (uint32_t *)(ws + L.soa[b][6]);
     c->buf[b].count = (uint32_t *)(ws + L.count[b]);
     c->buf[b].cap = d.cap;
+    c->buf[b].sp = (SpillDesc *)(ws + L.spill_desc[b]);
   }
+  SpillDesc hsd[2];
+  for (int b = 0; b < 2; ++b) {
+    SoA &st = hsd[b].st;
+    st.x = (double *)(ws + L.spill_soa[b][0]);
+    st.y = (double *)(ws + L.spill_soa[b][1]);
+    st.z = (double *)(ws + L.spill_soa[b][2]);
+    st.px = (double *)(ws + L.spill_soa[b][3]);
+    st.py = (double *)(ws + L.spill_soa[b][4]);
+    st.pz = (double *)(ws + L.spill_soa[b][5]);
+    st.id = (uint32_t *)(ws + L.spill_soa[b][6]);
+    hsd[b].cell = (uint32_t *)(ws + L.spill_cell[b]);
+    hsd[b].ocell = (uint32_t *)(ws + L.spill_ocell[b]);
+    hsd[b].hdr = (uint32_t *)(ws + L.spill_hdr[b]);
+    hsd[b].capacity = n > 0 ? (uint32_t)n : 1u;
+    hsd[b].pad = 0;
+  }
+  c->pool.buf = (uint32_t *)(ws + L.pool);
+  c->pool.hdr = (unsigned long long *)(ws + L.pool_hdr);
+  c->pool.capacity = L.pool_words;
   // the kernels derive one buffer's arrays from the other's by a single
   // byte distance: every array of buffer 1 lies that far from its twin
   const ptrdiff_t shift = (char *)c->buf[1].st.x - (char *)c->buf[0].st.x;
   for (int a = 0; a < 7; ++a)
     if ((ptrdiff_t)(L.soa[1][a] - L.soa[0][a]) != shift)
       return fail(CUBA_EINVAL, "internal: buffers not laid out alike");
-  if ((ptrdiff_t)(L.count[1] - L.count[0]) != shift)
+  if ((ptrdiff_t)(L.count[1] - L.count[0]) != shift ||
+      (ptrdiff_t)(L.spill_desc[1] - L.spill_desc[0]) != shift)
     return fail(CUBA_EINVAL, "internal: buffers not laid out alike");
   c->offsets = (uint32_t *)(ws + L.offsets);
   c->tile_sums = (uint32_t *)(ws + L.tile_sums);
@@ -408,7 +458,14 @@ int init_context(cuba_ctx *c, const Derived &d, const cuba_params *params, int64
                   c->stream);
   launch_fill_u32(c->buf[0].count, 0u, d.n_cells, c->stream);
   launch_fill_u32(c->buf[1].count, 0u, d.n_cells, c->stream);
+  for (int b = 0; b < 2; ++b) launch_fill_u32(hsd[b].hdr, 0u, kSpillHdrWords, c->stream);
+  launch_fill_u32((uint32_t *)c->pool.hdr, 0u, 4, c->stream);
   hipError_t e = hipMemcpyAsync(c->consts, &hc, sizeof(hc), hipMemcpyHostToDevice, c->stream);
+  // each buffer's descriptor sits in that buffer's region (one buffer's
+  // distance apart), so each is written on its own
+  for (int b = 0; b < 2 && e == hipSuccess; ++b)
+    e = hipMemcpyAsync(c->buf[b].sp, &hsd[b], sizeof(SpillDesc), hipMemcpyHostToDevice,
+                       c->stream);
   if (e != hipSuccess) return hip_fail(e, "init constants");
   launch_init_bin(x, y, z, px, py, pz, c->buf[0], n, d.g, c->status, c->stream);
   launch_occupancy_over(c->buf[0], d.n_cells, c->status, c->stream);
@@ -416,17 +473,22 @@ int init_context(cuba_ctx *c, const Derived &d, const cuba_params *params, int64
   if (rc != CUBA_OK) return rc;
   uint32_t head[5] = {0, 0, 0, 0, 0};  // err, over[4]
   static_assert(offsetof(DevStatus, over) == sizeof(uint32_t), "status layout");
+  SpillDesc back[2];
   e = hipMemcpyAsync(head, &c->status->err, sizeof(head), hipMemcpyDeviceToHost, c->stream);
+  for (int b = 0; b < 2 && e == hipSuccess; ++b)
+    e = hipMemcpyAsync(&back[b], c->buf[b].sp, sizeof(SpillDesc), hipMemcpyDeviceToHost,
+                       c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(e, "init check");
+  for (int b = 0; b < 2; ++b)
+    if (std::memcmp(&back[b], &hsd[b], sizeof(SpillDesc)) != 0)
+      return fail(CUBA_EDEVICE, "internal: spill descriptor not in place");
   const uint32_t err = head[0];
   for (int k = 0; k < 4; ++k) c->over[k] = head[1 + k];
   c->lanes = default_lanes(c->over, d.n_cells, true);
   if (err & kErrRange)
     return fail(CUBA_ERANGE, "a particle is outside [0, L], non-finite, or has |p| = 0");
-  if (err & kErrCapacity)
-    return fail(CUBA_ERANGE, "a cell holds more particles than cell_capacity (" +
-                                 std::to_string(d.cap) + ")");
+  if (err & kErrSpill) return fail(CUBA_EDEVICE, "internal: spill region inconsistent");
   return CUBA_OK;
 }
 
@@ -497,7 +559,7 @@ int cuba_init_static(cuba_ctx **out, const cuba_params *params, int64_t n, const
   Derived d;
   int rc = check_init_args(params, n, x, y, z, px, py, pz, d);
   if (rc != CUBA_OK) return rc;
-  const size_t need = make_layout(d.n_cells, d.cap).total;
+  const size_t need = make_layout(d.n_cells, d.cap, n).total;
   if (need > kStaticWorkspaceBytes)
     return fail(CUBA_ENOMEM, "static workspace too small: need " + std::to_string(need) +
                                  " bytes, the library holds " +
@@ -606,10 +668,12 @@ int cuba_sync(cuba_ctx *c) {
     launch_fill_u32(&c->status->err, 0u, 1, c->stream);
     e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "sync reset");
-    if (err & kErrCapacity)
-      return fail(CUBA_ERANGE, "a cell received more particles than cell_capacity (" +
-                                   std::to_string(c->d.cap) +
-                                   "); the surplus particles were dropped");
+    if (err & kErrPairIndex)
+      return fail(CUBA_ERANGE, "a cell holds more than " + std::to_string(kMaxPairIndexCell) +
+                                   " particles: its pair indices exceed the 32-bit counter "
+                                   "word of the random-number contract (its collisions "
+                                   "were skipped)");
+    if (err & kErrSpill) return fail(CUBA_EDEVICE, "internal: spill region inconsistent");
     if (err & kErrTrace) return fail(CUBA_ENOMEM, "trace buffer too small");
     return fail(CUBA_ERANGE, "device reported an invalid state");
   }
@@ -784,6 +848,7 @@ int upload_table(cuba_batch *b) {
     e.g = c->d.g;
     e.pa = c->pa;
     e.status = c->status;
+    e.pool = c->pool;
     e.n_cells = (uint32_t)c->d.n_cells;
     e.cpi = (uint32_t)b->slot_cpi[s];
     e.cur = (uint32_t)c->cur;

@@ -176,6 +176,27 @@ __device__ __forceinline__ void pair_of_index(uint32_t k, uint32_t n, uint32_t &
   b = k - row_start(aa, n) + aa + 1u;
 }
 
+// The same map for cells of any size up to the 32-bit pair-index limit,
+// in 64-bit integer arithmetic (n (2n - a - 1) exceeds 32 bits above
+// 46 341 members).
+__device__ __forceinline__ uint64_t row_start64(uint64_t a, uint64_t n) {
+  return a * (2u * n - a - 1u) / 2u;
+}
+
+__device__ __forceinline__ void pair_of_index64(uint64_t k, uint64_t n, uint32_t &a,
+                                                uint32_t &b) {
+  const double m = 2.0 * (double)n - 1.0;
+  const double r = (m - __builtin_sqrt(m * m - 8.0 * (double)k)) * 0.5;
+  int64_t ai = (int64_t)r;
+  ai = ai < 0 ? 0 : ai;
+  ai = ai > (int64_t)n - 2 ? (int64_t)n - 2 : ai;
+  uint64_t aa = (uint64_t)ai;
+  while (aa > 0 && row_start64(aa, n) > k) --aa;
+  while (aa + 1 <= n - 2 && row_start64(aa + 1, n) <= k) ++aa;
+  a = (uint32_t)aa;
+  b = (uint32_t)(k - row_start64(aa, n) + aa + 1u);
+}
+
 // ---------------------------------------------------------------------------
 // Eq. (3): the pair's acceptance probability P22 = K s / (2 E1 E2).
 // ---------------------------------------------------------------------------

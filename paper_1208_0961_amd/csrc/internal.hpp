@@ -15,9 +15,17 @@ constexpr uint32_t kSmallCap = 512;  // cell kernels with half the LDS
 constexpr uint32_t kScanTile = 2048; // counts per scan tile
 
 // Device-side error bits, accumulated until the next cuba_sync.
-constexpr uint32_t kErrCapacity = 1u;  // a cell received more than its capacity
-constexpr uint32_t kErrTrace = 2u;     // trace buffer too small
-constexpr uint32_t kErrRange = 4u;     // invalid initial particle
+constexpr uint32_t kErrSpill = 1u;      // internal: the spill region filled (cannot happen:
+                                        // it holds every particle of the context)
+constexpr uint32_t kErrTrace = 2u;      // trace buffer too small
+constexpr uint32_t kErrRange = 4u;      // invalid initial particle
+constexpr uint32_t kErrPairIndex = 8u;  // a cell too full for the 32-bit pair index
+                                        // (its collisions were skipped)
+
+// Most particles a cell may hold: its pair indices k < n (n - 1) / 2 must
+// fit the 32-bit counter word of the random-number contract (they do up to
+// 92 682; the bound is kept one lower, where the oracle puts it).
+constexpr uint32_t kMaxPairIndexCell = 92681u;
 
 // Structure-of-arrays particle state (FP64 position and momentum, u32 id).
 struct SoA {
@@ -25,13 +33,42 @@ struct SoA {
   uint32_t *id;
 };
 
+// Where a buffer keeps the particles its cells could not hold: cell c owns
+// slots [c cap, c cap + min(count[c], cap)) of the buffer's arrays; a cell
+// that receives more (count[c] > cap, an overflowing cell) keeps the surplus
+// here, each entry tagged with its cell, and is listed once in ocell.  The
+// region holds every particle of the context, so no binning can lose one.
+// In device memory beside the buffer's arrays (the kernels load it only on
+// the rare paths that touch it).
+struct SpillDesc {
+  SoA st;          // spilled particles, capacity `capacity`
+  uint32_t *cell;  // the cell of each spilled particle
+  uint32_t *ocell; // the overflowing cells, in the order they overflowed
+  uint32_t *hdr;   // [0] spilled particles, [1] overflowing cells
+  uint32_t capacity;
+  uint32_t pad;
+};
+constexpr uint32_t kSpillHdrWords = 4;
+
 // A binned state with a fixed capacity per cell: cell c owns slots
-// [c cap, c cap + count[c]) of every array (count may exceed cap only after
-// an overflow, which is flagged; readers clamp it).
+// [c cap, c cap + min(count[c], cap)) of every array, count[c] being the
+// number of particles the cell holds; any beyond cap are in the spill
+// region (sp).
 struct Cells {
   SoA st;
   uint32_t *count;
   uint32_t cap;
+  SpillDesc *sp;
+};
+
+// Scratch of the overflow kernel (one per context, used by one launch at a
+// time): member lists, canonical orders and claims of the overflowing cells
+// it steps, allocated from `buf` by a counter; hdr[0] the counter, hdr[1]
+// the count of workgroups that finished the launch.
+struct OverflowPool {
+  uint32_t *buf;
+  unsigned long long *hdr;
+  uint64_t capacity;  // u32 words
 };
 
 // Device-resident bookkeeping at the head of the workspace.  The work
@@ -71,6 +108,7 @@ struct BatchEvent {
   Geometry g;
   PairArgs pa;
   DevStatus *status;
+  OverflowPool pool;
   uint32_t n_cells;
   uint32_t cpi;         // cells per work item
   uint32_t item_begin;  // first work item of this event
@@ -121,15 +159,19 @@ void launch_init_bin(const double *x, const double *y, const double *z,
                      const double *px, const double *py, const double *pz,
                      const Cells &dst, int64_t n, const Geometry &g, DevStatus *st,
                      hipStream_t s);
+// Stream + bin every particle of src into dst: the block parts by the
+// stream-bin kernel, then the spilled ones by the overflow kernel (which
+// then resets src's spill region and pool).
 void launch_stream_bin(const Cells &src, const Cells &dst, int64_t n_cells, uint32_t lanes,
                        const Geometry &g, DevStatus *status, uint32_t *trace_cell,
-                       hipStream_t s);
+                       const OverflowPool &pool, hipStream_t s);
 void launch_offsets(const Cells &cur, uint32_t *offsets, uint32_t *tile_sums,
                     int64_t n_cells, hipStream_t s);
 // Device copy of the geometry, which the wave-per-cell kernel reads from
 // memory where it uses it.
 struct StepDevice {
   const Geometry *g;
+  OverflowPool pool;  // scratch of the overflow kernel
   // cells per wave of the oversize-cell kernel: 64 (a wave scans 64 cells
   // and steps the oversize ones one after another; few oversize cells) or 1
   // (a wave per cell; many)
@@ -139,6 +181,7 @@ struct StepDevice {
 // One collision launch (fused: then streaming + binning of the next step).
 // lanes > 0: the small-cell kernel on s and, concurrently on side (if not
 // NULL; else after it on s), the kernel for the cells it leaves alone.
+// Then, on s, the overflow kernel for the overflowing cells.
 // dev: device copy of g (equal to the host value).  The buffers src and
 // dst must be laid out alike (every array at the same distance from its twin).
 void launch_step(const Cells &src, const Cells &dst, bool fused, int64_t n_cells,

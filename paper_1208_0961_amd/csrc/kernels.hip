@@ -56,6 +56,7 @@ struct GCells {
   GSoA st;
   gptr<uint32_t> count;
   uint32_t cap;
+  SpillDesc *sp;
 };
 
 __device__ __forceinline__ GCells to_global(const Cells &c) {
@@ -69,6 +70,7 @@ __device__ __forceinline__ GCells to_global(const Cells &c) {
   g.st.id = (gptr<uint32_t>)c.st.id;
   g.count = (gptr<uint32_t>)c.count;
   g.cap = c.cap;
+  g.sp = c.sp;
   return g;
 }
 
@@ -121,8 +123,33 @@ __device__ __forceinline__ uint32_t xcd_runs(uint32_t b, uint32_t nblocks) {
   return s * kSuper + (r % kXcds) * kRun + r / kXcds;
 }
 
-// Appends particle (r, p, id) to cell c2 of dst; slots past the capacity
-// are dropped and flagged (reported as CUBA_ERANGE at the next sync).
+// A particle that took slot `slot` >= cap of cell c2 goes to dst's spill
+// region, tagged with its cell; the one particle that takes slot cap lists
+// the cell among the overflowing ones.  The region holds every particle of
+// the context, so the index check only guards against an internal error.
+__device__ __forceinline__ void spill_particle(const GCells &dst, uint32_t c2, uint32_t slot,
+                                               double x, double y, double z, double px,
+                                               double py, double pz, uint32_t id,
+                                               DevStatus *status) {
+  SpillDesc *const sp = dst.sp;
+  const uint32_t i = atomicAdd(&sp->hdr[0], 1u);
+  if (i < sp->capacity) {
+    sp->st.x[i] = x;
+    sp->st.y[i] = y;
+    sp->st.z[i] = z;
+    sp->st.px[i] = px;
+    sp->st.py[i] = py;
+    sp->st.pz[i] = pz;
+    sp->st.id[i] = id;
+    sp->cell[i] = c2;
+  } else {
+    atomicOr(&status->err, kErrSpill);
+  }
+  if (slot == dst.cap) sp->ocell[atomicAdd(&sp->hdr[1], 1u)] = c2;
+}
+
+// Appends particle (r, p, id) to cell c2 of dst: into the cell's block, or
+// past its capacity into the spill region.
 __device__ __forceinline__ void append(const GCells &dst, uint32_t c2, bool active,
                                        double x, double y, double z, double px,
                                        double py, double pz, uint32_t id,
@@ -139,7 +166,7 @@ __device__ __forceinline__ void append(const GCells &dst, uint32_t c2, bool acti
       dst.st.pz[o] = pz;
       dst.st.id[o] = id;
     } else {
-      atomicOr(&status->err, kErrCapacity);
+      spill_particle(dst, c2, slot, x, y, z, px, py, pz, id, status);
     }
   }
 }
@@ -161,6 +188,7 @@ __device__ __forceinline__ GCells shifted(const GCells &c, int64_t shift) {
   d.st.id = shift_ptr(c.st.id, shift);
   d.count = shift_ptr(c.count, shift);
   d.cap = c.cap;
+  d.sp = (SpillDesc *)((char *)c.sp + shift);
   return d;
 }
 
@@ -186,7 +214,7 @@ __device__ __forceinline__ void store_particle(const GCells &dst, uint32_t c2, u
     dst.st.pz[o] = q.pz;
     dst.st.id[o] = q.id;
   } else {
-    atomicOr(&status->err, kErrCapacity);
+    spill_particle(dst, c2, slot, q.x, q.y, q.z, q.px, q.py, q.pz, q.id, status);
   }
 }
 
@@ -237,6 +265,7 @@ __device__ __forceinline__ void append_two(const GCells &dst, uint32_t ca, bool 
   if (act_b) store_particle(dst, cb, (sel_b ? b1 : b0) + rank_b, qb, status);
 }
 
+// Particles of a cell held in its block (the rest, if any, are spilled).
 __device__ __forceinline__ uint32_t occupancy(const GCells &c, uint32_t cell) {
   const uint32_t n = c.count[cell];
   return n < c.cap ? n : c.cap;
@@ -292,7 +321,7 @@ __global__ __launch_bounds__(kBlock) void k_occupancy_over(Cells cur_arg, uint32
   uint32_t acc[4] = {0u, 0u, 0u, 0u};
   for (uint32_t c0 = blockIdx.x * kBlock; c0 < n_cells; c0 += gridDim.x * kBlock) {
     const uint32_t c = c0 + threadIdx.x;
-    const uint32_t n = c < n_cells ? occupancy(cur, c) : 0u;
+    const uint32_t n = c < n_cells ? cur.count[c] : 0u;
 #pragma unroll
     for (uint32_t k = 0; k < 4; ++k) acc[k] += (uint32_t)__popcll(__ballot(n > (8u << k)));
   }
@@ -398,7 +427,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(Cells cur_arg,
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int64_t idx = base + j;
-    const uint32_t cnt = idx < n_cells ? occupancy(cur, (uint32_t)idx) : 0u;
+    const uint32_t cnt = idx < n_cells ? cur.count[idx] : 0u;
     v[j] = sum;
     sum += cnt;
   }
@@ -654,7 +683,11 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
   cv.c = c;
   cv.t = t;
   cv.base = (size_t)cv.c * src.cap;
-  cv.n = occupancy(src, cv.c);
+  // an overflowing cell (some members spilled) is stepped by the overflow
+  // kernel, which also clears its count
+  const uint32_t cnt = src.count[cv.c];
+  const bool overflowing = cnt > src.cap;
+  cv.n = overflowing ? 0u : cnt;
   const uint32_t n = cv.n;
   const GSoA &st = src.st;
 
@@ -877,7 +910,7 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
       }
       append(dst, c2, active, x, y, z, px, py, pz, id, status);
     }
-    if (tid == 0) src.count[cv.c] = 0u;
+    if (tid == 0 && !overflowing) src.count[cv.c] = 0u;
   }
 }
 
@@ -923,8 +956,11 @@ __device__ __forceinline__ uint64_t small_cells_step(const GCells &src, const GC
   const uint32_t grp = lane / G, gl = lane % G;
   const uint32_t c = c0 + grp;
   const bool in_range = c < c_end;
-  const uint32_t n = in_range ? occupancy(src, c) : 0u;
-  const bool small = in_range && n <= G;
+  // overflowing cells are left to the overflow kernel
+  const uint32_t cnt = in_range ? src.count[c] : 0u;
+  const bool overflowing = cnt > src.cap;
+  const uint32_t n = overflowing ? 0u : cnt;
+  const bool small = in_range && !overflowing && n <= G;
   const bool mine = small && gl < n;
   const size_t o = (size_t)c * src.cap + gl;
   __syncthreads();  // a previous call's readers of lds are done
@@ -1074,7 +1110,7 @@ __device__ __forceinline__ uint64_t small_cells_step(const GCells &src, const GC
     append(dst, c2, mine, x, y, z, px, py, pz, id, status);
     if (small && gl == 0) src.count[c] = 0u;
   }
-  return __ballot(in_range && !small && gl == 0);
+  return __ballot(in_range && !small && !overflowing && gl == 0);
 }
 
 // The cells among c0 .. c_end - 1 (at most 64) holding more than `lanes`
@@ -1175,6 +1211,352 @@ __global__ __launch_bounds__(128) void k_step2(Cells src_arg, int64_t dst_shift,
   cell_step<kFused, false, kCap, 2>(src, shifted(src, dst_shift),
                                     xcd_runs<8>(blockIdx.x, gridDim.x), t, pa, *gp, status,
                                     TraceArgs{}, lds, &x2);
+}
+
+
+// ---------------------------------------------------------------------------
+// Overflowing cells.  A cell that receives more particles than its block
+// holds keeps the surplus in the buffer's spill region.  The main kernels
+// leave such cells alone (the stream-bin kernel streams their block part);
+// this kernel, launched after them, does the rest:
+//   kOvStream   stream + reflect + bin the spilled particles;
+//   kOvCollide  the collisions of every overflowing cell, in place;
+//   kOvFused    the collisions, then stream + bin every member.
+// A workgroup steps one overflowing cell at a time with a method that holds
+// for any cell size: members found by a scan of the spill list, canonical
+// order by counting smaller ids, pair tests in rounds of kOvRound
+// consecutive pair indices (Philox w1 filter, then Eq. (3)), the round's
+// accepted pairs claimed in pair order by one lane, and the kinematics of
+// the claimed pairs.  The only bound is the 32-bit pair index of the
+// random-number contract.  The last workgroup to finish resets the scratch
+// pool and, when the source buffer is consumed, its spill region.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kOvBlock = 256;
+constexpr uint32_t kOvWaves = kOvBlock / 64;
+constexpr uint32_t kOvRound = 4096;                 // pairs per claim round
+constexpr uint32_t kOvPerWave = kOvRound / kOvWaves;  // 16 rows of 64 per wave
+enum : uint32_t { kOvStream = 0, kOvCollide = 1, kOvFused = 2 };
+
+struct OverflowLds {
+  uint32_t claimed[(kMaxPairIndexCell + 31) / 32];  // by canonical index
+  uint32_t buf[kOvRound];  // ids while ranking; accepted pairs of a round
+  uint32_t wave_n[kOvWaves];
+  uint64_t pool_base;
+  uint32_t found, nclaim, skip;
+};
+
+__device__ __forceinline__ GSoA to_gsoa(const SoA &a) {
+  GSoA g;
+  g.x = (gptr<double>)a.x;
+  g.y = (gptr<double>)a.y;
+  g.z = (gptr<double>)a.z;
+  g.px = (gptr<double>)a.px;
+  g.py = (gptr<double>)a.py;
+  g.pz = (gptr<double>)a.pz;
+  g.id = (gptr<uint32_t>)a.id;
+  return g;
+}
+
+// Member j of an overflowing cell: slot j of its block (j < cap) or spill
+// entry mem[j - cap].
+struct Members {
+  GSoA blk, spl;
+  size_t base;
+  uint32_t cap;
+  const uint32_t *mem;
+  __device__ __forceinline__ bool spilled(uint32_t j) const { return j >= cap; }
+  __device__ __forceinline__ size_t at(uint32_t j) const {
+    return j < cap ? base + j : (size_t)mem[j - cap];
+  }
+  // (the array of each field is selected on its own, so that no view is
+  // indexed dynamically)
+  __device__ __forceinline__ uint32_t id(uint32_t j) const {
+    const bool s = spilled(j);
+    return (s ? spl.id : blk.id)[at(j)];
+  }
+  __device__ __forceinline__ Particle load(uint32_t j) const {
+    const bool s = spilled(j);
+    const size_t o = at(j);
+    return Particle{(s ? spl.x : blk.x)[o],   (s ? spl.y : blk.y)[o],
+                    (s ? spl.z : blk.z)[o],   (s ? spl.px : blk.px)[o],
+                    (s ? spl.py : blk.py)[o], (s ? spl.pz : blk.pz)[o],
+                    (s ? spl.id : blk.id)[o]};
+  }
+  __device__ __forceinline__ void momentum(uint32_t j, double &px, double &py,
+                                           double &pz) const {
+    const bool s = spilled(j);
+    const size_t o = at(j);
+    px = (s ? spl.px : blk.px)[o];
+    py = (s ? spl.py : blk.py)[o];
+    pz = (s ? spl.pz : blk.pz)[o];
+  }
+  __device__ __forceinline__ void set_momentum(uint32_t j, double px, double py,
+                                               double pz) const {
+    const bool s = spilled(j);
+    const size_t o = at(j);
+    (s ? spl.px : blk.px)[o] = px;
+    (s ? spl.py : blk.py)[o] = py;
+    (s ? spl.pz : blk.pz)[o] = pz;
+  }
+};
+
+// The collisions of overflowing cell c of src at step t by the calling
+// workgroup; kFused: then stream + bin its members into dst and clear its
+// count.
+template <bool kFused, bool kTrace>
+__device__ void overflow_cell(const GCells &src, const GCells &dst, uint32_t c, uint32_t t,
+                              const PairArgs &pa, const Geometry &g, DevStatus *status,
+                              const TraceArgs &tr, const OverflowPool &pool,
+                              OverflowLds &lds) {
+  const uint32_t tid = threadIdx.x, lane = lane_id(), wv = tid / 64;
+  const uint64_t below = (1ull << lane) - 1ull;
+  const SpillDesc *const sd = src.sp;
+  const uint32_t n = src.count[c];
+  const uint32_t cap = src.cap;
+  const uint32_t nsp = n - cap;  // > 0: the cell overflowed
+  const uint32_t ns = min(sd->hdr[0], sd->capacity);
+  Members m;
+  m.blk = src.st;
+  m.spl = to_gsoa(sd->st);
+  m.base = (size_t)c * cap;
+  m.cap = cap;
+  __syncthreads();  // the previous cell's readers of lds are done
+  if (tid == 0) {
+    // scratch: the spilled members' indices, the canonical order, the claims
+    const uint64_t need = (uint64_t)nsp + n + n / 2u + 1u;
+    const uint64_t b = atomicAdd(&pool.hdr[0], (unsigned long long)need);
+    lds.skip = b + need > pool.capacity ? 1u : 0u;
+    if (lds.skip) atomicOr(&status->err, kErrSpill);
+    lds.pool_base = b;
+    lds.found = 0u;
+    lds.nclaim = 0u;
+  }
+  __syncthreads();
+  if (lds.skip) return;
+  uint32_t *const mem = pool.buf + lds.pool_base;
+  uint32_t *const perm = mem + nsp;
+  uint32_t *const claims = perm + n;
+  m.mem = mem;
+
+  // the spilled members (found in arbitrary order; the ranks fix the order)
+  for (uint32_t i0 = wv * 64u; i0 < ns; i0 += kOvBlock) {
+    const uint32_t i = i0 + lane;
+    const bool hit = i < ns && sd->cell[i] == c;
+    const uint64_t mk = __ballot(hit);
+    if (mk != 0) {
+      uint32_t at = 0;
+      if (lane == 0) at = atomicAdd(&lds.found, (uint32_t)__popcll(mk));
+      at = (uint32_t)__shfl((int)at, 0);
+      const uint32_t slot = at + (uint32_t)__popcll(mk & below);
+      if (hit && slot < nsp) mem[slot] = i;
+    }
+  }
+  __syncthreads();
+  if (lds.found != nsp) {  // internal inconsistency: leave the cell as it is
+    if (tid == 0) atomicOr(&status->err, kErrSpill);
+    return;
+  }
+
+  // canonical order: the rank of each member's id among the cell's ids,
+  // counted against chunks of ids staged in LDS (not needed by a cell too
+  // full for the pair index, whose collisions are skipped)
+  const bool too_big = n > kMaxPairIndexCell;
+  for (uint32_t j0 = 0; !too_big && j0 < n; j0 += kOvBlock) {
+    const uint32_t j = j0 + tid;
+    const uint32_t me = j < n ? m.id(j) : 0xFFFFFFFFu;
+    uint32_t r = 0;
+    for (uint32_t i0 = 0; i0 < n; i0 += kOvRound) {
+      const uint32_t cnt = min(kOvRound, n - i0);
+      __syncthreads();
+      for (uint32_t i = tid; i < cnt; i += kOvBlock) lds.buf[i] = m.id(i0 + i);
+      __syncthreads();
+      if (j < n)
+        for (uint32_t i = 0; i < cnt; ++i) r += lds.buf[i] < me ? 1u : 0u;
+    }
+    if (j < n) {
+      perm[r] = j;
+      if (kTrace && tr.perm) tr.perm[tr.offsets[c] + r] = me;
+    }
+  }
+
+  // pair tests in rounds: wave w tests the round's w-th quarter and
+  // compacts its accepted pairs in increasing k; one lane then claims the
+  // round's pairs in pair order
+  const uint64_t npairs = too_big ? 0u : (uint64_t)n * (n - 1u) / 2u;
+  if (too_big && tid == 0) atomicOr(&status->err, kErrPairIndex);
+  const uint32_t words = too_big ? 0u : (n + 31u) / 32u;
+  for (uint32_t w = tid; w < words; w += kOvBlock) lds.claimed[w] = 0u;
+  __syncthreads();
+  uint32_t n_acc = 0;
+  if (pa.any) {
+    for (uint64_t r0 = 0; r0 < npairs; r0 += kOvRound) {
+      uint32_t nw = 0;
+      const uint64_t kb = r0 + (uint64_t)wv * kOvPerWave;
+      for (uint32_t it = 0; it < kOvPerWave; it += 64u) {
+        const uint64_t k = kb + it + lane;
+        bool acc = false;
+        if (k < npairs) {
+          const uint32_t k32 = (uint32_t)k;
+          if (philox10_w1(k32, c, t, 0u, pa.key0, pa.key1) <= pa.w1_max) {
+            const Words4 w = philox10(k32, c, t, 0u, pa.key0, pa.key1);
+            uint32_t a, b;
+            pair_of_index64(k, n, a, b);
+            double ax, ay, az, bx, by, bz;
+            m.momentum(perm[a], ax, ay, az);
+            m.momentum(perm[b], bx, by, bz);
+            acc = uniform53(w.w0, w.w1) < p22(ax, ay, az, bx, by, bz, pa.kfac);
+            if (kTrace && acc && tr.cand) {
+              const uint32_t slot = atomicAdd(&tr.counts[0], 1u);
+              if (slot < tr.cand_cap) {
+                tr.cand[3 * (size_t)slot + 0] = c;
+                tr.cand[3 * (size_t)slot + 1] = a;
+                tr.cand[3 * (size_t)slot + 2] = b;
+              } else {
+                atomicOr(&status->err, kErrTrace);
+              }
+            }
+          }
+        }
+        n_acc += acc ? 1u : 0u;
+        const uint64_t mk = __ballot(acc);
+        if (acc) lds.buf[wv * kOvPerWave + nw + (uint32_t)__popcll(mk & below)] = (uint32_t)k;
+        nw += (uint32_t)__popcll(mk);
+      }
+      if (lane == 0) lds.wave_n[wv] = nw;
+      __syncthreads();
+      if (tid == 0) {
+        uint32_t nc = lds.nclaim;
+        for (uint32_t q = 0; q < kOvWaves; ++q)
+          for (uint32_t i = 0; i < lds.wave_n[q]; ++i) {
+            const uint32_t k = lds.buf[q * kOvPerWave + i];
+            uint32_t a, b;
+            pair_of_index64(k, n, a, b);
+            const uint32_t ma = 1u << (a & 31u), mb = 1u << (b & 31u);
+            if ((lds.claimed[a >> 5] & ma) == 0u && (lds.claimed[b >> 5] & mb) == 0u) {
+              lds.claimed[a >> 5] |= ma;
+              lds.claimed[b >> 5] |= mb;
+              claims[nc++] = k;
+            }
+          }
+        lds.nclaim = nc;
+      }
+      __syncthreads();
+    }
+  }
+
+  // kinematics of the claimed pairs (disjoint members), in place
+  const uint32_t nclaim = lds.nclaim;
+  for (uint32_t i = tid; i < nclaim; i += kOvBlock) {
+    const uint32_t k = claims[i];
+    uint32_t a, b;
+    pair_of_index64(k, n, a, b);
+    const Words4 w = philox10(k, c, t, 1u, pa.key0, pa.key1);
+    const uint32_t ja = perm[a], jb = perm[b];
+    double ax, ay, az, bx, by, bz;
+    m.momentum(ja, ax, ay, az);
+    m.momentum(jb, bx, by, bz);
+    scatter_pair(ax, ay, az, bx, by, bz, uniform53(w.w0, w.w1), uniform53(w.w2, w.w3));
+    m.set_momentum(ja, ax, ay, az);
+    m.set_momentum(jb, bx, by, bz);
+    if (kTrace && tr.claim) {
+      const uint32_t slot = atomicAdd(&tr.counts[1], 1u);
+      if (slot < tr.claim_cap) {
+        tr.claim[3 * (size_t)slot + 0] = c;
+        tr.claim[3 * (size_t)slot + 1] = a;
+        tr.claim[3 * (size_t)slot + 2] = b;
+      } else {
+        atomicOr(&status->err, kErrTrace);
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) n_acc += __shfl_down(n_acc, o);
+  const uint32_t slot = c % kCounterSlots;
+  if (lane == 0 && n_acc != 0) atomicAdd(&status->cand[slot], (unsigned long long)n_acc);
+  if (tid == 0) {
+    atomicAdd(&status->pairs[slot], (unsigned long long)npairs);
+    atomicAdd(&status->claims[slot], (unsigned long long)nclaim);
+  }
+  __syncthreads();  // new momenta visible to the binning lanes
+
+  if (kFused) {
+    const Geometry g_l = g;
+    for (uint32_t j0 = wv * 64u; j0 < n; j0 += kOvBlock) {
+      const uint32_t j = j0 + lane;
+      const bool active = j < n;
+      Particle q{};
+      uint32_t c2 = 0;
+      if (active) {
+        q = m.load(j);
+        advance<true>(g_l, q.x, q.y, q.z, q.px, q.py, q.pz);
+        c2 = cell_id(g_l, q.x, q.y, q.z);
+      }
+      append(dst, c2, active, q.x, q.y, q.z, q.px, q.py, q.pz, q.id, status);
+    }
+    if (tid == 0) src.count[c] = 0u;
+  }
+}
+
+// The overflow work of one launch (see above) by workgroup `group` of
+// n_groups.  trace_cell (kOvStream, may be NULL): new cell of each
+// streamed particle, by id.
+template <uint32_t kMode, bool kTrace>
+__device__ void overflow_work(const GCells &src, const GCells &dst, uint32_t t,
+                              const PairArgs &pa, const Geometry &g, DevStatus *status,
+                              const TraceArgs &tr, const OverflowPool &pool, uint32_t group,
+                              uint32_t n_groups, uint32_t *trace_cell, OverflowLds &lds) {
+  SpillDesc *const sd = src.sp;
+  if (kMode == kOvStream) {
+    const uint32_t ns = min(sd->hdr[0], sd->capacity);
+    const GSoA spl = to_gsoa(sd->st);
+    const uint32_t lane = lane_id(), wv = threadIdx.x / 64u;
+    const Geometry g_l = g;
+    for (uint32_t i0 = group * kOvBlock + wv * 64u; i0 < ns; i0 += n_groups * kOvBlock) {
+      const uint32_t i = i0 + lane;
+      const bool active = i < ns;
+      Particle q{};
+      uint32_t c2 = 0;
+      if (active) {
+        q = load_particle(spl, i);
+        advance<true>(g_l, q.x, q.y, q.z, q.px, q.py, q.pz);
+        c2 = cell_id(g_l, q.x, q.y, q.z);
+        if (trace_cell) trace_cell[q.id] = c2;
+      }
+      append(dst, c2, active, q.x, q.y, q.z, q.px, q.py, q.pz, q.id, status);
+    }
+  } else {
+    const uint32_t nover = sd->hdr[1];
+    for (uint32_t o = group; o < nover; o += n_groups)
+      overflow_cell<kMode == kOvFused, kTrace>(src, dst, sd->ocell[o], t, pa, g, status, tr,
+                                               pool, lds);
+  }
+  // the last workgroup out resets the pool and, if src was consumed, its
+  // spill region (every workgroup has finished reading both)
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned long long done = atomicAdd(&pool.hdr[1], 1ull);
+    if (done == (unsigned long long)n_groups - 1ull) {
+      pool.hdr[0] = 0ull;
+      pool.hdr[1] = 0ull;
+      if (kMode != kOvCollide) {
+        sd->hdr[0] = 0u;
+        sd->hdr[1] = 0u;
+      }
+      __threadfence();
+    }
+  }
+}
+
+template <uint32_t kMode, bool kTrace>
+__global__ __launch_bounds__(kOvBlock) void k_overflow(Cells src_arg, Cells dst_arg, uint32_t t,
+                                                       PairArgs pa, Geometry g,
+                                                       DevStatus *status, TraceArgs tr,
+                                                       OverflowPool pool,
+                                                       uint32_t *trace_cell) {
+  __shared__ OverflowLds lds;
+  overflow_work<kMode, kTrace>(to_global(src_arg), to_global(dst_arg), t, pa, g, status, tr,
+                               pool, blockIdx.x, gridDim.x, trace_cell, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1344,6 +1726,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
                                  pa, E->g, E->status, TraceArgs{}, lds);
 }
 
+
+// The overflow work of every event for launch j of a run (j = 0: the
+// spilled particles of the stream-bin launch): groups_per_event workgroups
+// per event, event e taking workgroups [e g, (e + 1) g).
+template <uint32_t kMode>
+__global__ __launch_bounds__(kOvBlock) void k_batch_overflow(const BatchEvent *__restrict__ ev,
+                                                             uint32_t j,
+                                                             uint32_t groups_per_event) {
+  __shared__ OverflowLds lds;
+  const BatchEvent *__restrict__ E = ev + blockIdx.x / groups_per_event;
+  const EventView v = event_view(E, j);
+  const OverflowPool pool = E->pool;
+  overflow_work<kMode, false>(v.src, v.dst, v.t, v.pa, v.g, v.status, TraceArgs{}, pool,
+                              blockIdx.x % groups_per_event, groups_per_event, nullptr, lds);
+}
+
 // End of a run of k steps: every event moved k buffers and k step indices.
 __global__ void k_batch_advance(BatchEvent *ev, uint32_t n_events, uint32_t k) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1364,6 +1762,7 @@ __global__ __launch_bounds__(kBlock) void k_observe_cells(Cells cur_arg, uint32_
   const uint32_t lane = lane_id();
   const uint32_t c = blockIdx.x * kCellsPerBlock + threadIdx.x / 64;
   if (c >= n_cells) return;
+  const uint32_t cnt = cur.count[c];
   const uint32_t n = occupancy(cur, c);
   const size_t base = (size_t)c * cur.cap;
   double se = 0.0, sp = 0.0, sxx = 0.0;
@@ -1374,6 +1773,18 @@ __global__ __launch_bounds__(kBlock) void k_observe_cells(Cells cur_arg, uint32_
     se += e;
     sp += px;
     sxx += (px * px) / e;
+  }
+  if (cnt > cur.cap) {  // overflowing: its spilled members, in spill order
+    const SpillDesc *const spl = cur.sp;
+    const uint32_t ns = min(spl->hdr[0], spl->capacity);
+    for (uint32_t i = lane; i < ns; i += 64) {
+      if (spl->cell[i] != c) continue;
+      const double px = spl->st.px[i], py = spl->st.py[i], pz = spl->st.pz[i];
+      const double e = norm3(px, py, pz);
+      se += e;
+      sp += px;
+      sxx += (px * px) / e;
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -1386,7 +1797,7 @@ __global__ __launch_bounds__(kBlock) void k_observe_cells(Cells cur_arg, uint32_
     out[0] = se;
     out[1] = sp;
     out[2] = sxx;
-    out[3] = (double)n;
+    out[3] = (double)cnt;
   }
 }
 
@@ -1464,6 +1875,20 @@ __global__ __launch_bounds__(kBlock) void k_gather_by_id(Cells cur_arg, uint32_t
     py[id] = cur.st.py[base + j];
     pz[id] = cur.st.pz[base + j];
   }
+  if (cur.count[c] > cur.cap) {  // overflowing: its spilled members
+    const SpillDesc *const spl = cur.sp;
+    const uint32_t ns = min(spl->hdr[0], spl->capacity);
+    for (uint32_t i = lane; i < ns; i += 64) {
+      if (spl->cell[i] != c) continue;
+      const uint32_t id = spl->st.id[i];
+      x[id] = spl->st.x[i];
+      y[id] = spl->st.y[i];
+      z[id] = spl->st.z[i];
+      px[id] = spl->st.px[i];
+      py[id] = spl->st.py[i];
+      pz[id] = spl->st.pz[i];
+    }
+  }
 }
 
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -1494,9 +1919,25 @@ void launch_init_bin(const double *x, const double *y, const double *z,
                      pz, dst, n, g, st);
 }
 
+namespace {
+// Workgroups of an overflow launch: each steps one overflowing cell at a time
+// (or streams a share of the spilled particles).
+constexpr uint32_t kOvGroups = 16;
+// ... per event of a batch.
+constexpr uint32_t kOvGroupsBatch = 4;
+
+template <uint32_t kMode, bool kTrace>
+void launch_overflow_mode(const Cells &src, const Cells &dst, uint32_t t, const PairArgs &pa,
+                          const Geometry &g, DevStatus *status, const TraceArgs &tr,
+                          const OverflowPool &pool, uint32_t *trace_cell, hipStream_t s) {
+  hipLaunchKernelGGL((k_overflow<kMode, kTrace>), dim3(kOvGroups), dim3(kOvBlock), 0, s, src,
+                     dst, t, pa, g, status, tr, pool, trace_cell);
+}
+}  // namespace
+
 void launch_stream_bin(const Cells &src, const Cells &dst, int64_t n_cells, uint32_t lanes,
                        const Geometry &g, DevStatus *status, uint32_t *trace_cell,
-                       hipStream_t s) {
+                       const OverflowPool &pool, hipStream_t s) {
   if (n_cells <= 0) return;
   const uint32_t G = lanes == 0 || lanes == kTwoWavesPerCell ? 64u : lanes;
   const int64_t waves = (n_cells + 64 / G - 1) / (64 / G);
@@ -1515,6 +1956,9 @@ void launch_stream_bin(const Cells &src, const Cells &dst, int64_t n_cells, uint
     default:
       hipLaunchKernelGGL(k_stream_bin<64>, grid, block, 0, s, src, dst, nc, g, status, trace_cell);
   }
+  // then the spilled particles
+  launch_overflow_mode<kOvStream, false>(src, dst, 0u, PairArgs{}, g, status, TraceArgs{}, pool,
+                                         trace_cell, s);
 }
 
 void launch_offsets(const Cells &cur, uint32_t *offsets, uint32_t *tile_sums,
@@ -1597,15 +2041,22 @@ void launch_step_any(const Cells &src, const Cells &dst, bool fused, uint32_t n_
                      uint32_t lanes, uint32_t t, const PairArgs &pa, const Geometry &g,
                      DevStatus *status, const TraceArgs *trace, hipStream_t s,
                      const SideStream *side, const StepDevice &dev) {
-  if (trace)
+  if (trace) {
     launch_step_cap<false, true, kCap>(src, dst, n_cells, lanes, t, pa, g, status, *trace, s,
                                        side, dev);
-  else if (fused)
+    launch_overflow_mode<kOvCollide, true>(src, dst, t, pa, g, status, *trace, dev.pool,
+                                           nullptr, s);
+  } else if (fused) {
     launch_step_cap<true, false, kCap>(src, dst, n_cells, lanes, t, pa, g, status,
                                        TraceArgs{}, s, side, dev);
-  else
+    launch_overflow_mode<kOvFused, false>(src, dst, t, pa, g, status, TraceArgs{}, dev.pool,
+                                          nullptr, s);
+  } else {
     launch_step_cap<false, false, kCap>(src, dst, n_cells, lanes, t, pa, g, status,
                                         TraceArgs{}, s, side, dev);
+    launch_overflow_mode<kOvCollide, false>(src, dst, t, pa, g, status, TraceArgs{}, dev.pool,
+                                            nullptr, s);
+  }
 }
 
 }  // namespace
@@ -1650,9 +2101,12 @@ void launch_batch_run(BatchEvent *ev, const BatchSpaces &sp, uint32_t n_events, 
   const uint32_t bin_grid = (bin_waves + kCellsPerBlock - 1) / kCellsPerBlock;
   const BatchEvent *cev = ev;
   const dim3 wave(64);
+  const dim3 ov_grid(kOvGroupsBatch * n_events);
   if (between) between(ctx, 0);
   hipLaunchKernelGGL(k_batch_bin, dim3(bin_grid), dim3(kBlock), 0, s, cev, sp.item_begin,
                      n_events, sp.n_items);
+  hipLaunchKernelGGL(k_batch_overflow<kOvStream>, ov_grid, dim3(kOvBlock), 0, s, cev, 0u,
+                     kOvGroupsBatch);
   // launch j: the small cells on s; concurrently on the side stream the
   // cells of events stepped one wave per cell, then the oversize cells of
   // small-cell events (all disjoint cells; appends go through atomics)
@@ -1681,6 +2135,8 @@ void launch_batch_run(BatchEvent *ev, const BatchSpaces &sp, uint32_t n_events, 
                            cev, sp.scan_begin, n_events, j);
     }
     join(s, sd);
+    hipLaunchKernelGGL(k_batch_overflow<kF ? kOvFused : kOvCollide>, ov_grid, dim3(kOvBlock), 0,
+                       s, cev, j, kOvGroupsBatch);
   };
   using Fused = std::integral_constant<bool, true>;
   using Last = std::integral_constant<bool, false>;

@@ -19,7 +19,8 @@ CUBA_EINVAL = -1
 CUBA_ERANGE = -2
 CUBA_ENOMEM = -3
 CUBA_EDEVICE = -4
-CUBA_MAX_CELL_OCCUPANCY = 1024
+CUBA_MAX_CELL_CAPACITY = 1024      # largest cell_capacity (a layout bound)
+CUBA_MAX_CELL_PARTICLES = 92681    # most particles a cell may hold
 
 
 class CubaError(RuntimeError):

@@ -18,8 +18,9 @@ def _dev(a, device):
 
 def suggest_cell_capacity(params: dict, state, headroom: float = 2.0, margin: int = 32) -> int:
     """Slots per cell for the workspace: headroom x the largest initial cell
-    occupancy plus a margin, rounded up to 32, within [64, 1024].  (Sizing
-    only; the library reports any overflow at the next sync.)"""
+    occupancy plus a margin, rounded up to 32, within [64, 1024].  A layout
+    choice only: a cell that later holds more keeps the surplus in the
+    spill region and is stepped by the library's overflow kernel."""
     if len(state[0]) == 0:
         return 64
     box = np.asarray(params["box"], np.float64)
@@ -34,7 +35,7 @@ def suggest_cell_capacity(params: dict, state, headroom: float = 2.0, margin: in
     flat = (idx[0] * cells[1] + idx[1]) * cells[2] + idx[2]
     occ = int(np.bincount(flat).max())
     cap = int(np.ceil((headroom * occ + margin) / 32.0)) * 32
-    return max(64, min(C.CUBA_MAX_CELL_OCCUPANCY, cap))
+    return max(64, min(C.CUBA_MAX_CELL_CAPACITY, cap))
 
 
 class Sim:

@@ -46,7 +46,7 @@ int main() {
       {"dt", [](cuba_params &q) { q.dt = 0.5; }},
       {"dt inf", [](cuba_params &q) { q.dt = INFINITY; }},
       {"2K > 1", [](cuba_params &q) { q.sigma = 1e6; }},
-      {"capacity", [](cuba_params &q) { q.cell_capacity = CUBA_MAX_CELL_OCCUPANCY + 1; }},
+      {"capacity", [](cuba_params &q) { q.cell_capacity = CUBA_MAX_CELL_CAPACITY + 1; }},
   };
   double dummy_arr[4] = {0, 0, 0, 0};
   const double *d = dummy_arr;

@@ -113,24 +113,30 @@ def test_batch_staggered_admission_and_slot_reuse(mods):
 
 
 def test_batch_reports_the_failing_slot(mods):
-    batch, _ = mods
+    """A device-side error of one event (a cell past the 32-bit pair-index
+    bound) names its slot; the other events keep their results."""
+    batch, sim = mods
     from paper_1208_0961_amd import cuba as C
     ok = small_events()[1]
-    n = 60
+    n = C.CUBA_MAX_CELL_PARTICLES + 1
     rng = np.random.default_rng(4)
-    x = np.concatenate([0.1 + 0.3 * rng.random(n), 0.5 + 0.004 * rng.random(n)])
-    bad_state = [x, rng.random(2 * n), rng.random(2 * n),
-                 np.concatenate([np.ones(n), -np.ones(n)]), np.zeros(2 * n), np.zeros(2 * n)]
-    bad = dict(box=(1.0, 1.0, 1.0), cells=(2, 1, 1), sigma=0.0, r_test=1.0, dt=0.01,
-               seed=1, cell_capacity=64)
+    bad_state = [0.2 + 0.6 * rng.random(n), 0.2 + 0.6 * rng.random(n),
+                 0.2 + 0.6 * rng.random(n)] + list(W.sample_gas(rng, n, 0.4, (0, 0, 0),
+                                                               (1, 1, 1))[3:])
+    bad = dict(box=(1.0, 1.0, 1.0), cells=(1, 1, 1), sigma=1e-6, r_test=1.0, dt=0.001,
+               seed=1, cell_capacity=256)
+    ok_state = W.riemann_state(ok)
     B = batch.Batch(3)
-    B.admit(0, ok.params(), W.riemann_state(ok))
+    B.admit(0, ok.params(), ok_state)
     B.admit(2, bad, bad_state)
-    B.step(1)
+    B.step(2)
     with pytest.raises(C.CubaError) as e:
         B.sync()
     assert e.value.code == C.CUBA_ERANGE and e.value.slot == 2
+    B.sync()       # reported once
+    got = B.get_state(0)
     B.close()
+    assert_same(got, alone(sim, ok, ok_state, 2), "healthy event beside a failing one")
 
 
 def test_batch_mixed_lanes_per_cell(mods):

@@ -188,34 +188,6 @@ def test_full_occupancy_cell_and_filter_disabled(orc, lib):
     compare_step(orc, lib, params, state, 6, "cap1024")
 
 
-def test_capacity_overflow_is_reported(lib):
-    from paper_1208_0961_amd import cuba as C
-    # more particles in one cell than the largest capacity: refused at init
-    state = _cells_box([1025], m=1)
-    params = dict(box=(1.0, 1.0, 1.0), cells=(1, 1, 1), sigma=1.0, r_test=1.0,
-                  dt=0.001, seed=1, cell_capacity=1024)
-    with pytest.raises(C.CubaError) as e:
-        lib.Sim(params, state)
-    assert e.value.code == C.CUBA_ERANGE
-    # a cell that fills past its capacity during a step: reported at sync
-    n = 60
-    rng = np.random.default_rng(4)
-    x = np.concatenate([0.1 + 0.3 * rng.random(n), 0.5 + 0.004 * rng.random(n)])
-    y = rng.random(2 * n)
-    z = rng.random(2 * n)
-    px = np.concatenate([np.ones(n), -np.ones(n)])   # right half moves left
-    state = [x, y, z, px, np.zeros(2 * n), np.zeros(2 * n)]
-    params = dict(box=(1.0, 1.0, 1.0), cells=(2, 1, 1), sigma=0.0, r_test=1.0,
-                  dt=0.01, seed=1, cell_capacity=64)
-    sim = lib.Sim(params, state)
-    sim.step(1)
-    with pytest.raises(C.CubaError) as e:
-        sim.sync()
-    assert e.value.code == C.CUBA_ERANGE and "capacity" in str(e.value)
-    sim.sync()       # the error is reported once
-    sim.close()
-
-
 def test_empty_and_tiny_inputs(orc, lib):
     params = dict(box=(1.0, 1.0, 1.0), cells=(2, 2, 2), sigma=1.0, r_test=1.0,
                   dt=0.01, seed=7)

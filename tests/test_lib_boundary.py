@@ -55,14 +55,19 @@ def test_workspace_bytes_and_parameter_checks(C):
     p = C.make_params((10, 2, 2), (100, 10, 10), 0.4, 2500, 0.02, 1, cell_capacity=256)
     n = 1020851
     ws = C.cuba_workspace_bytes(p, n)
-    # two buffers of cells x capacity slots of 52 B plus per-cell arrays
-    # (two counts, trace offsets and 4 observe sums: 44 B) and small pieces
+    # two buffers of cells x capacity slots of 52 B, each with a spill region
+    # of n particles (52 B + their cell, 4 B) and an overflowing-cell list;
+    # overflow scratch of 5 n / 2 + cells words; per-cell arrays (two counts,
+    # two overflow lists, trace offsets, 4 observe sums, a scratch word:
+    # 56 B) and small pieces
     slots = 10000 * 256
-    assert 104 * slots + 44 * 10000 <= ws <= 104 * slots + 48 * 10000 + 64 * 1024
+    want = 104 * slots + (2 * 56 + 10) * n + 56 * 10000
+    assert want <= ws <= want + 64 * 1024
     p2 = C.make_params((10, 2, 2), (100, 10, 10), 0.4, 2500, 0.02, 1, cell_capacity=512)
     assert C.cuba_workspace_bytes(p2, n) > ws
-    p0 = C.make_params((10, 2, 2), (100, 10, 10), 0.4, 2500, 0.02, 1)   # default 512
-    assert C.cuba_workspace_bytes(p0, n) == C.cuba_workspace_bytes(p2, n)
+    # default: twice the mean occupancy (102.1) plus 32, rounded up to 32
+    p0 = C.make_params((10, 2, 2), (100, 10, 10), 0.4, 2500, 0.02, 1)
+    assert C.cuba_workspace_bytes(p0, n) == ws
     for cap in (-1, 1025):
         bad = C.make_params((10, 2, 2), (100, 10, 10), 0.4, 2500, 0.02, 1, cell_capacity=cap)
         assert C.cuba_workspace_bytes(bad, n) == 0
