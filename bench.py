@@ -68,15 +68,21 @@ def parse():
                     help="serve: number of requests")
     ap.add_argument("--retune", action="store_true",
                     help="batch: ignore a stored tuning table")
-    ap.add_argument("--serve-policy", choices=["srpt", "all"], default="all",
-                    help="serve: least remaining work first within a particle budget per "
-                         "run (srpt) or every live event in every run (all); the other "
-                         "policy runs on the same trace for comparison")
-    ap.add_argument("--serve-run-steps", type=int, default=200,
+    ap.add_argument("--serve-policy", choices=["fifo", "srpt", "all"], default="fifo",
+                    help="serve: the oldest requests in arrival order within a particle "
+                         "budget per run (fifo), the oldest then least remaining work "
+                         "first within the budget (srpt), or every live request in every "
+                         "run (all); the other policies run on the same trace for "
+                         "comparison")
+    ap.add_argument("--serve-run-steps", type=int, default=25,
                     help="serve: at most this many steps per run; a run ends early where "
                          "one of its requests ends or is due for an observation")
-    ap.add_argument("--serve-run-particles", type=int, default=2_000_000,
-                    help="serve, srpt: particles per run beside the oldest request")
+    ap.add_argument("--serve-run-particles", type=int, default=4_000_000,
+                    help="serve, fifo and srpt: particles per run (the oldest request "
+                         "always runs)")
+    ap.add_argument("--serve-fill-particles", type=int, default=1_000_000,
+                    help="serve, fifo: particles of further requests, least remaining "
+                         "work first, beside those taken in arrival order")
     ap.add_argument("--serve-observe", choices=["final", "50"], default="final",
                     help="serve: observe each request's profile at its end only (its "
                          "result) or also every 50 steps, in the server and in the "
@@ -354,10 +360,11 @@ def ensemble_leg(steps: int, warmup: int = 5, n_events: int = 256) -> dict:
 def serve_leg(n_requests: int) -> dict:
     """The served half of the metric on a short request stream (sizes 1e4 to
     4e6 test particles, 200 steps each, Poisson arrivals at 0.8 of the
-    server's measured capacity): p50/p99 time-to-result and particle-steps/s
-    against a one-at-a-time FIFO of plain runs on the same trace."""
+    server's measured capacity), served with runs of at most 25 steps:
+    p50/p99 time-to-result and particle-steps/s of each policy against a
+    one-at-a-time FIFO of plain runs on the same trace."""
     from paper_1208_0961_amd import serve
-    return serve.measure(n_requests)
+    return serve.measure(n_requests, other_policies=serve.Server.POLICIES)
 
 
 def bench_sigma_scan(a):

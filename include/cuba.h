@@ -301,7 +301,9 @@ size_t cuba_batch_workspace_bytes(int32_t max_slots);
  * caller.  stream: hipStream_t (must not be NULL if graphs are enabled).
  * The batch also creates one stream of its own (default priority), on which
  * the kernels of a step that are independent of the small-cell kernel run
- * concurrently, joined back into `stream` before the next step. */
+ * concurrently, joined back into `stream` before the next step, and two
+ * pinned host buffers through which a changed event table is uploaded
+ * without waiting for the stream. */
 int cuba_batch_create(cuba_batch **out, int32_t max_slots, void *workspace,
                       size_t ws_bytes, void *stream);
 
@@ -313,8 +315,24 @@ int cuba_batch_admit(cuba_batch *b, int32_t slot, const cuba_params *params,
                      const double *z, const double *px, const double *py,
                      const double *pz, void *workspace, size_t ws_bytes);
 
-/* Frees a slot (synchronizes the stream); the event's workspace may then
- * be reused by the caller. */
+/* As cuba_batch_admit, without waiting for the stream: for a serving loop
+ * that admits requests while earlier steps still run.  The initial state is
+ * not checked on the host; a particle outside [0, L], non-finite or with
+ * |p| = 0 is reported by cuba_batch_sync with this slot.  lanes: the event's
+ * lanes per cell (0, 8, 16, 32 or 64, as cuba_batch_set_cell_lanes; the
+ * synchronous admission chooses it from the initial occupancy, which this
+ * call does not read back).  Errors: as cuba_batch_admit, CUBA_EINVAL for
+ * other lanes. */
+int cuba_batch_admit_async(cuba_batch *b, int32_t slot, const cuba_params *params,
+                           int64_t n, const double *x, const double *y,
+                           const double *z, const double *px, const double *py,
+                           const double *pz, void *workspace, size_t ws_bytes,
+                           int32_t lanes);
+
+/* Frees a slot, without waiting for the stream: the steps already queued
+ * still run on the event's workspace, which the caller may reuse in stream
+ * order (e.g. through a stream-ordered allocator on the batch's stream) or
+ * after cuba_batch_sync. */
 int cuba_batch_retire(cuba_batch *b, int32_t slot);
 
 /* The context of an occupied slot, or NULL.  Owned by the batch. */

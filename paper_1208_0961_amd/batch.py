@@ -73,8 +73,35 @@ class Batch:
         self.slots[slot] = {"params": params, "n": n, "workspace": workspace,
                             "T00": T00, "T0x": T0x}
 
+    def admit_async(self, slot: int, params: dict, state, lanes: int = 0,
+                    workspace: torch.Tensor | None = None):
+        """As admit, without waiting for the stream (cuba_batch_admit_async):
+        errors of the initial state surface at the next sync; lanes: the
+        event's lanes per cell."""
+        params = with_capacity(params, state)
+        n = int(len(state[0]))
+        p = C.make_params(**params)
+        nbytes = C.cuba_workspace_bytes(p, n)
+        if nbytes == 0:
+            raise C.CubaError(C.CUBA_EINVAL, "cuba_workspace_bytes", C.cuba_last_error())
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(self.stream):
+            if workspace is None:
+                workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            arrs = [_dev(a, self.device) for a in state]
+            nx = int(params["cells"][0])
+            T00 = torch.empty(nx, dtype=torch.float64, device=self.device)
+            T0x = torch.empty(nx, dtype=torch.float64, device=self.device)
+        C.cuba_batch_admit_async(self.b, slot, p, n, *[a.data_ptr() for a in arrs],
+                                 workspace.data_ptr(), nbytes, lanes)
+        self.slots[slot] = {"params": params, "n": n, "workspace": workspace,
+                            "T00": T00, "T0x": T0x}
+
     def retire(self, slot: int) -> torch.Tensor:
-        """Frees the slot; returns the event's workspace for reuse."""
+        """Frees the slot without waiting for the stream (the queued steps
+        still use the workspace; a tensor allocated on this batch's stream is
+        reused by later allocations on it in stream order); returns the
+        event's workspace."""
         C.cuba_batch_retire(self.b, slot)
         return self.slots.pop(slot)["workspace"]
 

@@ -383,7 +383,7 @@ int check_init_args(const cuba_params *params, int64_t n, const double *x, const
 int init_context(cuba_ctx *c, const Derived &d, const cuba_params *params, int64_t n,
                  const double *x, const double *y, const double *z, const double *px,
                  const double *py, const double *pz, void *workspace, size_t ws_bytes,
-                 void *stream) {
+                 void *stream, bool validate = true) {
   int rc = CUBA_OK;
   if (!workspace) return fail(CUBA_EINVAL, "workspace is NULL");
   if (((uintptr_t)workspace & 255u) != 0)
@@ -460,17 +460,21 @@ int init_context(cuba_ctx *c, const Derived &d, const cuba_params *params, int64
   launch_fill_u32(c->buf[1].count, 0u, d.n_cells, c->stream);
   for (int b = 0; b < 2; ++b) launch_fill_u32(hsd[b].hdr, 0u, kSpillHdrWords, c->stream);
   launch_fill_u32((uint32_t *)c->pool.hdr, 0u, 4, c->stream);
-  hipError_t e = hipMemcpyAsync(c->consts, &hc, sizeof(hc), hipMemcpyHostToDevice, c->stream);
-  // each buffer's descriptor sits in that buffer's region (one buffer's
-  // distance apart), so each is written on its own
-  for (int b = 0; b < 2 && e == hipSuccess; ++b)
-    e = hipMemcpyAsync(c->buf[b].sp, &hsd[b], sizeof(SpillDesc), hipMemcpyHostToDevice,
-                       c->stream);
-  if (e != hipSuccess) return hip_fail(e, "init constants");
+  // the constants and (each in its buffer's region, one buffer's distance
+  // apart) the two spill descriptors, written by kernels in stream order
+  bool ok = launch_write_bytes(c->consts, &hc, sizeof(hc), c->stream);
+  for (int b = 0; b < 2; ++b)
+    ok = ok && launch_write_bytes(c->buf[b].sp, &hsd[b], sizeof(SpillDesc), c->stream);
+  if (!ok) return fail(CUBA_EDEVICE, "internal: constants do not fit a write launch");
   launch_init_bin(x, y, z, px, py, pz, c->buf[0], n, d.g, c->status, c->stream);
   launch_occupancy_over(c->buf[0], d.n_cells, c->status, c->stream);
   rc = check_launch("init launch");
   if (rc != CUBA_OK) return rc;
+  if (!validate) {  // errors of the state surface at the next sync
+    c->lanes = 0;
+    return CUBA_OK;
+  }
+  hipError_t e = hipSuccess;
   uint32_t head[5] = {0, 0, 0, 0, 0};  // err, over[4]
   static_assert(offsetof(DevStatus, over) == sizeof(uint32_t), "status layout");
   SpillDesc back[2];
@@ -675,6 +679,9 @@ int cuba_sync(cuba_ctx *c) {
                                    "were skipped)");
     if (err & kErrSpill) return fail(CUBA_EDEVICE, "internal: spill region inconsistent");
     if (err & kErrTrace) return fail(CUBA_ENOMEM, "trace buffer too small");
+    if (err & kErrRange)
+      return fail(CUBA_ERANGE, "a particle of the initial state is outside [0, L], "
+                               "non-finite, or has |p| = 0");
     return fail(CUBA_ERANGE, "device reported an invalid state");
   }
   return CUBA_OK;
@@ -792,6 +799,16 @@ struct cuba_batch {
   uint32_t persistent_waves = 0;
   bool use_graphs = false;
   std::map<int32_t, hipGraphExec_t> graphs;
+  // graphs replaced while a launch of them may still run: destroyed at the
+  // next sync
+  std::vector<hipGraphExec_t> stale_graphs;
+  // pinned staging of the table uploads (two, used in turn; an event marks
+  // when each one's copies have run), so that an upload does not wait for
+  // the stream
+  void *staging[2] = {nullptr, nullptr};
+  hipEvent_t staged[2] = {nullptr, nullptr};
+  bool staged_used[2] = {false, false};
+  int next_staging = 0;
   // stage timing of direct (non-graph) runs
   bool timing = false;
   size_t timing_cap = 0;
@@ -802,9 +819,35 @@ struct cuba_batch {
 
 namespace {
 
+// Work spaces of a batch: binning items, small-cell chunks, oversize scans,
+// and the one-wave-per-cell spaces of small and large cell capacity.
+constexpr int kSpaces = 5;
+
+// Graphs of the old table: set aside (a launch of them may still be in
+// flight) and destroyed once the stream has been synchronized.
 void drop_graphs(cuba_batch *b) {
-  for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto &kv : b->graphs) b->stale_graphs.push_back(kv.second);
   b->graphs.clear();
+}
+
+void destroy_stale_graphs(cuba_batch *b) {
+  for (hipGraphExec_t g : b->stale_graphs) (void)hipGraphExecDestroy(g);
+  b->stale_graphs.clear();
+}
+
+size_t staging_bytes(int32_t max_slots) {
+  return align256((size_t)max_slots * sizeof(BatchEvent)) +
+         (size_t)kSpaces * max_slots * sizeof(uint32_t);
+}
+
+// Frees the batch's own resources (streams, staging) and the batch.
+void release_batch(cuba_batch *b) {
+  for (int k = 0; k < 2; ++k) {
+    if (b->staged[k]) (void)hipEventDestroy(b->staged[k]);
+    if (b->staging[k]) (void)hipHostFree(b->staging[k]);
+  }
+  destroy_side(b->side);
+  delete b;
 }
 
 void drop_batch_timing(cuba_batch *b) {
@@ -827,9 +870,6 @@ int32_t default_cpi(const cuba_ctx *c) {
   return cpi;
 }
 
-// Work spaces of a batch: binning items, small-cell chunks, oversize scans,
-// and the one-wave-per-cell spaces of small and large cell capacity.
-constexpr int kSpaces = 5;
 
 // Rebuilds the device table and the work spaces from the live slots (in
 // slot order).
@@ -903,13 +943,24 @@ int upload_table(cuba_batch *b) {
         if (cell_space[i] == sp) run[sp] += host[i].n_cells;
       }
     }
-    hipError_t e = hipMemcpyAsync(b->dev_table, host.data(), ne * sizeof(BatchEvent),
-                                  hipMemcpyHostToDevice, b->stream);
+    // through pinned staging, in stream order, without waiting for the
+    // stream (only for the staging buffer's previous copies, two uploads ago)
+    const int k = b->next_staging;
+    b->next_staging ^= 1;
+    hipError_t e = b->staged_used[k] ? hipEventSynchronize(b->staged[k]) : hipSuccess;
+    if (e != hipSuccess) return hip_fail(e, "batch table staging");
+    char *const stage = (char *)b->staging[k];
+    const size_t begins_at = align256((size_t)b->max_slots * sizeof(BatchEvent));
+    std::memcpy(stage, host.data(), ne * sizeof(BatchEvent));
+    std::memcpy(stage + begins_at, begins.data(), begins.size() * sizeof(uint32_t));
+    e = hipMemcpyAsync(b->dev_table, stage, ne * sizeof(BatchEvent), hipMemcpyHostToDevice,
+                       b->stream);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(b->dev_begin, begins.data(), begins.size() * sizeof(uint32_t),
+      e = hipMemcpyAsync(b->dev_begin, stage + begins_at, begins.size() * sizeof(uint32_t),
                          hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess) e = hipEventRecord(b->staged[k], b->stream);
     if (e != hipSuccess) return hip_fail(e, "batch table upload");
+    b->staged_used[k] = true;
   }
   drop_graphs(b);
   b->dirty = false;
@@ -961,12 +1012,43 @@ int cuba_batch_create(cuba_batch **out, int32_t max_slots, void *workspace,
   b->slot_ctx.assign(max_slots, nullptr);
   b->slot_cpi.assign(max_slots, 1);
   b->slot_active.assign(max_slots, 1);
-  const hipError_t e = create_side(b->side);
+  hipError_t e = create_side(b->side);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+    e = hipHostMalloc(&b->staging[k], staging_bytes(max_slots), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged[k], hipEventDisableTiming);
+  }
   if (e != hipSuccess) {
-    delete b;
-    return hip_fail(e, "batch side stream");
+    release_batch(b);
+    return hip_fail(e, "batch side stream and staging");
   }
   *out = b;
+  return CUBA_OK;
+}
+
+int cuba_batch_admit_async(cuba_batch *b, int32_t slot, const cuba_params *params, int64_t n,
+                           const double *x, const double *y, const double *z,
+                           const double *px, const double *py, const double *pz,
+                           void *workspace, size_t ws_bytes, int32_t lanes) {
+  if (!b) return fail(CUBA_EINVAL, "batch is NULL");
+  if (slot < 0 || slot >= b->max_slots) return fail(CUBA_EINVAL, "slot out of range");
+  if (b->slot_ctx[slot]) return fail(CUBA_EINVAL, "slot is occupied");
+  if (!valid_cell_lanes(lanes)) return fail(CUBA_EINVAL, "lanes must be 0, 8, 16, 32 or 64");
+  Derived d;
+  int rc = check_init_args(params, n, x, y, z, px, py, pz, d);
+  if (rc != CUBA_OK) return rc;
+  cuba_ctx *c = new (std::nothrow) cuba_ctx();
+  if (!c) return fail(CUBA_ENOMEM, "host allocation failed");
+  rc = init_context(c, d, params, n, x, y, z, px, py, pz, workspace, ws_bytes,
+                    (void *)b->stream, false);
+  if (rc != CUBA_OK) {
+    delete c;
+    return rc;
+  }
+  c->lanes = (uint32_t)lanes;
+  b->slot_ctx[slot] = c;
+  b->slot_cpi[slot] = default_cpi(c);
+  b->slot_active[slot] = 1;
+  b->dirty = true;
   return CUBA_OK;
 }
 
@@ -1005,8 +1087,8 @@ int cuba_batch_retire(cuba_batch *b, int32_t slot) {
   if (!b) return fail(CUBA_EINVAL, "batch is NULL");
   if (slot < 0 || slot >= b->max_slots || !b->slot_ctx[slot])
     return fail(CUBA_EINVAL, "slot is not occupied");
-  const hipError_t e = hipStreamSynchronize(b->stream);
-  if (e != hipSuccess) return hip_fail(e, "retire sync");
+  // the event's device state is the caller's workspace; its host context
+  // is not read by work already queued on the stream
   cuba_destroy(b->slot_ctx[slot]);
   b->slot_ctx[slot] = nullptr;
   b->dirty = true;
@@ -1115,6 +1197,7 @@ int cuba_batch_sync(cuba_batch *b, int32_t *bad_slot) {
   if (bad_slot) *bad_slot = -1;
   const hipError_t e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return hip_fail(e, "batch sync");
+  destroy_stale_graphs(b);
   for (int32_t s = 0; s < b->max_slots; ++s) {
     if (!b->slot_ctx[s]) continue;
     const int rc = cuba_sync(b->slot_ctx[s]);
@@ -1176,10 +1259,10 @@ void cuba_batch_destroy(cuba_batch *b) {
   (void)hipStreamSynchronize(b->stream);
   (void)hipStreamSynchronize(b->side.stream);
   drop_graphs(b);
+  destroy_stale_graphs(b);
   drop_batch_timing(b);
   for (cuba_ctx *c : b->slot_ctx) cuba_destroy(c);
-  destroy_side(b->side);
-  delete b;
+  release_batch(b);
 }
 
 }  // extern "C"

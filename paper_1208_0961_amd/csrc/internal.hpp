@@ -155,6 +155,11 @@ struct SideStream {
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s);
 // *p = v on the device, in stream order.
 void launch_store_f64(double *p, double v, hipStream_t s);
+// Copies `bytes` (a multiple of 4, at most 256) from host memory to dst on
+// the device in stream order, the data travelling as a kernel argument (so
+// the call neither waits for the stream nor needs src after it returns).
+// False if the size or alignment does not fit.
+bool launch_write_bytes(void *dst, const void *src, size_t bytes, hipStream_t s);
 void launch_init_bin(const double *x, const double *y, const double *z,
                      const double *px, const double *py, const double *pz,
                      const Cells &dst, int64_t n, const Geometry &g, DevStatus *st,

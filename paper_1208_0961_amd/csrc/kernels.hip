@@ -281,6 +281,18 @@ __global__ __launch_bounds__(64) void k_store_f64(double *p, double v) {
   if (threadIdx.x == 0) *p = v;
 }
 
+// Up to kWriteWords words carried as a kernel argument and stored to device
+// memory in stream order (the host copy needs to live only until the launch
+// returns, and no host-to-device copy waits for the stream).
+constexpr uint32_t kWriteWords = 64;
+struct WriteWords {
+  uint32_t w[kWriteWords];
+};
+__global__ __launch_bounds__(64) void k_write_words(uint32_t *dst, WriteWords v,
+                                                    uint32_t nwords) {
+  for (uint32_t i = threadIdx.x; i < nwords; i += 64) dst[i] = v.w[i];
+}
+
 // Initial state (id order) -> validated and binned without streaming.
 __global__ __launch_bounds__(kBlock) void k_init_bin(
     const double *__restrict__ x, const double *__restrict__ y,
@@ -1908,6 +1920,15 @@ void launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s) {
 
 void launch_store_f64(double *p, double v, hipStream_t s) {
   hipLaunchKernelGGL(k_store_f64, dim3(1), dim3(64), 0, s, p, v);
+}
+
+bool launch_write_bytes(void *dst, const void *src, size_t bytes, hipStream_t s) {
+  if (bytes % 4 != 0 || bytes > sizeof(WriteWords) || ((uintptr_t)dst & 3u) != 0) return false;
+  WriteWords v{};
+  __builtin_memcpy(v.w, src, bytes);
+  hipLaunchKernelGGL(k_write_words, dim3(1), dim3(64), 0, s, (uint32_t *)dst, v,
+                     (uint32_t)(bytes / 4));
+  return true;
 }
 
 void launch_init_bin(const double *x, const double *y, const double *z,

@@ -104,6 +104,9 @@ def _load() -> ctypes.CDLL:
     L.cuba_batch_create.restype = ctypes.c_int
     L.cuba_batch_admit.argtypes = [vp, i32, P, i64] + [vp] * 6 + [vp, ctypes.c_size_t]
     L.cuba_batch_admit.restype = ctypes.c_int
+    L.cuba_batch_admit_async.argtypes = [vp, i32, P, i64] + [vp] * 6 + [vp, ctypes.c_size_t,
+                                                                         i32]
+    L.cuba_batch_admit_async.restype = ctypes.c_int
     L.cuba_batch_retire.argtypes = [vp, i32]
     L.cuba_batch_retire.restype = ctypes.c_int
     L.cuba_batch_slot.argtypes = [vp, i32]
@@ -310,6 +313,14 @@ def cuba_batch_admit(b: int, slot: int, params: cuba_params, n: int, x: int, y: 
                      ws_bytes: int) -> None:
     _check(_lib.cuba_batch_admit(b, int(slot), ctypes.byref(params), int(n), x, y, z, px,
                                  py, pz, workspace, int(ws_bytes)), "cuba_batch_admit")
+
+
+def cuba_batch_admit_async(b: int, slot: int, params: cuba_params, n: int, x: int, y: int,
+                           z: int, px: int, py: int, pz: int, workspace: int,
+                           ws_bytes: int, lanes: int) -> None:
+    _check(_lib.cuba_batch_admit_async(b, int(slot), ctypes.byref(params), int(n), x, y, z,
+                                       px, py, pz, workspace, int(ws_bytes), int(lanes)),
+           "cuba_batch_admit_async")
 
 
 def cuba_batch_retire(b: int, slot: int) -> None:

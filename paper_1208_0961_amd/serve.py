@@ -3,13 +3,14 @@
 Each request is one Riemann event (parameters from the ensemble
 distribution, an initial state drawn from its seed) to be advanced a fixed
 number of steps, with T00/T0x observed every 50 steps (or, with final_only,
-at the end only); the result is the final profile.  The server admits arrived requests in FIFO order as a batch
-slot and enough HBM (the event's workspace footprint) free up, advances all
-live events together in runs of at most `run_steps` steps (one launch per
-step for all of them), each ending where an event in it ends or is due for
-an observation, and retires events that are done.  Requests that arrive while
-others run join at the next run boundary, so their work overlaps on the
-device.
+at the end only); the result is the final profile.  The server admits
+arrived requests in FIFO order as a batch slot and enough HBM (the event's
+workspace footprint) free up, advances live events together in runs of at
+most `run_steps` steps (one launch per step for all of them), each ending
+where an event in it ends or is due for an observation, and retires events
+that are done.  Admission, retirement and result copies do not wait for the
+GPU: runs are queued back to back and requests that arrive while others are
+on the GPU join the next queued run, so their work overlaps on the device.
 """
 from __future__ import annotations
 
@@ -44,8 +45,8 @@ class Result:
     T00: np.ndarray
     T0x: np.ndarray
     state: list | None = None
-    admitted_run: int = 0     # runs completed before admission
-    finished_run: int = 0     # runs completed at its end
+    admitted_run: int = 0     # runs queued before admission
+    finished_run: int = 0     # runs queued up to its last
 
     @property
     def latency(self) -> float:
@@ -81,28 +82,49 @@ def footprint(req: Request) -> int:
 
 
 class Server:
-    """policy "all": every live event takes part in every run (processor
-    sharing).  policy "srpt": each run takes the oldest live event, then
-    the others in order of least remaining work (particles x steps left)
-    while they fit `run_particles`; the rest are held (cuba_batch_set_active)
-    until chosen.  Short requests then finish in runs that large ones do not
-    slow down, and the oldest one always advances, so none starves."""
+    """Continuous batching of Riemann-event requests on one GPU.
+
+    Requests are admitted in arrival order as a batch slot and HBM (the
+    event's workspace footprint) free up, without waiting for the GPU
+    (cuba_batch_admit_async); live events advance in runs of at most
+    `run_steps` steps, one launch per step for every event in the run; an
+    event that finishes is observed, its profile copied to pinned host
+    memory, and its slot retired, again without waiting.  The host queues a
+    run as soon as the previous one is queued, keeping at most `depth` runs
+    in flight, and collects each result when its copy has completed (the
+    time-to-result).  Requests that arrive while others are on the GPU join
+    the next queued run.
+
+    Which live events take part in a run:
+      "all"   every live event (processor sharing);
+      "srpt"  the oldest, then the others by least remaining work
+              (particles x steps left) while they fit `run_particles`;
+      "fifo"  the oldest events in arrival order while they fit
+              `run_particles` (at least one), then others by least remaining
+              work while they fit `fill_particles` more (small requests
+              slip in beside the large ones at the head of the queue);
+    the others are held (cuba_batch_set_active) until chosen."""
+
+    POLICIES = ("all", "srpt", "fifo")
 
     def __init__(self, max_slots: int = 256, hbm_budget: int | None = None,
                  run_steps: int = 25, device: str = "cuda", use_graphs: bool = False,
                  tuning: dict | None = None, keep_states: bool = False,
-                 policy: str = "all", run_particles: int = 2_000_000,
-                 final_only: bool = False):
-        if policy not in ("all", "srpt"):
-            raise ValueError("policy must be 'all' or 'srpt'")
+                 policy: str = "fifo", run_particles: int = 4_000_000,
+                 final_only: bool = False, depth: int = 2,
+                 fill_particles: int = 1_000_000):
+        if policy not in self.POLICIES:
+            raise ValueError(f"policy must be one of {self.POLICIES}")
         if run_steps < 1:
             raise ValueError("run_steps must be at least 1")
         self.device = device
         self.policy = policy
         self.run_particles = int(run_particles)
+        self.fill_particles = int(fill_particles)
         self.final_only = final_only
         self.run_steps = run_steps
         self.keep_states = keep_states
+        self.depth = max(1, int(depth))
         if hbm_budget is None:
             free, _ = torch.cuda.mem_get_info(device)
             hbm_budget = int(0.7 * free)
@@ -118,8 +140,8 @@ class Server:
         from . import autotune as AT
         with torch.cuda.stream(self.B.stream):
             state = W.riemann_state_torch(req.work, req.state_seed, device=self.device)
-        self.B.admit(slot, {**req.work.params(), "cell_capacity": W.capacity_for(req.work)},
-                     state)
+        self.B.admit_async(slot, {**req.work.params(),
+                                  "cell_capacity": W.capacity_for(req.work)}, state)
         if self.tuning:
             AT.settings_for(self.B, slot, req.work, self.tuning)
 
@@ -127,20 +149,33 @@ class Server:
         """Serves the requests.  realtime=True admits a request once its
         arrival time has passed on the wall clock; False treats every request
         as present at the start; "runs" reads arrival times as a count of
-        completed runs (a logical clock: admission mid-stream at a
-        reproducible point)."""
+        queued runs (a logical clock: admission mid-stream at a reproducible
+        point)."""
         if self.tuning:
             self.B.set_launch(int(self.tuning.get("persistent_waves", 0)), self.use_graphs)
         queue = deque(sorted(requests, key=lambda r: r.arrival))
         live: dict[int, dict] = {}
         used = 0
         results: list[Result] = []
+        pending: deque = deque()   # (done event, result fields, host T00, host T0x)
+        inflight: deque = deque()  # an event after each queued run
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0
         runs_done = [0]
         logical = realtime == "runs"
         clock = (lambda: runs_done[0]) if logical else now
-        while queue or live:
+        stream = self.B.stream
+
+        def collect(block: bool = False):
+            while pending and (block or pending[0][0].query()):
+                ev, fields, h00, h0x = pending.popleft()
+                ev.synchronize()
+                results.append(Result(**fields, finished=now(), T00=h00.numpy().copy(),
+                                      T0x=h0x.numpy().copy()))
+                block = False
+
+        while queue or live or pending:
+            collect()
             # admission: FIFO, by free slot and HBM footprint
             while queue and (not realtime or queue[0].arrival <= clock()):
                 req = queue[0]
@@ -156,19 +191,25 @@ class Server:
                 self.peak_live = max(self.peak_live, len(live))
                 self.peak_bytes = max(self.peak_bytes, used)
             if not live:
-                if queue and logical:
+                if pending:
+                    collect(block=not queue or (realtime and queue[0].arrival > clock()))
+                elif queue and logical:
                     runs_done[0] = max(runs_done[0], int(math.ceil(queue[0].arrival)))
                 elif queue and realtime:
-                    time.sleep(max(0.0, min(queue[0].arrival - now(), 0.01)))
+                    time.sleep(max(0.0, min(queue[0].arrival - now(), 0.002)))
                 continue
+            # at most `depth` runs in flight
+            while len(inflight) >= self.depth:
+                inflight.popleft().synchronize()
+                collect()
             active = self._choose(live)
             k = min(self.steps_to_stop(live[slot]["req"].work, live[slot]["done"])
                     for slot in active)
             self.B.step(k)
+            runs_done[0] += 1
             finished = []
-            for slot, ev in live.items():
-                if slot not in active:
-                    continue
+            for slot in sorted(active):
+                ev = live[slot]
                 ev["done"] += k
                 w = ev["req"].work
                 if ((not self.final_only and ev["done"] % w.observe_every == 0)
@@ -176,22 +217,29 @@ class Server:
                     self.B.observe_async(slot)
                 if ev["done"] >= w.steps:
                     finished.append(slot)
-            self.B.sync()
-            t_done = now()
-            runs_done[0] += 1
             for slot in finished:
                 ev = live.pop(slot)
                 s = self.B.slots[slot]
-                res = Result(ev["req"].rid, ev["req"].work.n, ev["req"].arrival,
-                             ev["admitted"], t_done, s["T00"].cpu().numpy().copy(),
-                             s["T0x"].cpu().numpy().copy(),
-                             admitted_run=ev["admitted_run"], finished_run=runs_done[0])
+                with torch.cuda.stream(stream):
+                    h00 = torch.empty(s["T00"].shape, dtype=torch.float64, pin_memory=True)
+                    h0x = torch.empty(s["T0x"].shape, dtype=torch.float64, pin_memory=True)
+                    h00.copy_(s["T00"], non_blocking=True)
+                    h0x.copy_(s["T0x"], non_blocking=True)
+                    done_ev = torch.cuda.Event()
+                    done_ev.record(stream)
+                fields = dict(rid=ev["req"].rid, n=ev["req"].work.n,
+                              arrival=ev["req"].arrival, admitted=ev["admitted"],
+                              admitted_run=ev["admitted_run"], finished_run=runs_done[0])
                 if self.keep_states:
-                    res.state = self.B.get_state(slot)
+                    fields["state"] = self.B.get_state(slot)
+                pending.append((done_ev, fields, h00, h0x))
                 self.B.retire(slot)
                 used -= ev["need"]
-                results.append(res)
-        return results
+            run_ev = torch.cuda.Event()
+            run_ev.record(stream)
+            inflight.append(run_ev)
+        self.B.sync()
+        return sorted(results, key=lambda r: r.finished)
 
     def steps_to_stop(self, work: W.Workload, done: int) -> int:
         """Steps an event that has done `done` of its steps may take in the
@@ -206,15 +254,31 @@ class Server:
         """The slots that take part in the next run (holding the others)."""
         if self.policy == "all":
             return set(live)
-        left = lambda s: live[s]["req"].work.n * (live[s]["req"].work.steps - live[s]["done"])
-        oldest = min(live, key=lambda s: (live[s]["req"].arrival, live[s]["req"].rid))
-        active, total = {oldest}, live[oldest]["req"].work.n
-        for slot in sorted(live, key=left):
-            n = live[slot]["req"].work.n
-            if slot == oldest or total + n > self.run_particles:
-                continue
-            active.add(slot)
-            total += n
+        age = lambda s: (live[s]["req"].arrival, live[s]["req"].rid)
+        size = lambda s: live[s]["req"].work.n
+        left = lambda s: size(s) * (live[s]["req"].work.steps - live[s]["done"])
+        if self.policy == "fifo":
+            order = sorted(live, key=age)
+            active, total = {order[0]}, size(order[0])
+            for slot in order[1:]:
+                if total + size(slot) > self.run_particles:
+                    break
+                active.add(slot)
+                total += size(slot)
+            extra = 0
+            for slot in sorted(live, key=left):
+                if slot in active or extra + size(slot) > self.fill_particles:
+                    continue
+                active.add(slot)
+                extra += size(slot)
+        else:
+            oldest = min(live, key=age)
+            active, total = {oldest}, size(oldest)
+            for slot in sorted(live, key=left):
+                if slot == oldest or total + size(slot) > self.run_particles:
+                    continue
+                active.add(slot)
+                total += size(slot)
         for slot, ev in live.items():
             want = slot in active
             if ev["active"] != want:
@@ -267,22 +331,25 @@ def percentiles(lat):
     return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
 
 
-def measure(n_req: int, policy: str = "all", run_steps: int = 200, final_only: bool = True,
-            run_particles: int = 2_000_000, other_policy: bool = False,
-            sequential: bool = True, seed: int = 5) -> dict:
+def measure(n_req: int, policy: str = "fifo", run_steps: int = 25, final_only: bool = True,
+            run_particles: int = 4_000_000, other_policies: tuple = (),
+            sequential: bool = True, seed: int = 5, load: float = 0.8,
+            fill_particles: int = 1_000_000) -> dict:
     """n_req requests (sizes 1e4 .. 4e6 test particles), Poisson arrivals at
-    0.8 of the server's batched capacity (measured on a closed batch of 64
+    `load` of the server's batched capacity (measured on a closed batch of 64
     requests); p50/p99 time-to-result and aggregate particle-steps/s of the
     served stream against a one-at-a-time FIFO of plain runs on the same
     trace (each request's service time measured alone, the FIFO recurrence
-    giving completion times)."""
+    giving completion times).  other_policies: further policies served on
+    the same trace, reported beside."""
     import sys
     from . import autotune as AT
     tuning = AT.load()
 
     def server(pol):
         return Server(tuning=tuning, use_graphs=False, policy=pol, run_steps=run_steps,
-                      run_particles=run_particles, final_only=final_only)
+                      run_particles=run_particles, final_only=final_only,
+                      fill_particles=fill_particles)
 
     # untimed warm-up of both paths (first launches load code objects and
     # grow the allocator's pools)
@@ -293,7 +360,7 @@ def measure(n_req: int, policy: str = "all", run_steps: int = 200, final_only: b
     run_alone(warm[0], final_only=final_only)
     # capacity: a closed batch of 64 requests all present at t = 0
     probe = request_stream(64, 0.0, seed=55)
-    srv = server(policy)
+    srv = server("all")
     t0 = time.perf_counter()
     srv.run(probe, realtime=False)
     cap_dt = time.perf_counter() - t0
@@ -301,7 +368,7 @@ def measure(n_req: int, policy: str = "all", run_steps: int = 200, final_only: b
     throughput = sum(r.work.n * r.work.steps for r in probe) / cap_dt
     reqs0 = request_stream(n_req, 1.0, seed=seed)
     mean_ps = float(np.mean([r.work.n * r.work.steps for r in reqs0]))
-    rate = 0.8 * throughput / mean_ps
+    rate = load * throughput / mean_ps
     reqs = request_stream(n_req, rate, seed=seed)
     print(f"# serve: {n_req} requests at {rate:.1f}/s (capacity {throughput:.3e} "
           f"particle-steps/s)", file=sys.stderr, flush=True)
@@ -309,11 +376,11 @@ def measure(n_req: int, policy: str = "all", run_steps: int = 200, final_only: b
     out = {"metric": "served request stream: p50/p99 time-to-result and particle-steps/s",
            "unit": "particle-steps/s", "policy": policy, "run_steps": run_steps,
            "observed": "final profile" if final_only else "every 50 steps",
-           "run_particles": run_particles, "requests": n_req,
+           "run_particles": run_particles, "fill_particles": fill_particles,
+           "requests": n_req, "load": load,
            "request_sizes": "1e4 .. 4e6 test particles, 200 steps",
            "arrival_rate_per_s": rate, "capacity_particle_steps_per_s": throughput}
-    pols = (policy, "all" if policy == "srpt" else "srpt") if other_policy else (policy,)
-    for pol in pols:
+    for pol in (policy,) + tuple(p for p in other_policies if p != policy):
         print(f"# serve policy {pol}", file=sys.stderr, flush=True)
         srv = server(pol)
         t0 = time.perf_counter()
@@ -351,9 +418,11 @@ def bench(a):
     particle-steps/s of the served stream against a one-at-a-time FIFO of
     plain runs on the same trace."""
     import json
-    out = measure(int(a.requests), policy=getattr(a, "serve_policy", "all"),
-                  run_steps=int(getattr(a, "serve_run_steps", 200)),
+    out = measure(int(a.requests), policy=getattr(a, "serve_policy", "fifo"),
+                  run_steps=int(getattr(a, "serve_run_steps", 25)),
                   final_only=getattr(a, "serve_observe", "final") == "final",
-                  run_particles=int(getattr(a, "serve_run_particles", 2_000_000)),
-                  other_policy=True, sequential=not getattr(a, "no_sequential", False))
+                  run_particles=int(getattr(a, "serve_run_particles", 4_000_000)),
+                  fill_particles=int(getattr(a, "serve_fill_particles", 1_000_000)),
+                  other_policies=Server.POLICIES,
+                  sequential=not getattr(a, "no_sequential", False))
     print(json.dumps(out), flush=True)

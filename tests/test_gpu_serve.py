@@ -24,7 +24,7 @@ def serve():
 # 40 does not, so runs stop early at every observation (40, 10, 40, 10)
 @pytest.mark.parametrize("policy,final_only,run_steps",
                          (("all", False, 25), ("srpt", False, 25), ("srpt", True, 50),
-                          ("all", False, 40)))
+                          ("all", False, 40), ("fifo", True, 25)))
 def test_results_same_alone_and_in_the_mix(serve, policy, final_only, run_steps):
     reqs = serve.request_stream(10, 0.0, seed=8, nmin=1e4, nmax=8e4, steps=100)
     budget = 3 * max(serve.footprint(r) for r in reqs)
@@ -37,7 +37,7 @@ def test_results_same_alone_and_in_the_mix(serve, policy, final_only, run_steps)
     res = srv.run(reqs, realtime=False)
     assert srv.peak_live <= 4 and srv.peak_bytes <= budget
     assert srv.peak_live >= 2          # the requests overlapped on the device
-    if policy == "srpt":
+    if policy in ("srpt", "fifo"):
         assert srv.peak_held >= 1
     srv.close()
     assert sorted(r.rid for r in res) == list(range(len(reqs)))
@@ -104,3 +104,31 @@ def test_served_requests_anchor_to_the_oracle(serve, orc):
             final_only=True)
         for d in range(6):
             assert np.array_equal(got[d], alone[d]), (rid, d)
+
+
+def test_async_admission_reports_a_bad_state_at_sync(serve):
+    """An event admitted without waiting for the GPU whose initial state has
+    a particle outside the box is reported by the next sync, with its slot;
+    the event beside it keeps its result."""
+    from paper_1208_0961_amd import batch, cuba as C, sim
+    from paper_1208_0961_amd import workload as W
+    w = W.TUBE_1D
+    good = W.riemann_state(w, seed=3)
+    bad = [a.copy() for a in W.riemann_state(w, seed=4)]
+    bad[0][17] = 10.5   # outside [0, 10]
+    B = batch.Batch(4)
+    B.admit_async(1, w.params(), good, lanes=0)
+    B.admit_async(3, w.params(), bad, lanes=0)
+    with pytest.raises(C.CubaError) as e:
+        B.sync()
+    assert e.value.code == C.CUBA_ERANGE and e.value.slot == 3
+    B.retire(3)
+    B.step(5)
+    got = B.get_state(1)
+    B.close()
+    s = sim.Sim(w.params(), good)
+    s.step(5)
+    want = s.get_state()
+    s.close()
+    for d in range(6):
+        assert np.array_equal(got[d], want[d]), d

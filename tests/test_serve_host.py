@@ -104,6 +104,27 @@ def test_srpt_policy_choice(serve):
     assert srv2._choose(live) == set(live) and srv2.B.calls == []
 
 
+def test_fifo_policy_choice(serve):
+    """fifo: the oldest events in arrival order while they fit the particle
+    budget (the oldest always), then others by least remaining work while
+    they fit the fill budget."""
+    live = _live(serve, [(0, 0.5), (150, 0.1), (0, 0.2), (100, 0.3)])
+    n = {s: ev["req"].work.n for s, ev in live.items()}
+    srv = serve.Server.__new__(serve.Server)
+    srv.policy, srv.peak_held, srv.B = "fifo", 0, _FakeBatch()
+    # arrival order: 1, 2, 3, 0; room for two in arrival order, no fill
+    srv.run_particles, srv.fill_particles = n[1] + n[2], 0
+    assert srv._choose(live) == {1, 2}
+    assert sorted(srv.B.calls) == [(0, False), (3, False)]
+    # a fill of one event: the least remaining work among the rest (slot 3,
+    # 100 steps done, before slot 0 with none)
+    srv.fill_particles = n[3]
+    assert srv._choose(live) == {1, 2, 3}
+    # the oldest runs even past the budget
+    srv.run_particles, srv.fill_particles = 1, 0
+    assert srv._choose(live) == {1}
+
+
 def test_server_rejects_unknown_policy(serve):
     with pytest.raises(ValueError):
         serve.Server(policy="lifo", hbm_budget=1 << 20)
