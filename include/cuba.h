@@ -108,9 +108,9 @@ typedef struct {
 
 /* Bytes of device workspace cuba_init needs for n particles with these
  * parameters (for admission by memory footprint): two state buffers of
- * cells x cell_capacity slots of 52 bytes, each with a spill region of n
- * particles (56 bytes each), scratch of 10 bytes per particle for stepping
- * overflowing cells, and per-cell bookkeeping.  Returns 0 if the parameters
+ * cells x cell_capacity slots of 52 bytes, each with n spill slots (56
+ * bytes each, with the cell tag), scratch of 12 bytes per particle for
+ * stepping overflowing cells, and per-cell bookkeeping.  Returns 0 if the parameters
  * are invalid.  The workspace must be 256-byte aligned. */
 size_t cuba_workspace_bytes(const cuba_params *params, int64_t n);
 

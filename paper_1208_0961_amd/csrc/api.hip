@@ -36,12 +36,12 @@ inline size_t align256(size_t v) { return (v + 255u) & ~(size_t)255u; }
 // Byte offsets of every array inside the workspace.
 struct Layout {
   size_t status;
-  size_t soa[2][7];  // x y z px py pz id, for the two buffers (C x cap slots)
+  size_t soa[2][7];  // x y z px py pz id, for the two buffers: C x cap block
+                     // slots, then n spill slots
   size_t count[2];   // per-cell particle counts of the two buffers
   size_t spill_desc[2];      // SpillDesc of each buffer
-  size_t spill_soa[2][7];    // spilled particles (n slots)
   size_t spill_cell[2], spill_ocell[2], spill_hdr[2];
-  size_t pool, pool_hdr;     // overflow-kernel scratch
+  size_t pool_desc, pool, pool_hdr;  // scratch for stepping overflowing cells
   uint64_t pool_words;
   size_t offsets, tile_sums, cell_sums;
   size_t consts;  // device copy of the geometry
@@ -53,10 +53,11 @@ struct DeviceConsts {
   Geometry g;
 };
 
-// The spill region of a buffer holds every particle of the context (so no
-// binning can lose one); the overflow kernel's pool holds, per overflowing
-// cell of n members, n - cap + n + n / 2 + 1 words, at most 5 n_total / 2
-// plus one word per cell in all.
+// The spill slots of a buffer hold every particle of the context (so no
+// binning can lose one); the pool holds, per overflowing cell of n members,
+// its n - cap spilled members' slots and, for a cell larger than the LDS
+// holds, n + n / 2 + 1 + (n + 31) / 32 words more: at most 3 n_total plus 3
+// words per cell in all.
 Layout make_layout(int64_t n_cells, uint32_t cap, int64_t n) {
   Layout L{};
   size_t off = 0;
@@ -73,17 +74,16 @@ Layout make_layout(int64_t n_cells, uint32_t cap, int64_t n) {
   // the two buffers are laid out alike (every array of buffer 1 at one
   // distance from its twin in buffer 0)
   for (int b = 0; b < 2; ++b) {
-    for (int a = 0; a < 6; ++a) L.soa[b][a] = take(slots * sizeof(double));
-    L.soa[b][6] = take(slots * sizeof(uint32_t));
+    for (int a = 0; a < 6; ++a) L.soa[b][a] = take((slots + sn) * sizeof(double));
+    L.soa[b][6] = take((slots + sn) * sizeof(uint32_t));
     L.count[b] = take(cc * sizeof(uint32_t));
     L.spill_desc[b] = take(sizeof(SpillDesc));
-    for (int a = 0; a < 6; ++a) L.spill_soa[b][a] = take(sn * sizeof(double));
-    L.spill_soa[b][6] = take(sn * sizeof(uint32_t));
     L.spill_cell[b] = take(sn * sizeof(uint32_t));
     L.spill_ocell[b] = take(cc * sizeof(uint32_t));
     L.spill_hdr[b] = take(kSpillHdrWords * sizeof(uint32_t));
   }
-  L.pool_words = (uint64_t)sn * 5u / 2u + cc + 64u;
+  L.pool_words = (uint64_t)sn * 3u + 3u * cc + 64u;
+  L.pool_desc = take(sizeof(OverflowPool));
   L.pool = take((size_t)L.pool_words * sizeof(uint32_t));
   L.pool_hdr = take(2 * sizeof(unsigned long long));
   L.offsets = take((cc + 1) * sizeof(uint32_t));
@@ -147,8 +147,9 @@ int derive(const cuba_params *p, int64_t n, Derived &d) {
   if (p->cell_capacity < 0 || p->cell_capacity > (int32_t)kCellCap)
     return fail(CUBA_EINVAL, "cell_capacity must be in [0, " + std::to_string(kCellCap) + "]");
   d.cap = p->cell_capacity == 0 ? default_capacity(n, nc) : (uint32_t)p->cell_capacity;
-  if ((size_t)nc * d.cap >= ((size_t)1 << 40))
-    return fail(CUBA_EINVAL, "cells x cell_capacity too large");
+  // slots (blocks, then spill slots) are addressed with 32-bit indices
+  if ((uint64_t)nc * d.cap + (uint64_t)(n > 0 ? n : 1) >= ((uint64_t)1 << 32))
+    return fail(CUBA_EINVAL, "cells x cell_capacity + n must stay below 2^32 slots");
   return CUBA_OK;
 }
 
@@ -229,7 +230,6 @@ struct cuba_ctx {
   DevStatus *status;
   Cells buf[2];
   int cur;
-  OverflowPool pool;
   uint32_t *offsets, *tile_sums;
   double *cell_sums;
   DeviceConsts *consts;  // in the workspace
@@ -250,6 +250,7 @@ int check_launch(const char *where) {
 }
 
 enum Stage { kStageBin = 0, kStageStep, kStageCollide, kStageObserve, kStageOffsets };
+static_assert(kStageOffsets + 1 == CUBA_NUM_STAGES, "stage count");
 
 // Runs launch(); while timing, brackets it with two events on the stream.
 template <typename F>
@@ -307,7 +308,7 @@ int apply_dt(cuba_ctx *c, double dt) {
 }
 
 StepDevice step_device(const cuba_ctx *c) {
-  return StepDevice{&c->consts->g, c->pool, over_span(c->over, c->lanes, c->d.n_cells)};
+  return StepDevice{&c->consts->g, over_span(c->over, c->lanes, c->d.n_cells)};
 }
 
 // nsteps steps: stream + bin into the other buffer, then nsteps - 1 fused
@@ -322,7 +323,8 @@ int run_steps(cuba_ctx *c, int32_t nsteps, const TraceArgs *trace_in) {
   const SideStream *side = nullptr;
   stage(c, kStageBin, [&] {
     launch_stream_bin(c->buf[c->cur], c->buf[c->cur ^ 1], c->d.n_cells, c->lanes, c->d.g,
-                      c->status, trace_in ? trace_in->cell : nullptr, c->pool, c->stream);
+                      c->status, trace_in ? trace_in->cell : nullptr, c->next_step,
+                      c->stream);
   });
   c->cur ^= 1;
   for (int32_t s = 1; s < nsteps; ++s) {
@@ -417,25 +419,20 @@ int init_context(cuba_ctx *c, const Derived &d, const cuba_params *params, int64
     c->buf[b].cap = d.cap;
     c->buf[b].sp = (SpillDesc *)(ws + L.spill_desc[b]);
   }
+  OverflowPool hpool{};
+  hpool.buf = (uint32_t *)(ws + L.pool);
+  hpool.hdr = (unsigned long long *)(ws + L.pool_hdr);
+  hpool.capacity = L.pool_words;
   SpillDesc hsd[2];
   for (int b = 0; b < 2; ++b) {
-    SoA &st = hsd[b].st;
-    st.x = (double *)(ws + L.spill_soa[b][0]);
-    st.y = (double *)(ws + L.spill_soa[b][1]);
-    st.z = (double *)(ws + L.spill_soa[b][2]);
-    st.px = (double *)(ws + L.spill_soa[b][3]);
-    st.py = (double *)(ws + L.spill_soa[b][4]);
-    st.pz = (double *)(ws + L.spill_soa[b][5]);
-    st.id = (uint32_t *)(ws + L.spill_soa[b][6]);
     hsd[b].cell = (uint32_t *)(ws + L.spill_cell[b]);
     hsd[b].ocell = (uint32_t *)(ws + L.spill_ocell[b]);
     hsd[b].hdr = (uint32_t *)(ws + L.spill_hdr[b]);
+    hsd[b].pool = (OverflowPool *)(ws + L.pool_desc);
+    hsd[b].base = (uint64_t)d.n_cells * d.cap;
     hsd[b].capacity = n > 0 ? (uint32_t)n : 1u;
     hsd[b].pad = 0;
   }
-  c->pool.buf = (uint32_t *)(ws + L.pool);
-  c->pool.hdr = (unsigned long long *)(ws + L.pool_hdr);
-  c->pool.capacity = L.pool_words;
   // the kernels derive one buffer's arrays from the other's by a single
   // byte distance: every array of buffer 1 lies that far from its twin
   const ptrdiff_t shift = (char *)c->buf[1].st.x - (char *)c->buf[0].st.x;
@@ -459,14 +456,17 @@ int init_context(cuba_ctx *c, const Derived &d, const cuba_params *params, int64
   launch_fill_u32(c->buf[0].count, 0u, d.n_cells, c->stream);
   launch_fill_u32(c->buf[1].count, 0u, d.n_cells, c->stream);
   for (int b = 0; b < 2; ++b) launch_fill_u32(hsd[b].hdr, 0u, kSpillHdrWords, c->stream);
-  launch_fill_u32((uint32_t *)c->pool.hdr, 0u, 4, c->stream);
+  launch_fill_u32((uint32_t *)hpool.hdr, 0u, 4, c->stream);
   // the constants and (each in its buffer's region, one buffer's distance
   // apart) the two spill descriptors, written by kernels in stream order
   bool ok = launch_write_bytes(c->consts, &hc, sizeof(hc), c->stream);
+  ok = ok && launch_write_bytes(hsd[0].pool, &hpool, sizeof(hpool), c->stream);
   for (int b = 0; b < 2; ++b)
     ok = ok && launch_write_bytes(c->buf[b].sp, &hsd[b], sizeof(SpillDesc), c->stream);
   if (!ok) return fail(CUBA_EDEVICE, "internal: constants do not fit a write launch");
-  launch_init_bin(x, y, z, px, py, pz, c->buf[0], n, d.g, c->status, c->stream);
+  // the initial binning is consumed by the stream-bin of step step0
+  launch_init_bin(x, y, z, px, py, pz, c->buf[0], n, d.g, c->status, c->next_step - 1u,
+                  c->stream);
   launch_occupancy_over(c->buf[0], d.n_cells, c->status, c->stream);
   rc = check_launch("init launch");
   if (rc != CUBA_OK) return rc;
@@ -637,7 +637,8 @@ int cuba_observe(cuba_ctx *c, double *T00, double *T0x) {
   if (!c || !T00 || !T0x) return fail(CUBA_EINVAL, "NULL argument");
   const SlabOut out{T00, T0x, nullptr, nullptr, nullptr, nullptr};
   stage(c, kStageObserve, [&] {
-    launch_observe(c->buf[c->cur], c->d.g, c->d.vol, c->cell_sums, out, c->stream);
+    launch_observe(c->buf[c->cur], c->d.g, c->d.vol, c->cell_sums, out, c->next_step - 1u,
+                   c->stream);
   });
   return check_launch("observe launch");
 }
@@ -647,7 +648,8 @@ int cuba_observe_moments(cuba_ctx *c, double *out) {
   const int64_t nx = c->d.g.n[0];
   const SlabOut o{out, out + nx, out + 2 * nx, out + 3 * nx, out + 4 * nx, out + 5 * nx};
   stage(c, kStageObserve, [&] {
-    launch_observe(c->buf[c->cur], c->d.g, c->d.vol, c->cell_sums, o, c->stream);
+    launch_observe(c->buf[c->cur], c->d.g, c->d.vol, c->cell_sums, o, c->next_step - 1u,
+                   c->stream);
   });
   return check_launch("observe launch");
 }
@@ -657,7 +659,8 @@ int cuba_get_state(cuba_ctx *c, double *x, double *y, double *z, double *px,
   if (!c) return fail(CUBA_EINVAL, "ctx is NULL");
   if (c->n > 0 && !(x && y && z && px && py && pz))
     return fail(CUBA_EINVAL, "NULL output array");
-  launch_gather_by_id(c->buf[c->cur], c->d.n_cells, x, y, z, px, py, pz, c->stream);
+  launch_gather_by_id(c->buf[c->cur], c->d.n_cells, x, y, z, px, py, pz, c->next_step - 1u,
+                      c->stream);
   return check_launch("get_state launch");
 }
 
@@ -888,7 +891,6 @@ int upload_table(cuba_batch *b) {
     e.g = c->d.g;
     e.pa = c->pa;
     e.status = c->status;
-    e.pool = c->pool;
     e.n_cells = (uint32_t)c->d.n_cells;
     e.cpi = (uint32_t)b->slot_cpi[s];
     e.cur = (uint32_t)c->cur;

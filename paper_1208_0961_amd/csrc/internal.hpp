@@ -33,27 +33,33 @@ struct SoA {
   uint32_t *id;
 };
 
-// Where a buffer keeps the particles its cells could not hold: cell c owns
-// slots [c cap, c cap + min(count[c], cap)) of the buffer's arrays; a cell
-// that receives more (count[c] > cap, an overflowing cell) keeps the surplus
-// here, each entry tagged with its cell, and is listed once in ocell.  The
-// region holds every particle of the context, so no binning can lose one.
-// In device memory beside the buffer's arrays (the kernels load it only on
-// the rare paths that touch it).
+// Where a buffer keeps the particles its cells could not hold.  Every array
+// of a buffer has n_cells * cap block slots followed by `capacity` spill
+// slots: cell c owns block slots [c cap, c cap + min(count[c], cap)), and a
+// cell that receives more (count[c] > cap, an overflowing cell) keeps the
+// surplus in spill slots, each tagged with its cell, the cell itself listed
+// once in ocell.  The spill slots hold every particle of the context, so no
+// binning can lose one.  Counters come in two sets, used by alternate
+// binnings of the buffer (set (b >> 1) & 1 for the binning of step b): a
+// launch that consumes one set clears the other, which no launch uses then.
+// In device memory beside the buffer's arrays (kernels load it only on the
+// rare paths that touch it).
+struct OverflowPool;
 struct SpillDesc {
-  SoA st;          // spilled particles, capacity `capacity`
-  uint32_t *cell;  // the cell of each spilled particle
-  uint32_t *ocell; // the overflowing cells, in the order they overflowed
-  uint32_t *hdr;   // [0] spilled particles, [1] overflowing cells
+  uint32_t *cell;   // the cell of each spilled particle
+  uint32_t *ocell;  // the overflowing cells, in the order they overflowed
+  uint32_t *hdr;    // per set q: [2q] spilled particles, [2q + 1] overflowing cells
+  OverflowPool *pool;  // scratch for stepping overflowing cells
+  uint64_t base;    // first spill slot: n_cells * cap
   uint32_t capacity;
   uint32_t pad;
 };
 constexpr uint32_t kSpillHdrWords = 4;
+__host__ __device__ inline uint32_t spill_set(uint32_t binning_step) {
+  return (binning_step >> 1) & 1u;
+}
 
-// A binned state with a fixed capacity per cell: cell c owns slots
-// [c cap, c cap + min(count[c], cap)) of every array, count[c] being the
-// number of particles the cell holds; any beyond cap are in the spill
-// region (sp).
+// A binned state with a fixed capacity per cell (see SpillDesc).
 struct Cells {
   SoA st;
   uint32_t *count;
@@ -61,14 +67,15 @@ struct Cells {
   SpillDesc *sp;
 };
 
-// Scratch of the overflow kernel (one per context, used by one launch at a
-// time): member lists, canonical orders and claims of the overflowing cells
-// it steps, allocated from `buf` by a counter; hdr[0] the counter, hdr[1]
-// the count of workgroups that finished the launch.
+// Scratch of the kernels stepping overflowing cells: the spilled members'
+// slots of each such cell, and for cells larger than the LDS holds their
+// canonical order, claimed flags and claims, allocated from `buf` by a
+// counter: counter t & 1 serves the collisions of step t (the launch of
+// step t clears counter (t + 1) & 1, last used two launches before).
 struct OverflowPool {
   uint32_t *buf;
-  unsigned long long *hdr;
-  uint64_t capacity;  // u32 words
+  unsigned long long *hdr;  // [2] counters
+  uint64_t capacity;        // u32 words
 };
 
 // Device-resident bookkeeping at the head of the workspace.  The work
@@ -108,7 +115,6 @@ struct BatchEvent {
   Geometry g;
   PairArgs pa;
   DevStatus *status;
-  OverflowPool pool;
   uint32_t n_cells;
   uint32_t cpi;         // cells per work item
   uint32_t item_begin;  // first work item of this event
@@ -160,23 +166,24 @@ void launch_store_f64(double *p, double v, hipStream_t s);
 // the call neither waits for the stream nor needs src after it returns).
 // False if the size or alignment does not fit.
 bool launch_write_bytes(void *dst, const void *src, size_t bytes, hipStream_t s);
+// Validates and bins the id-ordered initial state into dst; the binning is
+// that of step `binning_step` (step0 - 1: the stream-bin of step0 consumes
+// it).
 void launch_init_bin(const double *x, const double *y, const double *z,
                      const double *px, const double *py, const double *pz,
                      const Cells &dst, int64_t n, const Geometry &g, DevStatus *st,
-                     hipStream_t s);
-// Stream + bin every particle of src into dst: the block parts by the
-// stream-bin kernel, then the spilled ones by the overflow kernel (which
-// then resets src's spill region and pool).
+                     uint32_t binning_step, hipStream_t s);
+// Stream + bin every particle of src (the binning of step t - 1) into dst
+// (the binning of step t), spilled ones included.
 void launch_stream_bin(const Cells &src, const Cells &dst, int64_t n_cells, uint32_t lanes,
                        const Geometry &g, DevStatus *status, uint32_t *trace_cell,
-                       const OverflowPool &pool, hipStream_t s);
+                       uint32_t t, hipStream_t s);
 void launch_offsets(const Cells &cur, uint32_t *offsets, uint32_t *tile_sums,
                     int64_t n_cells, hipStream_t s);
 // Device copy of the geometry, which the wave-per-cell kernel reads from
 // memory where it uses it.
 struct StepDevice {
   const Geometry *g;
-  OverflowPool pool;  // scratch of the overflow kernel
   // cells per wave of the oversize-cell kernel: 64 (a wave scans 64 cells
   // and steps the oversize ones one after another; few oversize cells) or 1
   // (a wave per cell; many)
@@ -185,8 +192,8 @@ struct StepDevice {
 
 // One collision launch (fused: then streaming + binning of the next step).
 // lanes > 0: the small-cell kernel on s and, concurrently on side (if not
-// NULL; else after it on s), the kernel for the cells it leaves alone.
-// Then, on s, the overflow kernel for the overflowing cells.
+// NULL; else after it on s), the kernel for the cells it leaves alone
+// (overflowing cells among them).
 // dev: device copy of g (equal to the host value).  The buffers src and
 // dst must be laid out alike (every array at the same distance from its twin).
 void launch_step(const Cells &src, const Cells &dst, bool fused, int64_t n_cells,
@@ -202,9 +209,10 @@ struct SlabOut {
   double *T00, *T0x, *Txx, *n, *e, *v;
 };
 constexpr uint32_t kCellSums = 4;  // per cell: sum E, sum p_x, sum p_x^2 / E, count
-// cell_sums: scratch of kCellSums doubles per cell.
+// cell_sums: scratch of kCellSums doubles per cell.  cur holds the binning
+// of step binning_step.
 void launch_observe(const Cells &cur, const Geometry &g, double vol, double *cell_sums,
-                    const SlabOut &out, hipStream_t s);
+                    const SlabOut &out, uint32_t binning_step, hipStream_t s);
 // A run of k >= 1 steps of every event in the device table ev (n_events
 // live events): stream + bin, k - 1 fused steps, the last collisions, then
 // the table advance.  The work spaces: items of cells_per_item cells for the
@@ -224,6 +232,7 @@ void launch_batch_run(BatchEvent *ev, const BatchSpaces &spaces, uint32_t n_even
                       uint32_t persistent_waves, hipStream_t s, const SideStream *side,
                       void (*between)(void *, int), void *ctx);
 void launch_gather_by_id(const Cells &cur, int64_t n_cells, double *x, double *y,
-                         double *z, double *px, double *py, double *pz, hipStream_t s);
+                         double *z, double *px, double *py, double *pz,
+                         uint32_t binning_step, hipStream_t s);
 
 }  // namespace cuba

@@ -40,6 +40,15 @@ namespace {
 constexpr int kBlock = 256;
 constexpr uint32_t kCellsPerBlock = kBlock / 64;
 
+// Waves per SIMD the one-wave-per-cell kernels are held to: six with the
+// LDS of 512-slot cells (80 VGPRs; the rare paths for overflowing cells
+// would otherwise raise the count for all), four with that of 1024 (the
+// LDS allows no more).
+template <uint32_t kCap>
+constexpr int cell_waves() {
+  return kCap <= kSmallCap ? 6 : 4;
+}
+
 // Device views of the particle buffers with global-address-space pointers:
 // every kernel converts its Cells once at entry, so that all buffer accesses
 // compile to global (not flat) memory instructions, also where the pointers
@@ -57,6 +66,7 @@ struct GCells {
   gptr<uint32_t> count;
   uint32_t cap;
   SpillDesc *sp;
+  uint32_t q;  // the spill counter set of the binning this view holds or receives
 };
 
 __device__ __forceinline__ GCells to_global(const Cells &c) {
@@ -71,7 +81,14 @@ __device__ __forceinline__ GCells to_global(const Cells &c) {
   g.count = (gptr<uint32_t>)c.count;
   g.cap = c.cap;
   g.sp = c.sp;
+  g.q = 0u;
   return g;
+}
+
+// The view of a buffer holding (or receiving) the binning of step b.
+__device__ __forceinline__ GCells binning(GCells c, uint32_t b) {
+  c.q = spill_set(b);
+  return c;
 }
 
 __device__ __forceinline__ uint32_t atomic_add(gptr<uint32_t> p, uint32_t v) {
@@ -123,29 +140,31 @@ __device__ __forceinline__ uint32_t xcd_runs(uint32_t b, uint32_t nblocks) {
   return s * kSuper + (r % kXcds) * kRun + r / kXcds;
 }
 
-// A particle that took slot `slot` >= cap of cell c2 goes to dst's spill
-// region, tagged with its cell; the one particle that takes slot cap lists
-// the cell among the overflowing ones.  The region holds every particle of
-// the context, so the index check only guards against an internal error.
+// A particle that took slot `slot` >= cap of cell c2 goes to a spill slot
+// of dst, tagged with its cell; the one particle that takes slot cap lists
+// the cell among the overflowing ones.  The spill slots hold every particle
+// of the context, so the index check only guards against an internal error.
 __device__ __forceinline__ void spill_particle(const GCells &dst, uint32_t c2, uint32_t slot,
                                                double x, double y, double z, double px,
                                                double py, double pz, uint32_t id,
                                                DevStatus *status) {
   SpillDesc *const sp = dst.sp;
-  const uint32_t i = atomicAdd(&sp->hdr[0], 1u);
+  uint32_t *const h = sp->hdr + 2u * dst.q;
+  const uint32_t i = atomicAdd(&h[0], 1u);
   if (i < sp->capacity) {
-    sp->st.x[i] = x;
-    sp->st.y[i] = y;
-    sp->st.z[i] = z;
-    sp->st.px[i] = px;
-    sp->st.py[i] = py;
-    sp->st.pz[i] = pz;
-    sp->st.id[i] = id;
+    const size_t o = sp->base + i;
+    dst.st.x[o] = x;
+    dst.st.y[o] = y;
+    dst.st.z[o] = z;
+    dst.st.px[o] = px;
+    dst.st.py[o] = py;
+    dst.st.pz[o] = pz;
+    dst.st.id[o] = id;
     sp->cell[i] = c2;
   } else {
     atomicOr(&status->err, kErrSpill);
   }
-  if (slot == dst.cap) sp->ocell[atomicAdd(&sp->hdr[1], 1u)] = c2;
+  if (slot == dst.cap) sp->ocell[atomicAdd(&h[1], 1u)] = c2;
 }
 
 // Appends particle (r, p, id) to cell c2 of dst: into the cell's block, or
@@ -177,6 +196,11 @@ __device__ __forceinline__ gptr<T> shift_ptr(gptr<T> p, int64_t shift) {
   return (gptr<T>)((gptr<char>)p + shift);
 }
 
+// The destination of a collision launch of step t: src shifted by the
+// distance between the two buffers, receiving the binning of step t + 1.
+__device__ __forceinline__ GCells shifted(const GCells &c, int64_t shift);
+__device__ __forceinline__ GCells dst_of(const GCells &src, int64_t shift, uint32_t t);
+
 __device__ __forceinline__ GCells shifted(const GCells &c, int64_t shift) {
   GCells d;
   d.st.x = shift_ptr(c.st.x, shift);
@@ -189,7 +213,12 @@ __device__ __forceinline__ GCells shifted(const GCells &c, int64_t shift) {
   d.count = shift_ptr(c.count, shift);
   d.cap = c.cap;
   d.sp = (SpillDesc *)((char *)c.sp + shift);
+  d.q = c.q;
   return d;
+}
+
+__device__ __forceinline__ GCells dst_of(const GCells &src, int64_t shift, uint32_t t) {
+  return binning(shifted(src, shift), t + 1u);
 }
 
 // One particle in registers.
@@ -298,8 +327,8 @@ __global__ __launch_bounds__(kBlock) void k_init_bin(
     const double *__restrict__ x, const double *__restrict__ y,
     const double *__restrict__ z, const double *__restrict__ px,
     const double *__restrict__ py, const double *__restrict__ pz, Cells dst_arg,
-    int64_t n, Geometry g, DevStatus *status) {
-  const GCells dst = to_global(dst_arg);
+    int64_t n, Geometry g, DevStatus *status, uint32_t binning_step) {
+  const GCells dst = binning(to_global(dst_arg), binning_step);
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool active = i < n;
   double a = 0, b = 0, c = 0, qa = 0, qb = 0, qc = 0;
@@ -348,6 +377,39 @@ __global__ __launch_bounds__(kBlock) void k_occupancy_over(Cells cur_arg, uint32
   }
 }
 
+// Stream + reflect + bin the spilled members of overflowing cell cv of src
+// (found by a scan of the spill slots) into dst.  The whole wave.
+__device__ __forceinline__ void stream_spilled(const GCells &src, const GCells &dst, uint32_t cv,
+                                               const Geometry &g, DevStatus *status,
+                                               uint32_t *trace_cell) {
+  const SpillDesc *const sp = src.sp;
+  const uint32_t ns = min(sp->hdr[2u * src.q], sp->capacity);
+  const size_t sbase = sp->base;
+  const uint32_t lane = lane_id();
+  for (uint32_t i0 = 0; i0 < ns; i0 += 64u) {
+    const uint32_t i = i0 + lane;
+    const bool hit = i < ns && sp->cell[i] == cv;
+    if (__ballot(hit) == 0) continue;
+    Particle q{};
+    uint32_t c2 = 0;
+    if (hit) {
+      q = load_particle(src.st, sbase + i);
+      advance<true>(g, q.x, q.y, q.z, q.px, q.py, q.pz);
+      c2 = cell_id(g, q.x, q.y, q.z);
+      if (trace_cell) trace_cell[q.id] = c2;
+    }
+    append(dst, c2, hit, q.x, q.y, q.z, q.px, q.py, q.pz, q.id, status);
+  }
+}
+
+// Clears the spill counter set of `c` that no launch uses now: the one of
+// the binning two steps after (or before) the one c holds.
+__device__ __forceinline__ void clear_idle_spill_set(const GCells &c) {
+  uint32_t *const h = c.sp->hdr + 2u * (c.q ^ 1u);
+  h[0] = 0u;
+  h[1] = 0u;
+}
+
 // Stream + reflect + bin the particles of the source cells c0 .. c_end - 1
 // (at most 64 / G of them), G lanes per cell; G = 64 is one wave per cell.
 // Clears the source counts, so the source buffer can receive the next
@@ -360,8 +422,17 @@ __device__ __forceinline__ void cells_stream_bin(const GCells &src, const GCells
   const uint32_t lane = lane_id();
   const uint32_t c = c0 + lane / G, gl = lane % G;
   const bool in_range = c < c_end;
-  const uint32_t n = in_range ? occupancy(src, c) : 0u;
+  const uint32_t cnt = in_range ? src.count[c] : 0u;
+  const uint32_t n = cnt < src.cap ? cnt : src.cap;  // the block part
   const size_t base = (size_t)c * src.cap;
+  // then the spilled members of overflowing cells
+  const uint64_t ovm = __ballot(in_range && gl == 0 && cnt > src.cap);
+  if (ovm != 0) {
+    for (uint64_t m = ovm; m != 0; m &= m - 1ull) {
+      const uint32_t cv = (uint32_t)__builtin_amdgcn_readlane((int)c, __builtin_ctzll(m));
+      stream_spilled(src, dst, cv, g, status, trace_cell);
+    }
+  }
   if (G == 64) {
     // one cell: 128 particles per round, both halves' atomics in flight together
     for (uint32_t j0 = 0; j0 < n; j0 += 128) {
@@ -408,18 +479,20 @@ __device__ __forceinline__ void cells_stream_bin(const GCells &src, const GCells
   if (in_range && gl == 0) src.count[c] = 0u;
 }
 
-// Four waves per block; each wave takes 64 / G consecutive source cells.
+// Four waves per block; each wave takes 64 / G consecutive source cells;
+// src holds the binning of step t - 1, dst receives that of step t.
 template <uint32_t G>
 __global__ __launch_bounds__(kBlock) void k_stream_bin(Cells src_arg, Cells dst_arg,
                                                        uint32_t n_cells, Geometry g,
                                                        DevStatus *status,
-                                                       uint32_t *trace_cell) {
-  const GCells src = to_global(src_arg);
-  const GCells dst = to_global(dst_arg);
+                                                       uint32_t *trace_cell, uint32_t t) {
+  const GCells src = binning(to_global(src_arg), t - 1u);
+  const GCells dst = binning(to_global(dst_arg), t);
   constexpr uint32_t kPer = 64 / G;
   const uint32_t c0 =
       (xcd_runs<2>(blockIdx.x, gridDim.x) * kCellsPerBlock + threadIdx.x / 64) * kPer;
   if (c0 >= n_cells) return;
+  if (c0 == 0 && lane_id() == 0) clear_idle_spill_set(src);
   const uint32_t c_end = c0 + kPer < n_cells ? c0 + kPer : n_cells;
   cells_stream_bin<G>(src, dst, c0, c_end, g, status, trace_cell);
 }
@@ -488,9 +561,28 @@ __global__ __launch_bounds__(kBlock) void k_scan_carry(uint32_t *offsets,
 // ---------------------------------------------------------------------------
 // Collisions: one wave64 (one workgroup) per cell, or two (k_step2).
 // ---------------------------------------------------------------------------
+// A cell being stepped: member j is slot base + j of the buffer's arrays,
+// or, in an overflowing cell (ov), for j >= cap spill slot sbase + sidx[j -
+// cap] (at_spill).  ov is uniform over the workgroup, so normal cells take
+// the first form without a per-lane choice.  Once an overflowing cell's
+// slots are listed in LDS (slots), at() reads them there, which keeps fewer
+// values live than the two-part form.
 struct CellView {
   uint32_t c, n, t;
   size_t base;
+  uint32_t cap;
+  bool ov;
+  size_t sbase;
+  const uint32_t *sidx;
+  const uint32_t *slots;
+  __device__ __forceinline__ size_t at_spill(uint32_t j) const {
+    if (ov && j >= cap) return sbase + sidx[j - cap];
+    return base + j;
+  }
+  __device__ __forceinline__ size_t at(uint32_t j) const {
+    if (ov) return slots[j];
+    return base + j;
+  }
 };
 
 // Orders the calling wave's LDS accesses before and after this point for
@@ -530,7 +622,7 @@ __device__ __forceinline__ void resolve_filtered(
     const double u = uniform53(w.w0, w.w1);
     uint32_t a, b;
     pair_of_index(k, cv.n, a, b);
-    const size_t ia = cv.base + s_perm[a], ib = cv.base + s_perm[b];
+    const size_t ia = cv.at(s_perm[a]), ib = cv.at(s_perm[b]);
     const double P = p22(st.px[ia], st.py[ia], st.pz[ia], st.px[ib], st.py[ib],
                          st.pz[ib], pa.kfac);
     const bool acc = u < P;
@@ -648,6 +740,7 @@ struct CellLds {
   uint16_t perm[kCap];
   __align__(16) uint32_t bkt[kRankBuckets + 4];  // bucket ends, then starts
   uint32_t sorted[kCap];                         // ids in bucket order
+  uint32_t ov_pool_lo, ov_pool_hi, ov_ok, pad;   // an overflowing cell's scratch
 };
 
 // LDS of the second wave of a cell stepped by two: its filtered pairs, and
@@ -658,6 +751,205 @@ struct SecondWaveLds {
   uint32_t filt[kCap / 2];
   uint32_t n_filt, k_resume, nclaim, pad;
 };
+
+// The launch of step t clears the scratch that no launch uses now: src's
+// idle spill counter set and the pool counter of step t + 1.
+__device__ __forceinline__ void clear_idle_scratch(const GCells &src, uint32_t t) {
+  clear_idle_spill_set(src);
+  src.sp->pool->hdr[(t + 1u) & 1u] = 0ull;
+}
+
+// Wave 0 of an overflowing cell's workgroup: takes scratch from the pool
+// (counter t & 1) for the slots of the cell's spilled members -- and, for a
+// cell larger than the LDS holds, its canonical order, claimed flags and
+// claims -- and lists those slots (a scan of the spill slots, in increasing
+// order).  Leaves the scratch offset and a success flag in LDS.
+template <bool kFused, uint32_t kCap>
+__device__ void find_spilled(const GCells &src, const CellView &cv, CellLds<kFused, kCap> &lds,
+                             DevStatus *status) {
+  const uint32_t lane = lane_id();
+  const uint64_t below = (1ull << lane) - 1ull;
+  const SpillDesc *const sd = src.sp;
+  OverflowPool *const pool = sd->pool;
+  const uint32_t n = cv.n, nsp = n - cv.cap;
+  const uint32_t ns = min(sd->hdr[2u * src.q], sd->capacity);
+  uint64_t need = nsp;
+  if (n > kCap) need += (uint64_t)n + n / 2u + 1u + (n + 31u) / 32u;
+  uint32_t lo = 0, hi = 0;
+  if (lane == 0) {
+    const unsigned long long b = atomicAdd(&pool->hdr[cv.t & 1u], (unsigned long long)need);
+    lo = (uint32_t)b;
+    hi = (uint32_t)(b >> 32);
+  }
+  lo = (uint32_t)__shfl((int)lo, 0);
+  hi = (uint32_t)__shfl((int)hi, 0);
+  const uint64_t b = ((uint64_t)hi << 32) | lo;
+  bool ok = b + need <= pool->capacity;
+  if (ok) {
+    uint32_t *const mem = pool->buf + b;
+    uint32_t found = 0;
+    for (uint32_t i0 = 0; i0 < ns; i0 += 64u) {
+      const uint32_t i = i0 + lane;
+      const bool hit = i < ns && sd->cell[i] == cv.c;
+      const uint64_t mk = __ballot(hit);
+      if (hit) {
+        const uint32_t slot = found + (uint32_t)__popcll(mk & below);
+        if (slot < nsp) mem[slot] = i;
+      }
+      found += (uint32_t)__popcll(mk);
+    }
+    ok = found == nsp;
+  }
+  if (lane == 0) {
+    if (!ok) atomicOr(&status->err, kErrSpill);
+    lds.ov_pool_lo = lo;
+    lds.ov_pool_hi = hi;
+    lds.ov_ok = ok ? 1u : 0u;
+  }
+}
+
+// The collisions of an overflowing cell larger than the LDS holds (then,
+// kFused, the binning of its members), by one wave with its canonical
+// order, claimed flags and claims in global scratch: ranks by counting
+// smaller ids against chunks staged in LDS, pair tests 64 at a time in
+// increasing k (Philox w1 filter, then Eq. (3)), each row's accepted pairs
+// claimed in k order, then the kinematics.  A cell past the 32-bit pair
+// index skips its collisions (flagged); its members are still binned.
+template <bool kFused, bool kTrace, uint32_t kCap>
+__device__ void large_cell_step(const GCells &src, const GCells &dst, const CellView &cv,
+                                const PairArgs &pa, const Geometry &g, DevStatus *status,
+                                const TraceArgs &tr, CellLds<kFused, kCap> &lds) {
+  const uint32_t lane = lane_id();
+  const uint32_t n = cv.n;
+  uint32_t *const perm = const_cast<uint32_t *>(cv.sidx) + (n - cv.cap);
+  uint32_t *const claims = perm + n;
+  uint32_t *const bits = claims + n / 2u + 1u;
+  const GSoA &st = src.st;
+  uint32_t npairs = 0;  // < 2^32 below the pair-index bound
+  uint32_t nclaim = 0, n_acc = 0;
+  if (n > kMaxPairIndexCell) {
+    if (lane == 0) atomicOr(&status->err, kErrPairIndex);
+  } else {
+    for (uint32_t j0 = 0; j0 < n; j0 += 64u) {
+      const uint32_t j = j0 + lane;
+      const uint32_t me = j < n ? st.id[cv.at_spill(j)] : 0xFFFFFFFFu;
+      uint32_t r = 0;
+      for (uint32_t i0 = 0; i0 < n; i0 += kCap) {
+        const uint32_t cnt = min(kCap, n - i0);
+        wave_lds_sync();
+        for (uint32_t i = lane; i < cnt; i += 64u) lds.buf[i] = st.id[cv.at_spill(i0 + i)];
+        wave_lds_sync();
+        if (j < n)
+          for (uint32_t i = 0; i < cnt; ++i) r += lds.buf[i] < me ? 1u : 0u;
+      }
+      if (j < n) {
+        perm[r] = j;
+        if (kTrace && tr.perm) tr.perm[tr.offsets[cv.c] + r] = me;
+      }
+    }
+    for (uint32_t w = lane; w < (n + 31u) / 32u; w += 64u) bits[w] = 0u;
+    wave_lds_sync();
+    npairs = (uint32_t)((uint64_t)n * (n - 1u) / 2u);
+    // k0 + 64 stays below 2^32: npairs <= 4 294 930 221
+    for (uint32_t k0 = 0; pa.any && k0 < npairs; k0 += 64u) {
+      const uint32_t k = k0 + lane;
+      bool acc = false;
+      if (k < npairs && philox10_w1(k, cv.c, cv.t, 0u, pa.key0, pa.key1) <= pa.w1_max) {
+        const Words4 w = philox10(k, cv.c, cv.t, 0u, pa.key0, pa.key1);
+        uint32_t a, b;
+        pair_of_index64(k, n, a, b);
+        const size_t ia = cv.at_spill(perm[a]), ib = cv.at_spill(perm[b]);
+        acc = uniform53(w.w0, w.w1) <
+              p22(st.px[ia], st.py[ia], st.pz[ia], st.px[ib], st.py[ib], st.pz[ib], pa.kfac);
+        if (kTrace && acc && tr.cand) {
+          const uint32_t slot = atomicAdd(&tr.counts[0], 1u);
+          if (slot < tr.cand_cap) {
+            tr.cand[3 * (size_t)slot + 0] = cv.c;
+            tr.cand[3 * (size_t)slot + 1] = a;
+            tr.cand[3 * (size_t)slot + 2] = b;
+          } else {
+            atomicOr(&status->err, kErrTrace);
+          }
+        }
+      }
+      n_acc += acc ? 1u : 0u;
+      for (uint64_t m = __ballot(acc); m != 0; m &= m - 1ull) {
+        const uint32_t kk = k0 + (uint32_t)__builtin_ctzll(m);
+        uint32_t a, b;
+        pair_of_index64(kk, n, a, b);
+        const uint32_t wa = bits[a >> 5], wb = bits[b >> 5];
+        if (((wa >> (a & 31u)) & 1u) == 0u && ((wb >> (b & 31u)) & 1u) == 0u) {
+          if (lane == 0) {
+            if ((a >> 5) == (b >> 5)) {
+              bits[a >> 5] = wa | (1u << (a & 31u)) | (1u << (b & 31u));
+            } else {
+              bits[a >> 5] = wa | (1u << (a & 31u));
+              bits[b >> 5] = wb | (1u << (b & 31u));
+            }
+            claims[nclaim] = kk;
+          }
+          ++nclaim;
+          wave_lds_sync();
+        }
+      }
+    }
+  }
+  wave_lds_sync();
+  for (uint32_t i0 = 0; i0 < nclaim; i0 += 64u) {
+    const uint32_t i = i0 + lane;
+    if (i < nclaim) {
+      const uint32_t k = claims[i];
+      uint32_t a, b;
+      pair_of_index64(k, n, a, b);
+      const Words4 w = philox10(k, cv.c, cv.t, 1u, pa.key0, pa.key1);
+      const size_t ia = cv.at_spill(perm[a]), ib = cv.at_spill(perm[b]);
+      double ax = st.px[ia], ay = st.py[ia], az = st.pz[ia];
+      double bx = st.px[ib], by = st.py[ib], bz = st.pz[ib];
+      scatter_pair(ax, ay, az, bx, by, bz, uniform53(w.w0, w.w1), uniform53(w.w2, w.w3));
+      st.px[ia] = ax;
+      st.py[ia] = ay;
+      st.pz[ia] = az;
+      st.px[ib] = bx;
+      st.py[ib] = by;
+      st.pz[ib] = bz;
+      if (kTrace && tr.claim) {
+        const uint32_t slot = atomicAdd(&tr.counts[1], 1u);
+        if (slot < tr.claim_cap) {
+          tr.claim[3 * (size_t)slot + 0] = cv.c;
+          tr.claim[3 * (size_t)slot + 1] = a;
+          tr.claim[3 * (size_t)slot + 2] = b;
+        } else {
+          atomicOr(&status->err, kErrTrace);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) n_acc += __shfl_down(n_acc, o);
+  if (lane == 0) {
+    const uint32_t slot = cv.c % kCounterSlots;
+    atomicAdd(&status->pairs[slot], (unsigned long long)npairs);
+    atomicAdd(&status->cand[slot], (unsigned long long)n_acc);
+    atomicAdd(&status->claims[slot], (unsigned long long)nclaim);
+  }
+  wave_lds_sync();  // new momenta visible to the binning lanes
+  if (kFused) {
+    const Geometry g_l = g;
+    for (uint32_t j0 = 0; j0 < n; j0 += 64u) {
+      const uint32_t j = j0 + lane;
+      const bool active = j < n;
+      Particle q{};
+      uint32_t c2 = 0;
+      if (active) {
+        q = load_particle(st, cv.at_spill(j));
+        advance<true>(g_l, q.x, q.y, q.z, q.px, q.py, q.pz);
+        c2 = cell_id(g_l, q.x, q.y, q.z);
+      }
+      append(dst, c2, active, q.x, q.y, q.z, q.px, q.py, q.pz, q.id, status);
+    }
+    if (lane == 0) src.count[cv.c] = 0u;
+  }
+}
 
 // Collisions of cell c of src at step t by a workgroup of kW waves (1 or
 // 2).  kFused: afterwards stream and bin the cell's particles into dst for
@@ -695,11 +987,28 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
   cv.c = c;
   cv.t = t;
   cv.base = (size_t)cv.c * src.cap;
-  // an overflowing cell (some members spilled) is stepped by the overflow
-  // kernel, which also clears its count
-  const uint32_t cnt = src.count[cv.c];
-  const bool overflowing = cnt > src.cap;
-  cv.n = overflowing ? 0u : cnt;
+  cv.cap = src.cap;
+  cv.n = src.count[cv.c];
+  cv.ov = cv.n > src.cap;
+  cv.sbase = 0;
+  cv.sidx = nullptr;
+  cv.slots = lds.sorted;
+  if (cv.c == 0 && tid == 0) clear_idle_scratch(src, t);
+  if (cv.ov) {
+    // an overflowing cell: find its spilled members (wave 0), then step it
+    // here, in LDS if it fits, else with the global-memory method
+    if (wv == 0) find_spilled<kFused, kCap>(src, cv, lds, status);
+    __syncthreads();
+    if (lds.ov_ok == 0u) return;  // internal error, flagged
+    const SpillDesc *const sd = src.sp;
+    cv.sbase = sd->base;
+    cv.sidx = sd->pool->buf + (((uint64_t)lds.ov_pool_hi << 32) | lds.ov_pool_lo);
+    if (cv.n > kCap) {
+      if (wv == 0)
+        large_cell_step<kFused, kTrace, kCap>(src, dst, cv, pa, g, status, tr, lds);
+      return;
+    }
+  }
   const uint32_t n = cv.n;
   const GSoA &st = src.st;
 
@@ -708,7 +1017,7 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
     // ids to LDS, padded to a multiple of 4 with an id no particle has
     const uint32_t n4 = (n + 3u) & ~3u;
     for (uint32_t j = tid; j < n4; j += kT)
-      s_id[j] = j < n ? st.id[cv.base + j] : 0xFFFFFFFFu;
+      s_id[j] = j < n ? st.id[cv.at_spill(j)] : 0xFFFFFFFFu;
     __syncthreads();
 
     // canonical order: the rank of each id among the cell's ids
@@ -784,6 +1093,10 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
       }
     }
     __syncthreads();
+    if (cv.ov) {  // the members' slots, in LDS (the rank no longer needs it)
+      for (uint32_t j = tid; j < n; j += kT) lds.sorted[j] = (uint32_t)cv.at_spill(j);
+      __syncthreads();
+    }
 
     // every pair k = 0 .. n(n-1)/2 - 1 (test_pairs), then the exact test
     // and the claims of the filtered ones in increasing k
@@ -866,7 +1179,7 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
         const double uphi = uniform53(w.w2, w.w3);
         ja = s_perm[a];
         jb = s_perm[b];
-        const size_t ia = cv.base + ja, ib = cv.base + jb;
+        const size_t ia = cv.at(ja), ib = cv.at(jb);
         ax = st.px[ia];
         ay = st.py[ia];
         az = st.pz[ia];
@@ -894,7 +1207,7 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
     }
     if (kFused) __syncthreads();
   } else if (kTrace && n == 1 && tid == 0 && tr.perm) {
-    tr.perm[tr.offsets[cv.c]] = st.id[cv.base];
+    tr.perm[tr.offsets[cv.c]] = st.id[cv.at_spill(0)];
   }
 
   if (kFused) {
@@ -909,7 +1222,7 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
       double x = 0, y = 0, z = 0, px = 0, py = 0, pz = 0;
       uint32_t id = 0, c2 = 0;
       if (active) {
-        const size_t o = cv.base + j;
+        const size_t o = cv.at(j);
         x = st.x[o];
         y = st.y[o];
         z = st.z[o];
@@ -922,7 +1235,7 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
       }
       append(dst, c2, active, x, y, z, px, py, pz, id, status);
     }
-    if (tid == 0 && !overflowing) src.count[cv.c] = 0u;
+    if (tid == 0) src.count[cv.c] = 0u;
   }
 }
 
@@ -968,7 +1281,8 @@ __device__ __forceinline__ uint64_t small_cells_step(const GCells &src, const GC
   const uint32_t grp = lane / G, gl = lane % G;
   const uint32_t c = c0 + grp;
   const bool in_range = c < c_end;
-  // overflowing cells are left to the overflow kernel
+  if (c0 == 0 && lane == 0) clear_idle_scratch(src, t);
+  // overflowing cells are left to the kernel for larger cells
   const uint32_t cnt = in_range ? src.count[c] : 0u;
   const bool overflowing = cnt > src.cap;
   const uint32_t n = overflowing ? 0u : cnt;
@@ -1139,8 +1453,10 @@ __device__ __forceinline__ void large_cells_step(const GCells &src, const GCells
                                                  const TraceArgs &tr,
                                                  CellLds<kFused, kCap> &lds) {
   const uint32_t c = c0 + lane_id();
-  const uint32_t n = c < c_end ? occupancy(src, c) : 0u;
-  uint64_t big = __ballot(n > lanes);
+  const uint32_t n = c < c_end ? src.count[c] : 0u;
+  // the cells the small-cell kernel leaves: more particles than lanes, or
+  // overflowing (more than the block holds)
+  uint64_t big = __ballot(n > lanes || n > src.cap);
   while (big != 0) {
     const uint32_t l = (uint32_t)__builtin_ctzll(big);
     big &= big - 1ull;
@@ -1152,8 +1468,8 @@ template <bool kFused, bool kTrace, uint32_t G>
 __global__ __launch_bounds__(64) void k_step_small(Cells src_arg, Cells dst_arg, uint32_t n_cells,
                                                    uint32_t t, PairArgs pa, Geometry g,
                                                    DevStatus *status, TraceArgs tr) {
-  const GCells src = to_global(src_arg);
-  const GCells dst = to_global(dst_arg);
+  const GCells src = binning(to_global(src_arg), t);
+  const GCells dst = binning(to_global(dst_arg), t + 1u);
   __shared__ SmallLds lds;
   constexpr uint32_t kPer = 64 / G;
   const uint32_t c0 = xcd_runs<8>(blockIdx.x, gridDim.x) * kPer;
@@ -1164,12 +1480,13 @@ __global__ __launch_bounds__(64) void k_step_small(Cells src_arg, Cells dst_arg,
 // One wave per 64 consecutive cells: the cells holding more than `lanes`
 // particles.
 template <bool kFused, bool kTrace, uint32_t kCap>
-__global__ __launch_bounds__(64) void k_step_large(Cells src_arg, Cells dst_arg, uint32_t n_cells,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_step_large(
+    Cells src_arg, Cells dst_arg, uint32_t n_cells,
                                                    uint32_t lanes, uint32_t t, PairArgs pa,
                                                    Geometry g, DevStatus *status,
                                                    TraceArgs tr) {
-  const GCells src = to_global(src_arg);
-  const GCells dst = to_global(dst_arg);
+  const GCells src = binning(to_global(src_arg), t);
+  const GCells dst = binning(to_global(dst_arg), t + 1u);
   __shared__ CellLds<kFused, kCap> lds;
   const uint32_t c0 = blockIdx.x * 64u;
   const uint32_t c_end = c0 + 64u < n_cells ? c0 + 64u : n_cells;
@@ -1181,15 +1498,17 @@ __global__ __launch_bounds__(64) void k_step_large(Cells src_arg, Cells dst_arg,
 // oversize-cell launch when such cells are common (a wave that scans 64 of
 // them would step them one after another).
 template <bool kFused, bool kTrace, uint32_t kCap>
-__global__ __launch_bounds__(64) void k_step_over(Cells src_arg, int64_t dst_shift,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(cell_waves<kCap>()))) void k_step_over(
+    Cells src_arg, int64_t dst_shift,
                                                   uint32_t lanes, uint32_t t, PairArgs pa,
                                                   const Geometry *__restrict__ gp,
                                                   DevStatus *status, TraceArgs tr) {
-  const GCells src = to_global(src_arg);
+  const GCells src = binning(to_global(src_arg), t);
   __shared__ CellLds<kFused, kCap> lds;
   const uint32_t c = xcd_runs<8>(blockIdx.x, gridDim.x);
-  if (occupancy(src, c) <= lanes) return;
-  cell_step<kFused, kTrace, kCap>(src, shifted(src, dst_shift), c, t, pa, *gp, status, tr,
+  const uint32_t cnt = src.count[c];
+  if (cnt <= lanes && cnt <= src.cap) return;
+  cell_step<kFused, kTrace, kCap>(src, dst_of(src, dst_shift, t), c, t, pa, *gp, status, tr,
                                   lds);
 }
 
@@ -1200,12 +1519,13 @@ __global__ __launch_bounds__(64) void k_step_over(Cells src_arg, int64_t dst_shi
 // in the loop.  Derived from src, the dst pointers stay known to address
 // global memory.
 template <bool kFused, bool kTrace, uint32_t kCap>
-__global__ __launch_bounds__(64) void k_step(Cells src_arg, int64_t dst_shift, uint32_t t,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(cell_waves<kCap>()))) void k_step(
+    Cells src_arg, int64_t dst_shift, uint32_t t,
                                              PairArgs pa, const Geometry *__restrict__ gp,
                                              DevStatus *status, TraceArgs tr) {
-  const GCells src = to_global(src_arg);
+  const GCells src = binning(to_global(src_arg), t);
   __shared__ CellLds<kFused, kCap> lds;
-  cell_step<kFused, kTrace, kCap>(src, shifted(src, dst_shift),
+  cell_step<kFused, kTrace, kCap>(src, dst_of(src, dst_shift, t),
                                   xcd_runs<8>(blockIdx.x, gridDim.x), t, pa, *gp, status, tr,
                                   lds);
 }
@@ -1214,362 +1534,18 @@ __global__ __launch_bounds__(64) void k_step(Cells src_arg, int64_t dst_shift, u
 // box of few cells has twice as many, shorter waves to spread over the
 // SIMDs (the tail of a launch whose waves are long and few is idle time).
 template <bool kFused, uint32_t kCap>
-__global__ __launch_bounds__(128) void k_step2(Cells src_arg, int64_t dst_shift, uint32_t t,
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(cell_waves<kCap>()))) void k_step2(
+    Cells src_arg, int64_t dst_shift, uint32_t t,
                                                PairArgs pa, const Geometry *__restrict__ gp,
                                                DevStatus *status) {
-  const GCells src = to_global(src_arg);
+  const GCells src = binning(to_global(src_arg), t);
   __shared__ CellLds<kFused, kCap> lds;
   __shared__ SecondWaveLds<kCap> x2;
-  cell_step<kFused, false, kCap, 2>(src, shifted(src, dst_shift),
+  cell_step<kFused, false, kCap, 2>(src, dst_of(src, dst_shift, t),
                                     xcd_runs<8>(blockIdx.x, gridDim.x), t, pa, *gp, status,
                                     TraceArgs{}, lds, &x2);
 }
 
-
-// ---------------------------------------------------------------------------
-// Overflowing cells.  A cell that receives more particles than its block
-// holds keeps the surplus in the buffer's spill region.  The main kernels
-// leave such cells alone (the stream-bin kernel streams their block part);
-// this kernel, launched after them, does the rest:
-//   kOvStream   stream + reflect + bin the spilled particles;
-//   kOvCollide  the collisions of every overflowing cell, in place;
-//   kOvFused    the collisions, then stream + bin every member.
-// A workgroup steps one overflowing cell at a time with a method that holds
-// for any cell size: members found by a scan of the spill list, canonical
-// order by counting smaller ids, pair tests in rounds of kOvRound
-// consecutive pair indices (Philox w1 filter, then Eq. (3)), the round's
-// accepted pairs claimed in pair order by one lane, and the kinematics of
-// the claimed pairs.  The only bound is the 32-bit pair index of the
-// random-number contract.  The last workgroup to finish resets the scratch
-// pool and, when the source buffer is consumed, its spill region.
-// ---------------------------------------------------------------------------
-constexpr uint32_t kOvBlock = 256;
-constexpr uint32_t kOvWaves = kOvBlock / 64;
-constexpr uint32_t kOvRound = 4096;                 // pairs per claim round
-constexpr uint32_t kOvPerWave = kOvRound / kOvWaves;  // 16 rows of 64 per wave
-enum : uint32_t { kOvStream = 0, kOvCollide = 1, kOvFused = 2 };
-
-struct OverflowLds {
-  uint32_t claimed[(kMaxPairIndexCell + 31) / 32];  // by canonical index
-  uint32_t buf[kOvRound];  // ids while ranking; accepted pairs of a round
-  uint32_t wave_n[kOvWaves];
-  uint64_t pool_base;
-  uint32_t found, nclaim, skip;
-};
-
-__device__ __forceinline__ GSoA to_gsoa(const SoA &a) {
-  GSoA g;
-  g.x = (gptr<double>)a.x;
-  g.y = (gptr<double>)a.y;
-  g.z = (gptr<double>)a.z;
-  g.px = (gptr<double>)a.px;
-  g.py = (gptr<double>)a.py;
-  g.pz = (gptr<double>)a.pz;
-  g.id = (gptr<uint32_t>)a.id;
-  return g;
-}
-
-// Member j of an overflowing cell: slot j of its block (j < cap) or spill
-// entry mem[j - cap].
-struct Members {
-  GSoA blk, spl;
-  size_t base;
-  uint32_t cap;
-  const uint32_t *mem;
-  __device__ __forceinline__ bool spilled(uint32_t j) const { return j >= cap; }
-  __device__ __forceinline__ size_t at(uint32_t j) const {
-    return j < cap ? base + j : (size_t)mem[j - cap];
-  }
-  // (the array of each field is selected on its own, so that no view is
-  // indexed dynamically)
-  __device__ __forceinline__ uint32_t id(uint32_t j) const {
-    const bool s = spilled(j);
-    return (s ? spl.id : blk.id)[at(j)];
-  }
-  __device__ __forceinline__ Particle load(uint32_t j) const {
-    const bool s = spilled(j);
-    const size_t o = at(j);
-    return Particle{(s ? spl.x : blk.x)[o],   (s ? spl.y : blk.y)[o],
-                    (s ? spl.z : blk.z)[o],   (s ? spl.px : blk.px)[o],
-                    (s ? spl.py : blk.py)[o], (s ? spl.pz : blk.pz)[o],
-                    (s ? spl.id : blk.id)[o]};
-  }
-  __device__ __forceinline__ void momentum(uint32_t j, double &px, double &py,
-                                           double &pz) const {
-    const bool s = spilled(j);
-    const size_t o = at(j);
-    px = (s ? spl.px : blk.px)[o];
-    py = (s ? spl.py : blk.py)[o];
-    pz = (s ? spl.pz : blk.pz)[o];
-  }
-  __device__ __forceinline__ void set_momentum(uint32_t j, double px, double py,
-                                               double pz) const {
-    const bool s = spilled(j);
-    const size_t o = at(j);
-    (s ? spl.px : blk.px)[o] = px;
-    (s ? spl.py : blk.py)[o] = py;
-    (s ? spl.pz : blk.pz)[o] = pz;
-  }
-};
-
-// The collisions of overflowing cell c of src at step t by the calling
-// workgroup; kFused: then stream + bin its members into dst and clear its
-// count.
-template <bool kFused, bool kTrace>
-__device__ void overflow_cell(const GCells &src, const GCells &dst, uint32_t c, uint32_t t,
-                              const PairArgs &pa, const Geometry &g, DevStatus *status,
-                              const TraceArgs &tr, const OverflowPool &pool,
-                              OverflowLds &lds) {
-  const uint32_t tid = threadIdx.x, lane = lane_id(), wv = tid / 64;
-  const uint64_t below = (1ull << lane) - 1ull;
-  const SpillDesc *const sd = src.sp;
-  const uint32_t n = src.count[c];
-  const uint32_t cap = src.cap;
-  const uint32_t nsp = n - cap;  // > 0: the cell overflowed
-  const uint32_t ns = min(sd->hdr[0], sd->capacity);
-  Members m;
-  m.blk = src.st;
-  m.spl = to_gsoa(sd->st);
-  m.base = (size_t)c * cap;
-  m.cap = cap;
-  __syncthreads();  // the previous cell's readers of lds are done
-  if (tid == 0) {
-    // scratch: the spilled members' indices, the canonical order, the claims
-    const uint64_t need = (uint64_t)nsp + n + n / 2u + 1u;
-    const uint64_t b = atomicAdd(&pool.hdr[0], (unsigned long long)need);
-    lds.skip = b + need > pool.capacity ? 1u : 0u;
-    if (lds.skip) atomicOr(&status->err, kErrSpill);
-    lds.pool_base = b;
-    lds.found = 0u;
-    lds.nclaim = 0u;
-  }
-  __syncthreads();
-  if (lds.skip) return;
-  uint32_t *const mem = pool.buf + lds.pool_base;
-  uint32_t *const perm = mem + nsp;
-  uint32_t *const claims = perm + n;
-  m.mem = mem;
-
-  // the spilled members (found in arbitrary order; the ranks fix the order)
-  for (uint32_t i0 = wv * 64u; i0 < ns; i0 += kOvBlock) {
-    const uint32_t i = i0 + lane;
-    const bool hit = i < ns && sd->cell[i] == c;
-    const uint64_t mk = __ballot(hit);
-    if (mk != 0) {
-      uint32_t at = 0;
-      if (lane == 0) at = atomicAdd(&lds.found, (uint32_t)__popcll(mk));
-      at = (uint32_t)__shfl((int)at, 0);
-      const uint32_t slot = at + (uint32_t)__popcll(mk & below);
-      if (hit && slot < nsp) mem[slot] = i;
-    }
-  }
-  __syncthreads();
-  if (lds.found != nsp) {  // internal inconsistency: leave the cell as it is
-    if (tid == 0) atomicOr(&status->err, kErrSpill);
-    return;
-  }
-
-  // canonical order: the rank of each member's id among the cell's ids,
-  // counted against chunks of ids staged in LDS (not needed by a cell too
-  // full for the pair index, whose collisions are skipped)
-  const bool too_big = n > kMaxPairIndexCell;
-  for (uint32_t j0 = 0; !too_big && j0 < n; j0 += kOvBlock) {
-    const uint32_t j = j0 + tid;
-    const uint32_t me = j < n ? m.id(j) : 0xFFFFFFFFu;
-    uint32_t r = 0;
-    for (uint32_t i0 = 0; i0 < n; i0 += kOvRound) {
-      const uint32_t cnt = min(kOvRound, n - i0);
-      __syncthreads();
-      for (uint32_t i = tid; i < cnt; i += kOvBlock) lds.buf[i] = m.id(i0 + i);
-      __syncthreads();
-      if (j < n)
-        for (uint32_t i = 0; i < cnt; ++i) r += lds.buf[i] < me ? 1u : 0u;
-    }
-    if (j < n) {
-      perm[r] = j;
-      if (kTrace && tr.perm) tr.perm[tr.offsets[c] + r] = me;
-    }
-  }
-
-  // pair tests in rounds: wave w tests the round's w-th quarter and
-  // compacts its accepted pairs in increasing k; one lane then claims the
-  // round's pairs in pair order
-  const uint64_t npairs = too_big ? 0u : (uint64_t)n * (n - 1u) / 2u;
-  if (too_big && tid == 0) atomicOr(&status->err, kErrPairIndex);
-  const uint32_t words = too_big ? 0u : (n + 31u) / 32u;
-  for (uint32_t w = tid; w < words; w += kOvBlock) lds.claimed[w] = 0u;
-  __syncthreads();
-  uint32_t n_acc = 0;
-  if (pa.any) {
-    for (uint64_t r0 = 0; r0 < npairs; r0 += kOvRound) {
-      uint32_t nw = 0;
-      const uint64_t kb = r0 + (uint64_t)wv * kOvPerWave;
-      for (uint32_t it = 0; it < kOvPerWave; it += 64u) {
-        const uint64_t k = kb + it + lane;
-        bool acc = false;
-        if (k < npairs) {
-          const uint32_t k32 = (uint32_t)k;
-          if (philox10_w1(k32, c, t, 0u, pa.key0, pa.key1) <= pa.w1_max) {
-            const Words4 w = philox10(k32, c, t, 0u, pa.key0, pa.key1);
-            uint32_t a, b;
-            pair_of_index64(k, n, a, b);
-            double ax, ay, az, bx, by, bz;
-            m.momentum(perm[a], ax, ay, az);
-            m.momentum(perm[b], bx, by, bz);
-            acc = uniform53(w.w0, w.w1) < p22(ax, ay, az, bx, by, bz, pa.kfac);
-            if (kTrace && acc && tr.cand) {
-              const uint32_t slot = atomicAdd(&tr.counts[0], 1u);
-              if (slot < tr.cand_cap) {
-                tr.cand[3 * (size_t)slot + 0] = c;
-                tr.cand[3 * (size_t)slot + 1] = a;
-                tr.cand[3 * (size_t)slot + 2] = b;
-              } else {
-                atomicOr(&status->err, kErrTrace);
-              }
-            }
-          }
-        }
-        n_acc += acc ? 1u : 0u;
-        const uint64_t mk = __ballot(acc);
-        if (acc) lds.buf[wv * kOvPerWave + nw + (uint32_t)__popcll(mk & below)] = (uint32_t)k;
-        nw += (uint32_t)__popcll(mk);
-      }
-      if (lane == 0) lds.wave_n[wv] = nw;
-      __syncthreads();
-      if (tid == 0) {
-        uint32_t nc = lds.nclaim;
-        for (uint32_t q = 0; q < kOvWaves; ++q)
-          for (uint32_t i = 0; i < lds.wave_n[q]; ++i) {
-            const uint32_t k = lds.buf[q * kOvPerWave + i];
-            uint32_t a, b;
-            pair_of_index64(k, n, a, b);
-            const uint32_t ma = 1u << (a & 31u), mb = 1u << (b & 31u);
-            if ((lds.claimed[a >> 5] & ma) == 0u && (lds.claimed[b >> 5] & mb) == 0u) {
-              lds.claimed[a >> 5] |= ma;
-              lds.claimed[b >> 5] |= mb;
-              claims[nc++] = k;
-            }
-          }
-        lds.nclaim = nc;
-      }
-      __syncthreads();
-    }
-  }
-
-  // kinematics of the claimed pairs (disjoint members), in place
-  const uint32_t nclaim = lds.nclaim;
-  for (uint32_t i = tid; i < nclaim; i += kOvBlock) {
-    const uint32_t k = claims[i];
-    uint32_t a, b;
-    pair_of_index64(k, n, a, b);
-    const Words4 w = philox10(k, c, t, 1u, pa.key0, pa.key1);
-    const uint32_t ja = perm[a], jb = perm[b];
-    double ax, ay, az, bx, by, bz;
-    m.momentum(ja, ax, ay, az);
-    m.momentum(jb, bx, by, bz);
-    scatter_pair(ax, ay, az, bx, by, bz, uniform53(w.w0, w.w1), uniform53(w.w2, w.w3));
-    m.set_momentum(ja, ax, ay, az);
-    m.set_momentum(jb, bx, by, bz);
-    if (kTrace && tr.claim) {
-      const uint32_t slot = atomicAdd(&tr.counts[1], 1u);
-      if (slot < tr.claim_cap) {
-        tr.claim[3 * (size_t)slot + 0] = c;
-        tr.claim[3 * (size_t)slot + 1] = a;
-        tr.claim[3 * (size_t)slot + 2] = b;
-      } else {
-        atomicOr(&status->err, kErrTrace);
-      }
-    }
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) n_acc += __shfl_down(n_acc, o);
-  const uint32_t slot = c % kCounterSlots;
-  if (lane == 0 && n_acc != 0) atomicAdd(&status->cand[slot], (unsigned long long)n_acc);
-  if (tid == 0) {
-    atomicAdd(&status->pairs[slot], (unsigned long long)npairs);
-    atomicAdd(&status->claims[slot], (unsigned long long)nclaim);
-  }
-  __syncthreads();  // new momenta visible to the binning lanes
-
-  if (kFused) {
-    const Geometry g_l = g;
-    for (uint32_t j0 = wv * 64u; j0 < n; j0 += kOvBlock) {
-      const uint32_t j = j0 + lane;
-      const bool active = j < n;
-      Particle q{};
-      uint32_t c2 = 0;
-      if (active) {
-        q = m.load(j);
-        advance<true>(g_l, q.x, q.y, q.z, q.px, q.py, q.pz);
-        c2 = cell_id(g_l, q.x, q.y, q.z);
-      }
-      append(dst, c2, active, q.x, q.y, q.z, q.px, q.py, q.pz, q.id, status);
-    }
-    if (tid == 0) src.count[c] = 0u;
-  }
-}
-
-// The overflow work of one launch (see above) by workgroup `group` of
-// n_groups.  trace_cell (kOvStream, may be NULL): new cell of each
-// streamed particle, by id.
-template <uint32_t kMode, bool kTrace>
-__device__ void overflow_work(const GCells &src, const GCells &dst, uint32_t t,
-                              const PairArgs &pa, const Geometry &g, DevStatus *status,
-                              const TraceArgs &tr, const OverflowPool &pool, uint32_t group,
-                              uint32_t n_groups, uint32_t *trace_cell, OverflowLds &lds) {
-  SpillDesc *const sd = src.sp;
-  if (kMode == kOvStream) {
-    const uint32_t ns = min(sd->hdr[0], sd->capacity);
-    const GSoA spl = to_gsoa(sd->st);
-    const uint32_t lane = lane_id(), wv = threadIdx.x / 64u;
-    const Geometry g_l = g;
-    for (uint32_t i0 = group * kOvBlock + wv * 64u; i0 < ns; i0 += n_groups * kOvBlock) {
-      const uint32_t i = i0 + lane;
-      const bool active = i < ns;
-      Particle q{};
-      uint32_t c2 = 0;
-      if (active) {
-        q = load_particle(spl, i);
-        advance<true>(g_l, q.x, q.y, q.z, q.px, q.py, q.pz);
-        c2 = cell_id(g_l, q.x, q.y, q.z);
-        if (trace_cell) trace_cell[q.id] = c2;
-      }
-      append(dst, c2, active, q.x, q.y, q.z, q.px, q.py, q.pz, q.id, status);
-    }
-  } else {
-    const uint32_t nover = sd->hdr[1];
-    for (uint32_t o = group; o < nover; o += n_groups)
-      overflow_cell<kMode == kOvFused, kTrace>(src, dst, sd->ocell[o], t, pa, g, status, tr,
-                                               pool, lds);
-  }
-  // the last workgroup out resets the pool and, if src was consumed, its
-  // spill region (every workgroup has finished reading both)
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned long long done = atomicAdd(&pool.hdr[1], 1ull);
-    if (done == (unsigned long long)n_groups - 1ull) {
-      pool.hdr[0] = 0ull;
-      pool.hdr[1] = 0ull;
-      if (kMode != kOvCollide) {
-        sd->hdr[0] = 0u;
-        sd->hdr[1] = 0u;
-      }
-      __threadfence();
-    }
-  }
-}
-
-template <uint32_t kMode, bool kTrace>
-__global__ __launch_bounds__(kOvBlock) void k_overflow(Cells src_arg, Cells dst_arg, uint32_t t,
-                                                       PairArgs pa, Geometry g,
-                                                       DevStatus *status, TraceArgs tr,
-                                                       OverflowPool pool,
-                                                       uint32_t *trace_cell) {
-  __shared__ OverflowLds lds;
-  overflow_work<kMode, kTrace>(to_global(src_arg), to_global(dst_arg), t, pa, g, status, tr,
-                               pool, blockIdx.x, gridDim.x, trace_cell, lds);
-}
 
 // ---------------------------------------------------------------------------
 // Batched steps: all live events of a batch advance together.  Each kernel
@@ -1632,6 +1608,8 @@ __device__ __forceinline__ EventView event_view(const BatchEvent *__restrict__ E
   v.pa = E->pa;
   v.status = E->status;
   v.t = E->t + j - 1u;
+  v.src = binning(v.src, v.t);
+  v.dst = binning(v.dst, v.t + 1u);
   v.lanes = E->lanes;
   v.n_cells = E->n_cells;
   return v;
@@ -1652,6 +1630,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_bin(const BatchEvent *__restri
       src = to_global(E->buf[1]);
       dst = to_global(E->buf[0]);
     }
+    src = binning(src, E->t - 1u);
+    dst = binning(dst, E->t);
+    if (item == E->item_begin && lane_id() == 0) clear_idle_spill_set(src);
     const Geometry g = E->g;
     DevStatus *const status = E->status;
     const uint32_t cpi = E->cpi, n_cells = E->n_cells, lanes = E->lanes;
@@ -1704,7 +1685,8 @@ __global__ __launch_bounds__(64) void k_batch_step_small(const BatchEvent *__res
 // The cells of 64 consecutive cells of a small-cell event holding more than
 // its lanes per cell (rare), by the whole wave.
 template <bool kFused, uint32_t kCap>
-__global__ __launch_bounds__(64) void k_batch_step_scan(const BatchEvent *__restrict__ ev,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_step_scan(
+    const BatchEvent *__restrict__ ev,
                                                         const uint32_t *__restrict__ scan_begin,
                                                         uint32_t n_events, uint32_t j) {
   __shared__ CellLds<kFused, kCap> lds;
@@ -1721,7 +1703,8 @@ __global__ __launch_bounds__(64) void k_batch_step_scan(const BatchEvent *__rest
 // register budget of 5 waves per SIMD, as the plain kernel (it fits without
 // scratch; the event lookup would otherwise push it 1 register over).
 template <bool kFused, uint32_t kCap>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_batch_step_cells(const BatchEvent *__restrict__ ev,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(cell_waves<kCap>()))) void k_batch_step_cells(
+    const BatchEvent *__restrict__ ev,
                                                          const uint32_t *__restrict__ cell_begin,
                                                          uint32_t n_events, uint32_t j) {
   __shared__ CellLds<kFused, kCap> lds;
@@ -1731,28 +1714,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
   // (laid out alike), g is read by reference from the table where the
   // binning uses it (see k_step)
   const uint32_t s = (E->cur ^ (j & 1u)) & 1u;
-  const GCells src = to_global(E->buf[s]);
+  const uint32_t t = E->t + j - 1u;
+  const GCells src = binning(to_global(E->buf[s]), t);
   const int64_t shift = (const char *)E->buf[s ^ 1u].st.x - (const char *)E->buf[s].st.x;
   const PairArgs pa = E->pa;
-  cell_step<kFused, false, kCap>(src, shifted(src, shift), unit - E->cell_begin, E->t + j - 1u,
+  cell_step<kFused, false, kCap>(src, dst_of(src, shift, t), unit - E->cell_begin, t,
                                  pa, E->g, E->status, TraceArgs{}, lds);
 }
 
-
-// The overflow work of every event for launch j of a run (j = 0: the
-// spilled particles of the stream-bin launch): groups_per_event workgroups
-// per event, event e taking workgroups [e g, (e + 1) g).
-template <uint32_t kMode>
-__global__ __launch_bounds__(kOvBlock) void k_batch_overflow(const BatchEvent *__restrict__ ev,
-                                                             uint32_t j,
-                                                             uint32_t groups_per_event) {
-  __shared__ OverflowLds lds;
-  const BatchEvent *__restrict__ E = ev + blockIdx.x / groups_per_event;
-  const EventView v = event_view(E, j);
-  const OverflowPool pool = E->pool;
-  overflow_work<kMode, false>(v.src, v.dst, v.t, v.pa, v.g, v.status, TraceArgs{}, pool,
-                              blockIdx.x % groups_per_event, groups_per_event, nullptr, lds);
-}
 
 // End of a run of k steps: every event moved k buffers and k step indices.
 __global__ void k_batch_advance(BatchEvent *ev, uint32_t n_events, uint32_t k) {
@@ -1769,8 +1738,9 @@ __global__ void k_batch_advance(BatchEvent *ev, uint32_t n_events, uint32_t k) {
 // range [ix ny nz, (ix+1) ny nz).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_observe_cells(Cells cur_arg, uint32_t n_cells,
-                                                          double *cell_sums) {
-  const GCells cur = to_global(cur_arg);
+                                                          double *cell_sums,
+                                                          uint32_t binning_step) {
+  const GCells cur = binning(to_global(cur_arg), binning_step);
   const uint32_t lane = lane_id();
   const uint32_t c = blockIdx.x * kCellsPerBlock + threadIdx.x / 64;
   if (c >= n_cells) return;
@@ -1788,10 +1758,11 @@ __global__ __launch_bounds__(kBlock) void k_observe_cells(Cells cur_arg, uint32_
   }
   if (cnt > cur.cap) {  // overflowing: its spilled members, in spill order
     const SpillDesc *const spl = cur.sp;
-    const uint32_t ns = min(spl->hdr[0], spl->capacity);
+    const uint32_t ns = min(spl->hdr[2u * cur.q], spl->capacity);
     for (uint32_t i = lane; i < ns; i += 64) {
       if (spl->cell[i] != c) continue;
-      const double px = spl->st.px[i], py = spl->st.py[i], pz = spl->st.pz[i];
+      const size_t o = spl->base + i;
+      const double px = cur.st.px[o], py = cur.st.py[o], pz = cur.st.pz[o];
       const double e = norm3(px, py, pz);
       se += e;
       sp += px;
@@ -1871,8 +1842,8 @@ __global__ __launch_bounds__(kBlock) void k_observe_slabs(const double *cell_sum
 __global__ __launch_bounds__(kBlock) void k_gather_by_id(Cells cur_arg, uint32_t n_cells,
                                                          double *x, double *y, double *z,
                                                          double *px, double *py,
-                                                         double *pz) {
-  const GCells cur = to_global(cur_arg);
+                                                         double *pz, uint32_t binning_step) {
+  const GCells cur = binning(to_global(cur_arg), binning_step);
   const uint32_t lane = lane_id();
   const uint32_t c = blockIdx.x * kCellsPerBlock + threadIdx.x / 64;
   if (c >= n_cells) return;
@@ -1889,16 +1860,17 @@ __global__ __launch_bounds__(kBlock) void k_gather_by_id(Cells cur_arg, uint32_t
   }
   if (cur.count[c] > cur.cap) {  // overflowing: its spilled members
     const SpillDesc *const spl = cur.sp;
-    const uint32_t ns = min(spl->hdr[0], spl->capacity);
+    const uint32_t ns = min(spl->hdr[2u * cur.q], spl->capacity);
     for (uint32_t i = lane; i < ns; i += 64) {
       if (spl->cell[i] != c) continue;
-      const uint32_t id = spl->st.id[i];
-      x[id] = spl->st.x[i];
-      y[id] = spl->st.y[i];
-      z[id] = spl->st.z[i];
-      px[id] = spl->st.px[i];
-      py[id] = spl->st.py[i];
-      pz[id] = spl->st.pz[i];
+      const size_t o = spl->base + i;
+      const uint32_t id = cur.st.id[o];
+      x[id] = cur.st.x[o];
+      y[id] = cur.st.y[o];
+      z[id] = cur.st.z[o];
+      px[id] = cur.st.px[o];
+      py[id] = cur.st.py[o];
+      pz[id] = cur.st.pz[o];
     }
   }
 }
@@ -1934,31 +1906,15 @@ bool launch_write_bytes(void *dst, const void *src, size_t bytes, hipStream_t s)
 void launch_init_bin(const double *x, const double *y, const double *z,
                      const double *px, const double *py, const double *pz,
                      const Cells &dst, int64_t n, const Geometry &g, DevStatus *st,
-                     hipStream_t s) {
+                     uint32_t binning_step, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_init_bin, dim3(grid_for(n)), dim3(kBlock), 0, s, x, y, z, px, py,
-                     pz, dst, n, g, st);
+                     pz, dst, n, g, st, binning_step);
 }
-
-namespace {
-// Workgroups of an overflow launch: each steps one overflowing cell at a time
-// (or streams a share of the spilled particles).
-constexpr uint32_t kOvGroups = 16;
-// ... per event of a batch.
-constexpr uint32_t kOvGroupsBatch = 4;
-
-template <uint32_t kMode, bool kTrace>
-void launch_overflow_mode(const Cells &src, const Cells &dst, uint32_t t, const PairArgs &pa,
-                          const Geometry &g, DevStatus *status, const TraceArgs &tr,
-                          const OverflowPool &pool, uint32_t *trace_cell, hipStream_t s) {
-  hipLaunchKernelGGL((k_overflow<kMode, kTrace>), dim3(kOvGroups), dim3(kOvBlock), 0, s, src,
-                     dst, t, pa, g, status, tr, pool, trace_cell);
-}
-}  // namespace
 
 void launch_stream_bin(const Cells &src, const Cells &dst, int64_t n_cells, uint32_t lanes,
                        const Geometry &g, DevStatus *status, uint32_t *trace_cell,
-                       const OverflowPool &pool, hipStream_t s) {
+                       uint32_t t, hipStream_t s) {
   if (n_cells <= 0) return;
   const uint32_t G = lanes == 0 || lanes == kTwoWavesPerCell ? 64u : lanes;
   const int64_t waves = (n_cells + 64 / G - 1) / (64 / G);
@@ -1966,20 +1922,21 @@ void launch_stream_bin(const Cells &src, const Cells &dst, int64_t n_cells, uint
   const uint32_t nc = (uint32_t)n_cells;
   switch (G) {
     case 8:
-      hipLaunchKernelGGL(k_stream_bin<8>, grid, block, 0, s, src, dst, nc, g, status, trace_cell);
+      hipLaunchKernelGGL(k_stream_bin<8>, grid, block, 0, s, src, dst, nc, g, status, trace_cell,
+                         t);
       break;
     case 16:
-      hipLaunchKernelGGL(k_stream_bin<16>, grid, block, 0, s, src, dst, nc, g, status, trace_cell);
+      hipLaunchKernelGGL(k_stream_bin<16>, grid, block, 0, s, src, dst, nc, g, status, trace_cell,
+                         t);
       break;
     case 32:
-      hipLaunchKernelGGL(k_stream_bin<32>, grid, block, 0, s, src, dst, nc, g, status, trace_cell);
+      hipLaunchKernelGGL(k_stream_bin<32>, grid, block, 0, s, src, dst, nc, g, status, trace_cell,
+                         t);
       break;
     default:
-      hipLaunchKernelGGL(k_stream_bin<64>, grid, block, 0, s, src, dst, nc, g, status, trace_cell);
+      hipLaunchKernelGGL(k_stream_bin<64>, grid, block, 0, s, src, dst, nc, g, status, trace_cell,
+                         t);
   }
-  // then the spilled particles
-  launch_overflow_mode<kOvStream, false>(src, dst, 0u, PairArgs{}, g, status, TraceArgs{}, pool,
-                                         trace_cell, s);
 }
 
 void launch_offsets(const Cells &cur, uint32_t *offsets, uint32_t *tile_sums,
@@ -2062,22 +2019,15 @@ void launch_step_any(const Cells &src, const Cells &dst, bool fused, uint32_t n_
                      uint32_t lanes, uint32_t t, const PairArgs &pa, const Geometry &g,
                      DevStatus *status, const TraceArgs *trace, hipStream_t s,
                      const SideStream *side, const StepDevice &dev) {
-  if (trace) {
+  if (trace)
     launch_step_cap<false, true, kCap>(src, dst, n_cells, lanes, t, pa, g, status, *trace, s,
                                        side, dev);
-    launch_overflow_mode<kOvCollide, true>(src, dst, t, pa, g, status, *trace, dev.pool,
-                                           nullptr, s);
-  } else if (fused) {
+  else if (fused)
     launch_step_cap<true, false, kCap>(src, dst, n_cells, lanes, t, pa, g, status,
                                        TraceArgs{}, s, side, dev);
-    launch_overflow_mode<kOvFused, false>(src, dst, t, pa, g, status, TraceArgs{}, dev.pool,
-                                          nullptr, s);
-  } else {
+  else
     launch_step_cap<false, false, kCap>(src, dst, n_cells, lanes, t, pa, g, status,
                                         TraceArgs{}, s, side, dev);
-    launch_overflow_mode<kOvCollide, false>(src, dst, t, pa, g, status, TraceArgs{}, dev.pool,
-                                            nullptr, s);
-  }
 }
 
 }  // namespace
@@ -2105,10 +2055,10 @@ void launch_occupancy_over(const Cells &cur, int64_t n_cells, DevStatus *status,
 }
 
 void launch_observe(const Cells &cur, const Geometry &g, double vol, double *cell_sums,
-                    const SlabOut &out, hipStream_t s) {
+                    const SlabOut &out, uint32_t binning_step, hipStream_t s) {
   const int64_t n_cells = (int64_t)g.n[0] * g.n[1] * g.n[2];
   hipLaunchKernelGGL(k_observe_cells, dim3(cell_blocks(n_cells)), dim3(kBlock), 0, s, cur,
-                     (uint32_t)n_cells, cell_sums);
+                     (uint32_t)n_cells, cell_sums, binning_step);
   hipLaunchKernelGGL(k_observe_slabs, dim3((unsigned)g.n[0]), dim3(kBlock), 0, s,
                      (const double *)cell_sums, (uint32_t)(g.n[1] * g.n[2]), vol, out);
 }
@@ -2122,12 +2072,9 @@ void launch_batch_run(BatchEvent *ev, const BatchSpaces &sp, uint32_t n_events, 
   const uint32_t bin_grid = (bin_waves + kCellsPerBlock - 1) / kCellsPerBlock;
   const BatchEvent *cev = ev;
   const dim3 wave(64);
-  const dim3 ov_grid(kOvGroupsBatch * n_events);
   if (between) between(ctx, 0);
   hipLaunchKernelGGL(k_batch_bin, dim3(bin_grid), dim3(kBlock), 0, s, cev, sp.item_begin,
                      n_events, sp.n_items);
-  hipLaunchKernelGGL(k_batch_overflow<kOvStream>, ov_grid, dim3(kOvBlock), 0, s, cev, 0u,
-                     kOvGroupsBatch);
   // launch j: the small cells on s; concurrently on the side stream the
   // cells of events stepped one wave per cell, then the oversize cells of
   // small-cell events (all disjoint cells; appends go through atomics)
@@ -2156,8 +2103,6 @@ void launch_batch_run(BatchEvent *ev, const BatchSpaces &sp, uint32_t n_events, 
                            cev, sp.scan_begin, n_events, j);
     }
     join(s, sd);
-    hipLaunchKernelGGL(k_batch_overflow<kF ? kOvFused : kOvCollide>, ov_grid, dim3(kOvBlock), 0,
-                       s, cev, j, kOvGroupsBatch);
   };
   using Fused = std::integral_constant<bool, true>;
   using Last = std::integral_constant<bool, false>;
@@ -2173,10 +2118,11 @@ void launch_batch_run(BatchEvent *ev, const BatchSpaces &sp, uint32_t n_events, 
 }
 
 void launch_gather_by_id(const Cells &cur, int64_t n_cells, double *x, double *y,
-                         double *z, double *px, double *py, double *pz, hipStream_t s) {
+                         double *z, double *px, double *py, double *pz,
+                         uint32_t binning_step, hipStream_t s) {
   if (n_cells <= 0) return;
   hipLaunchKernelGGL(k_gather_by_id, dim3(cell_blocks(n_cells)), dim3(kBlock), 0, s, cur,
-                     (uint32_t)n_cells, x, y, z, px, py, pz);
+                     (uint32_t)n_cells, x, y, z, px, py, pz, binning_step);
 }
 
 }  // namespace cuba

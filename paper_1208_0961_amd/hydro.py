@@ -1,8 +1,9 @@
 """Exact solution of the 1-D Riemann problem of an ideal ultrarelativistic
 fluid (p = e/3) initially at rest on both sides, e_L > e_R: a rarefaction
-fan moves into the left state and a shock into the right one.  Used as the
+fan moves into the left state and a shock into the right one.  The
 large-cross-section limit of the kinetic evolution (the paper's Sec. 5
-benchmark compares against it qualitatively).  Written from the textbook
+benchmark compares against it qualitatively): the cross-section scan
+measures its distance to it, and tests pin the oracle's whole runs to it.  Written from the textbook
 relations: the Riemann invariant arctanh(v) + (sqrt(3)/4) ln e across the
 fan, and the Taub jump conditions across the shock."""
 import math

@@ -15,7 +15,7 @@ oracle, and the cross-section scan's approach to ideal hydrodynamics.
 import numpy as np
 import pytest
 
-import hydro
+from paper_1208_0961_amd import hydro
 from paper_1208_0961_amd import workload as W
 from test_gpu_parity import _orc_params, say, lib  # noqa: F401
 

@@ -112,17 +112,19 @@ def test_overflowing_cell_from_init(orc, lib):
     traced_step(orc, lib, params, state, 3, "one cell 1500 / 1024")
 
 
-@pytest.mark.parametrize("lanes", [0, 16, 128])
-def test_mixed_overflowing_and_normal_cells(orc, lib, lanes):
+@pytest.mark.parametrize("lanes,cap", [(0, 32), (16, 32), (128, 32), (64, 16)])
+def test_mixed_overflowing_and_normal_cells(orc, lib, lanes, cap):
     # 64 cells, a third of them past a block of 32 (up to 300 members), the
-    # rest below it, some empty; several steps, traced
+    # rest below it, some empty; several steps, traced.  With blocks of 16
+    # and 64 lanes per cell, cells of 17 .. 64 overflow while fitting the
+    # small-cell kernel's lanes
     rng = np.random.default_rng(7)
     occ = rng.integers(0, 30, 64)
     occ[rng.choice(64, 22, replace=False)] = rng.integers(33, 300, 22)
     occ[:3] = [0, 1, 2]
     state = cells_box(list(occ), m=4, seed=8)
     params = dict(box=(1.0, 1.0, 1.0), cells=(4, 4, 4), sigma=0.002, r_test=1.0,
-                  dt=0.01, seed=5, cell_capacity=32)
+                  dt=0.01, seed=5, cell_capacity=cap)
     for t in range(4):
         state, _ = traced_step(orc, lib, params, state, t, f"mixed lanes {lanes}", lanes)
 

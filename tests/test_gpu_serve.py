@@ -31,9 +31,10 @@ def test_results_same_alone_and_in_the_mix(serve, policy, final_only, run_steps)
     # srpt: a run holds about two of the requests, so events wait, are held
     # and resume between runs
     run_particles = 2 * max(r.work.n for r in reqs)
+    # (fifo without the fill of small requests, so that events are held)
     srv = serve.Server(max_slots=4, hbm_budget=budget, run_steps=run_steps,
                        keep_states=True, policy=policy, run_particles=run_particles,
-                       final_only=final_only)
+                       final_only=final_only, fill_particles=0)
     res = srv.run(reqs, realtime=False)
     assert srv.peak_live <= 4 and srv.peak_bytes <= budget
     assert srv.peak_live >= 2          # the requests overlapped on the device

@@ -5,7 +5,7 @@ import math
 
 import numpy as np
 
-import hydro
+from paper_1208_0961_amd import hydro
 from paper_1208_0961_amd import workload as W
 
 

@@ -55,13 +55,13 @@ def test_workspace_bytes_and_parameter_checks(C):
     p = C.make_params((10, 2, 2), (100, 10, 10), 0.4, 2500, 0.02, 1, cell_capacity=256)
     n = 1020851
     ws = C.cuba_workspace_bytes(p, n)
-    # two buffers of cells x capacity slots of 52 B, each with a spill region
-    # of n particles (52 B + their cell, 4 B) and an overflowing-cell list;
-    # overflow scratch of 5 n / 2 + cells words; per-cell arrays (two counts,
-    # two overflow lists, trace offsets, 4 observe sums, a scratch word:
-    # 56 B) and small pieces
+    # two buffers of cells x capacity slots of 52 B, each with n spill slots
+    # (52 B + their cell, 4 B) and an overflowing-cell list; scratch for
+    # overflowing cells of 3 n + 3 cells words; per-cell arrays (two counts,
+    # two overflow lists, trace offsets, 4 observe sums, three scratch
+    # words: 64 B) and small pieces
     slots = 10000 * 256
-    want = 104 * slots + (2 * 56 + 10) * n + 56 * 10000
+    want = 104 * slots + (2 * 56 + 12) * n + 64 * 10000
     assert want <= ws <= want + 64 * 1024
     p2 = C.make_params((10, 2, 2), (100, 10, 10), 0.4, 2500, 0.02, 1, cell_capacity=512)
     assert C.cuba_workspace_bytes(p2, n) > ws

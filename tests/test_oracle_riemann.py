@@ -7,7 +7,7 @@ r_test = 400 (N = 40 834), observed at t = 4 fm/c."""
 import numpy as np
 import pytest
 
-import hydro
+from paper_1208_0961_amd import hydro
 from paper_1208_0961_amd import workload as W
 
 

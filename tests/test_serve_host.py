@@ -38,9 +38,9 @@ def test_footprint_matches_workspace_formula(serve):
     cap = W.capacity_for(r.work)
     slots = r.work.n_cells * cap
     fp = serve.footprint(r)
-    # blocks (104 B a slot), spill regions and overflow scratch (122 B a
-    # particle), per-cell arrays (56 B a cell)
-    want = 104 * slots + 122 * r.work.n + 56 * r.work.n_cells
+    # blocks (104 B a slot), spill slots and overflow scratch (124 B a
+    # particle), per-cell arrays (64 B a cell)
+    want = 104 * slots + 124 * r.work.n + 64 * r.work.n_cells
     assert want <= fp <= want + 64 * 1024
 
 
