@@ -104,8 +104,8 @@ struct Derived {
 };
 
 // Default slots per cell: twice the mean occupancy plus 32, rounded up to
-// 32 (a Poisson cell exceeds it rarely; one that does is stepped by the
-// overflow kernel).
+// 32 (a Poisson cell exceeds it rarely; one that does keeps its surplus in
+// spill slots and takes the slower overflow path).
 uint32_t default_capacity(int64_t n, int64_t n_cells) {
   const double mean = n_cells > 0 ? (double)n / (double)n_cells : 0.0;
   double cap = std::ceil((2.0 * mean + 32.0) / 32.0) * 32.0;

@@ -19,8 +19,8 @@ def _dev(a, device):
 def suggest_cell_capacity(params: dict, state, headroom: float = 2.0, margin: int = 32) -> int:
     """Slots per cell for the workspace: headroom x the largest initial cell
     occupancy plus a margin, rounded up to 32, within [64, 1024].  A layout
-    choice only: a cell that later holds more keeps the surplus in the
-    spill region and is stepped by the library's overflow kernel."""
+    choice only: a cell that later holds more keeps the surplus in spill
+    slots and is stepped on the library's slower overflow path."""
     if len(state[0]) == 0:
         return 64
     box = np.asarray(params["box"], np.float64)

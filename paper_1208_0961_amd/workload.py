@@ -196,8 +196,8 @@ def max_mean_occupancy(w: Workload) -> float:
 def capacity_for(w: Workload, headroom: float = 1.5, margin: int = 32) -> int:
     """Cell capacity from the expected occupancy (mean + 5 sigma on the
     denser side) with headroom for the flow, so that cells rarely overflow
-    (an overflowing cell keeps its surplus in the spill region and is
-    stepped by the slower overflow kernel).  1.5x keeps the densest ensemble
+    (an overflowing cell keeps its surplus in spill slots and is stepped
+    on a slower path).  1.5x keeps the densest ensemble
     events at <= 512 slots, the limit of the kernels with the smaller LDS
     footprint."""
     m = max_mean_occupancy(w)

@@ -1,5 +1,6 @@
 """Cells that hold more particles than their block (cell_capacity): the
-surplus goes to the spill region and the overflow kernel steps the cell.
+surplus goes to spill slots and the collision kernels' overflow path
+steps the cell.
 Nothing is dropped, and every step keeps the parity contract with the
 oracle: cells, canonical order, candidates and claims identical, positions
 and unscattered momenta bit-exact, scattered momenta within 1e-12 (Ea + Eb).
@@ -131,7 +132,7 @@ def test_mixed_overflowing_and_normal_cells(orc, lib, lanes, cap):
 
 def test_fused_steps_with_overflow(orc, lib):
     # a fused step (collisions of step t, then the binning of t + 1, with
-    # the overflow kernel for the overflowing cells) from the traced state
+    # the overflow path for the overflowing cells) from the traced state
     rng = np.random.default_rng(9)
     occ = list(rng.integers(40, 140, 27))
     state = cells_box(occ, m=3, seed=10)
