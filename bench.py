@@ -68,12 +68,15 @@ def parse():
                     help="serve: number of requests")
     ap.add_argument("--retune", action="store_true",
                     help="batch: ignore a stored tuning table")
-    ap.add_argument("--serve-policy", choices=["fifo", "srpt", "all"], default="fifo",
-                    help="serve: the oldest requests in arrival order within a particle "
-                         "budget per run (fifo), the oldest then least remaining work "
-                         "first within the budget (srpt), or every live request in every "
-                         "run (all); the other policies run on the same trace for "
-                         "comparison")
+    ap.add_argument("--serve-policy", choices=["classes", "fifo", "srpt", "all"],
+                    default="classes",
+                    help="serve: short requests in a batch of their own, stepped to "
+                         "their end concurrently with the others on a second stream, the "
+                         "others as under fifo (classes); the oldest requests in arrival "
+                         "order within a particle budget per run (fifo); the oldest then "
+                         "least remaining work first within the budget (srpt); or every "
+                         "live request in every run (all); the other policies run on the "
+                         "same trace for comparison")
     ap.add_argument("--serve-run-steps", type=int, default=25,
                     help="serve: at most this many steps per run; a run ends early where "
                          "one of its requests ends or is due for an observation")
@@ -83,6 +86,9 @@ def parse():
     ap.add_argument("--serve-fill-particles", type=int, default=1_000_000,
                     help="serve, fifo: particles of further requests, least remaining "
                          "work first, beside those taken in arrival order")
+    ap.add_argument("--serve-short-particles", type=int, default=150_000,
+                    help="serve, classes: requests of at most this many particles go "
+                         "to the short batch")
     ap.add_argument("--serve-observe", choices=["final", "50"], default="final",
                     help="serve: observe each request's profile at its end only (its "
                          "result) or also every 50 steps, in the server and in the "
@@ -103,7 +109,7 @@ def parse():
                     help="default workload: skip the ensemble and serving legs")
     ap.add_argument("--extra-steps", type=int, default=50,
                     help="ensemble leg: timed steps of the batched ensemble")
-    ap.add_argument("--extra-requests", type=int, default=200,
+    ap.add_argument("--extra-requests", type=int, default=2000,
                     help="serving leg: requests in the served stream")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the run, copy a 1 GiB device buffer 3 times (a plain "
@@ -358,13 +364,14 @@ def ensemble_leg(steps: int, warmup: int = 5, n_events: int = 256) -> dict:
 
 
 def serve_leg(n_requests: int) -> dict:
-    """The served half of the metric on a short request stream (sizes 1e4 to
-    4e6 test particles, 200 steps each, Poisson arrivals at 0.8 of the
-    server's measured capacity), served with runs of at most 25 steps:
-    p50/p99 time-to-result and particle-steps/s of each policy against a
-    one-at-a-time FIFO of plain runs on the same trace."""
+    """The served half of the metric on a request stream (sizes 1e4 to 4e6
+    test particles, 200 steps each, Poisson arrivals at 0.8 of the server's
+    measured capacity), served with runs of at most 25 steps: p50/p99
+    time-to-result and particle-steps/s of the default policy and of fifo
+    (the others: --workload serve) against a one-at-a-time FIFO of plain
+    runs on the same trace."""
     from paper_1208_0961_amd import serve
-    return serve.measure(n_requests, other_policies=serve.Server.POLICIES)
+    return serve.measure(n_requests, other_policies=("fifo",))
 
 
 def bench_sigma_scan(a):

@@ -81,11 +81,23 @@ def footprint(req: Request) -> int:
                                   "cell_capacity": W.capacity_for(req.work)}, req.work.n)
 
 
+class _Lane:
+    """One batch of live events on its own stream, with the runs queued on
+    it that have not completed yet."""
+
+    def __init__(self, max_slots: int, device: str, use_graphs: bool, run_steps: int):
+        self.B = Batch(max_slots, device=device, use_graphs=use_graphs)
+        self.live: dict[int, dict] = {}
+        self.inflight: deque = deque()   # an event after each queued run
+        self.run_steps = run_steps
+
+
 class Server:
     """Continuous batching of Riemann-event requests on one GPU.
 
-    Requests are admitted in arrival order as a batch slot and HBM (the
-    event's workspace footprint) free up, without waiting for the GPU
+    Requests are admitted in arrival order as a slot (at most max_slots
+    live events) and HBM (the event's workspace footprint) free up, without
+    waiting for the GPU
     (cuba_batch_admit_async); live events advance in runs of at most
     `run_steps` steps, one launch per step for every event in the run; an
     event that finishes is observed, its profile copied to pinned host
@@ -96,23 +108,33 @@ class Server:
     the next queued run.
 
     Which live events take part in a run:
-      "all"   every live event (processor sharing);
-      "srpt"  the oldest, then the others by least remaining work
-              (particles x steps left) while they fit `run_particles`;
-      "fifo"  the oldest events in arrival order while they fit
-              `run_particles` (at least one), then others by least remaining
-              work while they fit `fill_particles` more (small requests
-              slip in beside the large ones at the head of the queue);
+      "all"     every live event (processor sharing);
+      "srpt"    the oldest, then the others by least remaining work
+                (particles x steps left) while they fit `run_particles`;
+      "fifo"    the oldest events in arrival order while they fit
+                `run_particles` (at least one), then others by least
+                remaining work while they fit `fill_particles` more (small
+                requests slip in beside the large ones at the head of the
+                queue);
+      "classes" two batches on two streams whose runs execute concurrently:
+                requests of at most `short_particles` particles go to the
+                short batch, whose runs take every live event there to its
+                end (or next observation) in one run, so a short request
+                waits only for the short run before it; the others go to
+                the long batch, stepped as under "fifo".  A step of a few
+                short events is bound by launch latency, not by the GPU's
+                throughput, so it fills the gaps of the long batch's steps
+                instead of queueing behind them.
     the others are held (cuba_batch_set_active) until chosen."""
 
-    POLICIES = ("all", "srpt", "fifo")
+    POLICIES = ("all", "srpt", "fifo", "classes")
 
     def __init__(self, max_slots: int = 256, hbm_budget: int | None = None,
                  run_steps: int = 25, device: str = "cuda", use_graphs: bool = False,
                  tuning: dict | None = None, keep_states: bool = False,
-                 policy: str = "fifo", run_particles: int = 4_000_000,
+                 policy: str = "classes", run_particles: int = 4_000_000,
                  final_only: bool = False, depth: int = 2,
-                 fill_particles: int = 1_000_000):
+                 fill_particles: int = 1_000_000, short_particles: int = 150_000):
         if policy not in self.POLICIES:
             raise ValueError(f"policy must be one of {self.POLICIES}")
         if run_steps < 1:
@@ -121,6 +143,7 @@ class Server:
         self.policy = policy
         self.run_particles = int(run_particles)
         self.fill_particles = int(fill_particles)
+        self.short_particles = int(short_particles) if policy == "classes" else 0
         self.final_only = final_only
         self.run_steps = run_steps
         self.keep_states = keep_states
@@ -129,21 +152,32 @@ class Server:
             free, _ = torch.cuda.mem_get_info(device)
             hbm_budget = int(0.7 * free)
         self.budget = hbm_budget
-        self.B = Batch(max_slots, device=device, use_graphs=use_graphs)
+        self.max_slots = int(max_slots)
+        self.lanes = [_Lane(max_slots, device, use_graphs, run_steps)]
+        if policy == "classes":
+            # short runs go to an event's end: no step bound of their own
+            self.lanes.append(_Lane(max_slots, device, use_graphs, 1 << 30))
+        self.B = self.lanes[0].B
         self.tuning = tuning
         self.use_graphs = use_graphs
         self.peak_live = 0
         self.peak_bytes = 0
         self.peak_held = 0
+        self.lane_runs = [0] * len(self.lanes)   # runs queued per lane
 
-    def _admit(self, slot: int, req: Request):
+    def _lane_for(self, req: Request) -> _Lane:
+        if len(self.lanes) > 1 and req.work.n <= self.short_particles:
+            return self.lanes[1]
+        return self.lanes[0]
+
+    def _admit(self, lane: _Lane, slot: int, req: Request):
         from . import autotune as AT
-        with torch.cuda.stream(self.B.stream):
+        with torch.cuda.stream(lane.B.stream):
             state = W.riemann_state_torch(req.work, req.state_seed, device=self.device)
-        self.B.admit_async(slot, {**req.work.params(),
+        lane.B.admit_async(slot, {**req.work.params(),
                                   "cell_capacity": W.capacity_for(req.work)}, state)
         if self.tuning:
-            AT.settings_for(self.B, slot, req.work, self.tuning)
+            AT.settings_for(lane.B, slot, req.work, self.tuning)
 
     def run(self, requests: list[Request], realtime=True) -> list[Result]:
         """Serves the requests.  realtime=True admits a request once its
@@ -152,19 +186,19 @@ class Server:
         queued runs (a logical clock: admission mid-stream at a reproducible
         point)."""
         if self.tuning:
-            self.B.set_launch(int(self.tuning.get("persistent_waves", 0)), self.use_graphs)
+            for lane in self.lanes:
+                lane.B.set_launch(int(self.tuning.get("persistent_waves", 0)), self.use_graphs)
         queue = deque(sorted(requests, key=lambda r: r.arrival))
-        live: dict[int, dict] = {}
         used = 0
         results: list[Result] = []
         pending: deque = deque()   # (done event, result fields, host T00, host T0x)
-        inflight: deque = deque()  # an event after each queued run
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0
         runs_done = [0]
         logical = realtime == "runs"
         clock = (lambda: runs_done[0]) if logical else now
-        stream = self.B.stream
+        lanes = self.lanes
+        n_live = lambda: sum(len(lane.live) for lane in lanes)
 
         def collect(block: bool = False):
             while pending and (block or pending[0][0].query()):
@@ -174,23 +208,24 @@ class Server:
                                       T0x=h0x.numpy().copy()))
                 block = False
 
-        while queue or live or pending:
+        while queue or n_live() or pending:
             collect()
             # admission: FIFO, by free slot and HBM footprint
             while queue and (not realtime or queue[0].arrival <= clock()):
                 req = queue[0]
                 need = footprint(req)
-                slot = self.B.free_slot()
-                if slot is None or (used + need > self.budget and live):
+                lane = self._lane_for(req)
+                slot = lane.B.free_slot() if n_live() < self.max_slots else None
+                if slot is None or (used + need > self.budget and n_live()):
                     break
                 queue.popleft()
-                self._admit(slot, req)
+                self._admit(lane, slot, req)
                 used += need
-                live[slot] = {"req": req, "need": need, "done": 0, "admitted": now(),
-                              "admitted_run": runs_done[0], "active": True}
-                self.peak_live = max(self.peak_live, len(live))
+                lane.live[slot] = {"req": req, "need": need, "done": 0, "admitted": now(),
+                                   "admitted_run": runs_done[0], "active": True}
+                self.peak_live = max(self.peak_live, n_live())
                 self.peak_bytes = max(self.peak_bytes, used)
-            if not live:
+            if not n_live():
                 if pending:
                     collect(block=not queue or (realtime and queue[0].arrival > clock()))
                 elif queue and logical:
@@ -198,97 +233,125 @@ class Server:
                 elif queue and realtime:
                     time.sleep(max(0.0, min(queue[0].arrival - now(), 0.002)))
                 continue
-            # at most `depth` runs in flight
-            while len(inflight) >= self.depth:
-                inflight.popleft().synchronize()
+            queued = False
+            for lane in lanes:
+                while lane.inflight and lane.inflight[0].query():
+                    lane.inflight.popleft()
+                if lane.live and len(lane.inflight) < self.depth:
+                    used -= self._queue_run(lane, pending, runs_done, now)
+                    queued = True
+            if not queued:
+                # every lane with live events has `depth` runs in flight
+                busy = [lane for lane in lanes if lane.live]
+                if len(busy) == 1 and not (realtime and queue and not logical):
+                    busy[0].inflight.popleft().synchronize()
+                else:
+                    time.sleep(0.0002)
                 collect()
-            active = self._choose(live)
-            k = min(self.steps_to_stop(live[slot]["req"].work, live[slot]["done"])
-                    for slot in active)
-            self.B.step(k)
-            runs_done[0] += 1
-            finished = []
-            for slot in sorted(active):
-                ev = live[slot]
-                ev["done"] += k
-                w = ev["req"].work
-                if ((not self.final_only and ev["done"] % w.observe_every == 0)
-                        or ev["done"] >= w.steps):
-                    self.B.observe_async(slot)
-                if ev["done"] >= w.steps:
-                    finished.append(slot)
-            for slot in finished:
-                ev = live.pop(slot)
-                s = self.B.slots[slot]
-                with torch.cuda.stream(stream):
-                    h00 = torch.empty(s["T00"].shape, dtype=torch.float64, pin_memory=True)
-                    h0x = torch.empty(s["T0x"].shape, dtype=torch.float64, pin_memory=True)
-                    h00.copy_(s["T00"], non_blocking=True)
-                    h0x.copy_(s["T0x"], non_blocking=True)
-                    done_ev = torch.cuda.Event()
-                    done_ev.record(stream)
-                fields = dict(rid=ev["req"].rid, n=ev["req"].work.n,
-                              arrival=ev["req"].arrival, admitted=ev["admitted"],
-                              admitted_run=ev["admitted_run"], finished_run=runs_done[0])
-                if self.keep_states:
-                    fields["state"] = self.B.get_state(slot)
-                pending.append((done_ev, fields, h00, h0x))
-                self.B.retire(slot)
-                used -= ev["need"]
-            run_ev = torch.cuda.Event()
-            run_ev.record(stream)
-            inflight.append(run_ev)
-        self.B.sync()
+        for lane in lanes:
+            lane.B.sync()
         return sorted(results, key=lambda r: r.finished)
 
-    def steps_to_stop(self, work: W.Workload, done: int) -> int:
+    def _queue_run(self, lane: _Lane, pending: deque, runs_done: list, now) -> int:
+        """Queues one run of the lane's chosen events, observes and retires
+        those that finish in it; returns the HBM footprint released."""
+        live = lane.live
+        B = lane.B
+        active = self._choose(lane)
+        k = min(self.steps_to_stop(live[slot]["req"].work, live[slot]["done"], lane.run_steps)
+                for slot in active)
+        B.step(k)
+        runs_done[0] += 1
+        self.lane_runs[self.lanes.index(lane)] += 1
+        finished = []
+        for slot in sorted(active):
+            ev = live[slot]
+            ev["done"] += k
+            w = ev["req"].work
+            if ((not self.final_only and ev["done"] % w.observe_every == 0)
+                    or ev["done"] >= w.steps):
+                B.observe_async(slot)
+            if ev["done"] >= w.steps:
+                finished.append(slot)
+        freed = 0
+        for slot in finished:
+            ev = live.pop(slot)
+            s = B.slots[slot]
+            with torch.cuda.stream(B.stream):
+                h00 = torch.empty(s["T00"].shape, dtype=torch.float64, pin_memory=True)
+                h0x = torch.empty(s["T0x"].shape, dtype=torch.float64, pin_memory=True)
+                h00.copy_(s["T00"], non_blocking=True)
+                h0x.copy_(s["T0x"], non_blocking=True)
+                done_ev = torch.cuda.Event()
+                done_ev.record(B.stream)
+            fields = dict(rid=ev["req"].rid, n=ev["req"].work.n,
+                          arrival=ev["req"].arrival, admitted=ev["admitted"],
+                          admitted_run=ev["admitted_run"], finished_run=runs_done[0])
+            if self.keep_states:
+                fields["state"] = B.get_state(slot)
+            pending.append((done_ev, fields, h00, h0x))
+            B.retire(slot)
+            freed += ev["need"]
+        run_ev = torch.cuda.Event()
+        run_ev.record(B.stream)
+        lane.inflight.append(run_ev)
+        return freed
+
+    def steps_to_stop(self, work: W.Workload, done: int, run_steps: int | None = None) -> int:
         """Steps an event that has done `done` of its steps may take in the
         next run: at most run_steps, and never past its end or (unless only
         its final profile is wanted) past its next observation."""
-        k = min(self.run_steps, work.steps - done)
+        k = min(self.run_steps if run_steps is None else run_steps, work.steps - done)
         if not self.final_only:
             k = min(k, work.observe_every - done % work.observe_every)
         return k
 
-    def _choose(self, live: dict) -> set:
-        """The slots that take part in the next run (holding the others)."""
-        if self.policy == "all":
-            return set(live)
-        age = lambda s: (live[s]["req"].arrival, live[s]["req"].rid)
-        size = lambda s: live[s]["req"].work.n
-        left = lambda s: size(s) * (live[s]["req"].work.steps - live[s]["done"])
-        if self.policy == "fifo":
-            order = sorted(live, key=age)
-            active, total = {order[0]}, size(order[0])
-            for slot in order[1:]:
-                if total + size(slot) > self.run_particles:
-                    break
-                active.add(slot)
-                total += size(slot)
-            extra = 0
-            for slot in sorted(live, key=left):
-                if slot in active or extra + size(slot) > self.fill_particles:
-                    continue
-                active.add(slot)
-                extra += size(slot)
+    def _choose(self, lane: _Lane) -> set:
+        """The slots of the lane that take part in its next run (holding
+        the others)."""
+        live = lane.live
+        policy = self.policy
+        if policy == "classes":
+            policy = "all" if lane is not self.lanes[0] else "fifo"
+        if policy == "all":
+            active = set(live)
         else:
-            oldest = min(live, key=age)
-            active, total = {oldest}, size(oldest)
-            for slot in sorted(live, key=left):
-                if slot == oldest or total + size(slot) > self.run_particles:
-                    continue
-                active.add(slot)
-                total += size(slot)
+            age = lambda s: (live[s]["req"].arrival, live[s]["req"].rid)
+            size = lambda s: live[s]["req"].work.n
+            left = lambda s: size(s) * (live[s]["req"].work.steps - live[s]["done"])
+            if policy == "fifo":
+                order = sorted(live, key=age)
+                active, total = {order[0]}, size(order[0])
+                for slot in order[1:]:
+                    if total + size(slot) > self.run_particles:
+                        break
+                    active.add(slot)
+                    total += size(slot)
+                extra = 0
+                for slot in sorted(live, key=left):
+                    if slot in active or extra + size(slot) > self.fill_particles:
+                        continue
+                    active.add(slot)
+                    extra += size(slot)
+            else:
+                oldest = min(live, key=age)
+                active, total = {oldest}, size(oldest)
+                for slot in sorted(live, key=left):
+                    if slot == oldest or total + size(slot) > self.run_particles:
+                        continue
+                    active.add(slot)
+                    total += size(slot)
         for slot, ev in live.items():
             want = slot in active
             if ev["active"] != want:
-                self.B.set_active(slot, want)
+                lane.B.set_active(slot, want)
                 ev["active"] = want
         self.peak_held = max(self.peak_held, len(live) - len(active))
         return active
 
     def close(self):
-        self.B.close()
+        for lane in self.lanes:
+            lane.B.close()
 
 
 def run_alone(req: Request, device: str = "cuda", keep_state: bool = False,
@@ -331,10 +394,11 @@ def percentiles(lat):
     return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
 
 
-def measure(n_req: int, policy: str = "fifo", run_steps: int = 25, final_only: bool = True,
-            run_particles: int = 4_000_000, other_policies: tuple = (),
-            sequential: bool = True, seed: int = 5, load: float = 0.8,
-            fill_particles: int = 1_000_000) -> dict:
+def measure(n_req: int, policy: str = "classes", run_steps: int = 25,
+            final_only: bool = True, run_particles: int = 4_000_000,
+            other_policies: tuple = (), sequential: bool = True, seed: int = 5,
+            load: float = 0.8, fill_particles: int = 1_000_000,
+            short_particles: int = 150_000) -> dict:
     """n_req requests (sizes 1e4 .. 4e6 test particles), Poisson arrivals at
     `load` of the server's batched capacity (measured on a closed batch of 64
     requests); p50/p99 time-to-result and aggregate particle-steps/s of the
@@ -349,7 +413,7 @@ def measure(n_req: int, policy: str = "fifo", run_steps: int = 25, final_only: b
     def server(pol):
         return Server(tuning=tuning, use_graphs=False, policy=pol, run_steps=run_steps,
                       run_particles=run_particles, final_only=final_only,
-                      fill_particles=fill_particles)
+                      fill_particles=fill_particles, short_particles=short_particles)
 
     # untimed warm-up of both paths (first launches load code objects and
     # grow the allocator's pools)
@@ -377,6 +441,7 @@ def measure(n_req: int, policy: str = "fifo", run_steps: int = 25, final_only: b
            "unit": "particle-steps/s", "policy": policy, "run_steps": run_steps,
            "observed": "final profile" if final_only else "every 50 steps",
            "run_particles": run_particles, "fill_particles": fill_particles,
+           "short_particles": short_particles if policy == "classes" else None,
            "requests": n_req, "load": load,
            "request_sizes": "1e4 .. 4e6 test particles, 200 steps",
            "arrival_rate_per_s": rate, "capacity_particle_steps_per_s": throughput}
@@ -386,7 +451,8 @@ def measure(n_req: int, policy: str = "fifo", run_steps: int = 25, final_only: b
         t0 = time.perf_counter()
         res = srv.run(reqs, realtime=True)
         makespan = time.perf_counter() - t0
-        peak = {"peak_live": srv.peak_live, "peak_bytes": srv.peak_bytes}
+        peak = {"peak_live": srv.peak_live, "peak_bytes": srv.peak_bytes,
+                "lane_runs": list(srv.lane_runs)}
         srv.close()
         assert len(res) == n_req
         p50, p99 = percentiles([r.latency for r in res])
@@ -418,11 +484,12 @@ def bench(a):
     particle-steps/s of the served stream against a one-at-a-time FIFO of
     plain runs on the same trace."""
     import json
-    out = measure(int(a.requests), policy=getattr(a, "serve_policy", "fifo"),
+    out = measure(int(a.requests), policy=getattr(a, "serve_policy", "classes"),
                   run_steps=int(getattr(a, "serve_run_steps", 25)),
                   final_only=getattr(a, "serve_observe", "final") == "final",
                   run_particles=int(getattr(a, "serve_run_particles", 4_000_000)),
                   fill_particles=int(getattr(a, "serve_fill_particles", 1_000_000)),
+                  short_particles=int(getattr(a, "serve_short_particles", 150_000)),
                   other_policies=Server.POLICIES,
                   sequential=not getattr(a, "no_sequential", False))
     print(json.dumps(out), flush=True)

@@ -24,22 +24,27 @@ def serve():
 # 40 does not, so runs stop early at every observation (40, 10, 40, 10)
 @pytest.mark.parametrize("policy,final_only,run_steps",
                          (("all", False, 25), ("srpt", False, 25), ("srpt", True, 50),
-                          ("all", False, 40), ("fifo", True, 25)))
+                          ("all", False, 40), ("fifo", True, 25), ("classes", True, 25),
+                          ("classes", False, 40)))
 def test_results_same_alone_and_in_the_mix(serve, policy, final_only, run_steps):
     reqs = serve.request_stream(10, 0.0, seed=8, nmin=1e4, nmax=8e4, steps=100)
     budget = 3 * max(serve.footprint(r) for r in reqs)
     # srpt: a run holds about two of the requests, so events wait, are held
     # and resume between runs
     run_particles = 2 * max(r.work.n for r in reqs)
+    # classes: about half the requests in each lane
+    short = int(np.median([r.work.n for r in reqs]))
     # (fifo without the fill of small requests, so that events are held)
     srv = serve.Server(max_slots=4, hbm_budget=budget, run_steps=run_steps,
                        keep_states=True, policy=policy, run_particles=run_particles,
-                       final_only=final_only, fill_particles=0)
+                       final_only=final_only, fill_particles=0, short_particles=short)
     res = srv.run(reqs, realtime=False)
     assert srv.peak_live <= 4 and srv.peak_bytes <= budget
     assert srv.peak_live >= 2          # the requests overlapped on the device
     if policy in ("srpt", "fifo"):
         assert srv.peak_held >= 1
+    if policy == "classes":
+        assert min(srv.lane_runs) >= 1   # both lanes ran
     srv.close()
     assert sorted(r.rid for r in res) == list(range(len(reqs)))
     by_id = {r.rid: r for r in reqs}

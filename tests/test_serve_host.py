@@ -59,6 +59,23 @@ class _FakeBatch:
         self.calls.append((slot, bool(active)))
 
 
+class _FakeLane:
+    """A lane as Server.run keeps it: live events and a fake batch."""
+
+    def __init__(self, live):
+        self.live = live
+        self.B = _FakeBatch()
+
+
+def _server(serve, policy, live, **attrs):
+    srv = serve.Server.__new__(serve.Server)
+    srv.policy, srv.peak_held = policy, 0
+    srv.lanes = [_FakeLane(live)]
+    for k, v in attrs.items():
+        setattr(srv, k, v)
+    return srv, srv.lanes[0]
+
+
 def _live(serve, specs):
     """live dict as Server.run keeps it: slot -> request of equal size with
     (steps done, arrival), active flag."""
@@ -78,30 +95,27 @@ def test_srpt_policy_choice(serve):
     is called only for events whose state changes."""
     live = _live(serve, [(0, 0.5), (150, 0.1), (0, 0.2), (100, 0.3)])
     n = {s: ev["req"].work.n for s, ev in live.items()}
-    srv = serve.Server.__new__(serve.Server)
-    srv.policy, srv.peak_held = "srpt", 0
-    srv.B = _FakeBatch()
     # room for the oldest (slot 1) and one more
-    srv.run_particles = n[1] + n[3]
-    act = srv._choose(live)
+    srv, lane = _server(serve, "srpt", live, run_particles=n[1] + n[3])
+    act = srv._choose(lane)
     left = {s: n[s] * (200 - live[s]["done"]) for s in live}
     assert 1 in act                           # oldest arrival
     # the event with the least remaining work besides the oldest is slot 3
     assert min((s for s in live if s != 1), key=left.get) == 3
     assert act == {1, 3}
-    assert sorted(srv.B.calls) == [(0, False), (2, False)]
+    assert sorted(lane.B.calls) == [(0, False), (2, False)]
     assert srv.peak_held == 2
     # nothing changes: no calls
-    srv.B.calls.clear()
-    assert srv._choose(live) == {1, 3} and srv.B.calls == []
+    lane.B.calls.clear()
+    assert srv._choose(lane) == {1, 3} and lane.B.calls == []
     # a budget below the oldest's size still runs the oldest alone
     srv.run_particles = 1
-    assert srv._choose(live) == {1}
-    assert srv.B.calls == [(3, False)]
+    assert srv._choose(lane) == {1}
+    assert lane.B.calls == [(3, False)]
     # policy all: every live event, no calls
-    srv2 = serve.Server.__new__(serve.Server)
-    srv2.policy, srv2.peak_held, srv2.B = "all", 0, _FakeBatch()
-    assert srv2._choose(live) == set(live) and srv2.B.calls == []
+    live2 = _live(serve, [(0, 0.5), (150, 0.1), (0, 0.2), (100, 0.3)])
+    srv2, lane2 = _server(serve, "all", live2)
+    assert srv2._choose(lane2) == set(live2) and lane2.B.calls == []
 
 
 def test_fifo_policy_choice(serve):
@@ -110,19 +124,48 @@ def test_fifo_policy_choice(serve):
     they fit the fill budget."""
     live = _live(serve, [(0, 0.5), (150, 0.1), (0, 0.2), (100, 0.3)])
     n = {s: ev["req"].work.n for s, ev in live.items()}
-    srv = serve.Server.__new__(serve.Server)
-    srv.policy, srv.peak_held, srv.B = "fifo", 0, _FakeBatch()
     # arrival order: 1, 2, 3, 0; room for two in arrival order, no fill
-    srv.run_particles, srv.fill_particles = n[1] + n[2], 0
-    assert srv._choose(live) == {1, 2}
-    assert sorted(srv.B.calls) == [(0, False), (3, False)]
+    srv, lane = _server(serve, "fifo", live, run_particles=n[1] + n[2], fill_particles=0)
+    assert srv._choose(lane) == {1, 2}
+    assert sorted(lane.B.calls) == [(0, False), (3, False)]
     # a fill of one event: the least remaining work among the rest (slot 3,
     # 100 steps done, before slot 0 with none)
     srv.fill_particles = n[3]
-    assert srv._choose(live) == {1, 2, 3}
+    assert srv._choose(lane) == {1, 2, 3}
     # the oldest runs even past the budget
     srv.run_particles, srv.fill_particles = 1, 0
-    assert srv._choose(live) == {1}
+    assert srv._choose(lane) == {1}
+
+
+def test_classes_policy_lanes(serve):
+    """classes: requests up to short_particles go to the short lane, whose
+    runs take every live event there to its end; the long lane is stepped
+    as under fifo."""
+    from paper_1208_0961_amd import workload as W
+    long_live = _live(serve, [(0, 0.5), (150, 0.1), (0, 0.2)])
+    short_live = _live(serve, [(0, 0.6), (0, 0.7)])
+    n = long_live[0]["req"].work.n
+    srv, long_lane = _server(serve, "classes", long_live, run_particles=n, fill_particles=0,
+                             short_particles=n, run_steps=25, final_only=True)
+    short_lane = _FakeLane(short_live)
+    short_lane.run_steps = 1 << 30
+    long_lane.run_steps = 25
+    srv.lanes.append(short_lane)
+    assert srv._choose(long_lane) == {1}          # fifo head, no room for more
+    assert sorted(long_lane.B.calls) == [(0, False), (2, False)]
+    assert srv._choose(short_lane) == {0, 1} and short_lane.B.calls == []
+    # a short run goes to the end of its events, a long one stops at run_steps
+    w = short_live[0]["req"].work
+    assert srv.steps_to_stop(w, 0, short_lane.run_steps) == w.steps
+    assert srv.steps_to_stop(w, 0, long_lane.run_steps) == 25
+    # lane by size
+    small = serve.Request(9, W.Workload("s", (10.0, 1.0, 1.0), (100, 5, 5), 50.0, 0.5, 0.02,
+                                        0.3, 0.24), 0.0, 0)
+    big = serve.Request(10, W.Workload("b", (10.0, 4.0, 4.0), (100, 20, 20), 2500.0, 0.5,
+                                       0.02, 0.5, 0.4), 0.0, 0)
+    srv.short_particles = 300_000
+    assert small.work.n <= 300_000 < big.work.n
+    assert srv._lane_for(small) is short_lane and srv._lane_for(big) is long_lane
 
 
 def test_server_rejects_unknown_policy(serve):
