@@ -95,8 +95,9 @@ def parse():
                          "one-at-a-time replay")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batch: skip the one-at-a-time comparison")
-    ap.add_argument("--lanes", type=int, default=None, choices=[0, 8, 16, 32, 64, 128],
-                    help="plain workloads: lanes per cell of the cell kernels, 128 for "
+    ap.add_argument("--lanes", type=int, default=None, choices=[0, 1, 8, 16, 32, 64, 128],
+                    help="plain workloads: lanes per cell of the cell kernels, 1 for "
+                         "packed cells, 128 for "
                          "two waves per cell (default: the library's choice from the "
                          "initial occupancy)")
     ap.add_argument("--cpu-steps", type=int, default=None,

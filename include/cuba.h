@@ -220,15 +220,23 @@ int cuba_sync(cuba_ctx *ctx);
  * without a mostly idle wave each; cells holding more particles than lanes
  * are stepped by the whole wave in a second kernel (a wave per 64 cells, or
  * a wave per cell once the initial state has more than one such cell in 64).
- * 128: a workgroup of two waves per cell, which split its pair tests (the
- * first wave claims every accepted pair in increasing pair order); for
- * boxes of fewer cells than the chip has SIMDs.  cuba_init chooses from the
- * initial occupancy: 128 below 1024 cells if at least half of them hold
- * more than 32 particles, else 0 below 16384 cells (launch-bound steps),
- * else the smallest of 8, 16, 32 that all but 0.2 % of the cells fit, else
- * 8 if at least a quarter of the cells hold at most 8 particles, else 0.
- * Errors: CUBA_EINVAL for NULL or any other value.  For an event in a batch
- * use cuba_batch_set_cell_lanes (which does not take 128). */
+ * 1 (packed): each wave takes 64 consecutive cells and packs whole cells, in
+ * order, into units of at most 64 particles, one particle per lane, testing
+ * pairs with the Philox filter first and the exact test in compacted rows;
+ * cells of more than 64 particles go to the second kernel.  For sparse
+ * boxes and boxes of dense and sparse regions.  128: a workgroup of two
+ * waves per cell, which split its pair tests (the first wave claims every
+ * accepted pair in increasing pair order); for boxes of fewer cells than the
+ * chip has SIMDs.  cuba_init chooses from the initial occupancy and
+ * K = sigma / r_test * dt / V_cell: 128 below 1024 cells if at least half of
+ * them hold more than 32 particles, else 0 below 16384 cells (launch-bound
+ * steps), else 1 if at most 0.2 % of the cells hold more than 64 particles
+ * and the mean occupancy is at most 8 (at most 12 if 2K >= 0.01), else the
+ * smallest of 8, 16, 32 that all but 0.2 % of the cells fit, else 1 if at
+ * least a quarter of the cells hold at most 8 particles and at most 0.2 %
+ * more than 64, else 0.  Errors: CUBA_EINVAL for NULL or any other value.
+ * For an event in a batch use cuba_batch_set_cell_lanes (which takes
+ * neither 1 nor 128). */
 int cuba_set_cell_lanes(cuba_ctx *ctx, int32_t lanes);
 int cuba_get_cell_lanes(const cuba_ctx *ctx, int32_t *lanes);
 

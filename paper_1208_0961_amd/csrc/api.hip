@@ -154,16 +154,20 @@ int derive(const cuba_params *p, int64_t n, Derived &d) {
 }
 
 // Lanes per cell from the occupancy at init (over[k] = cells holding more
-// than 8 << k particles):
+// than 8 << k particles) and the scattering constant K:
 //  * one wave per cell for boxes of fewer cells than a few waves per SIMD,
 //    whose steps are bound by launch latency, which the second kernel adds to;
+//  * on the plain path (plain: not in a batch), packed cells if at most a
+//    small fraction of the cells exceed 64 particles and the mean occupancy
+//    is at most 8, or at most 12 with 2K >= 1 % (where most pair-test rounds
+//    of the fixed-lane kernels hold a pair that passes the filter, and pay
+//    for its exact test in the whole wave);
 //  * else the smallest group of 8, 16 or 32 lanes that all but a small
 //    fraction of the cells fit (64-lane groups lost to one wave per cell
 //    in every measured occupancy mix);
-//  * else, on the plain path (plain: not in a batch), where the oversize
-//    cells take a wave each, 8 lanes if at least a quarter of the cells fit
-//    them: a box of dense and sparse regions steps each region with its
-//    own kernel;
+//  * else, on the plain path, packed cells if at least a quarter of the
+//    cells hold at most 8 particles and few exceed 64: a box of dense and
+//    sparse regions;
 //  * else one wave per cell.
 // Except: on the plain path, a box of fewer cells than the chip has SIMDs,
 // most of them holding more than 32 particles, takes two waves per cell (the
@@ -173,15 +177,21 @@ constexpr double kOversizeFraction = 2e-3;
 constexpr double kSparseFraction = 0.25;
 constexpr int64_t kSmallCellsMinCells = 16384;
 constexpr int64_t kTwoWaveMaxCells = 1024;
-uint32_t default_lanes(const uint32_t over[4], int64_t n_cells, bool plain) {
+constexpr double kPackedMean = 8.0, kPackedMeanHighK = 12.0, kHighTwoK = 0.01;
+uint32_t default_lanes(const uint32_t over[4], int64_t n_cells, int64_t n, double kfac,
+                       bool plain) {
   if (plain && n_cells < kTwoWaveMaxCells && 2 * (int64_t)over[2] >= n_cells)
     return kTwoWavesPerCell;
   if (n_cells < kSmallCellsMinCells) return 0;
   const double limit = kOversizeFraction * (double)n_cells;
+  const double mean = (double)n / (double)n_cells;
+  const bool packable = plain && (double)over[3] <= limit;
+  if (packable && (mean <= kPackedMean || (2.0 * kfac >= kHighTwoK && mean <= kPackedMeanHighK)))
+    return kPackedCells;
   for (uint32_t k = 0; k < 3; ++k)
     if ((double)over[k] <= limit) return 8u << k;
-  if (plain && (double)(n_cells - over[0]) >= kSparseFraction * (double)n_cells)
-    return 8;
+  if (packable && (double)(n_cells - over[0]) >= kSparseFraction * (double)n_cells)
+    return kPackedCells;
   return 0;
 }
 
@@ -489,7 +499,7 @@ int init_context(cuba_ctx *c, const Derived &d, const cuba_params *params, int64
       return fail(CUBA_EDEVICE, "internal: spill descriptor not in place");
   const uint32_t err = head[0];
   for (int k = 0; k < 4; ++k) c->over[k] = head[1 + k];
-  c->lanes = default_lanes(c->over, d.n_cells, true);
+  c->lanes = default_lanes(c->over, d.n_cells, n, d.kfac, true);
   if (err & kErrRange)
     return fail(CUBA_ERANGE, "a particle is outside [0, L], non-finite, or has |p| = 0");
   if (err & kErrSpill) return fail(CUBA_EDEVICE, "internal: spill region inconsistent");
@@ -586,7 +596,7 @@ int cuba_init_static(cuba_ctx **out, const cuba_params *params, int64_t n, const
 int cuba_set_cell_lanes(cuba_ctx *c, int32_t lanes) {
   if (!c) return fail(CUBA_EINVAL, "ctx is NULL");
   if (!valid_plain_cell_lanes(lanes))
-    return fail(CUBA_EINVAL, "lanes must be 0, 8, 16, 32, 64 or 128");
+    return fail(CUBA_EINVAL, "lanes must be 0, 1, 8, 16, 32, 64 or 128");
   c->lanes = (uint32_t)lanes;
   return CUBA_OK;
 }
@@ -1066,7 +1076,7 @@ int cuba_batch_admit(cuba_batch *b, int32_t slot, const cuba_params *params, int
                            (void *)b->stream);
   if (rc != CUBA_OK) return rc;
   // a batch steps the oversize cells of an event 64 to a wave
-  c->lanes = default_lanes(c->over, c->d.n_cells, false);
+  c->lanes = default_lanes(c->over, c->d.n_cells, c->n, c->d.kfac, false);
   b->slot_ctx[slot] = c;
   b->slot_cpi[slot] = default_cpi(c);
   b->slot_active[slot] = 1;

@@ -136,18 +136,19 @@ struct BatchSpaces {
   bool scan_large;  // some small-cell event has a cell capacity > kSmallCap
 };
 
-// Lanes-per-cell settings of the cell kernels: 0 runs one wave per cell;
-// 8, 16, 32 and 64 run 64 / lanes small cells per wave, one particle per
-// lane, and step larger cells with the whole wave.
-// Lanes per cell: 0 (one wave per cell), 8, 16, 32, 64 (64 / lanes cells
-// per wave, one particle per lane) or kTwoWavesPerCell (a workgroup of two
-// waves per cell; plain path only).
+// Lanes per cell of the cell kernels: 0 (one wave per cell), 8, 16, 32, 64
+// (64 / lanes cells per wave, one particle per lane; larger cells stepped by
+// a whole wave), kPackedCells (whole cells packed into waves of up to 64
+// particles, one per lane; plain path only) or kTwoWavesPerCell (a
+// workgroup of two waves per cell; plain path only).
+constexpr uint32_t kPackedCells = 1;
 constexpr uint32_t kTwoWavesPerCell = 128;
 inline bool valid_cell_lanes(int32_t v) {
   return v == 0 || v == 8 || v == 16 || v == 32 || v == 64;
 }
 inline bool valid_plain_cell_lanes(int32_t v) {
-  return valid_cell_lanes(v) || v == (int32_t)kTwoWavesPerCell;
+  return valid_cell_lanes(v) || v == (int32_t)kTwoWavesPerCell ||
+         v == (int32_t)kPackedCells;
 }
 
 // A second stream on which a step runs work that is independent of the

@@ -1477,6 +1477,294 @@ __global__ __launch_bounds__(64) void k_step_small(Cells src_arg, Cells dst_arg,
   (void)small_cells_step<kFused, kTrace, G>(src, dst, c0, c_end, t, pa, g, status, tr, lds);
 }
 
+// ---------------------------------------------------------------------------
+// Packed cells: a wave takes a tile of 64 consecutive cells and packs whole
+// cells, in cell order, into units of at most 64 particles, one particle per
+// lane (a unit ends before the cell that would not fit).  So a sparse box
+// steps with few idle lanes whatever its mix of occupancies, where a fixed
+// number of lanes per cell idles most of them in its emptier cells.  Each
+// unit:
+//   1. loads its particles (a lane each), ids and positions into LDS;
+//   2. ranks each id among its cell's ids and stores the momentum at the
+//      canonical position (cell start + rank);
+//   3. tests each cell's pairs k = i, i + n, i + 2n, ... in its n lanes with
+//      the Philox w1 filter, appending the passing ones to an LDS list (in
+//      increasing k per cell);
+//   4. in rows of 64 list entries: the exact Eq. (3) test, one entry a
+//      lane, then the greedy claims of the row's accepted pairs in list
+//      order, with the claimed flags of all canonical positions in one
+//      wave-uniform mask (a row is resolved early when the list nears full,
+//      which keeps each cell's claims in increasing k);
+//   5. computes the kinematics of each claimed pair in both of its lanes
+//      (same inputs and code, so the same result) and keeps its half;
+//   6. fused: streams and bins every particle; else writes the scattered
+//      momenta back.
+// Cells holding more than 64 particles, or more than their block holds,
+// are left to the kernel for larger cells.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kPackedMax = 64;    // particles of a unit, and of a cell it takes
+constexpr uint32_t kPackedFilt = 256;  // filtered pairs held before a row is resolved
+
+struct PackedLds {
+  __align__(16) uint32_t id[64];   // by lane: the unit's particles, cell by cell
+  double x[64], y[64], z[64];      // by lane
+  double px[64], py[64], pz[64];   // by canonical position
+  uint32_t filt[kPackedFilt];      // filtered pairs: tile cell << 16 | k
+  uint32_t incl[64];               // by tile cell: inclusive prefix of the packed counts
+  uint32_t start[64], cnt[64];     // by tile cell: first lane, particles
+  uint32_t partner[64];            // by canonical position: the claimed partner's
+};
+
+// Exact test and claims of filt[i0 .. i0 + 63] (< nf), in list order.
+template <bool kTrace>
+__device__ __forceinline__ void packed_resolve_row(
+    uint32_t i0, uint32_t nf, uint32_t c0, uint32_t t, const PairArgs &pa, PackedLds &lds,
+    uint64_t &claimed, uint32_t &nclaim, uint32_t &n_acc, const TraceArgs &tr,
+    DevStatus *status) {
+  const uint32_t lane = lane_id();
+  const uint32_t i = i0 + lane;
+  bool acc = false;
+  uint32_t v = 0;
+  if (i < nf) {
+    const uint32_t e = lds.filt[i];
+    const uint32_t cl = e >> 16, k = e & 0xFFFFu;
+    const uint32_t n = lds.cnt[cl], st = lds.start[cl];
+    const Words4 w = philox10(k, c0 + cl, t, 0u, pa.key0, pa.key1);
+    uint32_t a, b;
+    pair_of_index(k, n, a, b);
+    acc = uniform53(w.w0, w.w1) < p22(lds.px[st + a], lds.py[st + a], lds.pz[st + a],
+                                      lds.px[st + b], lds.py[st + b], lds.pz[st + b],
+                                      pa.kfac);
+    v = (st + a) << 8 | (st + b);
+    if (kTrace && acc && tr.cand) {
+      const uint32_t slot = atomicAdd(&tr.counts[0], 1u);
+      if (slot < tr.cand_cap) {
+        tr.cand[3 * (size_t)slot + 0] = c0 + cl;
+        tr.cand[3 * (size_t)slot + 1] = a;
+        tr.cand[3 * (size_t)slot + 2] = b;
+      } else {
+        atomicOr(&status->err, kErrTrace);
+      }
+    }
+  }
+  n_acc += acc ? 1u : 0u;
+  for (uint64_t m = __ballot(acc); m != 0; m &= m - 1ull) {
+    const uint32_t l = (uint32_t)__builtin_ctzll(m);
+    const uint32_t vl = (uint32_t)__shfl((int)v, (int)l);
+    const uint32_t pa_ = vl >> 8, pb_ = vl & 0xFFu;
+    const uint64_t ab = (1ull << pa_) | (1ull << pb_);
+    if ((claimed & ab) == 0) {
+      claimed |= ab;
+      if (lane == 0) {
+        lds.partner[pa_] = pb_;
+        lds.partner[pb_] = pa_;
+      }
+      ++nclaim;
+      if (kTrace && tr.claim && lane == l) {
+        const uint32_t e = lds.filt[i];
+        const uint32_t cl = e >> 16, st = lds.start[cl];
+        const uint32_t slot = atomicAdd(&tr.counts[1], 1u);
+        if (slot < tr.claim_cap) {
+          tr.claim[3 * (size_t)slot + 0] = c0 + cl;
+          tr.claim[3 * (size_t)slot + 1] = pa_ - st;
+          tr.claim[3 * (size_t)slot + 2] = pb_ - st;
+        } else {
+          atomicOr(&status->err, kErrTrace);
+        }
+      }
+    }
+  }
+}
+
+template <bool kFused, bool kTrace>
+__device__ __forceinline__ void packed_cells_step(const GCells &src, const GCells &dst,
+                                                  uint32_t c0, uint32_t n_cells, uint32_t t,
+                                                  const PairArgs &pa, const Geometry &g,
+                                                  DevStatus *status, const TraceArgs &tr,
+                                                  PackedLds &lds) {
+  constexpr uint32_t kNone = 0xFFFFFFFFu;
+  const uint32_t lane = lane_id();
+  const uint64_t below = (1ull << lane) - 1ull;
+  if (c0 == 0 && lane == 0) clear_idle_scratch(src, t);
+  // the tile's cells, one a lane; overflowing and larger cells are left out
+  const uint32_t cc = c0 + lane;
+  const uint32_t ccnt = cc < n_cells ? src.count[cc] : 0u;
+  const bool packed = cc < n_cells && ccnt <= kPackedMax && ccnt <= src.cap;
+  const uint32_t nl = packed ? ccnt : 0u;
+  uint32_t incl = nl;  // inclusive prefix of the packed counts
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t up = (uint32_t)__shfl_up((int)incl, o);
+    if ((int)lane >= o) incl += up;
+  }
+  const uint32_t total = (uint32_t)__shfl((int)incl, 63);
+  uint32_t cnt_pairs = 0, n_acc = 0, n_claims = 0;
+  for (uint32_t base = 0; base < total;) {
+    // the unit: the cells whose particles end within base + 64 (a prefix of
+    // the tile's lanes beyond the previous unit; each cell fits alone)
+    const uint64_t fit = __ballot(incl <= base + kPackedMax);
+    const uint32_t e = 63u - (uint32_t)__builtin_clzll(fit);
+    const uint32_t end = (uint32_t)__shfl((int)incl, (int)e);
+    const uint32_t p = end - base;  // particles of the unit
+    const bool in_unit = nl > 0 && incl - nl >= base && lane <= e;
+    wave_lds_sync();  // the previous unit's readers of lds are done
+    lds.incl[lane] = incl;
+    if (in_unit) {
+      lds.start[lane] = incl - nl - base;
+      lds.cnt[lane] = nl;
+      cnt_pairs += nl * (nl - 1u) / 2u;
+    }
+    wave_lds_sync();
+    // each lane's cell: the first tile cell whose particles end beyond it
+    // (binary search of the inclusive prefix)
+    const bool mine = lane < p;
+    uint32_t cl = 0;
+    {
+      const uint32_t key = base + lane;
+      uint32_t lo = 0, hi = 63;  // first index with incl > key, in [lo, hi]
+      for (int it = 0; it < 6; ++it) {
+        const uint32_t mid = (lo + hi) / 2u;
+        if (lds.incl[mid] > key) hi = mid; else lo = mid + 1u;
+      }
+      cl = mine ? lo : 0u;
+    }
+    const uint32_t st = mine ? lds.start[cl] : 0u;
+    const uint32_t n = mine ? lds.cnt[cl] : 0u;
+    const uint32_t gl = lane - st;
+    const uint32_t c = c0 + cl;
+    {
+      uint32_t id = kNone;
+      if (mine) {
+        const size_t o = (size_t)c * src.cap + gl;
+        lds.x[lane] = src.st.x[o];
+        lds.y[lane] = src.st.y[o];
+        lds.z[lane] = src.st.z[o];
+        lds.px[lane] = src.st.px[o];  // by lane until ranked
+        lds.py[lane] = src.st.py[o];
+        lds.pz[lane] = src.st.pz[o];
+        id = src.st.id[o];
+      }
+      lds.id[lane] = id;
+    }
+    wave_lds_sync();
+    // canonical rank among the cell's ids; the momenta move to their
+    // canonical positions
+    uint32_t pos;
+    {
+      const uint32_t id = lds.id[lane];
+      const uint32_t maxn = wave_max(n);
+      uint32_t r = 0;
+      for (uint32_t m = 0; m < maxn; ++m)
+        if (m < n) r += lds.id[st + m] < id ? 1u : 0u;
+      pos = st + r;
+      const double qx = lds.px[lane], qy = lds.py[lane], qz = lds.pz[lane];
+      wave_lds_sync();
+      if (mine) {
+        lds.px[pos] = qx;
+        lds.py[pos] = qy;
+        lds.pz[pos] = qz;
+        if (kTrace && tr.perm) tr.perm[tr.offsets[c] + r] = id;
+      }
+    }
+    wave_lds_sync();
+
+    // pair tests, the w1 filter first, in passes that fill the list; then
+    // the exact test and claims of the list by rows
+    uint64_t claimed = 0;
+    uint32_t nclaim = 0;
+    if (pa.any) {
+      const uint32_t npairs = n * (n - 1u) / 2u;
+      uint32_t k = gl;
+      while (__ballot(k < npairs) != 0) {
+        uint32_t nf = 0;
+        do {
+          const bool pass = k < npairs &&
+                            philox10_w1(k, c, t, 0u, pa.key0, pa.key1) <= pa.w1_max;
+          const uint64_t mk = __ballot(pass);
+          if (pass) lds.filt[nf + (uint32_t)__popcll(mk & below)] = cl << 16 | k;
+          nf += (uint32_t)__popcll(mk);
+          k += n;
+        } while (nf <= kPackedFilt - 64u && __ballot(k < npairs) != 0);
+        wave_lds_sync();
+        for (uint32_t i0 = 0; i0 < nf; i0 += 64u)
+          packed_resolve_row<kTrace>(i0, nf, c0, t, pa, lds, claimed, nclaim, n_acc, tr,
+                                     status);
+        wave_lds_sync();
+      }
+    }
+    n_claims += nclaim;
+
+    // kinematics of the claimed pairs, in both lanes of each
+    double px = lds.px[pos], py = lds.py[pos], pz = lds.pz[pos];
+    const bool scat = mine && ((claimed >> pos) & 1ull) != 0;
+    if (scat) {
+      const uint32_t other = lds.partner[pos];
+      const bool lo = pos < other;
+      const uint32_t A = lo ? pos : other, B = lo ? other : pos;
+      const uint32_t ra = A - st, rb = B - st;
+      const uint32_t k = row_start(ra, n) + (rb - ra - 1u);
+      const Words4 w = philox10(k, c, t, 1u, pa.key0, pa.key1);
+      double ax = lds.px[A], ay = lds.py[A], az = lds.pz[A];
+      double bx = lds.px[B], by = lds.py[B], bz = lds.pz[B];
+      scatter_pair(ax, ay, az, bx, by, bz, uniform53(w.w0, w.w1), uniform53(w.w2, w.w3));
+      px = lo ? ax : bx;
+      py = lo ? ay : by;
+      pz = lo ? az : bz;
+      if (!kFused) {
+        const size_t o = (size_t)c * src.cap + gl;
+        src.st.px[o] = px;
+        src.st.py[o] = py;
+        src.st.pz[o] = pz;
+      }
+    }
+    if (kFused) {
+      double x = 0, y = 0, z = 0;
+      uint32_t c2 = 0, id = 0;
+      if (mine) {
+        const Geometry g_l = g;
+        x = lds.x[lane];
+        y = lds.y[lane];
+        z = lds.z[lane];
+        id = lds.id[lane];
+        advance<true>(g_l, x, y, z, px, py, pz);
+        c2 = cell_id(g_l, x, y, z);
+      }
+      append(dst, c2, mine, x, y, z, px, py, pz, id, status);
+    }
+    base = end;
+  }
+  // work counters of the tile, in one slot; the packed cells' counts
+  // cleared for the buffer's next use
+#pragma unroll
+  for (int s = 32; s > 0; s >>= 1) {
+    cnt_pairs += __shfl_down(cnt_pairs, s);
+    n_acc += __shfl_down(n_acc, s);
+  }
+  if (lane == 0 && cnt_pairs != 0) {
+    const uint32_t slot = c0 % kCounterSlots;
+    atomicAdd(&status->pairs[slot], (unsigned long long)cnt_pairs);
+    atomicAdd(&status->cand[slot], (unsigned long long)n_acc);
+    atomicAdd(&status->claims[slot], (unsigned long long)n_claims);
+  }
+  if (kFused && packed) src.count[cc] = 0u;
+}
+
+// dst is src shifted by dst_shift bytes and g is read from device memory
+// where the binning uses it (as for k_step: fewer values held through the
+// loops).  Five waves per SIMD: the compiler's choice (4, 101-104 VGPRs)
+// made the 32^3 fm^3 set's fused step 5 % slower, six (80 VGPRs, 12
+// spilled) 4 %.
+template <bool kFused, bool kTrace>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_step_packed(
+    Cells src_arg, int64_t dst_shift, uint32_t n_cells, uint32_t t, PairArgs pa,
+    const Geometry *__restrict__ gp, DevStatus *status, TraceArgs tr) {
+  const GCells src = binning(to_global(src_arg), t);
+  __shared__ PackedLds lds;
+  const uint32_t c0 = xcd_runs<8>(blockIdx.x, gridDim.x) * 64u;
+  packed_cells_step<kFused, kTrace>(src, dst_of(src, dst_shift, t), c0, n_cells, t, pa, *gp,
+                                    status, tr, lds);
+}
+
 // One wave per 64 consecutive cells: the cells holding more than `lanes`
 // particles.
 template <bool kFused, bool kTrace, uint32_t kCap>
@@ -1916,7 +2204,9 @@ void launch_stream_bin(const Cells &src, const Cells &dst, int64_t n_cells, uint
                        const Geometry &g, DevStatus *status, uint32_t *trace_cell,
                        uint32_t t, hipStream_t s) {
   if (n_cells <= 0) return;
-  const uint32_t G = lanes == 0 || lanes == kTwoWavesPerCell ? 64u : lanes;
+  const uint32_t G = lanes == 0 || lanes == kTwoWavesPerCell ? 64u
+                     : lanes == kPackedCells                 ? 16u
+                                                             : lanes;
   const int64_t waves = (n_cells + 64 / G - 1) / (64 / G);
   const dim3 grid(cell_blocks(waves)), block(kBlock);
   const uint32_t nc = (uint32_t)n_cells;
@@ -1985,8 +2275,16 @@ void launch_step_cap(const Cells &src, const Cells &dst, uint32_t n_cells, uint3
   // the small cells and, concurrently, the cells the small-cell kernel
   // leaves alone (disjoint cells; both append to dst through atomics)
   fork(s, side);
-  const dim3 grid((n_cells + 64 / lanes - 1) / (64 / lanes));
+  const uint32_t per = lanes == kPackedCells ? 64u : 64u / lanes;  // cells per wave
+  const dim3 grid((n_cells + per - 1) / per);
+  // the particles above which a cell goes to the second kernel
+  const uint32_t thr = lanes == kPackedCells ? kPackedMax : lanes;
   switch (lanes) {
+    case kPackedCells:
+      hipLaunchKernelGGL((k_step_packed<kFused, kTrace>), grid, block, 0, s, src,
+                         (int64_t)((const char *)dst.st.x - (const char *)src.st.x), n_cells, t,
+                         pa, dev.g, status, tr);
+      break;
     case 8:
       hipLaunchKernelGGL((k_step_small<kFused, kTrace, 8>), grid, block, 0, s, src, dst,
                          n_cells, t, pa, g, status, tr);
@@ -2006,11 +2304,11 @@ void launch_step_cap(const Cells &src, const Cells &dst, uint32_t n_cells, uint3
   hipStream_t so = side ? side->stream : s;
   if (dev.over_span == 1)
     hipLaunchKernelGGL((k_step_over<kFused, kTrace, kCap>), dim3(n_cells), block, 0, so, src,
-                       (int64_t)((const char *)dst.st.x - (const char *)src.st.x), lanes, t,
+                       (int64_t)((const char *)dst.st.x - (const char *)src.st.x), thr, t,
                        pa, dev.g, status, tr);
   else
     hipLaunchKernelGGL((k_step_large<kFused, kTrace, kCap>), dim3((n_cells + 63) / 64), block,
-                       0, so, src, dst, n_cells, lanes, t, pa, g, status, tr);
+                       0, so, src, dst, n_cells, thr, t, pa, g, status, tr);
   join(s, side);
 }
 

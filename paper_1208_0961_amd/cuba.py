@@ -239,6 +239,7 @@ def cuba_sync(ctx: int) -> None:
 
 CELL_LANES = (0, 8, 16, 32, 64)      # every context, batched or not
 TWO_WAVES_PER_CELL = 128             # plain contexts only
+PACKED_CELLS = 1                     # plain contexts only: whole cells packed into waves
 
 
 def cuba_set_cell_lanes(ctx: int, lanes: int) -> None:

@@ -113,7 +113,7 @@ def test_overflowing_cell_from_init(orc, lib):
     traced_step(orc, lib, params, state, 3, "one cell 1500 / 1024")
 
 
-@pytest.mark.parametrize("lanes,cap", [(0, 32), (16, 32), (128, 32), (64, 16)])
+@pytest.mark.parametrize("lanes,cap", [(0, 32), (16, 32), (128, 32), (64, 16), (1, 32)])
 def test_mixed_overflowing_and_normal_cells(orc, lib, lanes, cap):
     # 64 cells, a third of them past a block of 32 (up to 300 members), the
     # rest below it, some empty; several steps, traced.  With blocks of 16

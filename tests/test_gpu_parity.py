@@ -355,10 +355,11 @@ def _full_size_step_check(orc, got_prev, got, params, t, label, threads=16):
 
 def test_paper_parameter_set_full_size(orc, lib):
     """The paper's own set-up at full size (128^3 cells, 24.9 M particles) in
-    the benchmark's launch configuration (8 lanes per cell, oversize cells a
-    wave each): one step (stream-bin and collide-only kernels) and a second
-    step from it (fused kernel) against one traced oracle step each, and
-    the scattered particles against twice the claims counted on the device."""
+    the benchmark's launch configuration (packed cells, the library's choice
+    for this box): one step (stream-bin and collide-only kernels) and a
+    second step from it (fused kernel) against one traced oracle step each,
+    and the scattered particles against twice the claims counted on the
+    device."""
     import torch
     from paper_1208_0961_amd import cuba as C
     w = W.PAPER_32
@@ -366,7 +367,7 @@ def test_paper_parameter_set_full_size(orc, lib):
     st0 = [a.cpu().numpy() for a in W.riemann_state_torch(w, seed=77, device="cuda")]
     say(f"[paper32] {w.n} particles, 1 step")
     a = lib.Sim(params, st0)
-    assert a.cell_lanes == 8
+    assert a.cell_lanes == C.PACKED_CELLS
     a.step(1)
     s1 = a.get_state()
     claims1 = C.cuba_counters(a.ctx)["claims"]

@@ -18,6 +18,8 @@ from test_gpu_parity import compare_step, _cells_box, _orc_params, _rows, say, l
 pytestmark = pytest.mark.gpu
 
 LANES = (8, 16, 32, 64)
+PACKED = 1                  # whole cells packed into waves of up to 64 particles
+SETTINGS = (PACKED,) + LANES
 
 
 def sparse_workload(mean_scale=1.0, seed=31):
@@ -27,7 +29,7 @@ def sparse_workload(mean_scale=1.0, seed=31):
                       0.9 * mean_scale, 0.02, 0.45, 0.36, seed=seed)
 
 
-@pytest.mark.parametrize("lanes", LANES)
+@pytest.mark.parametrize("lanes", SETTINGS)
 def test_small_cells_trace_parity_sparse(orc, lib, lanes):  # noqa: F811
     w = sparse_workload()
     state = W.riemann_state(w, seed=5)
@@ -38,7 +40,7 @@ def test_small_cells_trace_parity_sparse(orc, lib, lanes):  # noqa: F811
     assert n_claim > 300
 
 
-@pytest.mark.parametrize("lanes", LANES)
+@pytest.mark.parametrize("lanes", SETTINGS)
 def test_small_cells_trace_parity_ragged(orc, lib, lanes):  # noqa: F811
     # occupancies on both sides of every group size, the 64-lane limit, and
     # cells the whole wave must take over
@@ -52,17 +54,18 @@ def test_small_cells_trace_parity_ragged(orc, lib, lanes):  # noqa: F811
     assert len(tr["claim"]) > 50
 
 
-@pytest.mark.parametrize("lanes", LANES)
+@pytest.mark.parametrize("lanes", SETTINGS)
 def test_small_cells_every_pair_passes_filter(orc, lib, lanes):  # noqa: F811
     # 2K = 1: the w1 filter passes every pair, so every pair takes the exact
-    # test and many claims compete inside each cell
-    occ = [lanes, lanes - 1, 3, 2] * 2
+    # test and many claims compete inside each cell (packed: cells of up to
+    # 64 particles, whose 2016 pairs fill the filtered-pair list many times)
+    occ = [lanes, lanes - 1, 3, 2] * 2 if lanes != PACKED else [64, 63, 40, 2] * 2
     state = _cells_box(occ, m=2)
     V = 1.0 / 8.0
     params = dict(box=(1.0, 1.0, 1.0), cells=(2, 2, 2), sigma=0.5 * V / 0.001,
                   r_test=1.0, dt=0.001, seed=4242)
     _, tr = compare_step(orc, lib, params, state, 9, "K=1/2", lanes=lanes)
-    assert len(tr["claim"]) >= lanes // 2
+    assert len(tr["claim"]) >= (lanes if lanes != PACKED else 64) // 2
 
 
 def _fused_step_check(orc, lib, params, state, nsteps, lanes, label):  # noqa: F811
@@ -99,7 +102,7 @@ def _fused_step_check(orc, lib, params, state, nsteps, lanes, label):  # noqa: F
     return len(tr["claim"])
 
 
-@pytest.mark.parametrize("lanes", (0,) + LANES)
+@pytest.mark.parametrize("lanes", (0,) + SETTINGS)
 def test_fused_small_cell_steps_match_oracle(orc, lib, lanes):  # noqa: F811
     w = sparse_workload(seed=11)
     state = W.riemann_state(w, seed=12)
@@ -118,7 +121,7 @@ def test_lanes_settings_agree_bit_for_bit(lib):  # noqa: F811
     w = sparse_workload(mean_scale=2.0, seed=21)
     state = W.riemann_state(w, seed=22)
     ref = None
-    for lanes in (0,) + LANES:
+    for lanes in (0,) + SETTINGS:
         s = lib.Sim(w.params(), state, cell_lanes=lanes)
         assert s.cell_lanes == lanes
         s.step(13)
@@ -139,8 +142,8 @@ def test_lanes_setting_is_validated(lib):  # noqa: F811
     from paper_1208_0961_amd import cuba as C
     w = sparse_workload()
     s = lib.Sim(w.params(), W.riemann_state(w))
-    assert s.cell_lanes in (0,) + LANES
-    for bad in (-1, 1, 4, 12, 256):
+    assert s.cell_lanes in (0,) + SETTINGS
+    for bad in (-1, 2, 4, 12, 256):
         with pytest.raises(C.CubaError) as e:
             s.cell_lanes = bad
         assert e.value.code == C.CUBA_EINVAL
@@ -160,20 +163,24 @@ def _grid_state(occ, m=32, T=0.4, seed=9):
 
 
 def test_default_lanes_rule(lib):  # noqa: F811
-    """cuba_init's choice from the initial occupancy (32^3 cells), and the
-    batch's, which never leaves a large share of the cells oversize."""
+    """cuba_init's choice from the initial occupancy and K (32^3 cells), and
+    the batch's, which never leaves a large share of the cells oversize."""
     import torch
     from paper_1208_0961_amd import batch
     m = 32
     C = m ** 3
     half = np.where(np.arange(C) < C // 2, 40, 3)
-    cases = [("all 3", np.full(C, 3), 8, 8), ("all 12", np.full(C, 12), 16, 16),
-             ("all 25", np.full(C, 25), 32, 32), ("all 40", np.full(C, 40), 0, 0),
-             ("dense and sparse halves", half, 8, 0)]
+    # 2K = 6.6 % (sigma 0.1), or 0.066 % (sigma 0.001)
+    cases = [("all 3", np.full(C, 3), 0.1, PACKED, 8),
+             ("all 12", np.full(C, 12), 0.1, PACKED, 16),
+             ("all 12, small K", np.full(C, 12), 0.001, 16, 16),
+             ("all 25", np.full(C, 25), 0.1, 32, 32), ("all 40", np.full(C, 40), 0.1, 0, 0),
+             ("dense and sparse halves", half, 0.1, PACKED, 0)]
     params = dict(box=(1.0, 1.0, 1.0), cells=(m, m, m), sigma=0.1, r_test=100.0,
                   dt=0.001, seed=5, cell_capacity=64)
-    for label, occ, want_plain, want_batch in cases:
+    for label, occ, sigma, want_plain, want_batch in cases:
         state = _grid_state(occ)
+        params = dict(params, sigma=sigma)
         s = lib.Sim(params, state)
         got = s.cell_lanes
         s.close()

@@ -53,7 +53,7 @@ def _truncate(schedule, m):
     return out
 
 
-@pytest.mark.parametrize("lanes", (0, 8))
+@pytest.mark.parametrize("lanes", (0, 8, 1))
 def test_dt_changes_match_oracle(orc, lib, lanes):  # noqa: F811
     w = _workload()
     params = w.params()
