@@ -497,6 +497,14 @@ __global__ __launch_bounds__(kBlock) void k_stream_bin(Cells src_arg, Cells dst_
   cells_stream_bin<G>(src, dst, c0, c_end, g, status, trace_cell);
 }
 
+// Orders the calling wave's LDS accesses before and after this point for
+// its own lanes (LDS executes one wave's operations in order; the fence
+// keeps the compiler from moving accesses across and waits for them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Exclusive scan of the counts into compact offsets (trace only; the counts
 // are left intact).  Tile-local pass, then carries from earlier tiles.
 __global__ __launch_bounds__(kBlock) void k_scan_tiles(Cells cur_arg,
@@ -584,14 +592,6 @@ struct CellView {
     return base + j;
   }
 };
-
-// Orders the calling wave's LDS accesses before and after this point for
-// its own lanes (LDS executes one wave's operations in order; the fence
-// keeps the compiler from moving accesses across and waits for them).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-}
 
 // kBlockSync: the workgroup is this one wave, and its barriers order the
 // LDS accesses; otherwise a wave that shares its workgroup with others
@@ -2204,6 +2204,9 @@ void launch_stream_bin(const Cells &src, const Cells &dst, int64_t n_cells, uint
                        const Geometry &g, DevStatus *status, uint32_t *trace_cell,
                        uint32_t t, hipStream_t s) {
   if (n_cells <= 0) return;
+  // (packed cells: 16 lanes a cell; a stream-bin that packs 64 particles
+  // a round whatever their cells measured the same on the 32^3 fm^3 set,
+  // whose sparse cells' cost is their partly used cache lines)
   const uint32_t G = lanes == 0 || lanes == kTwoWavesPerCell ? 64u
                      : lanes == kPackedCells                 ? 16u
                                                              : lanes;
