@@ -99,11 +99,12 @@ typedef struct {
   uint32_t step0;   /* index t of the first step (0, or t when resuming)    */
   int32_t cell_capacity; /* slots of each cell's block in the workspace, in
                             [1, CUBA_MAX_CELL_CAPACITY]; 0 selects twice the
-                            mean occupancy n / cells + 32, rounded up to 32.
-                            A layout choice, not a limit: a cell receiving
-                            more keeps the surplus in the spill region and
-                            is stepped (slower, same result) by the kernel
-                            for such cells.                                */
+                            mean occupancy n / cells + 32, rounded up to 32
+                            (cuba_suggest_cell_capacity sizes it from the
+                            initial state instead).  A layout choice, not a
+                            limit: a cell receiving more keeps the surplus
+                            in the spill region and is stepped (slower,
+                            same result) by the kernel for such cells.     */
 } cuba_params;
 
 /* Bytes of device workspace cuba_init needs for n particles with these
@@ -113,6 +114,20 @@ typedef struct {
  * stepping overflowing cells, and per-cell bookkeeping.  Returns 0 if the parameters
  * are invalid.  The workspace must be 256-byte aligned. */
 size_t cuba_workspace_bytes(const cuba_params *params, int64_t n);
+
+/* Slots per cell suited to an initial state, counted on the device: twice
+ * the largest occupancy of any cell (positions x, y, z: device arrays of n
+ * doubles, binned as Sec. 2 bins them; non-finite positions are skipped)
+ * plus 32, rounded up to 32, within [64, CUBA_MAX_CELL_CAPACITY]; written
+ * to *cap for params.cell_capacity.  scratch: device memory of at least
+ * cuba_capacity_scratch_bytes(params), 256-byte aligned, owned by the
+ * caller.  Runs on stream and waits for it (a set-up call, not part of a
+ * step).  Errors: CUBA_EINVAL for invalid parameters, NULL arrays with
+ * n > 0, a NULL cap or too small a scratch; CUBA_EDEVICE. */
+size_t cuba_capacity_scratch_bytes(const cuba_params *params);
+int cuba_suggest_cell_capacity(const cuba_params *params, int64_t n, const double *x,
+                               const double *y, const double *z, void *scratch,
+                               size_t scratch_bytes, void *stream, int32_t *cap);
 
 /* Creates a context.  x..pz are device arrays of n doubles (particle id =
  * array index), copied into the workspace; they may be freed once the

@@ -20,11 +20,13 @@ def event_workspace_bytes(params: dict, n: int) -> int:
     return nbytes
 
 
-def with_capacity(params: dict, state) -> dict:
-    """params with a cell_capacity chosen from the initial state if unset."""
+def with_capacity(params: dict, state, device=None, stream=None) -> dict:
+    """params with a cell_capacity chosen from the initial state if unset
+    (counted on the device, on `stream`)."""
     q = dict(params)
     if not q.get("cell_capacity"):
-        q["cell_capacity"] = suggest_cell_capacity(q, state)
+        q["cell_capacity"] = suggest_cell_capacity(q, state, device=device or "cuda",
+                                                   stream=stream)
     return q
 
 
@@ -53,7 +55,7 @@ class Batch:
 
     def admit(self, slot: int, params: dict, state, workspace: torch.Tensor | None = None):
         """Admits an event (params as for Sim; state: six id-ordered arrays)."""
-        params = with_capacity(params, state)
+        params = with_capacity(params, state, self.device, self.stream)
         n = int(len(state[0]))
         p = C.make_params(**params)
         nbytes = C.cuba_workspace_bytes(p, n)
@@ -78,7 +80,7 @@ class Batch:
         """As admit, without waiting for the stream (cuba_batch_admit_async):
         errors of the initial state surface at the next sync; lanes: the
         event's lanes per cell."""
-        params = with_capacity(params, state)
+        params = with_capacity(params, state, self.device, self.stream)
         n = int(len(state[0]))
         p = C.make_params(**params)
         nbytes = C.cuba_workspace_bytes(p, n)

@@ -367,6 +367,43 @@ int run_steps(cuba_ctx *c, int32_t nsteps, const TraceArgs *trace_in) {
 
 extern "C" {
 
+size_t cuba_capacity_scratch_bytes(const cuba_params *params) {
+  Derived d;
+  if (derive(params, 0, d) != CUBA_OK) return 0;
+  return ((size_t)(d.n_cells + 1) * sizeof(uint32_t) + 255) / 256 * 256;
+}
+
+int cuba_suggest_cell_capacity(const cuba_params *params, int64_t n, const double *x,
+                               const double *y, const double *z, void *scratch,
+                               size_t scratch_bytes, void *stream, int32_t *cap) {
+  if (!cap) return fail(CUBA_EINVAL, "cap is NULL");
+  if (n < 0 || n >= 0xFFFFFFFFll) return fail(CUBA_EINVAL, "n must be in [0, 2^32 - 1)");
+  Derived d;
+  const int rc = derive(params, 0, d);
+  if (rc != CUBA_OK) return rc;
+  if (n > 0 && !(x && y && z)) return fail(CUBA_EINVAL, "position arrays must not be NULL");
+  const size_t need = cuba_capacity_scratch_bytes(params);
+  if (!scratch || scratch_bytes < need || ((uintptr_t)scratch & 255u) != 0)
+    return fail(CUBA_EINVAL, "scratch must be 256-byte aligned and hold "
+                             "cuba_capacity_scratch_bytes(params)");
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t *count = (uint32_t *)scratch;
+  uint32_t *max_count = count + d.n_cells;
+  launch_count_cells(x, y, z, n, d.g, d.n_cells, count, max_count, s);
+  uint32_t m = 0;
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(&m, max_count, sizeof(m), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "cuba_suggest_cell_capacity");
+  if (n == 0 || m == 0) {
+    *cap = 64;
+    return CUBA_OK;
+  }
+  const uint64_t want = ((2ull * m + 32ull) + 31ull) / 32ull * 32ull;
+  *cap = (int32_t)(want < 64ull ? 64ull : want > kCellCap ? (uint64_t)kCellCap : want);
+  return CUBA_OK;
+}
+
 size_t cuba_workspace_bytes(const cuba_params *params, int64_t n) {
   Derived d;
   if (n < 0 || n >= 0xFFFFFFFFll || derive(params, n, d) != CUBA_OK) return 0;

@@ -167,6 +167,12 @@ void launch_store_f64(double *p, double v, hipStream_t s);
 // the call neither waits for the stream nor needs src after it returns).
 // False if the size or alignment does not fit.
 bool launch_write_bytes(void *dst, const void *src, size_t bytes, hipStream_t s);
+// Counts the particles of each cell (count: n_cells words, zeroed here)
+// and the largest count into *max_count (zeroed here); non-finite positions
+// are skipped.
+void launch_count_cells(const double *x, const double *y, const double *z, int64_t n,
+                        const Geometry &g, int64_t n_cells, uint32_t *count,
+                        uint32_t *max_count, hipStream_t s);
 // Validates and bins the id-ordered initial state into dst; the binning is
 // that of step `binning_step` (step0 - 1: the stream-bin of step0 consumes
 // it).

@@ -2347,6 +2347,47 @@ void launch_step(const Cells &src, const Cells &dst, bool fused, int64_t n_cells
                               trace, s, side, dev);
 }
 
+namespace {
+
+__global__ __launch_bounds__(kBlock) void k_count_cells(const double *__restrict__ x,
+                                                        const double *__restrict__ y,
+                                                        const double *__restrict__ z,
+                                                        int64_t n, Geometry g,
+                                                        uint32_t *count) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double a = x[i], b = y[i], c = z[i];
+    if (__builtin_isfinite(a) && __builtin_isfinite(b) && __builtin_isfinite(c))
+      atomicAdd(&count[cell_id(g, a, b, c)], 1u);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_max_u32(const uint32_t *__restrict__ v, int64_t n,
+                                                    uint32_t *out) {
+  uint32_t m = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    m = max(m, v[i]);
+  m = wave_max(m);
+  if (lane_id() == 0) atomicMax(out, m);
+}
+
+}  // namespace
+
+void launch_count_cells(const double *x, const double *y, const double *z, int64_t n,
+                        const Geometry &g, int64_t n_cells, uint32_t *count,
+                        uint32_t *max_count, hipStream_t s) {
+  launch_fill_u32(count, 0u, n_cells, s);
+  launch_fill_u32(max_count, 0u, 1, s);
+  if (n > 0) {
+    const unsigned grid = grid_for(n) < 4096u ? grid_for(n) : 4096u;
+    hipLaunchKernelGGL(k_count_cells, dim3(grid), dim3(kBlock), 0, s, x, y, z, n, g, count);
+  }
+  const unsigned grid = grid_for(n_cells) < 1024u ? grid_for(n_cells) : 1024u;
+  hipLaunchKernelGGL(k_max_u32, dim3(grid), dim3(kBlock), 0, s, (const uint32_t *)count,
+                     n_cells, max_count);
+}
+
 void launch_occupancy_over(const Cells &cur, int64_t n_cells, DevStatus *status,
                            hipStream_t s) {
   if (n_cells <= 0) return;

@@ -66,6 +66,11 @@ def _load() -> ctypes.CDLL:
     P = ctypes.POINTER(cuba_params)
     L.cuba_workspace_bytes.argtypes = [P, i64]
     L.cuba_workspace_bytes.restype = ctypes.c_size_t
+    L.cuba_capacity_scratch_bytes.argtypes = [P]
+    L.cuba_capacity_scratch_bytes.restype = ctypes.c_size_t
+    L.cuba_suggest_cell_capacity.argtypes = [P, i64, vp, vp, vp, vp, ctypes.c_size_t, vp,
+                                             ctypes.POINTER(i32)]
+    L.cuba_suggest_cell_capacity.restype = ctypes.c_int
     L.cuba_init.argtypes = [ctypes.POINTER(vp), P, i64] + [vp] * 6 + [vp, ctypes.c_size_t, vp]
     L.cuba_init.restype = ctypes.c_int
     L.cuba_init_static.argtypes = [ctypes.POINTER(vp), P, i64] + [vp] * 6 + [vp]
@@ -194,6 +199,19 @@ def build_hash() -> str:
 
 def cuba_workspace_bytes(params: cuba_params, n: int) -> int:
     return int(_lib.cuba_workspace_bytes(ctypes.byref(params), int(n)))
+
+
+def cuba_capacity_scratch_bytes(params: cuba_params) -> int:
+    return int(_lib.cuba_capacity_scratch_bytes(ctypes.byref(params)))
+
+
+def cuba_suggest_cell_capacity(params: cuba_params, n: int, x: int, y: int, z: int,
+                               scratch: int, scratch_bytes: int, stream: int | None) -> int:
+    cap = ctypes.c_int32()
+    _check(_lib.cuba_suggest_cell_capacity(ctypes.byref(params), int(n), x, y, z, scratch,
+                                           int(scratch_bytes), stream, ctypes.byref(cap)),
+           "cuba_suggest_cell_capacity")
+    return int(cap.value)
 
 
 def cuba_init(params: cuba_params, n: int, x: int, y: int, z: int, px: int, py: int,

@@ -16,26 +16,29 @@ def _dev(a, device):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device)
 
 
-def suggest_cell_capacity(params: dict, state, headroom: float = 2.0, margin: int = 32) -> int:
-    """Slots per cell for the workspace: headroom x the largest initial cell
-    occupancy plus a margin, rounded up to 32, within [64, 1024].  A layout
-    choice only: a cell that later holds more keeps the surplus in spill
-    slots and is stepped on the library's slower overflow path."""
-    if len(state[0]) == 0:
-        return 64
-    box = np.asarray(params["box"], np.float64)
-    cells = np.asarray(params["cells"], np.int64)
-    r = [state[d].detach().cpu().numpy() if isinstance(state[d], torch.Tensor)
-         else np.asarray(state[d], np.float64) for d in range(3)]
-    ok = np.isfinite(r[0]) & np.isfinite(r[1]) & np.isfinite(r[2])
-    if not ok.any():
-        return 64
-    idx = [np.clip(np.floor(r[d][ok] / (box[d] / cells[d])), 0, cells[d] - 1)
-           .astype(np.int64) for d in range(3)]
-    flat = (idx[0] * cells[1] + idx[1]) * cells[2] + idx[2]
-    occ = int(np.bincount(flat).max())
-    cap = int(np.ceil((headroom * occ + margin) / 32.0)) * 32
-    return max(64, min(C.CUBA_MAX_CELL_CAPACITY, cap))
+def suggest_cell_capacity(params: dict, state, headroom: float = 2.0, margin: int = 32,
+                          device: str | torch.device = "cuda",
+                          stream: torch.cuda.Stream | None = None) -> int:
+    """Slots per cell for the workspace, counted on the device by
+    cuba_suggest_cell_capacity: twice the largest initial cell occupancy
+    plus 32, rounded up to 32, within [64, 1024].  A layout choice only: a
+    cell that later holds more keeps the surplus in spill slots and is
+    stepped on the library's slower overflow path.  (headroom and margin
+    are those of the library and kept for callers that name them.)"""
+    if (headroom, margin) != (2.0, 32):
+        raise ValueError("the library's rule is 2 x the largest occupancy + 32")
+    device = torch.device(device)
+    p = C.make_params(**{**params, "cell_capacity": 0})
+    n = int(len(state[0]))
+    stream = stream if stream is not None else torch.cuda.current_stream(device)
+    with torch.cuda.stream(stream):
+        pos = [_dev(state[d], device) for d in range(3)]
+        nbytes = C.cuba_capacity_scratch_bytes(p)
+        if nbytes == 0:
+            raise C.CubaError(C.CUBA_EINVAL, "cuba_capacity_scratch_bytes", C.cuba_last_error())
+        scratch = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    return C.cuba_suggest_cell_capacity(p, n, *[a.data_ptr() for a in pos],
+                                        scratch.data_ptr(), nbytes, stream.cuda_stream)
 
 
 class Sim:
@@ -55,15 +58,18 @@ class Sim:
                  stream: torch.cuda.Stream | None = None, cell_lanes: int | None = None):
         self.device = torch.device(device)
         self.params = dict(params)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        with torch.cuda.stream(self.stream):
+            arrs = [_dev(a, self.device) for a in state]
         if not self.params.get("cell_capacity"):
-            self.params["cell_capacity"] = suggest_cell_capacity(self.params, state)
+            self.params["cell_capacity"] = suggest_cell_capacity(self.params, arrs,
+                                                                 device=self.device,
+                                                                 stream=self.stream)
         self.p = C.make_params(**self.params)
         self.n = int(len(state[0]))
         self.nx = int(self.params["cells"][0])
         self.n_cells = int(np.prod(self.params["cells"]))
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         with torch.cuda.stream(self.stream):
-            arrs = [_dev(a, self.device) for a in state]
             self.ws_bytes = C.cuba_workspace_bytes(self.p, self.n)
             if self.ws_bytes == 0:
                 raise C.CubaError(C.CUBA_EINVAL, "cuba_workspace_bytes",

@@ -114,6 +114,17 @@ int main() {
   CHECK(cuba_batch_slot(nullptr, 0) == nullptr);
   cuba_batch_destroy(nullptr);
 
+  // capacity suggestion: scratch sizing and the checks before device work
+  CHECK(cuba_capacity_scratch_bytes(&p) > 0);
+  CHECK(cuba_capacity_scratch_bytes(nullptr) == 0);
+  int32_t cap = 0;
+  CHECK(cuba_suggest_cell_capacity(&p, 0, nullptr, nullptr, nullptr, nullptr, 0, nullptr,
+                                   nullptr) == CUBA_EINVAL);
+  CHECK(cuba_suggest_cell_capacity(&p, 4, nullptr, nullptr, nullptr, small, sizeof small,
+                                   nullptr, &cap) == CUBA_EINVAL);
+  CHECK(cuba_suggest_cell_capacity(&p, 0, nullptr, nullptr, nullptr, nullptr, 0, nullptr,
+                                   &cap) == CUBA_EINVAL);
+
   for (int code = 1; code >= -5; --code) CHECK(std::strlen(cuba_strerror(code)) > 0);
   CHECK(std::strncmp(cuba_build_info(), "sources ", 8) == 0);
   std::printf("api sanitizer run ok\n");

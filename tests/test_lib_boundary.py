@@ -121,3 +121,33 @@ def test_lanes_and_batch_arguments_checked_on_the_host(C):
     assert rc == C.CUBA_EINVAL and b.value is None
     rc = L.cuba_batch_create(ctypes.byref(b), 4, 256, 16, None)
     assert rc == C.CUBA_ENOMEM and b.value is None
+
+
+def test_capacity_suggestion_checked_on_the_host(C):
+    """cuba_suggest_cell_capacity: its scratch size (one word a cell plus
+    one, 256-byte aligned) and the argument checks made before any device
+    work."""
+    L = C._lib
+    good = C.make_params((10.0, 1.0, 1.0), (100, 1, 1), 0.4, 100.0, 0.02, 7)
+    assert C.cuba_capacity_scratch_bytes(good) == 512
+    big = C.make_params((10.0, 2.0, 2.0), (100, 10, 10), 0.4, 2500.0, 0.02, 7)
+    assert C.cuba_capacity_scratch_bytes(big) == (10001 * 4 + 255) // 256 * 256
+    bad = C.make_params((10.0, 1.0, 1.0), (0, 1, 1), 0.4, 100.0, 0.02, 7)
+    assert C.cuba_capacity_scratch_bytes(bad) == 0
+    cap = ctypes.c_int32()
+    rc = L.cuba_suggest_cell_capacity(ctypes.byref(good), 0, None, None, None, 256, 512,
+                                      None, None)
+    assert rc == C.CUBA_EINVAL and "cap" in C.cuba_last_error()
+    rc = L.cuba_suggest_cell_capacity(ctypes.byref(bad), 0, None, None, None, 256, 512,
+                                      None, ctypes.byref(cap))
+    assert rc == C.CUBA_EINVAL
+    rc = L.cuba_suggest_cell_capacity(ctypes.byref(good), 5, None, None, None, 256, 512,
+                                      None, ctypes.byref(cap))
+    assert rc == C.CUBA_EINVAL and "NULL" in C.cuba_last_error()
+    rc = L.cuba_suggest_cell_capacity(ctypes.byref(good), -1, None, None, None, 256, 512,
+                                      None, ctypes.byref(cap))
+    assert rc == C.CUBA_EINVAL
+    for scratch, nbytes in ((256, 256), (8, 512), (None, 512)):
+        rc = L.cuba_suggest_cell_capacity(ctypes.byref(good), 0, None, None, None, scratch,
+                                          nbytes, None, ctypes.byref(cap))
+        assert rc == C.CUBA_EINVAL and "scratch" in C.cuba_last_error()
