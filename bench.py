@@ -119,6 +119,10 @@ def parse():
                     help="rocprofv3 counter_collection.csv files of a --calibrate-copy run "
                          "(FETCH_SIZE, WRITE_SIZE): write the measured HBM traffic of "
                          "the dominant kernel to profiles/ and exit")
+    ap.add_argument("--pmc-fp64", metavar="FP64_CSV",
+                    help="with --pmc-csv: a counter pass with SQ_INSTS_VALU_ADD_F64, "
+                         "_MUL_F64, _FMA_F64 and _TRANS_F64; adds the FP64 operations the "
+                         "dominant kernel executes per launch")
     ap.add_argument("--pmc-sq", nargs=2, metavar=("SQ_CSV", "KERNEL_STATS_CSV"),
                     help="with --pmc-csv: a counter pass with SQ_ACTIVE_INST_VALU and the "
                          "kernel_stats.csv of a --kernel-trace --stats run of the same "
@@ -200,6 +204,8 @@ def write_traffic(a):
            "fetch_scale": fscale, "write_scale": wscale}
     if a.pmc_sq:
         out.update(valu_busy(*a.pmc_sq))
+    if a.pmc_fp64:
+        out.update(fp64_executed(a.pmc_fp64))
     with open(traffic_path(a.workload), "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out))
@@ -277,6 +283,27 @@ def valu_busy(sq_csv: str, stats_csv: str) -> dict:
     ns = float(stats[0]["AverageNs"])
     return {"valu_busy": 4.0 * active / (SIMDS * ns * 1e-9 * CLOCK_HZ),
             "sq_active_inst_valu_per_launch": active, "trace_avg_ns": ns}
+
+
+def fp64_executed(csv_path: str) -> dict:
+    """FP64 operations the dominant kernel executes per launch: 64 lanes x
+    (add + mul + transcendental + 2 x fma) wave-instructions, from the SQ
+    FP64 instruction counters (executed work, against the algorithmic count
+    of 12 flops per pair test: the kernel evaluates Eq. (3) only for the
+    pairs that pass the Philox w1 filter)."""
+    import csv
+    weight = {"SQ_INSTS_VALU_ADD_F64": 1, "SQ_INSTS_VALU_MUL_F64": 1,
+              "SQ_INSTS_VALU_TRANS_F64": 1, "SQ_INSTS_VALU_FMA_F64": 2}
+    per = {}
+    for r in csv.DictReader(open(csv_path)):
+        if (r["Counter_Name"] in weight
+                and DOMINANT_KERNEL.replace(" ", "") in r["Kernel_Name"].replace(" ", "")):
+            per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    if not per:
+        raise SystemExit(f"{csv_path}: no FP64 counters of {DOMINANT_KERNEL}")
+    flops = sum(64.0 * weight[k] * sum(v) / len(v) for k, v in per.items())
+    return {"fp64_executed_flops_per_launch": flops,
+            "fp64_wave_instructions_per_launch": {k: sum(v) / len(v) for k, v in per.items()}}
 
 
 def measured_profile(workload: str):
@@ -581,6 +608,12 @@ def main():
     fp64_tflops = FP64_FLOPS_PER_PAIR * pairs_per_step / (step_ms * 1e-3) / 1e12
     int32_tops = PHILOX_OPS_PER_PAIR * pairs_per_step / (step_ms * 1e-3) / 1e12
     prof = measured_profile(a.workload)
+    fp64_exec = None
+    if prof and prof.get("fp64_executed_flops_per_launch") is not None:
+        ex = prof["fp64_executed_flops_per_launch"] / (step_ms * 1e-3) / 1e12
+        fp64_exec = {"achieved": ex, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": ex / FP64_PEAK_TFLOPS,
+                     "flops_per_launch": prof["fp64_executed_flops_per_launch"]}
 
     def gbs(nbytes, ms):
         return nbytes / (ms * 1e-3) / 1e9
@@ -647,7 +680,11 @@ def main():
                      "int32_issue": {"achieved": int32_tops, "peak": INT32_PEAK_TOPS,
                                      "unit": "Tops/s", "frac": int32_tops / INT32_PEAK_TOPS,
                                      "ops_per_pair_test": PHILOX_OPS_PER_PAIR},
-                     "valu_busy": prof.get("valu_busy") if prof else None},
+                     "valu_busy": prof.get("valu_busy") if prof else None,
+                     "basis": "algorithmic: 12 FP64 flops per pair test of Eq. (3) over all "
+                              "pair tests; the kernel runs Eq. (3) only for pairs that pass "
+                              "the Philox w1 filter (fp64_executed: the counters' count)",
+                     "fp64_executed": fp64_exec},
         "hbm": hbm,
         "stages": stage_out,
         "cpu_baseline": cpu,

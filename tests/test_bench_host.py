@@ -65,7 +65,8 @@ def test_traffic_scaled_by_the_copy_reading(bench, tmp_path, monkeypatch):
     _counter_csv(write, "WRITE_SIZE", [(step, 10000, 5000.0), (copy, 65536, gib_kib)])
     out = tmp_path / "traffic.json"
     monkeypatch.setattr(bench, "traffic_path", lambda workload: str(out))
-    a = argparse.Namespace(pmc_csv=[str(fetch), str(write)], workload="unit", pmc_sq=None)
+    a = argparse.Namespace(pmc_csv=[str(fetch), str(write)], workload="unit", pmc_sq=None,
+                           pmc_fp64=None)
     bench.write_traffic(a)
     t = json.load(open(out))
     assert t["fetch_scale"] == pytest.approx(2.0) and t["write_scale"] == pytest.approx(1.0)
@@ -104,3 +105,24 @@ def test_valu_busy_from_sq_counter_and_trace(bench, tmp_path):
 def test_usable_cores_reports_affinity_and_count(bench):
     c = bench.usable_cores()
     assert 1 <= c["usable"] <= c["affinity"] <= (c["cpu_count"] or c["affinity"])
+
+
+def test_fp64_executed_from_counters(bench, tmp_path):
+    """Executed FP64 operations per launch: 64 lanes x (add + mul +
+    transcendental + 2 fma) wave-instructions, averaged over the dominant
+    kernel's dispatches; other kernels are ignored."""
+    step = "void cuba::k_step<true, false, 512u>(cuba::Cells, long)"
+    other = "void cuba::k_stream_bin<64u>(cuba::Cells)"
+    path = tmp_path / "fp64.csv"
+    cols = ["Dispatch_Id", "Grid_Size", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    rows = [(step, "SQ_INSTS_VALU_ADD_F64", 10.0), (step, "SQ_INSTS_VALU_ADD_F64", 30.0),
+            (step, "SQ_INSTS_VALU_MUL_F64", 5.0), (step, "SQ_INSTS_VALU_FMA_F64", 7.0),
+            (step, "SQ_INSTS_VALU_TRANS_F64", 1.0), (other, "SQ_INSTS_VALU_FMA_F64", 1e9)]
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=cols)
+        w.writeheader()
+        for i, (name, ctr, v) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i, "Grid_Size": 64, "Kernel_Name": name,
+                        "Counter_Name": ctr, "Counter_Value": v})
+    out = bench.fp64_executed(str(path))
+    assert out["fp64_executed_flops_per_launch"] == pytest.approx(64 * (20 + 5 + 2 * 7 + 1))
