@@ -370,6 +370,22 @@ cuba_ctx *cuba_batch_slot(cuba_batch *b, int32_t slot);
  * slot. */
 int cuba_batch_set_active(cuba_batch *b, int32_t slot, int32_t active);
 
+/* Observation inside runs (the T00 and T0x profiles of Fig. 2, as
+ * cuba_batch_observe computes them): after each step s of the slot's
+ * event with (s + 1) % every == 0, the collision launch of that step
+ * writes the event's per-cell sums and a launch after it writes the
+ * profiles to row ((s + 1) / every) % rows of out, a device array of
+ * rows x 2 x cells[0] doubles (per row: T00, then T0x), in stream order.
+ * So a run of cuba_batch_step need not end at an observation.  The steps
+ * of a run observe whatever step they fall on, the last one included.
+ * every = 0 turns it off.  out is owned by the caller and must outlive
+ * the runs that write it.  Takes effect at the next cuba_batch_step
+ * (which rebuilds the event table); retiring the slot turns it off.
+ * Errors: CUBA_EINVAL for an empty slot, every < 0, or every > 0 with a
+ * NULL out or rows < 1. */
+int cuba_batch_set_observe(cuba_batch *b, int32_t slot, int32_t every, double *out,
+                           int32_t rows);
+
 /* Cells per binning work item of a slot's event (default: about 64
  * particles per item, at most 64 cells; 64 cells for events with lanes per
  * cell > 0); set by the autotuner.  The collision kernels take fixed units:

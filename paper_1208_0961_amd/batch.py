@@ -125,6 +125,24 @@ class Batch:
         part again (cuba_batch_set_active)."""
         C.cuba_batch_set_active(self.b, slot, active)
 
+    def set_observe(self, slot: int, every: int, rows: int = 1) -> torch.Tensor | None:
+        """Observation inside runs (cuba_batch_set_observe): after every
+        `every` steps of the slot's event its T00 and T0x profiles go to row
+        (step / every) % rows of the returned device tensor [rows, 2, nx]
+        (T00, T0x), written by the run's own launches; every = 0 turns it
+        off (returns None)."""
+        s = self.slots[slot]
+        if every <= 0:
+            C.cuba_batch_set_observe(self.b, slot, 0, None, 0)
+            s.pop("obs", None)
+            return None
+        nx = int(s["params"]["cells"][0])
+        with torch.cuda.stream(self.stream):
+            out = torch.zeros((rows, 2, nx), dtype=torch.float64, device=self.device)
+        C.cuba_batch_set_observe(self.b, slot, every, out.data_ptr(), rows)
+        s["obs"] = out   # kept alive with the slot
+        return out
+
     def set_dt(self, slot: int, dt: float) -> None:
         """The slot's time step from its next step on (cuba_batch_set_dt)."""
         C.cuba_batch_set_dt(self.b, slot, dt)

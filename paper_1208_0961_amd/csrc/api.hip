@@ -842,6 +842,10 @@ struct cuba_batch {
   std::vector<cuba_ctx *> slot_ctx;
   std::vector<int32_t> slot_cpi;
   std::vector<uint8_t> slot_active;  // 0: admitted but held out of the steps
+  // observation inside runs (cuba_batch_set_observe): interval (0: off),
+  // output rows and the caller's output
+  std::vector<int32_t> slot_obs_every, slot_obs_rows;
+  std::vector<double *> slot_obs_out;
   std::vector<int32_t> table_slots;  // slots in table order
   BatchSpaces spaces{};  // unit counts of the work spaces (device begins in dev_begin)
   SideStream side{};     // library-owned stream for concurrent kernels of a step
@@ -928,6 +932,7 @@ int upload_table(cuba_batch *b) {
   b->table_slots.clear();
   uint64_t items = 0, chunks = 0, scans = 0, cells[2] = {0, 0};
   bool scan_large = false;
+  uint32_t obs_nx = 0;
   std::vector<int> cell_space;
   for (int32_t s = 0; s < b->max_slots; ++s) {
     cuba_ctx *c = b->slot_ctx[s];
@@ -943,6 +948,14 @@ int upload_table(cuba_batch *b) {
     e.cur = (uint32_t)c->cur;
     e.t = c->next_step;
     e.lanes = c->lanes;
+    if (b->slot_obs_every[s] > 0) {
+      e.obs_every = (uint32_t)b->slot_obs_every[s];
+      e.obs_rows = (uint32_t)b->slot_obs_rows[s];
+      e.obs_sums = c->cell_sums;
+      e.obs_out = b->slot_obs_out[s];
+      e.obs_vol = c->d.vol;
+      if ((uint32_t)c->d.g.n[0] > obs_nx) obs_nx = (uint32_t)c->d.g.n[0];
+    }
     const int space = c->d.cap <= kSmallCap ? 0 : 1;
     e.item_begin = (uint32_t)items;
     e.chunk_begin = (uint32_t)chunks;
@@ -978,6 +991,7 @@ int upload_table(cuba_batch *b) {
   b->spaces.n_cells[0] = (uint32_t)cells[0];
   b->spaces.n_cells[1] = (uint32_t)cells[1];
   b->spaces.scan_large = scan_large;
+  b->spaces.obs_nx = obs_nx;
   if (ne > 0) {
     // an event outside a cells space gets that space's running total (the
     // next event's begin), so the lookup never lands on it
@@ -1061,6 +1075,9 @@ int cuba_batch_create(cuba_batch **out, int32_t max_slots, void *workspace,
   b->slot_ctx.assign(max_slots, nullptr);
   b->slot_cpi.assign(max_slots, 1);
   b->slot_active.assign(max_slots, 1);
+  b->slot_obs_every.assign(max_slots, 0);
+  b->slot_obs_rows.assign(max_slots, 0);
+  b->slot_obs_out.assign(max_slots, nullptr);
   hipError_t e = create_side(b->side);
   for (int k = 0; k < 2 && e == hipSuccess; ++k) {
     e = hipHostMalloc(&b->staging[k], staging_bytes(max_slots), hipHostMallocDefault);
@@ -1140,6 +1157,23 @@ int cuba_batch_retire(cuba_batch *b, int32_t slot) {
   // is not read by work already queued on the stream
   cuba_destroy(b->slot_ctx[slot]);
   b->slot_ctx[slot] = nullptr;
+  b->slot_obs_every[slot] = 0;
+  b->slot_obs_rows[slot] = 0;
+  b->slot_obs_out[slot] = nullptr;
+  b->dirty = true;
+  return CUBA_OK;
+}
+
+int cuba_batch_set_observe(cuba_batch *b, int32_t slot, int32_t every, double *out,
+                           int32_t rows) {
+  if (!b || slot < 0 || slot >= b->max_slots || !b->slot_ctx[slot])
+    return fail(CUBA_EINVAL, "slot is not occupied");
+  if (every < 0) return fail(CUBA_EINVAL, "every must be >= 0");
+  if (every > 0 && (!out || rows < 1))
+    return fail(CUBA_EINVAL, "an observing slot needs an output of at least one row");
+  b->slot_obs_every[slot] = every;
+  b->slot_obs_rows[slot] = every > 0 ? rows : 0;
+  b->slot_obs_out[slot] = every > 0 ? out : nullptr;
   b->dirty = true;
   return CUBA_OK;
 }

@@ -125,7 +125,16 @@ struct BatchEvent {
   uint32_t scan_begin;  // first oversize-cell scan unit (64 cells), if lanes > 0
   uint32_t cell_begin;  // first unit in its one-wave-per-cell space, if lanes = 0
                         // (space 0: cell capacity <= kSmallCap, space 1: larger)
-  uint32_t pad[3];
+  // observation inside runs: after each step s with (s + 1) % obs_every == 0
+  // (obs_every > 0), the collision launch writes the per-cell sums into
+  // obs_sums and a slab launch writes T00 and T0x into row
+  // ((s + 1) / obs_every) % obs_rows of obs_out (rows of 2 nx doubles)
+  uint32_t obs_every;
+  uint32_t obs_rows;
+  uint32_t pad;
+  double *obs_sums;
+  double *obs_out;
+  double obs_vol;       // slab volume
 };
 
 // The work spaces of a batch run (see launch_batch_run): unit counts and,
@@ -134,6 +143,7 @@ struct BatchSpaces {
   const uint32_t *item_begin, *chunk_begin, *scan_begin, *cell_begin[2];
   uint32_t n_items, n_chunks, n_scans, n_cells[2];
   bool scan_large;  // some small-cell event has a cell capacity > kSmallCap
+  uint32_t obs_nx;  // > 0: some event observes inside runs; its largest nx
 };
 
 // Lanes per cell of the cell kernels: 0 (one wave per cell), 8, 16, 32, 64

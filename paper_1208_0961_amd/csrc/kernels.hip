@@ -759,6 +759,35 @@ __device__ __forceinline__ void clear_idle_scratch(const GCells &src, uint32_t t
   src.sp->pool->hdr[(t + 1u) & 1u] = 0ull;
 }
 
+// Observation sums of a cell (Sec. 5 profiles): sum E, sum p_x and
+// sum p_x^2 / E of the momenta after the step's collisions, accumulated per
+// lane, then reduced over the wave and written with the cell's count by
+// lane 0 (obs: kCellSums doubles a cell).
+__device__ __forceinline__ void obs_add(double px, double py, double pz, double &se,
+                                        double &sp, double &sxx) {
+  const double e = norm3(px, py, pz);
+  se += e;
+  sp += px;
+  sxx += (px * px) / e;
+}
+
+__device__ __forceinline__ void obs_write_wave(double *obs, uint32_t c, uint32_t cnt,
+                                               double se, double sp, double sxx) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    se += __shfl_down(se, o);
+    sp += __shfl_down(sp, o);
+    sxx += __shfl_down(sxx, o);
+  }
+  if (lane_id() == 0) {
+    double *const out = obs + kCellSums * (size_t)c;
+    out[0] = se;
+    out[1] = sp;
+    out[2] = sxx;
+    out[3] = (double)cnt;
+  }
+}
+
 // Wave 0 of an overflowing cell's workgroup: takes scratch from the pool
 // (counter t & 1) for the slots of the cell's spilled members -- and, for a
 // cell larger than the LDS holds, its canonical order, claimed flags and
@@ -818,7 +847,8 @@ __device__ void find_spilled(const GCells &src, const CellView &cv, CellLds<kFus
 template <bool kFused, bool kTrace, uint32_t kCap>
 __device__ void large_cell_step(const GCells &src, const GCells &dst, const CellView &cv,
                                 const PairArgs &pa, const Geometry &g, DevStatus *status,
-                                const TraceArgs &tr, CellLds<kFused, kCap> &lds) {
+                                const TraceArgs &tr, CellLds<kFused, kCap> &lds,
+                                double *obs) {
   const uint32_t lane = lane_id();
   const uint32_t n = cv.n;
   uint32_t *const perm = const_cast<uint32_t *>(cv.sidx) + (n - cv.cap);
@@ -933,6 +963,7 @@ __device__ void large_cell_step(const GCells &src, const GCells &dst, const Cell
     atomicAdd(&status->claims[slot], (unsigned long long)nclaim);
   }
   wave_lds_sync();  // new momenta visible to the binning lanes
+  double se = 0.0, sp = 0.0, sxx = 0.0;
   if (kFused) {
     const Geometry g_l = g;
     for (uint32_t j0 = 0; j0 < n; j0 += 64u) {
@@ -942,13 +973,20 @@ __device__ void large_cell_step(const GCells &src, const GCells &dst, const Cell
       uint32_t c2 = 0;
       if (active) {
         q = load_particle(st, cv.at_spill(j));
+        if (obs) obs_add(q.px, q.py, q.pz, se, sp, sxx);
         advance<true>(g_l, q.x, q.y, q.z, q.px, q.py, q.pz);
         c2 = cell_id(g_l, q.x, q.y, q.z);
       }
       append(dst, c2, active, q.x, q.y, q.z, q.px, q.py, q.pz, q.id, status);
     }
     if (lane == 0) src.count[cv.c] = 0u;
+  } else if (obs) {
+    for (uint32_t j = lane; j < n; j += 64u) {
+      const size_t o = cv.at_spill(j);
+      obs_add(st.px[o], st.py[o], st.pz[o], se, sp, sxx);
+    }
   }
+  if (obs) obs_write_wave(obs, cv.c, n, se, sp, sxx);
 }
 
 // Collisions of cell c of src at step t by a workgroup of kW waves (1 or
@@ -968,7 +1006,8 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
                                           uint32_t t, const PairArgs &pa,
                                           const Geometry &g, DevStatus *status,
                                           const TraceArgs &tr, CellLds<kFused, kCap> &lds,
-                                          SecondWaveLds<kCap> *x2 = nullptr) {
+                                          SecondWaveLds<kCap> *x2 = nullptr,
+                                          double *obs = nullptr) {
   static_assert(kW == 1 || (kW == 2 && !kTrace), "one or two waves, traces with one");
   constexpr uint32_t kT = 64 * kW;
   // filtered pairs and claimed pairs share the id buffer, kCap / 2 each
@@ -1005,12 +1044,15 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
     cv.sidx = sd->pool->buf + (((uint64_t)lds.ov_pool_hi << 32) | lds.ov_pool_lo);
     if (cv.n > kCap) {
       if (wv == 0)
-        large_cell_step<kFused, kTrace, kCap>(src, dst, cv, pa, g, status, tr, lds);
+        large_cell_step<kFused, kTrace, kCap>(src, dst, cv, pa, g, status, tr, lds,
+                                              kW == 1 ? obs : nullptr);
       return;
     }
   }
   const uint32_t n = cv.n;
   const GSoA &st = src.st;
+  // observation sums only for one wave per cell (the batch's shape)
+  double *const ob = kW == 1 ? obs : nullptr;
 
   uint32_t nclaim = 0;
   if (n >= 2) {
@@ -1205,7 +1247,7 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
         }
       }
     }
-    if (kFused) __syncthreads();
+    if (kFused || ob) __syncthreads();
   } else if (kTrace && n == 1 && tid == 0 && tr.perm) {
     tr.perm[tr.offsets[cv.c]] = st.id[cv.at_spill(0)];
   }
@@ -1216,6 +1258,7 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
     // geometry is copied to registers once: read through a reference it
     // would be reloaded after every store.
     const Geometry g_l = g;
+    double se = 0.0, sp = 0.0, sxx = 0.0;
     for (uint32_t j0 = wv * 64u; j0 < n; j0 += kT) {
       const uint32_t j = j0 + lane;
       const bool active = j < n;
@@ -1230,12 +1273,21 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
         py = st.py[o];
         pz = st.pz[o];
         id = st.id[o];
+        if (ob) obs_add(px, py, pz, se, sp, sxx);
         advance<true>(g_l, x, y, z, px, py, pz);
         c2 = cell_id(g_l, x, y, z);
       }
       append(dst, c2, active, x, y, z, px, py, pz, id, status);
     }
     if (tid == 0) src.count[cv.c] = 0u;
+    if (ob) obs_write_wave(ob, cv.c, n, se, sp, sxx);
+  } else if (ob) {
+    double se = 0.0, sp = 0.0, sxx = 0.0;
+    for (uint32_t j = lane; j < n; j += 64u) {
+      const size_t o = cv.at(j);
+      obs_add(st.px[o], st.py[o], st.pz[o], se, sp, sxx);
+    }
+    obs_write_wave(ob, cv.c, n, se, sp, sxx);
   }
 }
 
@@ -1274,7 +1326,8 @@ __device__ __forceinline__ uint64_t small_cells_step(const GCells &src, const GC
                                                      uint32_t c0, uint32_t c_end,
                                                      uint32_t t, const PairArgs &pa,
                                                      const Geometry &g, DevStatus *status,
-                                                     const TraceArgs &tr, SmallLds &lds) {
+                                                     const TraceArgs &tr, SmallLds &lds,
+                                                     double *obs = nullptr) {
   static_assert(G == 8 || G == 16 || G == 32 || G == 64, "lanes per cell");
   constexpr uint32_t kNone = 0xFFFFFFFFu;
   const uint32_t lane = lane_id();
@@ -1422,6 +1475,23 @@ __device__ __forceinline__ uint64_t small_cells_step(const GCells &src, const GC
     }
   }
 
+  if (obs) {  // the cell's sums over its G lanes, written by its first lane
+    double se = 0.0, sp = 0.0, sxx = 0.0;
+    if (mine) obs_add(px, py, pz, se, sp, sxx);
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+      se += __shfl_xor(se, o);
+      sp += __shfl_xor(sp, o);
+      sxx += __shfl_xor(sxx, o);
+    }
+    if (small && gl == 0) {
+      double *const out = obs + kCellSums * (size_t)c;
+      out[0] = se;
+      out[1] = sp;
+      out[2] = sxx;
+      out[3] = (double)n;
+    }
+  }
   if (kFused) {
     double x = 0, y = 0, z = 0;
     uint32_t id = 0, c2 = 0;
@@ -1451,7 +1521,8 @@ __device__ __forceinline__ void large_cells_step(const GCells &src, const GCells
                                                  uint32_t t, const PairArgs &pa,
                                                  const Geometry &g, DevStatus *status,
                                                  const TraceArgs &tr,
-                                                 CellLds<kFused, kCap> &lds) {
+                                                 CellLds<kFused, kCap> &lds,
+                                                 double *obs = nullptr) {
   const uint32_t c = c0 + lane_id();
   const uint32_t n = c < c_end ? src.count[c] : 0u;
   // the cells the small-cell kernel leaves: more particles than lanes, or
@@ -1460,7 +1531,7 @@ __device__ __forceinline__ void large_cells_step(const GCells &src, const GCells
   while (big != 0) {
     const uint32_t l = (uint32_t)__builtin_ctzll(big);
     big &= big - 1ull;
-    cell_step<kFused, kTrace, kCap>(src, dst, c0 + l, t, pa, g, status, tr, lds);
+    cell_step<kFused, kTrace, kCap>(src, dst, c0 + l, t, pa, g, status, tr, lds, nullptr, obs);
   }
 }
 
@@ -1903,6 +1974,14 @@ __device__ __forceinline__ EventView event_view(const BatchEvent *__restrict__ E
   return v;
 }
 
+// Where launch j of a run writes the event's observation sums: its per-cell
+// sums array if the step the launch collides (t + j - 1) ends an
+// observation interval, else nowhere.
+__device__ __forceinline__ double *obs_target(const BatchEvent *__restrict__ E, uint32_t j) {
+  const uint32_t every = E->obs_every;
+  return every != 0u && (E->t + j) % every == 0u ? E->obs_sums : nullptr;
+}
+
 __global__ __launch_bounds__(kBlock) void k_batch_bin(const BatchEvent *__restrict__ ev,
                                                       const uint32_t *__restrict__ item_begin,
                                                       uint32_t n_events, uint32_t n_items) {
@@ -1955,18 +2034,23 @@ __global__ __launch_bounds__(64) void k_batch_step_small(const BatchEvent *__res
   const uint32_t c0 = (chunk - E->chunk_begin) * per;
   const uint32_t c1 = c0 + per < v.n_cells ? c0 + per : v.n_cells;
   const TraceArgs none{};
+  double *const obs = obs_target(E, j);
   switch (v.lanes) {
     case 8:
-      small_cells_step<kFused, false, 8>(v.src, v.dst, c0, c1, v.t, v.pa, v.g, v.status, none, lds);
+      small_cells_step<kFused, false, 8>(v.src, v.dst, c0, c1, v.t, v.pa, v.g, v.status, none, lds,
+                                         obs);
       break;
     case 16:
-      small_cells_step<kFused, false, 16>(v.src, v.dst, c0, c1, v.t, v.pa, v.g, v.status, none, lds);
+      small_cells_step<kFused, false, 16>(v.src, v.dst, c0, c1, v.t, v.pa, v.g, v.status, none,
+                                          lds, obs);
       break;
     case 32:
-      small_cells_step<kFused, false, 32>(v.src, v.dst, c0, c1, v.t, v.pa, v.g, v.status, none, lds);
+      small_cells_step<kFused, false, 32>(v.src, v.dst, c0, c1, v.t, v.pa, v.g, v.status, none,
+                                          lds, obs);
       break;
     default:
-      small_cells_step<kFused, false, 64>(v.src, v.dst, c0, c1, v.t, v.pa, v.g, v.status, none, lds);
+      small_cells_step<kFused, false, 64>(v.src, v.dst, c0, c1, v.t, v.pa, v.g, v.status, none,
+                                          lds, obs);
   }
 }
 
@@ -1984,7 +2068,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   const uint32_t c0 = (unit - E->scan_begin) * 64u;
   const uint32_t c1 = c0 + 64u < v.n_cells ? c0 + 64u : v.n_cells;
   large_cells_step<kFused, false, kCap>(v.src, v.dst, c0, c1, v.lanes, v.t, v.pa, v.g,
-                                        v.status, TraceArgs{}, lds);
+                                        v.status, TraceArgs{}, lds, obs_target(E, j));
 }
 
 // One wave per cell of the events stepped one wave per cell.  Held to the
@@ -2007,8 +2091,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(cell_waves<k
   const int64_t shift = (const char *)E->buf[s ^ 1u].st.x - (const char *)E->buf[s].st.x;
   const PairArgs pa = E->pa;
   cell_step<kFused, false, kCap>(src, dst_of(src, shift, t), unit - E->cell_begin, t,
-                                 pa, E->g, E->status, TraceArgs{}, lds);
+                                 pa, E->g, E->status, TraceArgs{}, lds, nullptr,
+                                 obs_target(E, j));
 }
+
 
 
 // End of a run of k steps: every event moved k buffers and k step indices.
@@ -2086,12 +2172,11 @@ __device__ __forceinline__ void rest_frame(double t00, double t0x, double txx, d
   v = den > 0.0 ? t0x / den : 0.0;
 }
 
-// Slab sums over the slab's cells in cell order, then the moments.
-__global__ __launch_bounds__(kBlock) void k_observe_slabs(const double *cell_sums,
-                                                          uint32_t cells_per_slab,
-                                                          double vol, SlabOut out) {
+// Slab ix's sums over its cells in cell order, then the moments (a
+// workgroup of kBlock threads).
+__device__ __forceinline__ void slab_moments(const double *cell_sums, uint32_t cells_per_slab,
+                                             double vol, uint32_t ix, const SlabOut &out) {
   __shared__ double s_sum[kCellSums][kBlock / 64];
-  const uint32_t ix = blockIdx.x;
   const size_t c0 = (size_t)ix * cells_per_slab;
   double acc[kCellSums] = {0.0, 0.0, 0.0, 0.0};
   for (uint32_t j = threadIdx.x; j < cells_per_slab; j += kBlock)
@@ -2125,6 +2210,32 @@ __global__ __launch_bounds__(kBlock) void k_observe_slabs(const double *cell_sum
       if (out.v) out.v[ix] = v;
     }
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_observe_slabs(const double *cell_sums,
+                                                          uint32_t cells_per_slab,
+                                                          double vol, SlabOut out) {
+  slab_moments(cell_sums, cells_per_slab, vol, blockIdx.x, out);
+}
+
+// The slabs of the events observed after launch j of a run: block (ix,
+// event) sums slab ix of an event due for an observation (its cells' sums,
+// written by the launch) into T00 and T0x of the observation's row.
+__global__ __launch_bounds__(kBlock) void k_batch_observe(const BatchEvent *__restrict__ ev,
+                                                          uint32_t n_events, uint32_t j) {
+  const uint32_t e = blockIdx.y;
+  if (e >= n_events) return;
+  const BatchEvent *__restrict__ E = ev + e;
+  const uint32_t every = E->obs_every;
+  if (every == 0u || (E->t + j) % every != 0u) return;
+  const uint32_t nx = (uint32_t)E->g.n[0];
+  if (blockIdx.x >= nx) return;
+  const uint32_t row = ((E->t + j) / every) % E->obs_rows;
+  double *const out = E->obs_out + (size_t)row * 2u * nx;
+  SlabOut o{};
+  o.T00 = out;
+  o.T0x = out + nx;
+  slab_moments(E->obs_sums, (uint32_t)(E->g.n[1] * E->g.n[2]), E->obs_vol, blockIdx.x, o);
 }
 
 __global__ __launch_bounds__(kBlock) void k_gather_by_id(Cells cur_arg, uint32_t n_cells,
@@ -2445,6 +2556,10 @@ void launch_batch_run(BatchEvent *ev, const BatchSpaces &sp, uint32_t n_events, 
                            cev, sp.scan_begin, n_events, j);
     }
     join(s, sd);
+    // the events due for an observation after this launch
+    if (sp.obs_nx > 0)
+      hipLaunchKernelGGL(k_batch_observe, dim3(sp.obs_nx, n_events), dim3(kBlock), 0, s, cev,
+                         n_events, j);
   };
   using Fused = std::integral_constant<bool, true>;
   using Last = std::integral_constant<bool, false>;

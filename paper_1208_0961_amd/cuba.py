@@ -124,6 +124,8 @@ def _load() -> ctypes.CDLL:
     L.cuba_batch_observe_moments.restype = ctypes.c_int
     L.cuba_batch_observe.argtypes = [vp, i32, vp, vp]
     L.cuba_batch_observe.restype = ctypes.c_int
+    L.cuba_batch_set_observe.argtypes = [vp, i32, i32, vp, i32]
+    L.cuba_batch_set_observe.restype = ctypes.c_int
     L.cuba_batch_set_cell_lanes.argtypes = [vp, i32, i32]
     L.cuba_batch_set_cell_lanes.restype = ctypes.c_int
     L.cuba_batch_set_active.argtypes = [vp, i32, i32]
@@ -368,6 +370,11 @@ def cuba_batch_observe_moments(b: int, slot: int, out: int) -> None:
 
 def cuba_batch_observe(b: int, slot: int, T00: int, T0x: int) -> None:
     _check(_lib.cuba_batch_observe(b, int(slot), T00, T0x), "cuba_batch_observe")
+
+
+def cuba_batch_set_observe(b: int, slot: int, every: int, out: int | None, rows: int) -> None:
+    _check(_lib.cuba_batch_set_observe(b, int(slot), int(every), out, int(rows)),
+           "cuba_batch_set_observe")
 
 
 def cuba_batch_set_cell_lanes(b: int, slot: int, lanes: int) -> None:

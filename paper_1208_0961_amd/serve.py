@@ -134,7 +134,8 @@ class Server:
                  tuning: dict | None = None, keep_states: bool = False,
                  policy: str = "classes", run_particles: int = 4_000_000,
                  final_only: bool = False, depth: int = 2,
-                 fill_particles: int = 1_000_000, short_particles: int = 150_000):
+                 fill_particles: int = 1_000_000, short_particles: int = 150_000,
+                 observe_in_runs: bool = True):
         if policy not in self.POLICIES:
             raise ValueError(f"policy must be one of {self.POLICIES}")
         if run_steps < 1:
@@ -145,6 +146,11 @@ class Server:
         self.fill_particles = int(fill_particles)
         self.short_particles = int(short_particles) if policy == "classes" else 0
         self.final_only = final_only
+        # observations every observe_every steps are written by the runs'
+        # own launches (cuba_batch_set_observe), so runs need not stop at
+        # them; False stops each run at the next observation and observes
+        # from the host between runs
+        self.observe_in_runs = bool(observe_in_runs) and not final_only
         self.run_steps = run_steps
         self.keep_states = keep_states
         self.depth = max(1, int(depth))
@@ -176,6 +182,9 @@ class Server:
             state = W.riemann_state_torch(req.work, req.state_seed, device=self.device)
         lane.B.admit_async(slot, {**req.work.params(),
                                   "cell_capacity": W.capacity_for(req.work)}, state)
+        if self.observe_in_runs:
+            w = req.work
+            lane.B.set_observe(slot, w.observe_every, rows=max(1, w.steps // w.observe_every))
         if self.tuning:
             AT.settings_for(lane.B, slot, req.work, self.tuning)
 
@@ -268,7 +277,12 @@ class Server:
             ev = live[slot]
             ev["done"] += k
             w = ev["req"].work
-            if ((not self.final_only and ev["done"] % w.observe_every == 0)
+            if self.observe_in_runs:
+                # written by the run itself; the end, if it is no observation
+                # step, from the host
+                if ev["done"] >= w.steps and w.steps % w.observe_every != 0:
+                    B.observe_async(slot)
+            elif ((not self.final_only and ev["done"] % w.observe_every == 0)
                     or ev["done"] >= w.steps):
                 B.observe_async(slot)
             if ev["done"] >= w.steps:
@@ -277,11 +291,17 @@ class Server:
         for slot in finished:
             ev = live.pop(slot)
             s = B.slots[slot]
+            w = ev["req"].work
+            t00, t0x = s["T00"], s["T0x"]
+            if self.observe_in_runs and w.steps % w.observe_every == 0:
+                obs = s["obs"]
+                row = (w.steps // w.observe_every) % obs.shape[0]
+                t00, t0x = obs[row, 0], obs[row, 1]
             with torch.cuda.stream(B.stream):
-                h00 = torch.empty(s["T00"].shape, dtype=torch.float64, pin_memory=True)
-                h0x = torch.empty(s["T0x"].shape, dtype=torch.float64, pin_memory=True)
-                h00.copy_(s["T00"], non_blocking=True)
-                h0x.copy_(s["T0x"], non_blocking=True)
+                h00 = torch.empty(t00.shape, dtype=torch.float64, pin_memory=True)
+                h0x = torch.empty(t0x.shape, dtype=torch.float64, pin_memory=True)
+                h00.copy_(t00, non_blocking=True)
+                h0x.copy_(t0x, non_blocking=True)
                 done_ev = torch.cuda.Event()
                 done_ev.record(B.stream)
             fields = dict(rid=ev["req"].rid, n=ev["req"].work.n,
@@ -300,9 +320,10 @@ class Server:
     def steps_to_stop(self, work: W.Workload, done: int, run_steps: int | None = None) -> int:
         """Steps an event that has done `done` of its steps may take in the
         next run: at most run_steps, and never past its end or (unless only
-        its final profile is wanted) past its next observation."""
+        its final profile is wanted, or the runs write the observations) past
+        its next observation."""
         k = min(self.run_steps if run_steps is None else run_steps, work.steps - done)
-        if not self.final_only:
+        if not self.final_only and not getattr(self, "observe_in_runs", False):
             k = min(k, work.observe_every - done % work.observe_every)
         return k
 

@@ -267,3 +267,50 @@ def test_full_ensemble_sampled_parity(mods, orc):
                           <= 1e-12 * pair_e[scattered]), (i, d)
         scattered_total += int(scattered.sum())
     assert scattered_total > 1000
+
+
+@pytest.mark.parametrize("graphs", (False, True))
+def test_observation_inside_runs(mods, graphs):
+    """Observations written by the runs' own launches (cuba_batch_set_observe)
+    equal the plain path's cuba_observe at the same steps: every 7 steps of
+    each event, in runs of 10 steps that do not stop there (the last launch
+    of a run observing too), for events stepped a wave per cell, with 8, 16
+    and 32 lanes per cell, and one whose cells overflow their blocks; an
+    event without observation and a held event are left alone."""
+    import torch
+    batch, sim = mods
+    evs = small_events()
+    states = [W.riemann_state(w, seed=60 + i) for i, w in enumerate(evs)]
+    settings = [0, 8, 16, 32, 0]
+    every, rows = 7, 4
+    B = batch.Batch(len(evs) + 1, use_graphs=graphs)
+    outs = []
+    for i, (lanes, w, st) in enumerate(zip(settings, evs, states)):
+        params = w.params()
+        if i == 4:
+            params = {**params, "cell_capacity": 8}   # overflowing cells
+        B.admit(i, params, st)
+        B.set_cell_lanes(i, lanes)
+        outs.append(B.set_observe(i, every, rows))
+    # a held event and an unobserved one beside them
+    B.admit(5, evs[1].params(), states[1])
+    B.set_active(5, False)
+    for k in (10, 10, 10):
+        B.step(k)
+    B.sync()
+    torch.cuda.synchronize()
+    for i, (w, st) in enumerate(zip(evs, states)):
+        params = w.params() if i != 4 else {**w.params(), "cell_capacity": 8}
+        s = sim.Sim(params, st)
+        done = 0
+        for t in (7, 14, 21, 28):
+            s.step(t - done)
+            done = t
+            T00, T0x = s.observe()
+            got = outs[i][(t // every) % rows].cpu().numpy()
+            say(f"[obs] event {i} after step {t}")
+            assert np.allclose(got[0], T00, rtol=1e-12, atol=0), (i, t)
+            assert np.allclose(got[1], T0x, rtol=1e-12, atol=1e-12 * np.abs(T00).max()), (i, t)
+        s.close()
+    assert B.next_step(5) == 0
+    B.close()

@@ -21,12 +21,15 @@ def serve():
 
 
 # run lengths: 25 and 50 divide the 100 steps and the 50-step observations;
-# 40 does not, so runs stop early at every observation (40, 10, 40, 10)
-@pytest.mark.parametrize("policy,final_only,run_steps",
-                         (("all", False, 25), ("srpt", False, 25), ("srpt", True, 50),
-                          ("all", False, 40), ("fifo", True, 25), ("classes", True, 25),
-                          ("classes", False, 40)))
-def test_results_same_alone_and_in_the_mix(serve, policy, final_only, run_steps):
+# 40 does not: with the observations written inside the runs, runs of 40
+# steps observe in their middle; with observations from the host between
+# runs (in_runs False), runs stop early at every observation (40, 10, 40, 10)
+@pytest.mark.parametrize("policy,final_only,run_steps,in_runs",
+                         (("all", False, 25, True), ("srpt", False, 25, False),
+                          ("srpt", True, 50, True), ("all", False, 40, True),
+                          ("all", False, 40, False), ("fifo", True, 25, True),
+                          ("classes", True, 25, True), ("classes", False, 40, True)))
+def test_results_same_alone_and_in_the_mix(serve, policy, final_only, run_steps, in_runs):
     reqs = serve.request_stream(10, 0.0, seed=8, nmin=1e4, nmax=8e4, steps=100)
     budget = 3 * max(serve.footprint(r) for r in reqs)
     # srpt: a run holds about two of the requests, so events wait, are held
@@ -37,7 +40,8 @@ def test_results_same_alone_and_in_the_mix(serve, policy, final_only, run_steps)
     # (fifo without the fill of small requests, so that events are held)
     srv = serve.Server(max_slots=4, hbm_budget=budget, run_steps=run_steps,
                        keep_states=True, policy=policy, run_particles=run_particles,
-                       final_only=final_only, fill_particles=0, short_particles=short)
+                       final_only=final_only, fill_particles=0, short_particles=short,
+                       observe_in_runs=in_runs)
     res = srv.run(reqs, realtime=False)
     assert srv.peak_live <= 4 and srv.peak_bytes <= budget
     assert srv.peak_live >= 2          # the requests overlapped on the device

@@ -198,6 +198,10 @@ def test_runs_stop_at_ends_and_observations(serve):
     assert srv.steps_to_stop(w, 0) == 130 and srv.steps_to_stop(w, 125) == 5
     srv.final_only = False
     assert srv.steps_to_stop(w, 0) == 50 and srv.steps_to_stop(w, 120) == 10
+    # observations written inside the runs: only the end and run_steps stop
+    srv.observe_in_runs = True
+    srv.run_steps = 40
+    assert srv.steps_to_stop(w, 0) == 40 and srv.steps_to_stop(w, 120) == 10
 
 
 def test_server_rejects_empty_runs(serve):
