@@ -112,6 +112,7 @@ int main() {
   CHECK(cuba_batch_step(nullptr, 1) == CUBA_EINVAL);
   CHECK(cuba_batch_sync(nullptr, &bad_slot) == CUBA_EINVAL);
   CHECK(cuba_batch_slot(nullptr, 0) == nullptr);
+  CHECK(cuba_batch_set_observe(nullptr, 0, 7, nullptr, 1) == CUBA_EINVAL);
   cuba_batch_destroy(nullptr);
 
   // capacity suggestion: scratch sizing and the checks before device work
