@@ -1261,8 +1261,22 @@ int cuba_batch_step(cuba_batch *b, int32_t nsteps) {
       const hipError_t e = hipGraphLaunch(it->second, b->stream);
       if (e != hipSuccess) return hip_fail(e, "graph launch");
     } else {
+      // the launches after which an event observes (direct launches only)
+      std::vector<uint8_t> obs_at;
+      if (b->spaces.obs_nx > 0) {
+        obs_at.assign((size_t)nsteps + 1, 0);
+        for (int32_t s : b->table_slots) {
+          const int32_t every = b->slot_obs_every[s];
+          if (every <= 0) continue;
+          const uint32_t t0 = b->slot_ctx[s]->next_step;
+          // launch j collides step t0 + j - 1, due when (t0 + j) % every == 0
+          for (uint64_t j = every - t0 % (uint32_t)every; j <= (uint64_t)nsteps; j += every)
+            obs_at[j] = 1;
+        }
+      }
       launch_batch_run(b->dev_table, b->spaces, n_events, nsteps, b->persistent_waves,
-                       b->stream, &b->side, b->timing ? batch_between : nullptr, b);
+                       b->stream, &b->side, b->timing ? batch_between : nullptr, b,
+                       obs_at.empty() ? nullptr : obs_at.data());
       const int rc = check_launch("batch run launch");
       if (rc != CUBA_OK) return rc;
     }

@@ -245,9 +245,14 @@ void launch_observe(const Cells &cur, const Geometry &g, double vol, double *cel
 // between (may be NULL) is called before each step of the run with
 // its kind (0 stream-bin, 1 fused step, 2 collide) and with -1 after the last
 // one: a hook for stage timing.
+// obs_at (may be NULL): obs_at[j] != 0 for the launches j after which some
+// event of the run is due for an observation inside the run (NULL: the
+// observation launch follows every launch while spaces.obs_nx > 0, as a
+// graph captured once for many runs needs).
 void launch_batch_run(BatchEvent *ev, const BatchSpaces &spaces, uint32_t n_events, int32_t k,
                       uint32_t persistent_waves, hipStream_t s, const SideStream *side,
-                      void (*between)(void *, int), void *ctx);
+                      void (*between)(void *, int), void *ctx,
+                      const uint8_t *obs_at = nullptr);
 void launch_gather_by_id(const Cells &cur, int64_t n_cells, double *x, double *y,
                          double *z, double *px, double *py, double *pz,
                          uint32_t binning_step, hipStream_t s);

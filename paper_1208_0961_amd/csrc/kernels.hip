@@ -2518,7 +2518,7 @@ void launch_observe(const Cells &cur, const Geometry &g, double vol, double *cel
 
 void launch_batch_run(BatchEvent *ev, const BatchSpaces &sp, uint32_t n_events, int32_t k,
                       uint32_t persistent_waves, hipStream_t s, const SideStream *side,
-                      void (*between)(void *, int), void *ctx) {
+                      void (*between)(void *, int), void *ctx, const uint8_t *obs_at) {
   if (n_events == 0 || sp.n_items == 0 || k <= 0) return;
   const uint32_t bin_waves =
       persistent_waves > 0 && persistent_waves < sp.n_items ? persistent_waves : sp.n_items;
@@ -2557,7 +2557,7 @@ void launch_batch_run(BatchEvent *ev, const BatchSpaces &sp, uint32_t n_events, 
     }
     join(s, sd);
     // the events due for an observation after this launch
-    if (sp.obs_nx > 0)
+    if (sp.obs_nx > 0 && (!obs_at || obs_at[j]))
       hipLaunchKernelGGL(k_batch_observe, dim3(sp.obs_nx, n_events), dim3(kBlock), 0, s, cev,
                          n_events, j);
   };

@@ -135,7 +135,7 @@ class Server:
                  policy: str = "classes", run_particles: int = 4_000_000,
                  final_only: bool = False, depth: int = 2,
                  fill_particles: int = 1_000_000, short_particles: int = 150_000,
-                 observe_in_runs: bool = True):
+                 observe_in_runs: bool = True, short_run_steps: int = 1 << 30):
         if policy not in self.POLICIES:
             raise ValueError(f"policy must be one of {self.POLICIES}")
         if run_steps < 1:
@@ -161,8 +161,8 @@ class Server:
         self.max_slots = int(max_slots)
         self.lanes = [_Lane(max_slots, device, use_graphs, run_steps)]
         if policy == "classes":
-            # short runs go to an event's end: no step bound of their own
-            self.lanes.append(_Lane(max_slots, device, use_graphs, 1 << 30))
+            # short runs: at most short_run_steps (default: to the events' end)
+            self.lanes.append(_Lane(max_slots, device, use_graphs, int(short_run_steps)))
         self.B = self.lanes[0].B
         self.tuning = tuning
         self.use_graphs = use_graphs
