@@ -1621,7 +1621,7 @@ __device__ __forceinline__ void packed_resolve_row(
   n_acc += acc ? 1u : 0u;
   for (uint64_t m = __ballot(acc); m != 0; m &= m - 1ull) {
     const uint32_t l = (uint32_t)__builtin_ctzll(m);
-    const uint32_t vl = (uint32_t)__shfl((int)v, (int)l);
+    const uint32_t vl = (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l);
     const uint32_t pa_ = vl >> 8, pb_ = vl & 0xFFu;
     const uint64_t ab = (1ull << pa_) | (1ull << pb_);
     if ((claimed & ab) == 0) {
@@ -1668,14 +1668,14 @@ __device__ __forceinline__ void packed_cells_step(const GCells &src, const GCell
     const uint32_t up = (uint32_t)__shfl_up((int)incl, o);
     if ((int)lane >= o) incl += up;
   }
-  const uint32_t total = (uint32_t)__shfl((int)incl, 63);
+  const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
   uint32_t cnt_pairs = 0, n_acc = 0, n_claims = 0;
   for (uint32_t base = 0; base < total;) {
     // the unit: the cells whose particles end within base + 64 (a prefix of
     // the tile's lanes beyond the previous unit; each cell fits alone)
     const uint64_t fit = __ballot(incl <= base + kPackedMax);
     const uint32_t e = 63u - (uint32_t)__builtin_clzll(fit);
-    const uint32_t end = (uint32_t)__shfl((int)incl, (int)e);
+    const uint32_t end = (uint32_t)__builtin_amdgcn_readlane((int)incl, (int)e);
     const uint32_t p = end - base;  // particles of the unit
     const bool in_unit = nl > 0 && incl - nl >= base && lane <= e;
     wave_lds_sync();  // the previous unit's readers of lds are done
