@@ -640,9 +640,13 @@ __device__ __forceinline__ void resolve_filtered(
     }
   }
   cell_sync<kBlockSync>();
-  for (uint32_t i = 0; i < nf; ++i) {
-    const uint32_t v = s_filt[i];
-    if (v & 0x80000000u) {
+  // the accepted entries in list order: a row of 64 entries at a time, its
+  // accepted ones taken from their lanes in lane order
+  for (uint32_t i0 = 0; i0 < nf; i0 += 64u) {
+    const uint32_t vr = i0 + lane < nf ? s_filt[i0 + lane] : 0u;
+    for (uint64_t m = __ballot((vr & 0x80000000u) != 0u); m != 0; m &= m - 1ull) {
+      const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)vr,
+                                                             (int)__builtin_ctzll(m));
       const uint32_t a = (v >> 10) & 1023u, b = v & 1023u;
       const bool own_a = (a & 63u) == lane, own_b = (b & 63u) == lane;
       const bool hit = (own_a && ((claimed_bits >> (a >> 6)) & 1u)) ||
