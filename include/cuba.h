@@ -316,12 +316,13 @@ const char *cuba_build_info(void);
  * ------------------------------------------------------------------------ */
 typedef struct cuba_batch cuba_batch;
 
-/* Device bytes of the batch's event table for max_slots slots. */
+/* Device bytes of the batch's event table for max_slots slots (0 unless
+ * 1 <= max_slots <= 65535). */
 size_t cuba_batch_workspace_bytes(int32_t max_slots);
 
 /* Creates a batch.  workspace: device memory of ws_bytes >=
  * cuba_batch_workspace_bytes(max_slots), 256-byte aligned, owned by the
- * caller.  stream: hipStream_t (must not be NULL if graphs are enabled).
+ * caller.  max_slots: 1 .. 65535, else CUBA_EINVAL.  stream: hipStream_t (must not be NULL if graphs are enabled).
  * The batch also creates one stream of its own (default priority), on which
  * the kernels of a step that are independent of the small-cell kernel run
  * concurrently, joined back into `stream` before the next step, and two

@@ -873,6 +873,10 @@ struct cuba_batch {
 
 namespace {
 
+// The observation kernel takes the events along the grid's y dimension,
+// which holds at most 65535 workgroups.
+constexpr int32_t kMaxBatchSlots = 65535;
+
 // Work spaces of a batch: binning items, small-cell chunks, oversize scans,
 // and the one-wave-per-cell spaces of small and large cell capacity.
 constexpr int kSpaces = 5;
@@ -1051,7 +1055,7 @@ void batch_between(void *vb, int next) {
 extern "C" {
 
 size_t cuba_batch_workspace_bytes(int32_t max_slots) {
-  if (max_slots < 1) return 0;
+  if (max_slots < 1 || max_slots > kMaxBatchSlots) return 0;
   return align256((size_t)max_slots * sizeof(BatchEvent)) +
          align256((size_t)kSpaces * max_slots * sizeof(uint32_t));
 }
@@ -1060,7 +1064,8 @@ int cuba_batch_create(cuba_batch **out, int32_t max_slots, void *workspace,
                       size_t ws_bytes, void *stream) {
   if (!out) return fail(CUBA_EINVAL, "out is NULL");
   *out = nullptr;
-  if (max_slots < 1) return fail(CUBA_EINVAL, "max_slots must be >= 1");
+  if (max_slots < 1 || max_slots > kMaxBatchSlots)
+    return fail(CUBA_EINVAL, "max_slots must be in 1 .. 65535");
   if (!workspace || ((uintptr_t)workspace & 255u) != 0)
     return fail(CUBA_EINVAL, "batch workspace must be non-NULL and 256-byte aligned");
   if (ws_bytes < cuba_batch_workspace_bytes(max_slots))

@@ -81,6 +81,24 @@ def footprint(req: Request) -> int:
                                   "cell_capacity": W.capacity_for(req.work)}, req.work.n)
 
 
+def collect_ready(pending: deque, results: list, now, block: bool = False):
+    """Moves every queued result whose copy to the host has completed from
+    `pending` (entries (done event, result fields, host T00, host T0x)) to
+    `results`, stamped with now().  The lanes' results complete out of
+    order, so a short run's result does not wait behind a long run queued
+    before it; block=True first waits for the oldest one."""
+    if block and pending:
+        pending[0][0].synchronize()
+    for _ in range(len(pending)):
+        item = pending.popleft()
+        if not item[0].query():
+            pending.append(item)      # those left keep their order
+            continue
+        _, fields, h00, h0x = item
+        results.append(Result(**fields, finished=now(), T00=h00.numpy().copy(),
+                              T0x=h0x.numpy().copy()))
+
+
 class _Lane:
     """One batch of live events on its own stream, with the runs queued on
     it that have not completed yet."""
@@ -210,12 +228,7 @@ class Server:
         n_live = lambda: sum(len(lane.live) for lane in lanes)
 
         def collect(block: bool = False):
-            while pending and (block or pending[0][0].query()):
-                ev, fields, h00, h0x = pending.popleft()
-                ev.synchronize()
-                results.append(Result(**fields, finished=now(), T00=h00.numpy().copy(),
-                                      T0x=h0x.numpy().copy()))
-                block = False
+            collect_ready(pending, results, now, block)
 
         while queue or n_live() or pending:
             collect()

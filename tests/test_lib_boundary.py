@@ -117,7 +117,12 @@ def test_lanes_and_batch_arguments_checked_on_the_host(C):
         nb = C.cuba_batch_workspace_bytes(slots)
         assert nb % 256 == 0 and nb > prev and nb >= slots * (200 + 16)
         prev = nb
+    # the slot count is bounded by the grid's y dimension (65535)
+    assert C.cuba_batch_workspace_bytes(65535) > 0
+    assert C.cuba_batch_workspace_bytes(65536) == 0
     b = ctypes.c_void_p()
+    rc = L.cuba_batch_create(ctypes.byref(b), 65536, 256, 1 << 30, None)
+    assert rc == C.CUBA_EINVAL and b.value is None
     rc = L.cuba_batch_create(ctypes.byref(b), 4, 8, 1 << 20, None)
     assert rc == C.CUBA_EINVAL and b.value is None
     rc = L.cuba_batch_create(ctypes.byref(b), 4, 256, 16, None)

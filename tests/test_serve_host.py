@@ -207,3 +207,37 @@ def test_runs_stop_at_ends_and_observations(serve):
 def test_server_rejects_empty_runs(serve):
     with pytest.raises(ValueError):
         serve.Server(run_steps=0, hbm_budget=1 << 20)
+
+
+class _FakeEvent:
+    def __init__(self, done):
+        self.done = done
+        self.waited = False
+
+    def query(self):
+        return self.done
+
+    def synchronize(self):
+        self.waited = True
+        self.done = True
+
+
+def test_results_are_collected_out_of_order(serve):
+    """A result whose copy has completed is collected even when one queued
+    before it (the long lane's) is still on the GPU; block waits for the
+    oldest."""
+    import torch
+    from collections import deque
+    h = torch.zeros(2, dtype=torch.float64)
+    long_ev, short_ev, later_ev = _FakeEvent(False), _FakeEvent(True), _FakeEvent(False)
+    fields = lambda rid: dict(rid=rid, n=1, arrival=0.0, admitted=0.0)
+    pending = deque([(long_ev, fields(0), h, h), (short_ev, fields(1), h, h),
+                     (later_ev, fields(2), h, h)])
+    results = []
+    serve.collect_ready(pending, results, lambda: 1.0)
+    assert [r.rid for r in results] == [1]
+    assert [p[1]["rid"] for p in pending] == [0, 2]
+    serve.collect_ready(pending, results, lambda: 2.0, block=True)
+    assert long_ev.waited and not later_ev.waited
+    assert [r.rid for r in results] == [1, 0] and results[1].finished == 2.0
+    assert [p[1]["rid"] for p in pending] == [2]
