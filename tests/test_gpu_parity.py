@@ -36,7 +36,8 @@ def lib():
 
 
 def _orc_params(orc, params, t0=0):
-    q = {k: v for k, v in params.items() if k != "step0"}
+    # the block capacity is the GPU layout's, not the method's
+    q = {k: v for k, v in params.items() if k not in ("step0", "cell_capacity")}
     return orc.make_params(**q)
 
 
