@@ -52,6 +52,9 @@ BYTES_BIN = 52 + 52
 # rank: 32 B) and scatter (read cell, rank, state, id: 60 B; write state and
 # id: 52 B).
 BYTES_BIN_ALGO = 80 + 112
+# Of the fused-step launches of the timed run, every STEP_EVERY-th is timed
+# with HIP events (the other stages at every launch).
+STEP_EVERY = 10
 
 
 def parse():
@@ -577,7 +580,10 @@ def main():
         k = min(a.steps - done, w.observe_every - t_abs % w.observe_every)
         runs.append((k, (t_abs + k) % w.observe_every == 0))
         done += k
-    C.cuba_timing_begin(sim.ctx, 2 * a.steps + 6 * len(runs) + 16)
+    # HIP events around every launch of the rare stages and around every
+    # STEP_EVERY-th fused step: a bracketed launch delays the next one by a
+    # few microseconds, which would otherwise slow the timed run itself
+    C.cuba_timing_begin_sampled(sim.ctx, 2 * a.steps + 6 * len(runs) + 16, STEP_EVERY)
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -621,7 +627,8 @@ def main():
     stage_out = {}
     for name in C.STAGES:
         ms, k = stages[name]
-        stage_out[name] = {"ms_per_launch": ms / k if k else None, "launches": k}
+        stage_out[name] = {"ms_per_launch": ms / k if k else None, "launches_timed": k}
+    stage_out["step"]["timed_every"] = STEP_EVERY
     stage_out["bin"]["gbs_moved"] = gbs(BYTES_BIN * w.n, avg_ms("bin"))
     stage_out["step"]["pair_tests_per_launch"] = pairs_per_step
     stage_out["step"]["binning_gbs_moved"] = gbs(BYTES_BIN * w.n, step_ms)

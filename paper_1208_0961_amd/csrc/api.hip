@@ -247,6 +247,8 @@ struct cuba_ctx {
   // stage timing (cuba_timing_begin / cuba_timing_end)
   bool timing = false;
   size_t timing_cap = 0;
+  uint32_t timing_step_every = 1;  // time every n-th fused-step launch
+  uint64_t step_launches = 0;      // fused-step launches since timing began
   std::vector<hipEvent_t> event_pool;
   std::vector<TimedLaunch> timed;
 };
@@ -262,10 +264,14 @@ int check_launch(const char *where) {
 enum Stage { kStageBin = 0, kStageStep, kStageCollide, kStageObserve, kStageOffsets };
 static_assert(kStageOffsets + 1 == CUBA_NUM_STAGES, "stage count");
 
-// Runs launch(); while timing, brackets it with two events on the stream.
+// Runs launch(); while timing, brackets it with two events on the stream
+// (fused steps: every timing_step_every-th one only).
 template <typename F>
 void stage(cuba_ctx *c, int which, F &&launch) {
-  if (c->timing && c->timed.size() < c->timing_cap) {
+  bool sampled = true;
+  if (c->timing && which == kStageStep)
+    sampled = c->step_launches++ % c->timing_step_every == 0;
+  if (c->timing && sampled && c->timed.size() < c->timing_cap) {
     const size_t k = c->timed.size();
     TimedLaunch t{which, c->event_pool[2 * k], c->event_pool[2 * k + 1]};
     (void)hipEventRecord(t.before, c->stream);
@@ -283,6 +289,8 @@ void drop_timing(cuba_ctx *c) {
   c->timed.clear();
   c->timing = false;
   c->timing_cap = 0;
+  c->timing_step_every = 1;
+  c->step_launches = 0;
 }
 
 // Device copy of the geometry.
@@ -762,7 +770,11 @@ int cuba_counters(cuba_ctx *c, uint64_t out[3]) {
 }
 
 int cuba_timing_begin(cuba_ctx *c, int32_t max_launches) {
-  if (!c || max_launches < 1) return fail(CUBA_EINVAL, "bad timing arguments");
+  return cuba_timing_begin_sampled(c, max_launches, 1);
+}
+
+int cuba_timing_begin_sampled(cuba_ctx *c, int32_t max_launches, int32_t step_every) {
+  if (!c || max_launches < 1 || step_every < 1) return fail(CUBA_EINVAL, "bad timing arguments");
   drop_timing(c);
   c->event_pool.resize(2 * (size_t)max_launches);
   for (size_t k = 0; k < c->event_pool.size(); ++k) {
@@ -775,6 +787,7 @@ int cuba_timing_begin(cuba_ctx *c, int32_t max_launches) {
   }
   c->timed.reserve((size_t)max_launches);
   c->timing_cap = (size_t)max_launches;
+  c->timing_step_every = (uint32_t)step_every;
   c->timing = true;
   return CUBA_OK;
 }

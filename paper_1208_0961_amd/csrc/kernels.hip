@@ -743,7 +743,7 @@ struct CellLds {
   __align__(16) uint32_t buf[kCap];
   uint16_t perm[kCap];
   __align__(16) uint32_t bkt[kRankBuckets + 4];  // bucket ends, then starts
-  uint32_t sorted[kCap];                         // ids in bucket order
+  __align__(16) uint32_t sorted[kCap];           // ids in bucket order
   uint32_t ov_pool_lo, ov_pool_hi, ov_ok, pad;   // an overflowing cell's scratch
 };
 
@@ -1022,6 +1022,21 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
   uint32_t *const s_claim = lds.buf + kFilt;
   uint16_t *const s_perm = lds.perm;
   __syncthreads();
+  // A fused one-wave step of a cell whose members are all in its block
+  // keeps the new momenta of up to kMomCap claims in LDS (where the rank
+  // sorted its ids; claim i's two members at 2i, 2i + 1, and by member a
+  // byte map to them, in the rank's buckets) for its binning, instead of
+  // writing them back to the source block, whose lines would then be
+  // written to memory once more though no one reads them again.
+  constexpr bool kMomInLds = kFused && kW == 1;
+  constexpr uint32_t kMomCap = kCap / 12u;  // 6 doubles a claim in sorted[]
+  static_assert(6u * kMomCap * sizeof(double) <= kCap * sizeof(uint32_t), "claim momenta");
+  static_assert(2u * kMomCap + 2u <= 255u && kCap <= 4u * (kRankBuckets + 4u), "claim map");
+  double *const s_mx = reinterpret_cast<double *>(lds.sorted);
+  double *const s_my = s_mx + 2u * kMomCap;
+  double *const s_mz = s_my + 2u * kMomCap;
+  uint8_t *const s_cmap = reinterpret_cast<uint8_t *>(lds.bkt);
+  bool mom_lds = false;
 
   const uint32_t lane = lane_id();
   const uint32_t tid = kW == 1 ? lane : (uint32_t)threadIdx.x;
@@ -1142,6 +1157,11 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
     if (cv.ov) {  // the members' slots, in LDS (the rank no longer needs it)
       for (uint32_t j = tid; j < n; j += kT) lds.sorted[j] = (uint32_t)cv.at_spill(j);
       __syncthreads();
+    } else if (kMomInLds) {
+      // the claim map (one byte a member, zero: not scattered), in the
+      // rank's buckets; the barrier after the pair tests orders it
+      for (uint32_t j = lane * 4u; j < n; j += 256u)
+        *reinterpret_cast<uint32_t *>(s_cmap + j) = 0u;
     }
 
     // every pair k = 0 .. n(n-1)/2 - 1 (test_pairs), then the exact test
@@ -1210,7 +1230,9 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
     }
 
     // kinematics of the claimed pairs (disjoint: one writer per particle),
-    // written back in place; a fused step then bins every particle
+    // written back in place, or for the binning below into LDS; a fused
+    // step then bins every particle
+    mom_lds = kMomInLds && !cv.ov && nclaim <= kMomCap;
     for (uint32_t i0 = wv * 64u; i0 < nclaim; i0 += kT) {
       const uint32_t i = i0 + lane;
       const bool active = i < nclaim;
@@ -1233,12 +1255,23 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
         by = st.py[ib];
         bz = st.pz[ib];
         scatter_pair(ax, ay, az, bx, by, bz, uc, uphi);
-        st.px[ia] = ax;
-        st.py[ia] = ay;
-        st.pz[ia] = az;
-        st.px[ib] = bx;
-        st.py[ib] = by;
-        st.pz[ib] = bz;
+        if (mom_lds) {
+          s_mx[2u * i] = ax;
+          s_my[2u * i] = ay;
+          s_mz[2u * i] = az;
+          s_mx[2u * i + 1u] = bx;
+          s_my[2u * i + 1u] = by;
+          s_mz[2u * i + 1u] = bz;
+          s_cmap[ja] = (uint8_t)(2u * i + 1u);
+          s_cmap[jb] = (uint8_t)(2u * i + 2u);
+        } else {
+          st.px[ia] = ax;
+          st.py[ia] = ay;
+          st.pz[ia] = az;
+          st.px[ib] = bx;
+          st.py[ib] = by;
+          st.pz[ib] = bz;
+        }
         if (kTrace && tr.claim) {
           const uint32_t slot = atomicAdd(&tr.counts[1], 1u);
           if (slot < tr.claim_cap) {
@@ -1277,6 +1310,14 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
         py = st.py[o];
         pz = st.pz[o];
         id = st.id[o];
+        if (mom_lds) {
+          const uint32_t m = s_cmap[j];
+          if (m != 0u) {
+            px = s_mx[m - 1u];
+            py = s_my[m - 1u];
+            pz = s_mz[m - 1u];
+          }
+        }
         if (ob) obs_add(px, py, pz, se, sp, sxx);
         advance<true>(g_l, x, y, z, px, py, pz);
         c2 = cell_id(g_l, x, y, z);

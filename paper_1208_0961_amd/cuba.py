@@ -100,6 +100,8 @@ def _load() -> ctypes.CDLL:
     L.cuba_counters.restype = ctypes.c_int
     L.cuba_timing_begin.argtypes = [vp, i32]
     L.cuba_timing_begin.restype = ctypes.c_int
+    L.cuba_timing_begin_sampled.argtypes = [vp, i32, i32]
+    L.cuba_timing_begin_sampled.restype = ctypes.c_int
     L.cuba_timing_end.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_int64)]
     L.cuba_timing_end.restype = ctypes.c_int
@@ -303,6 +305,11 @@ def cuba_counters(ctx: int):
 
 def cuba_timing_begin(ctx: int, max_launches: int) -> None:
     _check(_lib.cuba_timing_begin(ctx, int(max_launches)), "cuba_timing_begin")
+
+
+def cuba_timing_begin_sampled(ctx: int, max_launches: int, step_every: int) -> None:
+    _check(_lib.cuba_timing_begin_sampled(ctx, int(max_launches), int(step_every)),
+           "cuba_timing_begin_sampled")
 
 
 def cuba_timing_end(ctx: int):

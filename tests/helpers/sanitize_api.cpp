@@ -99,6 +99,7 @@ int main() {
   CHECK(cuba_info(nullptr, nullptr, nullptr, nullptr) == CUBA_EINVAL);
   CHECK(cuba_counters(nullptr, counters) == CUBA_EINVAL);
   CHECK(cuba_timing_begin(nullptr, 4) == CUBA_EINVAL);
+  CHECK(cuba_timing_begin_sampled(nullptr, 4, 10) == CUBA_EINVAL);
   CHECK(cuba_timing_end(nullptr, ms, launches) == CUBA_EINVAL);
   cuba_destroy(nullptr);
 

@@ -204,3 +204,27 @@ def test_default_lanes_rule(lib):  # noqa: F811
         B.close()
         say(f"[lanes] 512 cells of {occ}: plain {got}, batch {got_b}")
         assert (got, got_b) == (want, 0)
+
+
+@pytest.mark.parametrize("two_k", (1.0, 0.3))
+def test_fused_claimed_momenta_in_lds_or_written_back(orc, lib, two_k):  # noqa: F811
+    # one wave per cell, fused: a cell keeps the new momenta of up to
+    # cap / 12 claims (42 at 512 slots) in LDS for its binning and writes
+    # more back to its block first; at 2K = 1 every pair passes the filter,
+    # so the cells below hold claims on both sides of that bound
+    occ = [200, 96, 88, 60, 30, 2, 1, 0]
+    state = _cells_box(occ, m=2)
+    V = 1.0 / 8.0
+    params = dict(box=(1.0, 1.0, 1.0), cells=(2, 2, 2), sigma=two_k * 0.5 * V / 0.001,
+                  r_test=1.0, dt=0.001, seed=31)
+    claims = _fused_step_check(orc, lib, params, state, 3, 0, f"claim momenta 2K={two_k}")
+    assert claims > (150 if two_k == 1.0 else 20)
+
+
+def test_fused_full_cell_one_wave(orc, lib):  # noqa: F811
+    # the 1024-slot kernel (85 claims in LDS) with a cell at the occupancy
+    # limit and 2K = 1: hundreds of claims, written back
+    state = _cells_box([1024], m=1, seed=17)
+    params = dict(box=(1.0, 1.0, 1.0), cells=(1, 1, 1), sigma=500.0, r_test=1.0,
+                  dt=0.001, seed=99)
+    assert _fused_step_check(orc, lib, params, state, 2, 0, "cap1024 one wave") > 400

@@ -109,6 +109,7 @@ def test_lanes_and_batch_arguments_checked_on_the_host(C):
     assert L.cuba_get_cell_lanes(None, ctypes.byref(out)) == C.CUBA_EINVAL
     assert L.cuba_batch_set_cell_lanes(None, 0, 8) == C.CUBA_EINVAL
     assert L.cuba_batch_set_observe(None, 0, 7, None, 1) == C.CUBA_EINVAL
+    assert L.cuba_timing_begin_sampled(None, 8, 10) == C.CUBA_EINVAL
     # batch table: the event descriptors plus four work-space index arrays,
     # 256-byte aligned pieces, growing with the slot count
     assert C.cuba_batch_workspace_bytes(0) == 0
