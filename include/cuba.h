@@ -289,13 +289,14 @@ int cuba_counters(cuba_ctx *ctx, uint64_t out[3]);
 #define CUBA_NUM_STAGES 5
 int cuba_timing_begin(cuba_ctx *ctx, int32_t max_launches);
 /* As cuba_timing_begin, but of the fused-step launches (stage 1, the one a
- * run repeats) only every step_every-th is bracketed, starting with the
- * first; the others run with no events around them.  Two events around a
- * launch delay the next launch by a few microseconds, so a timed run that
- * brackets every launch runs slower than an untimed one; sampling keeps
- * that out of the run while the average duration still comes from its own
- * launches.  Errors: CUBA_EINVAL for NULL, max_launches < 1 or
- * step_every < 1. */
+ * run repeats) only every step_every-th is timed, starting with the first;
+ * the others run with no events.  Events between launches delay the next
+ * launch by a few microseconds, so a run that times every launch runs
+ * slower than an untimed one; sampling keeps that out of the run while the
+ * average duration still comes from its own launches.  (A collision launch
+ * that is one kernel carries its events on its own dispatch, so they read
+ * the kernel's duration; other launches are bracketed by two events.)
+ * Errors: CUBA_EINVAL for NULL, max_launches < 1 or step_every < 1. */
 int cuba_timing_begin_sampled(cuba_ctx *ctx, int32_t max_launches, int32_t step_every);
 int cuba_timing_end(cuba_ctx *ctx, double stage_ms[CUBA_NUM_STAGES],
                     int64_t stage_launches[CUBA_NUM_STAGES]);

@@ -264,8 +264,12 @@ int check_launch(const char *where) {
 enum Stage { kStageBin = 0, kStageStep, kStageCollide, kStageObserve, kStageOffsets };
 static_assert(kStageOffsets + 1 == CUBA_NUM_STAGES, "stage count");
 
-// Runs launch(); while timing, brackets it with two events on the stream
-// (fused steps: every timing_step_every-th one only).
+// Runs launch(events) while timing (fused steps: every
+// timing_step_every-th one only), else launch(nullptr).  The collision
+// stages take the events into their launch (on the kernel's own dispatch
+// where it is one kernel: two event packets between launches would delay
+// the next one and read a few microseconds above the kernel's duration);
+// the other stages are bracketed here.
 template <typename F>
 void stage(cuba_ctx *c, int which, F &&launch) {
   bool sampled = true;
@@ -274,14 +278,19 @@ void stage(cuba_ctx *c, int which, F &&launch) {
   if (c->timing && sampled && c->timed.size() < c->timing_cap) {
     const size_t k = c->timed.size();
     TimedLaunch t{which, c->event_pool[2 * k], c->event_pool[2 * k + 1]};
-    (void)hipEventRecord(t.before, c->stream);
-    launch();
-    (void)hipEventRecord(t.after, c->stream);
+    if (which == kStageStep || which == kStageCollide) {
+      launch(&t);
+    } else {
+      (void)hipEventRecord(t.before, c->stream);
+      launch(&t);
+      (void)hipEventRecord(t.after, c->stream);
+    }
     c->timed.push_back(t);
   } else {
-    launch();
+    launch(nullptr);
   }
 }
+
 
 void drop_timing(cuba_ctx *c) {
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
@@ -329,6 +338,16 @@ StepDevice step_device(const cuba_ctx *c) {
   return StepDevice{&c->consts->g, over_span(c->over, c->lanes, c->d.n_cells)};
 }
 
+// The step launch's device arguments, with the stage's timing events.
+StepDevice timed_step_device(const cuba_ctx *c, const TimedLaunch *t) {
+  StepDevice dev = step_device(c);
+  if (t) {
+    dev.ev_start = t->before;
+    dev.ev_stop = t->after;
+  }
+  return dev;
+}
+
 // nsteps steps: stream + bin into the other buffer, then nsteps - 1 fused
 // steps (collide, then stream + bin into the other buffer), then the last
 // collisions in place.  With a trace (nsteps = 1) the binning records cells
@@ -339,17 +358,17 @@ int run_steps(cuba_ctx *c, int32_t nsteps, const TraceArgs *trace_in) {
   // stream: a fork to a second stream and back costs more per step than
   // the overlap gains for a single event (measured on MI355X)
   const SideStream *side = nullptr;
-  stage(c, kStageBin, [&] {
+  stage(c, kStageBin, [&](const TimedLaunch *) {
     launch_stream_bin(c->buf[c->cur], c->buf[c->cur ^ 1], c->d.n_cells, c->lanes, c->d.g,
                       c->status, trace_in ? trace_in->cell : nullptr, c->next_step,
                       c->stream);
   });
   c->cur ^= 1;
   for (int32_t s = 1; s < nsteps; ++s) {
-    stage(c, kStageStep, [&] {
+    stage(c, kStageStep, [&](const TimedLaunch *t) {
       launch_step(c->buf[c->cur], c->buf[c->cur ^ 1], true, c->d.n_cells, c->lanes,
                   c->next_step, c->pa, c->d.g, c->status, nullptr, c->stream, side,
-                  step_device(c));
+                  timed_step_device(c, t));
     });
     c->cur ^= 1;
     c->next_step += 1;
@@ -357,15 +376,15 @@ int run_steps(cuba_ctx *c, int32_t nsteps, const TraceArgs *trace_in) {
   TraceArgs tr{};
   if (trace_in) {
     tr = *trace_in;
-    stage(c, kStageOffsets, [&] {
+    stage(c, kStageOffsets, [&](const TimedLaunch *) {
       launch_offsets(c->buf[c->cur], const_cast<uint32_t *>(tr.offsets), c->tile_sums,
                      c->d.n_cells, c->stream);
     });
   }
-  stage(c, kStageCollide, [&] {
+  stage(c, kStageCollide, [&](const TimedLaunch *t) {
     launch_step(c->buf[c->cur], c->buf[c->cur ^ 1], false, c->d.n_cells, c->lanes,
                 c->next_step, c->pa, c->d.g, c->status, trace_in ? &tr : nullptr, c->stream,
-                side, step_device(c));
+                side, timed_step_device(c, t));
   });
   c->next_step += 1;
   return check_launch("step launch");
@@ -691,7 +710,7 @@ int cuba_trace_step(cuba_ctx *c, const cuba_trace *t) {
 int cuba_observe(cuba_ctx *c, double *T00, double *T0x) {
   if (!c || !T00 || !T0x) return fail(CUBA_EINVAL, "NULL argument");
   const SlabOut out{T00, T0x, nullptr, nullptr, nullptr, nullptr};
-  stage(c, kStageObserve, [&] {
+  stage(c, kStageObserve, [&](const TimedLaunch *) {
     launch_observe(c->buf[c->cur], c->d.g, c->d.vol, c->cell_sums, out, c->next_step - 1u,
                    c->stream);
   });
@@ -702,7 +721,7 @@ int cuba_observe_moments(cuba_ctx *c, double *out) {
   if (!c || !out) return fail(CUBA_EINVAL, "NULL argument");
   const int64_t nx = c->d.g.n[0];
   const SlabOut o{out, out + nx, out + 2 * nx, out + 3 * nx, out + 4 * nx, out + 5 * nx};
-  stage(c, kStageObserve, [&] {
+  stage(c, kStageObserve, [&](const TimedLaunch *) {
     launch_observe(c->buf[c->cur], c->d.g, c->d.vol, c->cell_sums, o, c->next_step - 1u,
                    c->stream);
   });

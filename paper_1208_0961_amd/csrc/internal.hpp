@@ -205,6 +205,9 @@ struct StepDevice {
   // and steps the oversize ones one after another; few oversize cells) or 1
   // (a wave per cell; many)
   uint32_t over_span;
+  // stage timing: events that the launch records at its start and end (on
+  // its first kernel's dispatch when it is one kernel), or null
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr;
 };
 
 // One collision launch (fused: then streaming + binning of the next step).

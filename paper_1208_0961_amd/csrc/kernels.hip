@@ -28,6 +28,7 @@
 // A run of n steps is one stream_bin, n-1 fused steps and one collide-only
 // step, which leaves the state binned and collided (positions of step t+n-1).
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <type_traits>
 
@@ -2419,20 +2420,32 @@ void launch_step_cap(const Cells &src, const Cells &dst, uint32_t n_cells, uint3
                      const TraceArgs &tr, hipStream_t s, const SideStream *side,
                      const StepDevice &dev) {
   const dim3 block(64);
+  const int64_t shift = (int64_t)((const char *)dst.st.x - (const char *)src.st.x);
+  // one kernel: timing events ride on its dispatch (no packets of their own
+  // between launches)
   if (lanes == kTwoWavesPerCell && !kTrace) {
-    hipLaunchKernelGGL((k_step2<kFused, kCap>), dim3(n_cells), dim3(128), 0, s, src,
-                       (int64_t)((const char *)dst.st.x - (const char *)src.st.x), t, pa,
-                       dev.g, status);
+    if (dev.ev_start)
+      hipExtLaunchKernelGGL((k_step2<kFused, kCap>), dim3(n_cells), dim3(128), 0, s,
+                            dev.ev_start, dev.ev_stop, 0u, src, shift, t, pa, dev.g, status);
+    else
+      hipLaunchKernelGGL((k_step2<kFused, kCap>), dim3(n_cells), dim3(128), 0, s, src, shift,
+                         t, pa, dev.g, status);
     return;
   }
   if (lanes == 0 || lanes == kTwoWavesPerCell) {
-    hipLaunchKernelGGL((k_step<kFused, kTrace, kCap>), dim3(n_cells), block, 0, s, src,
-                       (int64_t)((const char *)dst.st.x - (const char *)src.st.x), t, pa,
-                       dev.g, status, tr);
+    if (dev.ev_start)
+      hipExtLaunchKernelGGL((k_step<kFused, kTrace, kCap>), dim3(n_cells), block, 0, s,
+                            dev.ev_start, dev.ev_stop, 0u, src, shift, t, pa, dev.g, status,
+                            tr);
+    else
+      hipLaunchKernelGGL((k_step<kFused, kTrace, kCap>), dim3(n_cells), block, 0, s, src,
+                         shift, t, pa, dev.g, status, tr);
     return;
   }
   // the small cells and, concurrently, the cells the small-cell kernel
-  // leaves alone (disjoint cells; both append to dst through atomics)
+  // leaves alone (disjoint cells; both append to dst through atomics); timed
+  // by events recorded around the whole launch
+  if (dev.ev_start) (void)hipEventRecord(dev.ev_start, s);
   fork(s, side);
   const uint32_t per = lanes == kPackedCells ? 64u : 64u / lanes;  // cells per wave
   const dim3 grid((n_cells + per - 1) / per);
@@ -2469,6 +2482,7 @@ void launch_step_cap(const Cells &src, const Cells &dst, uint32_t n_cells, uint3
     hipLaunchKernelGGL((k_step_large<kFused, kTrace, kCap>), dim3((n_cells + 63) / 64), block,
                        0, so, src, dst, n_cells, thr, t, pa, g, status, tr);
   join(s, side);
+  if (dev.ev_stop) (void)hipEventRecord(dev.ev_stop, s);
 }
 
 template <uint32_t kCap>
