@@ -10,13 +10,17 @@ from test_gpu_parity import lib, say  # noqa: F401
 pytestmark = pytest.mark.gpu
 
 
-def test_stage_timing_every_launch_and_sampled(lib):  # noqa: F811
+@pytest.mark.parametrize("lanes", (128, 0, 8, 1))
+def test_stage_timing_every_launch_and_sampled(lib, lanes):  # noqa: F811
+    # one-kernel launches (two waves or one wave per cell) carry the events
+    # on their dispatch; the small-cell and packed launches (two kernels,
+    # forked) are bracketed
     from paper_1208_0961_amd import cuba as C
     w = W.TUBE_1D
-    s = lib.Sim(w.params(), W.riemann_state(w))
+    s = lib.Sim(w.params(), W.riemann_state(w), cell_lanes=lanes)
     # a call of 25 steps: one stream-bin launch, 24 fused steps, one
     # collide-only launch
-    say("[timing] every launch")
+    say(f"[timing] every launch, lanes {lanes}")
     C.cuba_timing_begin(s.ctx, 100)
     s.step(25)
     s.observe_async()
