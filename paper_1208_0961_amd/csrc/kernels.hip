@@ -13,10 +13,10 @@
 //                  rank counting, all n(n-1)/2 pair tests over the lanes with
 //                  a Philox block each, ballot compaction of the pairs that
 //                  can pass, exact Eq. (3) test on those, greedy claim in
-//                  pair order, CM kinematics (written back in place).  With
-//                  F (fused) the same wave then streams and bins its
-//                  particles for step t+1, so the binning traffic overlaps
-//                  the ALU-bound pair tests.
+//                  pair order, CM kinematics (written back in place, or
+//                  with F kept in LDS).  With F (fused) the same wave then
+//                  streams and bins its particles for step t+1, so the
+//                  binning traffic overlaps the ALU-bound pair tests.
 //   k_step_small   64 / G cells per wave, one particle per lane (sparse
 //                  cells); k_step_large / k_step_over step the cells that
 //                  do not fit G lanes.
@@ -1291,10 +1291,10 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
   }
 
   if (kFused) {
-    // stream and bin every particle (scattered momenta were written back
-    // in place; the barrier above makes them visible to all lanes).  The
-    // geometry is copied to registers once: read through a reference it
-    // would be reloaded after every store.
+    // stream and bin every particle (scattered momenta are in LDS or were
+    // written back in place; the barrier above makes them visible to all
+    // lanes).  The geometry is copied to registers once: read through a
+    // reference it would be reloaded after every store.
     const Geometry g_l = g;
     double se = 0.0, sp = 0.0, sxx = 0.0;
     for (uint32_t j0 = wv * 64u; j0 < n; j0 += kT) {
