@@ -265,11 +265,11 @@ enum Stage { kStageBin = 0, kStageStep, kStageCollide, kStageObserve, kStageOffs
 static_assert(kStageOffsets + 1 == CUBA_NUM_STAGES, "stage count");
 
 // Runs launch(events) while timing (fused steps: every
-// timing_step_every-th one only), else launch(nullptr).  The collision
-// stages take the events into their launch (on the kernel's own dispatch
-// where it is one kernel: two event packets between launches would delay
-// the next one and read a few microseconds above the kernel's duration);
-// the other stages are bracketed here.
+// timing_step_every-th one only), else launch(nullptr).  The binning and
+// collision stages take the events into their launch (on the kernel's own
+// dispatch where it is one kernel: two event packets between launches
+// would delay the next one and read a few microseconds above the kernel's
+// duration); the other stages are bracketed here.
 template <typename F>
 void stage(cuba_ctx *c, int which, F &&launch) {
   bool sampled = true;
@@ -278,7 +278,7 @@ void stage(cuba_ctx *c, int which, F &&launch) {
   if (c->timing && sampled && c->timed.size() < c->timing_cap) {
     const size_t k = c->timed.size();
     TimedLaunch t{which, c->event_pool[2 * k], c->event_pool[2 * k + 1]};
-    if (which == kStageStep || which == kStageCollide) {
+    if (which == kStageBin || which == kStageStep || which == kStageCollide) {
       launch(&t);
     } else {
       (void)hipEventRecord(t.before, c->stream);
@@ -358,10 +358,10 @@ int run_steps(cuba_ctx *c, int32_t nsteps, const TraceArgs *trace_in) {
   // stream: a fork to a second stream and back costs more per step than
   // the overlap gains for a single event (measured on MI355X)
   const SideStream *side = nullptr;
-  stage(c, kStageBin, [&](const TimedLaunch *) {
+  stage(c, kStageBin, [&](const TimedLaunch *t) {
     launch_stream_bin(c->buf[c->cur], c->buf[c->cur ^ 1], c->d.n_cells, c->lanes, c->d.g,
                       c->status, trace_in ? trace_in->cell : nullptr, c->next_step,
-                      c->stream);
+                      c->stream, t ? t->before : nullptr, t ? t->after : nullptr);
   });
   c->cur ^= 1;
   for (int32_t s = 1; s < nsteps; ++s) {

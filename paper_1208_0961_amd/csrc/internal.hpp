@@ -191,10 +191,12 @@ void launch_init_bin(const double *x, const double *y, const double *z,
                      const Cells &dst, int64_t n, const Geometry &g, DevStatus *st,
                      uint32_t binning_step, hipStream_t s);
 // Stream + bin every particle of src (the binning of step t - 1) into dst
-// (the binning of step t), spilled ones included.
+// (the binning of step t), spilled ones included; ev_start / ev_stop: stage
+// timing events recorded on the kernel's dispatch, or null.
 void launch_stream_bin(const Cells &src, const Cells &dst, int64_t n_cells, uint32_t lanes,
                        const Geometry &g, DevStatus *status, uint32_t *trace_cell,
-                       uint32_t t, hipStream_t s);
+                       uint32_t t, hipStream_t s, hipEvent_t ev_start = nullptr,
+                       hipEvent_t ev_stop = nullptr);
 void launch_offsets(const Cells &cur, uint32_t *offsets, uint32_t *tile_sums,
                     int64_t n_cells, hipStream_t s);
 // Device copy of the geometry, which the wave-per-cell kernel reads from

@@ -1053,6 +1053,11 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
   cv.sidx = nullptr;
   cv.slots = lds.sorted;
   if (cv.c == 0 && tid == 0) clear_idle_scratch(src, t);
+  // Wave priority: the phases that are chains of dependent loads, LDS
+  // atomics and barriers (ids and rank; claims, kinematics and binning)
+  // issue ahead of the other waves' pair-test loops, which keep the VALU
+  // busy meanwhile; the pair tests run at the base priority.
+  if (kW == 1) __builtin_amdgcn_s_setprio(1);
   if (cv.ov) {
     // an overflowing cell: find its spilled members (wave 0), then step it
     // here, in LDS if it fits, else with the global-memory method
@@ -1169,6 +1174,7 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
     // and the claims of the filtered ones in increasing k
     const uint32_t npairs = n * (n - 1u) / 2u;
     uint32_t nf = 0, claimed_bits = 0, n_acc = 0;
+    if (kW == 1) __builtin_amdgcn_s_setprio(0);
     if (kW == 1) {
       if (pa.any)
         test_pairs<true, kTrace, true, kFilt>(0u, npairs, cv, pa, st, s_perm, s_filt, nf,
@@ -1220,6 +1226,7 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
       nclaim = x2->nclaim;
     }
 
+    if (kW == 1) __builtin_amdgcn_s_setprio(1);
     // work counters (spread over slots by cell against contention)
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) n_acc += __shfl_down(n_acc, o);
@@ -2348,6 +2355,28 @@ bool launch_write_bytes(void *dst, const void *src, size_t bytes, hipStream_t s)
   return true;
 }
 
+namespace {
+
+// A kernel launch that records the stage-timing events ev_start / ev_stop on
+// its own dispatch when given (no event packets between launches, and the
+// events read the kernel's duration), else a plain launch.
+template <typename K, typename... Args>
+void launch_timed(K kernel, dim3 grid, dim3 block, hipStream_t s, hipEvent_t ev_start,
+                  hipEvent_t ev_stop, Args... args) {
+  if (ev_start)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, ev_start, ev_stop, 0u, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
+
+// A timed stage that launches nothing still records its events.
+void record_empty(hipEvent_t ev_start, hipEvent_t ev_stop, hipStream_t s) {
+  if (ev_start) (void)hipEventRecord(ev_start, s);
+  if (ev_stop) (void)hipEventRecord(ev_stop, s);
+}
+
+}  // namespace
+
 void launch_init_bin(const double *x, const double *y, const double *z,
                      const double *px, const double *py, const double *pz,
                      const Cells &dst, int64_t n, const Geometry &g, DevStatus *st,
@@ -2359,8 +2388,11 @@ void launch_init_bin(const double *x, const double *y, const double *z,
 
 void launch_stream_bin(const Cells &src, const Cells &dst, int64_t n_cells, uint32_t lanes,
                        const Geometry &g, DevStatus *status, uint32_t *trace_cell,
-                       uint32_t t, hipStream_t s) {
-  if (n_cells <= 0) return;
+                       uint32_t t, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+  if (n_cells <= 0) {
+    record_empty(ev_start, ev_stop, s);
+    return;
+  }
   // (packed cells: 16 lanes a cell; a stream-bin that packs 64 particles
   // a round whatever their cells measured the same on the 32^3 fm^3 set,
   // whose sparse cells' cost is their partly used cache lines)
@@ -2372,20 +2404,20 @@ void launch_stream_bin(const Cells &src, const Cells &dst, int64_t n_cells, uint
   const uint32_t nc = (uint32_t)n_cells;
   switch (G) {
     case 8:
-      hipLaunchKernelGGL(k_stream_bin<8>, grid, block, 0, s, src, dst, nc, g, status, trace_cell,
-                         t);
+      launch_timed(k_stream_bin<8>, grid, block, s, ev_start, ev_stop, src, dst, nc, g, status,
+                   trace_cell, t);
       break;
     case 16:
-      hipLaunchKernelGGL(k_stream_bin<16>, grid, block, 0, s, src, dst, nc, g, status, trace_cell,
-                         t);
+      launch_timed(k_stream_bin<16>, grid, block, s, ev_start, ev_stop, src, dst, nc, g, status,
+                   trace_cell, t);
       break;
     case 32:
-      hipLaunchKernelGGL(k_stream_bin<32>, grid, block, 0, s, src, dst, nc, g, status, trace_cell,
-                         t);
+      launch_timed(k_stream_bin<32>, grid, block, s, ev_start, ev_stop, src, dst, nc, g, status,
+                   trace_cell, t);
       break;
     default:
-      hipLaunchKernelGGL(k_stream_bin<64>, grid, block, 0, s, src, dst, nc, g, status, trace_cell,
-                         t);
+      launch_timed(k_stream_bin<64>, grid, block, s, ev_start, ev_stop, src, dst, nc, g, status,
+                   trace_cell, t);
   }
 }
 
@@ -2424,22 +2456,13 @@ void launch_step_cap(const Cells &src, const Cells &dst, uint32_t n_cells, uint3
   // one kernel: timing events ride on its dispatch (no packets of their own
   // between launches)
   if (lanes == kTwoWavesPerCell && !kTrace) {
-    if (dev.ev_start)
-      hipExtLaunchKernelGGL((k_step2<kFused, kCap>), dim3(n_cells), dim3(128), 0, s,
-                            dev.ev_start, dev.ev_stop, 0u, src, shift, t, pa, dev.g, status);
-    else
-      hipLaunchKernelGGL((k_step2<kFused, kCap>), dim3(n_cells), dim3(128), 0, s, src, shift,
-                         t, pa, dev.g, status);
+    launch_timed(k_step2<kFused, kCap>, dim3(n_cells), dim3(128), s, dev.ev_start, dev.ev_stop,
+                 src, shift, t, pa, dev.g, status);
     return;
   }
   if (lanes == 0 || lanes == kTwoWavesPerCell) {
-    if (dev.ev_start)
-      hipExtLaunchKernelGGL((k_step<kFused, kTrace, kCap>), dim3(n_cells), block, 0, s,
-                            dev.ev_start, dev.ev_stop, 0u, src, shift, t, pa, dev.g, status,
-                            tr);
-    else
-      hipLaunchKernelGGL((k_step<kFused, kTrace, kCap>), dim3(n_cells), block, 0, s, src,
-                         shift, t, pa, dev.g, status, tr);
+    launch_timed(k_step<kFused, kTrace, kCap>, dim3(n_cells), block, s, dev.ev_start,
+                 dev.ev_stop, src, shift, t, pa, dev.g, status, tr);
     return;
   }
   // the small cells and, concurrently, the cells the small-cell kernel
@@ -2507,7 +2530,10 @@ void launch_step(const Cells &src, const Cells &dst, bool fused, int64_t n_cells
                  uint32_t lanes, uint32_t t, const PairArgs &pa, const Geometry &g,
                  DevStatus *status, const TraceArgs *trace, hipStream_t s,
                  const SideStream *side, const StepDevice &dev) {
-  if (n_cells <= 0) return;
+  if (n_cells <= 0) {
+    record_empty(dev.ev_start, dev.ev_stop, s);
+    return;
+  }
   // cells of at most 512 slots use the kernels with half the LDS
   if (src.cap <= kSmallCap)
     launch_step_any<kSmallCap>(src, dst, fused, (uint32_t)n_cells, lanes, t, pa, g, status,
