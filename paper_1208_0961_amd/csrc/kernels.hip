@@ -1706,6 +1706,9 @@ __device__ __forceinline__ void packed_cells_step(const GCells &src, const GCell
                                                   const PairArgs &pa, const Geometry &g,
                                                   DevStatus *status, const TraceArgs &tr,
                                                   PackedLds &lds) {
+  // wave priority as in cell_step: the filter loop at the base priority,
+  // the latency-bound rest of a unit above it
+  __builtin_amdgcn_s_setprio(1);
   constexpr uint32_t kNone = 0xFFFFFFFFu;
   const uint32_t lane = lane_id();
   const uint64_t below = (1ull << lane) - 1ull;
@@ -1801,6 +1804,7 @@ __device__ __forceinline__ void packed_cells_step(const GCells &src, const GCell
       uint32_t k = gl;
       while (__ballot(k < npairs) != 0) {
         uint32_t nf = 0;
+        __builtin_amdgcn_s_setprio(0);
         do {
           const bool pass = k < npairs &&
                             philox10_w1(k, c, t, 0u, pa.key0, pa.key1) <= pa.w1_max;
@@ -1809,6 +1813,7 @@ __device__ __forceinline__ void packed_cells_step(const GCells &src, const GCell
           nf += (uint32_t)__popcll(mk);
           k += n;
         } while (nf <= kPackedFilt - 64u && __ballot(k < npairs) != 0);
+        __builtin_amdgcn_s_setprio(1);
         wave_lds_sync();
         for (uint32_t i0 = 0; i0 < nf; i0 += 64u)
           packed_resolve_row<kTrace>(i0, nf, c0, t, pa, lds, claimed, nclaim, n_acc, tr,
