@@ -1985,20 +1985,19 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(cell_waves<
 // ---------------------------------------------------------------------------
 // The event of `unit` in a work space: the number of entries of begin[]
 // that are <= unit, minus one (begin[] is ascending from 0; an event with
-// no units has the begin of the next one, so it is never the answer).  The
-// lanes load 64 entries at a time, all loads independent, and a ballot
-// counts them.  `unit` must be the same in every lane of the wave.
+// no units has the begin of the next one, so it is never the answer).  Each
+// lane counts the entries lane, lane + 64, ... (independent loads, no
+// cross-lane step inside the loop, so they are all in flight together),
+// then the wave sums the counts.  `unit` must be the same in every lane of
+// the wave; so is the result.
 __device__ __forceinline__ uint32_t find_event(const uint32_t *__restrict__ begin,
                                                uint32_t n_events, uint32_t unit) {
-  const uint32_t lane = lane_id();
   uint32_t count = 0;
 #pragma unroll 4
-  for (uint32_t e0 = 0; e0 < n_events; e0 += 64) {
-    const uint32_t e = e0 + lane;
-    const bool le = e < n_events && begin[e] <= unit;
-    count += (uint32_t)__popcll(__ballot(le));
-  }
-  return count - 1u;
+  for (uint32_t e = lane_id(); e < n_events; e += 64) count += begin[e] <= unit ? 1u : 0u;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) count += (uint32_t)__shfl_xor((int)count, o);
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)count) - 1u;
 }
 
 // The event's fields for launch j of a run, loaded once into registers (the
