@@ -275,10 +275,12 @@ int cuba_info(const cuba_ctx *ctx, uint32_t *next_step, int64_t *n,
 int cuba_counters(cuba_ctx *ctx, uint64_t out[3]);
 
 /* Stage timing.  cuba_timing_begin makes the following steps and
- * observations record HIP events on the context's stream around each
- * kernel launch, for at most max_launches launches; cuba_timing_end waits
- * for the stream and writes, per stage, the summed duration in ms and the
- * number of launches timed.  Stages (index into the arrays):
+ * observations record two HIP events on the context's stream for each
+ * launch, for at most max_launches launches: on the kernel's own dispatch
+ * where the stage is one kernel (so they read its duration), else around
+ * the stage's kernels.  cuba_timing_end waits for the stream and writes,
+ * per stage, the summed duration in ms and the number of launches timed.
+ * Stages (index into the arrays):
  *   0 bin      stream + reflect + bin (first step of a cuba_step call)
  *   1 step     fused: pair tests, claims and kinematics of step t, then
  *              stream + reflect + bin of step t+1
