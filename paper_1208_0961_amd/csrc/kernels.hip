@@ -720,9 +720,11 @@ __device__ __forceinline__ uint32_t test_pairs(
 }
 
 // Cells of more than kBucketRankMin particles rank their ids through
-// kRankBuckets buckets by value; smaller cells count all ids.
+// kRankBuckets buckets by value; smaller cells (one particle a lane) count
+// all ids, a shorter chain of independent LDS reads than the buckets'
+// reductions, scan and atomics.
 constexpr uint32_t kRankBuckets = 256;
-constexpr uint32_t kBucketRankMin = 48;
+constexpr uint32_t kBucketRankMin = 63;
 
 __device__ __forceinline__ uint32_t wave_min(uint32_t v) {
 #pragma unroll

@@ -6,7 +6,7 @@ wave per cell, so:
 
 * fused steps (and the collide-only step that ends a run) match one oracle
   step from the GPU's previous state, on a dense tube, on ragged cells (the
-  counting rank below 49 particles, fewer pairs than one 128-pair block),
+  counting rank below 64 particles, fewer pairs than one 128-pair block),
   and on a cell at the 1024 cap with 2K = 1, where every pair passes the
   Philox filter and the second wave's buffer fills, so that the first wave
   resumes the tests where it stopped;
@@ -31,7 +31,7 @@ def test_two_waves_dense_tube(orc, lib):  # noqa: F811
 
 
 def test_two_waves_ragged_cells(orc, lib):  # noqa: F811
-    occ = [0, 1, 2, 3, 9, 17, 23, 33, 48, 49, 65, 120, 200, 300] + [4] * 50
+    occ = [0, 1, 2, 3, 9, 17, 23, 33, 48, 63, 64, 65, 120, 200, 300] + [4] * 49
     state = _cells_box(occ, seed=8)
     params = dict(box=(1.0, 1.0, 1.0), cells=(4, 4, 4), sigma=2.0, r_test=1.0,
                   dt=0.001, seed=3)
