@@ -168,13 +168,12 @@ __device__ __forceinline__ void spill_particle(const GCells &dst, uint32_t c2, u
   if (slot == dst.cap) sp->ocell[atomicAdd(&h[1], 1u)] = c2;
 }
 
-// Appends particle (r, p, id) to cell c2 of dst: into the cell's block, or
-// past its capacity into the spill region.
-__device__ __forceinline__ void append(const GCells &dst, uint32_t c2, bool active,
-                                       double x, double y, double z, double px,
-                                       double py, double pz, uint32_t id,
-                                       DevStatus *status) {
-  const uint32_t slot = aggregated_fetch_add(dst.count, c2, active);
+// Stores particle (r, p, id) at slot `slot` of cell c2 of dst: in the
+// cell's block, or past its capacity in the spill region.
+__device__ __forceinline__ void store_at_slot(const GCells &dst, uint32_t c2, uint32_t slot,
+                                              bool active, double x, double y, double z,
+                                              double px, double py, double pz, uint32_t id,
+                                              DevStatus *status) {
   if (active) {
     if (slot < dst.cap) {
       const size_t o = (size_t)c2 * dst.cap + slot;
@@ -189,6 +188,16 @@ __device__ __forceinline__ void append(const GCells &dst, uint32_t c2, bool acti
       spill_particle(dst, c2, slot, x, y, z, px, py, pz, id, status);
     }
   }
+}
+
+// Appends particle (r, p, id) to cell c2 of dst (a slot by the
+// wave-aggregated counter atomic).
+__device__ __forceinline__ void append(const GCells &dst, uint32_t c2, bool active,
+                                       double x, double y, double z, double px,
+                                       double py, double pz, uint32_t id,
+                                       DevStatus *status) {
+  const uint32_t slot = aggregated_fetch_add(dst.count, c2, active);
+  store_at_slot(dst, c2, slot, active, x, y, z, px, py, pz, id, status);
 }
 
 // The buffer laid out like c, `shift` bytes away.
@@ -504,6 +513,40 @@ __global__ __launch_bounds__(kBlock) void k_stream_bin(Cells src_arg, Cells dst_
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   __builtin_amdgcn_wave_barrier();
+}
+
+// Slots in the destination cells of a wave's particles that all move from
+// cell c0 to c0 or one of its 26 neighbours, direction
+// dir = 9 (dx + 1) + 3 (dy + 1) + (dz + 1) for axis offsets dx, dy, dz in
+// {-1, 0, 1} (x-major ids: the neighbour is c0 + dx sx + dy sy + dz).  LDS
+// atomics number each direction's lanes; lane d then adds direction d's
+// count to that cell's counter, one global atomic for every direction in
+// use, so the wave makes one round trip and no loop over its distinct
+// destinations.  s_dir: 54 words of LDS owned by the wave.  Every lane of
+// the wave calls it; an inactive lane passes dir 13 and ignores the result.
+__device__ __forceinline__ uint32_t neighbour_fetch_add(gptr<uint32_t> ctr, uint32_t c0,
+                                                        uint32_t sx, uint32_t sy, uint32_t dir,
+                                                        bool active, uint32_t *s_dir) {
+  const uint32_t lane = lane_id();
+  if (lane < 27u) s_dir[lane] = 0u;
+  wave_lds_sync();
+  uint32_t rank = 0;
+  if (active) rank = atomicAdd(&s_dir[dir], 1u);
+  wave_lds_sync();
+  if (lane < 27u) {
+    const uint32_t cnt = s_dir[lane];
+    uint32_t base = 0;
+    if (cnt != 0u) {
+      const int32_t dx = (int32_t)(lane / 9u) - 1, dy = (int32_t)(lane / 3u % 3u) - 1,
+                    dz = (int32_t)(lane % 3u) - 1;
+      const uint32_t key =
+          (uint32_t)((int32_t)c0 + dx * (int32_t)sx + dy * (int32_t)sy + dz);
+      base = atomic_add(ctr + key, cnt);
+    }
+    s_dir[27u + lane] = base;
+  }
+  wave_lds_sync();
+  return s_dir[27u + dir] + rank;
 }
 
 // Exclusive scan of the counts into compact offsets (trace only; the counts
@@ -1306,11 +1349,17 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
     // reference it would be reloaded after every store.
     const Geometry g_l = g;
     double se = 0.0, sp = 0.0, sxx = 0.0;
+    // the source cell's axis indices, for the direction of each move
+    const uint32_t sy = (uint32_t)g_l.n[2], sx = (uint32_t)g_l.n[1] * sy;
+    const int32_t cx = (int32_t)(cv.c / sx), cy = (int32_t)(cv.c % sx / sy),
+                  cz = (int32_t)(cv.c % sy);
+    uint32_t *const s_dir = lds.buf + (kW == 1 ? 0u : 64u * wv);  // the ids' dead buffer
     for (uint32_t j0 = wv * 64u; j0 < n; j0 += kT) {
       const uint32_t j = j0 + lane;
       const bool active = j < n;
       double x = 0, y = 0, z = 0, px = 0, py = 0, pz = 0;
-      uint32_t id = 0, c2 = 0;
+      uint32_t id = 0, c2 = 0, dir = 13u;
+      bool near = true;
       if (active) {
         const size_t o = cv.at(j);
         x = st.x[o];
@@ -1330,9 +1379,21 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
         }
         if (ob) obs_add(px, py, pz, se, sp, sxx);
         advance<true>(g_l, x, y, z, px, py, pz);
-        c2 = cell_id(g_l, x, y, z);
+        const int32_t ix = axis_index(x, g_l.dx[0], g_l.n[0]);
+        const int32_t iy = axis_index(y, g_l.dx[1], g_l.n[1]);
+        const int32_t iz = axis_index(z, g_l.dx[2], g_l.n[2]);
+        c2 = (uint32_t)((ix * g_l.n[1] + iy) * g_l.n[2] + iz);
+        const int32_t dx = ix - cx, dy = iy - cy, dz = iz - cz;
+        // a move of less than a cell edge crosses at most one face per axis
+        near = dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
+        dir = near ? (uint32_t)(9 * (dx + 1) + 3 * (dy + 1) + (dz + 1)) : 13u;
       }
-      append(dst, c2, active, x, y, z, px, py, pz, id, status);
+      if (__ballot(!near) == 0ull) {
+        const uint32_t slot = neighbour_fetch_add(dst.count, cv.c, sx, sy, dir, active, s_dir);
+        store_at_slot(dst, c2, slot, active, x, y, z, px, py, pz, id, status);
+      } else {
+        append(dst, c2, active, x, y, z, px, py, pz, id, status);
+      }
     }
     if (tid == 0) src.count[cv.c] = 0u;
     if (ob) obs_write_wave(ob, cv.c, n, se, sp, sxx);
