@@ -769,16 +769,41 @@ __device__ __forceinline__ uint32_t test_pairs(
 constexpr uint32_t kRankBuckets = 256;
 constexpr uint32_t kBucketRankMin = 63;
 
+// Minimum / maximum over the wave's 64 lanes, the same in every lane.  DPP
+// moves within the VALU instead of LDS permutes: within quads, half rows
+// and rows, then row 15's result into rows 1 and 3 and row 31's into rows
+// 2 and 3, so that lane 63 holds the whole wave's; lanes a move does not
+// write keep their own value.
+template <typename Op>
+__device__ __forceinline__ uint32_t wave_reduce(uint32_t v, Op op) {
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false));
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false));
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x141, 0xF, 0xF, false));
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x140, 0xF, 0xF, false));
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x142, 0xA, 0xF, false));
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x143, 0xC, 0xF, false));
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Inclusive prefix sum over the wave's lanes (every lane active): DPP
+// shifts by 1, 2, 4 and 8 within rows (lanes without a source add 0), then
+// row 15's sum into rows 1 and 3 and row 31's into rows 2 and 3.
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);
+  return x;
+}
+
 __device__ __forceinline__ uint32_t wave_min(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
-  return v;
+  return wave_reduce(v, [](uint32_t a, uint32_t b) { return a < b ? a : b; });
 }
 
 __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
-  return v;
+  return wave_reduce(v, [](uint32_t a, uint32_t b) { return a > b ? a : b; });
 }
 
 // LDS of a cell: buf holds the cell's ids while the canonical
@@ -1160,12 +1185,7 @@ __device__ __forceinline__ void cell_step(const GCells &src, const GCells &dst, 
         q.y += q.x;
         q.z += q.y;
         q.w += q.z;
-        uint32_t incl = q.w;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-          const uint32_t up = (uint32_t)__shfl_up((int)incl, o);
-          if ((int)lane >= o) incl += up;
-        }
+        const uint32_t incl = wave_inclusive_sum(q.w);
         const uint32_t excl = incl - q.w;
         q.x += excl;
         q.y += excl;
@@ -1781,12 +1801,7 @@ __device__ __forceinline__ void packed_cells_step(const GCells &src, const GCell
   const uint32_t ccnt = cc < n_cells ? src.count[cc] : 0u;
   const bool packed = cc < n_cells && ccnt <= kPackedMax && ccnt <= src.cap;
   const uint32_t nl = packed ? ccnt : 0u;
-  uint32_t incl = nl;  // inclusive prefix of the packed counts
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t up = (uint32_t)__shfl_up((int)incl, o);
-    if ((int)lane >= o) incl += up;
-  }
+  const uint32_t incl = wave_inclusive_sum(nl);  // inclusive prefix of the packed counts
   const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
   uint32_t cnt_pairs = 0, n_acc = 0, n_claims = 0;
   for (uint32_t base = 0; base < total;) {
