@@ -769,7 +769,8 @@ __device__ __forceinline__ uint32_t test_pairs(
 constexpr uint32_t kRankBuckets = 256;
 constexpr uint32_t kBucketRankMin = 63;
 
-// Minimum / maximum over the wave's 64 lanes, the same in every lane.  DPP
+// Minimum / maximum over the wave's 64 lanes (every lane active), the same
+// in every lane.  DPP
 // moves within the VALU instead of LDS permutes: within quads, half rows
 // and rows, then row 15's result into rows 1 and 3 and row 31's into rows
 // 2 and 3, so that lane 63 holds the whole wave's; lanes a move does not
